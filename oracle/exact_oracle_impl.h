@@ -1,0 +1,435 @@
+/*
+ * Body of the EXACT CPU oracle, written once and instantiated for several
+ * scalar types by exact_oracle.c (REAL = double, long double, float; FN()
+ * appends the type suffix to every exported name).  Everything here is plain
+ * loops in the order the definitions are stated; see exact_oracle.c for the
+ * definitions and their sources in the paper.
+ *
+ * TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may call this code.  It is never part of the product path.
+ */
+
+/* ---------------------------------------------------------------- geometry */
+
+/* theta_v = half_turns * pi * v / V (views evenly spaced, endpoint excluded). */
+static REAL FN(view_angle)(const ora_geom *g, int v)
+{
+    return (REAL)g->half_turns * (REAL)ORA_PI * (REAL)v / (REAL)g->n_views;
+}
+
+/* Stepping axis, decided by an integer test so that 45 and 135 degrees are
+ * row-stepping without any rounding dependence. */
+static int FN(row_stepping)(const ora_geom *g, int v)
+{
+    long q = ((long)g->half_turns * (long)v) % (long)g->n_views;
+    return 4 * q <= g->n_views || 4 * q >= 3L * g->n_views;
+}
+
+/* Per-view quantities of the definition. */
+typedef struct {
+    REAL ct, st;   /* cos theta, sin theta */
+    REAL wstep;    /* pixel width / |cos| (row-stepping) or / |sin| (column)  */
+    int row;       /* 1: one tap pair per image row; 0: per image column       */
+} FN(view);
+
+static FN(view) FN(make_view)(const ora_geom *g, int v)
+{
+    FN(view) w;
+    REAL th = FN(view_angle)(g, v);
+    w.ct = cos(th);
+    w.st = sin(th);
+    w.row = FN(row_stepping)(g, v);
+    w.wstep = (REAL)g->pixel_cm / (w.row ? fabs(w.ct) : fabs(w.st));
+    return w;
+}
+
+/* Detector coordinate of bin b: u_b = (b - (B-1)/2) * bin width. */
+static REAL FN(bin_centre)(const ora_geom *g, int b)
+{
+    return ((REAL)b - (REAL)(g->n_bins - 1) / 2) * (REAL)g->bin_cm;
+}
+
+/* Fractional image coordinate where ray (view w, detector u) crosses the
+ * centre line of row/column `k` (row index for row-stepping views, column
+ * index otherwise), in pixel units with 0 at the first pixel centre. */
+static REAL FN(crossing)(const ora_geom *g, const FN(view) *w, REAL u, int k)
+{
+    REAL c = (REAL)(g->n_pix - 1) / 2;
+    REAL dpix = (REAL)g->pixel_cm;
+    REAL along = ((REAL)k - c) * dpix;        /* eta_k (row) or xi_k (column) */
+    if (w->row)
+        return ((u - along * w->st) / w->ct) / dpix + c;
+    return ((u - along * w->ct) / w->st) / dpix + c;
+}
+
+/* One matrix entry A[(v,b), (iy,ix)] straight from the definition:
+ * wstep * max(0, 1 - |f - j|) where f is the crossing on the stepping line
+ * through the pixel and j the pixel's index across that line. */
+static REAL FN(entry)(const ora_geom *g, const FN(view) *w, int b, int iy, int ix)
+{
+    REAL u = FN(bin_centre)(g, b);
+    REAL f = FN(crossing)(g, w, u, w->row ? iy : ix);
+    REAL tent = 1 - fabs(f - (REAL)(w->row ? ix : iy));
+    return tent > 0 ? w->wstep * tent : 0;
+}
+
+/* --------------------------------------------------------- linear operators */
+
+/* s = A x.  For each ray, walk the stepping lines in increasing order; on
+ * each line only the two pixels bracketing the crossing can have a positive
+ * tent weight. */
+static void FN(forward_rays)(const ora_geom *g, const REAL *x, int nsel,
+                             const long *sel, REAL *s)
+{
+    int N = g->n_pix, B = g->n_bins;
+    for (int q = 0; q < nsel; ++q) {
+        long i = sel ? sel[q] : q;
+        int v = (int)(i / B), b = (int)(i % B);
+        FN(view) w = FN(make_view)(g, v);
+        REAL u = FN(bin_centre)(g, b);
+        REAL acc = 0;
+        for (int k = 0; k < N; ++k) {
+            REAL f = FN(crossing)(g, &w, u, k);
+            REAL fl = floor(f);
+            if (fl < -1 || fl > N - 1)
+                continue;
+            for (int j = (int)fl; j <= (int)fl + 1; ++j) {
+                if (j < 0 || j >= N)
+                    continue;
+                REAL tent = 1 - fabs(f - (REAL)j);
+                if (tent <= 0)
+                    continue;
+                long p = w.row ? (long)k * N + j : (long)j * N + k;
+                acc += w.wstep * tent * x[p];
+            }
+        }
+        s[q] = acc;
+    }
+}
+
+/* img = A^T r in scatter form: every ray adds its weighted value into the
+ * pixels it touches, in ray order. */
+static void FN(back_scatter)(const ora_geom *g, const REAL *r, REAL *img)
+{
+    int N = g->n_pix, V = g->n_views, B = g->n_bins;
+    for (long p = 0; p < (long)N * N; ++p)
+        img[p] = 0;
+    for (int v = 0; v < V; ++v) {
+        FN(view) w = FN(make_view)(g, v);
+        for (int b = 0; b < B; ++b) {
+            REAL rv = r[(long)v * B + b];
+            REAL u = FN(bin_centre)(g, b);
+            for (int k = 0; k < N; ++k) {
+                REAL f = FN(crossing)(g, &w, u, k);
+                REAL fl = floor(f);
+                if (fl < -1 || fl > N - 1)
+                    continue;
+                for (int j = (int)fl; j <= (int)fl + 1; ++j) {
+                    if (j < 0 || j >= N)
+                        continue;
+                    REAL tent = 1 - fabs(f - (REAL)j);
+                    if (tent <= 0)
+                        continue;
+                    long p = w.row ? (long)k * N + j : (long)j * N + k;
+                    img[p] += w.wstep * tent * rv;
+                }
+            }
+        }
+    }
+}
+
+/* (A^T r)_p for selected pixels, one at a time: the sum over every ray of
+ * entry(ray, p) * r_ray.  Slow (V*B entries per pixel) and used for sampled
+ * checks at full problem sizes. */
+static void FN(back_pixels)(const ora_geom *g, const REAL *r, int nsel,
+                            const long *sel, REAL *out)
+{
+    int N = g->n_pix, V = g->n_views, B = g->n_bins;
+    for (int q = 0; q < nsel; ++q) {
+        int iy = (int)(sel[q] / N), ix = (int)(sel[q] % N);
+        REAL acc = 0;
+        for (int v = 0; v < V; ++v) {
+            FN(view) w = FN(make_view)(g, v);
+            for (int b = 0; b < B; ++b) {
+                REAL a = FN(entry)(g, &w, b, iy, ix);
+                if (a != 0)
+                    acc += a * r[(long)v * B + b];
+            }
+        }
+        out[q] = acc;
+    }
+}
+
+/* ------------------------------------------------------- spectral model */
+
+/* Literal per-window residual: r_i = sum_j y[j][i] - sum_j sum_k
+ * Iwk[j][k] exp(-mu_k max(s_i, 0)). */
+static void FN(residual)(long n, int K, int Wn, const REAL *mu, const REAL *Iwk,
+                         const REAL *y, const REAL *s, REAL *r, REAL *model)
+{
+    for (long i = 0; i < n; ++i) {
+        REAL sp = s[i] > 0 ? s[i] : 0;
+        REAL ysum = 0, m = 0;
+        for (int j = 0; j < Wn; ++j)
+            ysum += y[(long)j * n + i];
+        for (int j = 0; j < Wn; ++j)
+            for (int k = 0; k < K; ++k)
+                m += Iwk[(long)j * K + k] * exp(-mu[k] * sp);
+        r[i] = ysum - m;
+        if (model)
+            model[i] = m;
+    }
+}
+
+typedef struct {
+    int K, Wn;
+    REAL *mu, *Iwk, *y;      /* [K], [Wn*K], [Wn*n] */
+} FN(spec);
+
+/* F(x) = (1/n) A^T (Y - model(Ax)), n = number of rays. */
+static void FN(apply_F)(const ora_geom *g, const FN(spec) *sp, const REAL *x,
+                        REAL *F, REAL *s, REAL *r)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    FN(forward_rays)(g, x, (int)n, 0, s);
+    FN(residual)(n, sp->K, sp->Wn, sp->mu, sp->Iwk, sp->y, s, r, 0);
+    FN(back_scatter)(g, r, F);
+    for (long p = 0; p < d; ++p)
+        F[p] = F[p] / (REAL)n;
+}
+
+/* ------------------------------------------------------ helpers (copy in) */
+
+static REAL *FN(to_real)(const double *a, long len)
+{
+    REAL *o = (REAL *)calloc((size_t)(len > 0 ? len : 1), sizeof(REAL));
+    for (long i = 0; i < len; ++i)
+        o[i] = (REAL)a[i];
+    return o;
+}
+
+static void FN(to_double)(const REAL *a, long len, double *o)
+{
+    for (long i = 0; i < len; ++i)
+        o[i] = (double)a[i];
+}
+
+static REAL FN(dot)(const REAL *a, const REAL *b, long len)
+{
+    REAL acc = 0;
+    for (long i = 0; i < len; ++i)
+        acc += a[i] * b[i];
+    return acc;
+}
+
+static FN(spec) FN(load_spec)(const ora_geom *g, int K, int Wn, const double *mu,
+                              const double *Iwk, const double *y)
+{
+    FN(spec) sp;
+    long n = (long)g->n_views * g->n_bins;
+    sp.K = K;
+    sp.Wn = Wn;
+    sp.mu = FN(to_real)(mu, K);
+    sp.Iwk = FN(to_real)(Iwk, (long)Wn * K);
+    sp.y = y ? FN(to_real)(y, (long)Wn * n) : 0;
+    return sp;
+}
+
+static void FN(free_spec)(FN(spec) *sp)
+{
+    free(sp->mu);
+    free(sp->Iwk);
+    free(sp->y);
+}
+
+/* ------------------------------------------------------------ exported API */
+
+void FN(ora_forward)(const ora_geom *g, const double *x, double *s)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    REAL *xr = FN(to_real)(x, d);
+    REAL *sr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    FN(forward_rays)(g, xr, (int)n, 0, sr);
+    FN(to_double)(sr, n, s);
+    free(xr);
+    free(sr);
+}
+
+void FN(ora_forward_rays)(const ora_geom *g, const double *x, int nsel,
+                          const long *sel, double *s)
+{
+    long d = (long)g->n_pix * g->n_pix;
+    REAL *xr = FN(to_real)(x, d);
+    REAL *sr = (REAL *)malloc(sizeof(REAL) * (size_t)(nsel > 0 ? nsel : 1));
+    FN(forward_rays)(g, xr, nsel, sel, sr);
+    FN(to_double)(sr, nsel, s);
+    free(xr);
+    free(sr);
+}
+
+void FN(ora_back)(const ora_geom *g, const double *r, double *img)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    REAL *rr = FN(to_real)(r, n);
+    REAL *ir = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    FN(back_scatter)(g, rr, ir);
+    FN(to_double)(ir, d, img);
+    free(rr);
+    free(ir);
+}
+
+void FN(ora_back_pixels)(const ora_geom *g, const double *r, int nsel,
+                         const long *sel, double *out)
+{
+    long n = (long)g->n_views * g->n_bins;
+    REAL *rr = FN(to_real)(r, n);
+    REAL *o = (REAL *)malloc(sizeof(REAL) * (size_t)(nsel > 0 ? nsel : 1));
+    FN(back_pixels)(g, rr, nsel, sel, o);
+    FN(to_double)(o, nsel, out);
+    free(rr);
+    free(o);
+}
+
+void FN(ora_residual)(long n, int K, int Wn, const double *mu, const double *Iwk,
+                      const double *y, const double *s, double *r, double *model)
+{
+    REAL *mur = FN(to_real)(mu, K), *Ir = FN(to_real)(Iwk, (long)Wn * K);
+    REAL *yr = FN(to_real)(y, (long)Wn * n), *sr = FN(to_real)(s, n);
+    REAL *rr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *mr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    FN(residual)(n, K, Wn, mur, Ir, yr, sr, rr, mr);
+    FN(to_double)(rr, n, r);
+    if (model)
+        FN(to_double)(mr, n, model);
+    free(mur); free(Ir); free(yr); free(sr); free(rr); free(mr);
+}
+
+/* F(x); optionally also returns s = Ax and r (each may be NULL). */
+void FN(ora_operator)(const ora_geom *g, int K, int Wn, const double *mu,
+                      const double *Iwk, const double *y, const double *x,
+                      double *F, double *s_out, double *r_out)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    REAL *xr = FN(to_real)(x, d);
+    REAL *Fr = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *sr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *rr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    FN(apply_F)(g, &sp, xr, Fr, sr, rr);
+    FN(to_double)(Fr, d, F);
+    if (s_out)
+        FN(to_double)(sr, n, s_out);
+    if (r_out)
+        FN(to_double)(rr, n, r_out);
+    FN(free_spec)(&sp);
+    free(xr); free(Fr); free(sr); free(rr);
+}
+
+/*
+ * Projected extragradient, x in/out (x_1 on entry, last iterate on exit):
+ *   x_{t+1/2} = max(0, x_t - gamma F(x_t))
+ *   x_{t+1}   = max(0, x_t - gamma F(x_{t+1/2}))
+ * for t = 1..max_iters.  If tol > 0, after step t the natural residual
+ * rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| (undefined, hence not tested, while
+ * x_t = 0) is compared with tol and the loop stops with x_{t+1} once
+ * rho_t <= tol.  rho_hist (nullable, length max_iters) receives rho_t
+ * (-1 where undefined).  Returns the number of steps taken.
+ */
+int FN(ora_eg)(const ora_geom *g, int K, int Wn, const double *mu,
+               const double *Iwk, const double *y, double *x, double gamma,
+               int max_iters, double tol, double *rho_hist)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    REAL *xt = FN(to_real)(x, d);
+    REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL gm = (REAL)gamma;
+    int t;
+    for (t = 1; t <= max_iters; ++t) {
+        FN(apply_F)(g, &sp, xt, F, s, r);
+        REAL num = 0, den = 0;
+        for (long p = 0; p < d; ++p) {
+            REAL z = xt[p] - gm * F[p];
+            xh[p] = z > 0 ? z : 0;
+            num += (xh[p] - xt[p]) * (xh[p] - xt[p]);
+            den += xt[p] * xt[p];
+        }
+        double rho = den > 0 ? (double)sqrt(num / den) : -1.0;
+        if (rho_hist)
+            rho_hist[t - 1] = rho;
+        FN(apply_F)(g, &sp, xh, F, s, r);
+        for (long p = 0; p < d; ++p) {
+            REAL z = xt[p] - gm * F[p];
+            xt[p] = z > 0 ? z : 0;
+        }
+        if (tol > 0 && rho >= 0 && rho <= tol)
+            break;
+    }
+    if (t > max_iters)
+        t = max_iters;
+    FN(to_double)(xt, d, x);
+    FN(free_spec)(&sp);
+    free(xt); free(xh); free(F); free(s); free(r);
+    return t;
+}
+
+/*
+ * Largest eigenvalue of Sigma = A^T A / n by power iteration from the
+ * constant unit vector, with Rayleigh quotients; stops when the quotient
+ * changes by less than rel_tol (relative) or after max_iters products.
+ */
+double FN(ora_power)(const ora_geom *g, int max_iters, double rel_tol, int *iters_out)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    REAL *v = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *u = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL lam = 0;
+    int it;
+    for (long p = 0; p < d; ++p)
+        v[p] = 1 / sqrt((REAL)d);
+    for (it = 1; it <= max_iters; ++it) {
+        FN(forward_rays)(g, v, (int)n, 0, s);
+        FN(back_scatter)(g, s, u);
+        for (long p = 0; p < d; ++p)
+            u[p] = u[p] / (REAL)n;
+        REAL lam_new = FN(dot)(v, u, d) / FN(dot)(v, v, d);
+        REAL nu = sqrt(FN(dot)(u, u, d));
+        for (long p = 0; p < d; ++p)
+            v[p] = u[p] / nu;
+        int done = it > 1 && fabs(lam_new - lam) <= (REAL)rel_tol * fabs(lam_new);
+        lam = lam_new;
+        if (done)
+            break;
+    }
+    if (iters_out)
+        *iters_out = it > max_iters ? max_iters : it;
+    free(v); free(u); free(s);
+    return (double)lam;
+}
+
+/* Number of positive entries of A (exact count under the definition). */
+long FN(ora_nnz)(const ora_geom *g)
+{
+    int N = g->n_pix, V = g->n_views, B = g->n_bins;
+    long cnt = 0;
+    for (int v = 0; v < V; ++v) {
+        FN(view) w = FN(make_view)(g, v);
+        for (int b = 0; b < B; ++b) {
+            REAL u = FN(bin_centre)(g, b);
+            for (int k = 0; k < N; ++k) {
+                REAL f = FN(crossing)(g, &w, u, k);
+                REAL fl = floor(f);
+                if (fl < -1 || fl > N - 1)
+                    continue;
+                for (int j = (int)fl; j <= (int)fl + 1; ++j)
+                    if (j >= 0 && j < N && 1 - fabs(f - (REAL)j) > 0)
+                        ++cnt;
+            }
+        }
+    }
+    return cnt;
+}
