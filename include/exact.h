@@ -1,0 +1,222 @@
+/*
+ * exact.h -- C ABI of libexact, the MI355X (gfx950) implementation of the
+ * hot path of EXACT (EXtragradient Algorithm for Computed Tomography):
+ * projected extragradient for single-material polychromatic CT,
+ * arXiv 2503.19925.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Geometry.  2-D parallel beam.  The image is N x N square pixels of side
+ *  pixel_cm centred at the origin; pixel (iy, ix) has centre
+ *  ((ix - c) pixel_cm, (iy - c) pixel_cm) with c = (N-1)/2 and iy = 0 the
+ *  bottom row.  View v (0 <= v < V) is at theta_v = half_turns * pi * v / V;
+ *  detector bin b (0 <= b < B) sits at u_b = (b - (B-1)/2) bin_cm; ray
+ *  i = v*B + b is the line {p : p . (cos theta_v, sin theta_v) = u_b}.
+ *  A is Joseph's matrix: a ray walks the image rows (views with
+ *  |cos| >= |sin|, ties at 45/135 degrees decided by the integer test
+ *  4q <= V or 4q >= 3V, q = half_turns*v mod V) or columns, and on each
+ *  line puts tent weight max(0, 1 - |f - j|) on the pixels j next to its
+ *  crossing f, times the path length per line pixel_cm/|cos| (rows) or
+ *  pixel_cm/|sin| (columns).  Entries are nonnegative, as the paper
+ *  requires of A (Sec. 1, forward model and the notation list below it).
+ *
+ *  Layouts (all device memory, float32, row-major, no padding):
+ *    image   x[N*N]        p = iy*N + ix
+ *    sinogram s[V*B]       i = v*B + b   (bins fastest)
+ *    counts  y[Wn*V*B]     window-major: y[j*V*B + i]
+ *
+ *  Units: x in g/cm^3, lengths in cm, line integrals in g/cm^2, mu in
+ *  cm^2/g, counts in photons.
+ *
+ *  Ownership.  The caller allocates and owns every device buffer passed in
+ *  (the library never frees them).  The library owns the geometry handle
+ *  and its device tables, and any scratch it needs (allocated stream-ordered
+ *  and released before the call's work completes on the stream).  Host
+ *  spectrum arrays are copied during the call.
+ *
+ *  Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every call
+ *  except exact_solve and exact_step_size is stream-ordered and returns
+ *  before the GPU work finishes.  A geometry handle may be used from several
+ *  streams at once.
+ *
+ *  Errors.  0 on success; a negative errno value on failure (-EINVAL bad
+ *  argument, -ENOMEM out of memory, -EIO a HIP runtime error); see
+ *  exact_last_error() for a message.  exact_solve returns EXACT_ENOTCONV
+ *  (+1) when max_iters ends the run before the tolerance is met.  No C++
+ *  exception crosses this interface.
+ */
+#ifndef EXACT_H
+#define EXACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXACT_ENOTCONV 1
+
+typedef struct exact_geometry_s *exact_geometry;
+
+/*
+ * Known spectrum of the single material (paper Sec. 1, eq.
+ * model:multi-material with one material; Sec. 1.2, eq. function-h-plus):
+ * expected counts in window j on ray i are
+ *     sum_k weight[j*K + k] * exp(-mu[k] * max(<a_i, x>, 0)),
+ * weight[j][k] = Ibar_j * s_{jk} >= 0.  Host pointers, copied by each call.
+ * Requirements: K >= 1, Wn >= 1, every mu[k] > 0 and finite, every weight
+ * finite and >= 0, each window's row sum > 0.
+ */
+typedef struct {
+    int32_t n_energies;     /* K  */
+    int32_t n_windows;      /* Wn */
+    const double *mu;       /* [K]      */
+    const double *weight;   /* [Wn][K]  */
+} exact_spectrum;
+
+/* Stop rules for exact_solve. */
+#define EXACT_STOP_NATURAL_RESIDUAL 0
+
+typedef struct {
+    double gamma;        /* step size; <= 0 selects gamma_scale / L (below)  */
+    double gamma_scale;  /* c in gamma = c / (lambda_max(A^T A / n) *
+                            sum_k J_k mu_k), J_k = sum_j weight[j][k];
+                            Theorem 2 uses c = 1/4 (default)                */
+    int32_t max_iters;   /* full extragradient steps (two F evaluations each) */
+    double tol;          /* stop after step t once rho_t <= tol; 0 = run all */
+    int32_t stop_mode;   /* EXACT_STOP_NATURAL_RESIDUAL                      */
+    int32_t check_every; /* steps between host reads of the device stop flag */
+    int32_t power_iters; /* cap on power-iteration steps for lambda_max     */
+} exact_solve_opts;
+
+typedef struct {
+    int32_t iters;       /* steps taken                                      */
+    double resid;        /* last rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| (-1 if
+                            undefined, i.e. x_t = 0)                         */
+    double gamma;        /* step size used                                   */
+    double lambda_hat;   /* lambda_max estimate (0 if gamma was given)       */
+    double ms;           /* wall time of the call                            */
+} exact_solve_info;
+
+/* Fills opts with the defaults: gamma 0 (automatic), gamma_scale 0.25,
+ * max_iters 500, tol 0, natural-residual stop, check_every 16,
+ * power_iters 100. */
+void exact_solve_opts_default(exact_solve_opts *opts);
+
+/*
+ * Builds the per-view tables of the geometry above and uploads them to the
+ * current HIP device.  n_pix, n_views, n_bins >= 1; n_pix <= 16384 and
+ * n_views * n_bins < 2^31; half_turns 1 (180 degrees) or 2 (360 degrees);
+ * pixel_cm, bin_cm > 0 and finite.  *out receives the handle.
+ */
+int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins,
+                          int32_t half_turns, double pixel_cm, double bin_cm,
+                          exact_geometry *out);
+
+/* Releases the handle (synchronises the device first).  NULL is a no-op. */
+int exact_geometry_destroy(exact_geometry g);
+
+/*
+ * Line integrals s = A x (the inner product <a_i, x> of paper Sec. 1.2,
+ * eq. model-pre, for every ray).  x_dev [N*N], s_dev [V*B].
+ */
+int exact_forward(exact_geometry g, const float *x_dev, float *s_dev,
+                  void *stream);
+
+/*
+ * Back-projection img = A^T r (the sum over rays of r_i a_i in the operator
+ * of paper Sec. 1.2, eq. operator, without its 1/n).  Exact transpose of
+ * exact_forward: the same weights, computed per pixel (gather), with no
+ * atomics, so results are bitwise reproducible.  r_dev [V*B], img_dev [N*N].
+ */
+int exact_backproject(exact_geometry g, const float *r_dev, float *img_dev,
+                      void *stream);
+
+/*
+ * The monotone operator of paper Sec. 1.2, eq. operator, summed over
+ * windows:
+ *     F(x) = (1/n) A^T r,   r_i = sum_j y[j][i] - sum_k J_k exp(-mu_k (Ax)_i+),
+ * n = V*B (rays), J_k = sum_j weight[j][k].  y_dev [Wn*V*B], x_dev [N*N],
+ * F_dev [N*N]; r_dev [V*B] receives r, or NULL.
+ */
+int exact_operator(exact_geometry g, const exact_spectrum *sp,
+                   const float *y_dev, const float *x_dev, float *F_dev,
+                   float *r_dev, void *stream);
+
+/*
+ * lambda_max(Sigma), Sigma = A^T A / n (paper Sec. 1.3), by power iteration
+ * from the constant vector with double-precision Rayleigh quotients (at
+ * most max_iters steps, stopping when the quotient changes by less than
+ * 1e-7 relative), and the step size gamma = gamma_scale / (lambda *
+ * sum_k J_k mu_k) of Theorem 2 when sp is not NULL.  Blocks until done.
+ * gamma_out may be NULL.
+ */
+int exact_step_size(exact_geometry g, const exact_spectrum *sp,
+                    int32_t max_iters, double gamma_scale, double *lambda_out,
+                    double *gamma_out, void *stream);
+
+/*
+ * Projected extragradient (paper Sec. 1.2, eq. extragrad-method) over
+ * X = {x >= 0} (the orthant projection of Sec. 3.1):
+ *     x_{t+1/2} = max(0, x_t - gamma F(x_t)),
+ *     x_{t+1}   = max(0, x_t - gamma F(x_{t+1/2})),   t = 1, 2, ...
+ * x_dev holds x_1 >= 0 on entry and the last iterate on return.  With
+ * tol > 0 the run stops after the first step t with
+ * rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| <= tol (norms in double), returning
+ * x_{t+1}; otherwise it runs max_iters steps.  Blocks until done; info
+ * (nullable) receives the summary.  Returns EXACT_ENOTCONV if tol > 0 and
+ * max_iters steps did not reach it (x_dev then holds the last iterate).
+ * Checks on the device that y is finite and >= 0 and x_1 finite and >= 0
+ * (-EINVAL otherwise, x_dev unchanged).
+ */
+int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
+                float *x_dev, const exact_solve_opts *opts,
+                exact_solve_info *info, void *stream);
+
+/*
+ * Resident solver: the same iteration as exact_solve, split so that a caller
+ * can keep the run's state on the device and advance it in pieces.
+ *
+ * exact_solver_create validates the inputs (as exact_solve does), computes
+ * the step size (power iteration when opts->gamma <= 0), allocates the run's
+ * device state (about 16 N^2 + 8 V B bytes) and captures one full
+ * extragradient step as a HIP graph.  y_dev is read during the call only;
+ * x_dev is the iterate, updated in place by every step: it must stay valid
+ * and must not be written by the caller until exact_solver_destroy.  Blocks
+ * until set-up is done.
+ *
+ * exact_solver_step enqueues n_steps full steps on `stream` (asynchronous,
+ * ordered after the stream's earlier work and before its later work).
+ * Steps after the run has stopped (tolerance met or max_iters reached) are
+ * no-ops on the device, so over-enqueueing is harmless.
+ *
+ * exact_solver_poll waits for the enqueued steps, fills info (nullable)
+ * and returns 1 once the run has stopped, 0 while it is still running.
+ *
+ * exact_solver_destroy waits for the run's work and frees its state.
+ */
+typedef struct exact_solver_s *exact_solver;
+
+int exact_solver_create(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
+                        float *x_dev, const exact_solve_opts *opts, exact_solver *out,
+                        void *stream);
+int exact_solver_step(exact_solver s, int32_t n_steps, void *stream);
+int exact_solver_poll(exact_solver s, exact_solve_info *info);
+int exact_solver_destroy(exact_solver s);
+
+/*
+ * Exact number of positive entries of A (the tent weights that round to a
+ * positive float), counted on the device with the projectors' own weight
+ * expression.  Blocks until done.
+ */
+int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *exact_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXACT_H */

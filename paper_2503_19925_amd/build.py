@@ -1,0 +1,39 @@
+"""Builds libexact.so (HIP for gfx950) in the package directory.
+
+    python -m paper_2503_19925_amd.build
+
+Flags: gfx950 only; packed-FP32 instruction selection disabled (some forms
+have produced wrong results on these parts); floating-point contraction off
+so that every fused multiply-add in the kernels is an explicit fma/fmaf
+(the projector weights must be bit-identical in the forward and the
+back-projector).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libexact.so")
+SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_capi.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-command-line-argument"]
+
+
+def build(verbose=False):
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+                             "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of
+// libexact.  Not installed; the public interface is include/exact.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace exact {
+
+// Largest number of energy bins the fused epilogue takes by value.
+constexpr int kMaxEnergies = 128;
+
+// One view of the Joseph projector, in pixel-index units.
+//
+// A ray (v, b) crosses stepping line k (row iy for row-stepping views,
+// column ix otherwise) at the fractional pixel index
+//     f(b, k) = fma(k, Q, fma(b, P, A))            (double, exactly this form)
+// and puts weight wstep * (float)(1 - |f - j|) on pixel j of that line when
+// positive.  Forward and back-projection evaluate this same expression, so
+// both apply bit-identical matrix entries.
+//
+// The back-projector finds the bins whose crossing on line k falls within
+// one pixel of pixel j from the float estimate fb = fmaf(j, cbpix,
+// fmaf(k, cbk, cb0)), scanning every b with |b - fb| <= halfw.
+struct alignas(16) ViewGeom {
+    double A, P, Q;
+    float cb0, cbpix, cbk, halfw;
+    float wstep;
+    int32_t col;     // 0: row-stepping (k = iy, j = ix); 1: column (k = ix, j = iy)
+};
+static_assert(sizeof(ViewGeom) == 48, "ViewGeom layout");
+
+// Spectrum collapsed over windows, passed to kernels by value.
+struct SpecArg {
+    int32_t K;
+    float J[kMaxEnergies];    // J_k = sum_j weight[j][k]
+    float mu[kMaxEnergies];
+};
+
+// Device-side state of one extragradient run.
+struct SolveState {
+    double rho;          // last natural residual (-1 if undefined)
+    double lam;          // power iteration: Rayleigh quotient
+    double unorm;        // power iteration: ||u||
+    double tol;
+    int32_t t;           // steps completed
+    int32_t done;        // nonzero: every later kernel of the run is a no-op
+    int32_t converged;
+    int32_t max_iters;
+};
+
+struct Geo {
+    const ViewGeom *views;
+    int N, V, B;
+};
+
+// Partial sums produced per workgroup by the update and dot kernels.
+constexpr int kTile = 32;
+
+int num_tiles(int N);
+int num_dot_parts(long d);
+int num_count_parts(const Geo &g);
+
+hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st);
+
+hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st);
+hipError_t launch_fill(float *x, float value, long count, hipStream_t st);
+hipError_t launch_forward(const Geo &g, const float *x, const float *xT,
+                          float *s, const int32_t *skip, hipStream_t st);
+hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT,
+                                   const float *Y, const SpecArg &sp, float *r,
+                                   const int32_t *skip, hipStream_t st);
+hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
+                       const int32_t *skip, hipStream_t st);
+hipError_t launch_window_sum(const float *y, int Wn, long n, float *Y,
+                             int32_t *bad, hipStream_t st);
+hipError_t launch_count_bad(const float *x, long count, int32_t *bad,
+                            hipStream_t st);
+hipError_t launch_state_init(SolveState *state, double tol, int max_iters,
+                             hipStream_t st);
+// z = max(0, x - gamma g) for every pixel, written to z and (transposed) zT.
+// With partials != nullptr also writes per-tile double partial sums of
+// ||z - x||^2 and ||x||^2 (2 per tile).  z may alias x.
+hipError_t launch_eg_update(const float *x, const float *g, float gamma, float *z,
+                            float *zT, int N, double *partials,
+                            const int32_t *skip, hipStream_t st);
+// Fixed-order reduction of the update partials; sets rho_t, advances t and
+// raises done when rho_t <= tol or t reaches max_iters.
+hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *state,
+                            hipStream_t st);
+// Power iteration helpers: partials of <v,u>, <v,v>, <u,u>; reduction into
+// state->lam and state->unorm; v = u / unorm (and its transpose).
+hipError_t launch_dot3(const float *v, const float *u, int N, double *partials,
+                       hipStream_t st);
+hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *state,
+                              hipStream_t st);
+hipError_t launch_normalize(const float *u, float *v, float *vT, int N,
+                            const SolveState *state, hipStream_t st);
+
+}  // namespace exact

@@ -1,0 +1,545 @@
+// HIP kernels of libexact for CDNA4 (gfx950, wave64).
+//
+// Joseph forward projector with the polychromatic residual fused in, the
+// gather back-projector that applies the identical transposed weights, the
+// projected extragradient update and the double-precision reductions behind
+// the step size and the stop test.  Everything here is deterministic: no
+// atomics, fixed summation orders.
+#include "exact_internal.h"
+
+#include <cmath>
+
+namespace exact {
+namespace {
+
+constexpr int kFwdThreads = 64;     // one wave: 64 consecutive bins of a view
+constexpr int kBackX = 16, kBackY = 16;
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ bool skipped(const int32_t *skip)
+{
+    return skip != nullptr && *skip != 0;
+}
+
+// Kahan-compensated accumulation.
+struct Kahan {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float t)
+    {
+        const float y = t - c;
+        const float u = s + y;
+        c = (u - s) - y;
+        s = u;
+    }
+    __device__ __forceinline__ float value() const { return s - c; }
+};
+
+// Fixed-order sum of one double per thread over a kRedThreads block.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThreads])
+{
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        lds[q][t] = v[q];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                lds[q][t] += lds[q][t + w];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        v[q] = lds[q][0];
+}
+
+// ---------------------------------------------------------------- forward
+
+// One lane per ray (v, b).  The ray walks its stepping lines k in increasing
+// order; on each it interpolates between the two pixels around the crossing.
+// Column-stepping views read the transposed image so that the lanes of a
+// wave touch neighbouring addresses on every line.
+template <bool kResid>
+__global__ __launch_bounds__(kFwdThreads) void k_forward(
+    const ViewGeom *__restrict__ views, int N, int B, const float *__restrict__ x,
+    const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
+    float *__restrict__ out, const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    const int v = blockIdx.y;
+    const int b = blockIdx.x * kFwdThreads + threadIdx.x;
+    if (b >= B)
+        return;
+    const ViewGeom G = views[v];
+    const float *__restrict__ img = G.col ? xT : x;
+    const double base = fma((double)b, G.P, G.A);
+
+    // Lines whose crossing lies in (-1, N); outside that range no tap is in
+    // the image.  The per-line bounds test below stays authoritative.
+    double lo = 0.0, hi = (double)(N - 1);
+    if (G.Q != 0.0) {
+        const double ka = (-1.0 - base) / G.Q, kb = ((double)N - base) / G.Q;
+        lo = fmax(lo, floor(fmin(ka, kb)));
+        hi = fmin(hi, ceil(fmax(ka, kb)));
+    } else if (!(base > -1.0 && base < (double)N)) {
+        hi = -1.0;
+    }
+    const int k0 = (int)lo, k1 = (int)hi;
+
+    Kahan acc;
+    for (int k = k0; k <= k1; ++k) {
+        const double f = fma((double)k, G.Q, base);
+        const double fl = floor(f);
+        if (fl < -1.0 || fl > (double)(N - 1))
+            continue;
+        const int j0 = (int)fl;
+        const float w0 = (float)(1.0 - fabs(f - fl));
+        const float w1 = (float)(1.0 - fabs(f - (fl + 1.0)));
+        const float *row = img + (size_t)k * N;
+        const float v0 = j0 >= 0 ? row[j0] : 0.f;
+        const float v1 = j0 + 1 <= N - 1 ? row[j0 + 1] : 0.f;
+        acc.add(fmaf(w1, v1, w0 * v0));
+    }
+    const float s = acc.value() * G.wstep;
+    const size_t i = (size_t)v * B + b;
+    if (kResid) {
+        // r_i = Y_i - sum_k J_k exp(-mu_k max(s_i, 0))
+        const float sp0 = fmaxf(s, 0.f);
+        float m = 0.f;
+        for (int q = 0; q < sp.K; ++q)
+            m = fmaf(sp.J[q], expf(-sp.mu[q] * sp0), m);
+        out[i] = Y[i] - m;
+    } else {
+        out[i] = s;
+    }
+}
+
+// Number of positive matrix entries on each ray, summed per workgroup:
+// the forward walk with the same weight expression, counting w > 0.
+__global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__restrict__ views,
+                                                           int N, int B,
+                                                           long long *__restrict__ parts)
+{
+    __shared__ long long red[kFwdThreads];
+    const int v = blockIdx.y;
+    const int b = blockIdx.x * kFwdThreads + threadIdx.x;
+    long long cnt = 0;
+    if (b < B) {
+        const ViewGeom G = views[v];
+        const double base = fma((double)b, G.P, G.A);
+        for (int k = 0; k < N; ++k) {
+            const double f = fma((double)k, G.Q, base);
+            const double fl = floor(f);
+            if (fl < -1.0 || fl > (double)(N - 1))
+                continue;
+            const int j0 = (int)fl;
+            const float w0 = (float)(1.0 - fabs(f - fl));
+            const float w1 = (float)(1.0 - fabs(f - (fl + 1.0)));
+            cnt += (j0 >= 0 && w0 > 0.f) ? 1 : 0;
+            cnt += (j0 + 1 <= N - 1 && w1 > 0.f) ? 1 : 0;
+        }
+    }
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = kFwdThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        parts[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------- back
+
+// One lane per pixel; for every view it gathers the (at most three for
+// bins of pixel width) rays whose crossing on the pixel's stepping line is
+// within one pixel, with the forward kernel's own weight expression.
+__global__ __launch_bounds__(kBackX *kBackY) void k_back(
+    const ViewGeom *__restrict__ views, int N, int V, int B, const float *__restrict__ r,
+    float *__restrict__ img, float scale, const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    const int ix = blockIdx.x * kBackX + threadIdx.x;
+    const int iy = blockIdx.y * kBackY + threadIdx.y;
+    if (ix >= N || iy >= N)
+        return;
+    Kahan acc;
+    for (int v = 0; v < V; ++v) {
+        const ViewGeom G = views[v];
+        const int k = G.col ? ix : iy;
+        const int j = G.col ? iy : ix;
+        const double kd = (double)k, jd = (double)j;
+        const float fb = fmaf((float)j, G.cbpix, fmaf((float)k, G.cbk, G.cb0));
+        const int blo = max((int)ceilf(fb - G.halfw), 0);
+        const int bhi = min((int)floorf(fb + G.halfw), B - 1);
+        const float *rv = r + (size_t)v * B;
+        float sv = 0.f;
+        for (int b = blo; b <= bhi; ++b) {
+            const double f = fma(kd, G.Q, fma((double)b, G.P, G.A));
+            const float w = (float)(1.0 - fabs(f - jd));
+            if (w > 0.f)
+                sv = fmaf(w, rv[b], sv);
+        }
+        acc.add(sv * G.wstep);
+    }
+    img[(size_t)iy * N + ix] = acc.value() * scale;
+}
+
+// ------------------------------------------------------ elementwise / tiles
+
+__global__ __launch_bounds__(kTile * 8) void k_transpose(const float *__restrict__ x,
+                                                         float *__restrict__ xT, int N)
+{
+    __shared__ float tile[kTile][kTile + 1];
+    const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int iy = by + rr, ix = bx + threadIdx.x;
+        if (iy < N && ix < N)
+            tile[rr][threadIdx.x] = x[(size_t)iy * N + ix];
+    }
+    __syncthreads();
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int ixT = bx + rr, iyT = by + threadIdx.x;
+        if (ixT < N && iyT < N)
+            xT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
+    }
+}
+
+__global__ void k_fill(float *__restrict__ x, float value, long count)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < count;
+         i += (long)gridDim.x * blockDim.x)
+        x[i] = value;
+}
+
+__global__ void k_window_sum(const float *__restrict__ y, int Wn, long n,
+                             float *__restrict__ Y, int32_t *__restrict__ bad)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        bool ok = true;
+        for (int j = 0; j < Wn; ++j) {
+            const float yv = y[(size_t)j * n + i];
+            ok = ok && isfinite(yv) && yv >= 0.f;
+            s += yv;
+        }
+        Y[i] = s;
+        if (!ok && bad)
+            *bad = 1;
+    }
+}
+
+__global__ void k_count_bad(const float *__restrict__ x, long count, int32_t *__restrict__ bad)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < count;
+         i += (long)gridDim.x * blockDim.x) {
+        const float v = x[i];
+        if (!(isfinite(v) && v >= 0.f))
+            *bad = 1;
+    }
+}
+
+__global__ void k_state_init(SolveState *st, double tol, int max_iters)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->rho = -1.0;
+        st->lam = 0.0;
+        st->unorm = 0.0;
+        st->tol = tol;
+        st->t = 0;
+        st->done = max_iters <= 0 ? 1 : 0;
+        st->converged = 0;
+        st->max_iters = max_iters;
+    }
+}
+
+// z = max(0, x - gamma g); z and its transpose; optional partials.
+template <bool kPartials>
+__global__ __launch_bounds__(kTile * 8) void k_eg_update(
+    const float *x, const float *__restrict__ g, float gamma, float *z,
+    float *__restrict__ zT, int N, double *__restrict__ partials,
+    const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    __shared__ float tile[kTile][kTile + 1];
+    __shared__ double red[2][kRedThreads];
+    const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+    double num = 0.0, den = 0.0;
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int iy = by + rr, ix = bx + threadIdx.x;
+        if (iy < N && ix < N) {
+            const size_t p = (size_t)iy * N + ix;
+            const float xv = x[p];
+            const float zv = fmaxf(0.f, fmaf(-gamma, g[p], xv));
+            z[p] = zv;
+            tile[rr][threadIdx.x] = zv;
+            if (kPartials) {
+                const double dz = (double)zv - (double)xv;
+                num = fma(dz, dz, num);
+                den = fma((double)xv, (double)xv, den);
+            }
+        }
+    }
+    __syncthreads();
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int ixT = bx + rr, iyT = by + threadIdx.x;
+        if (ixT < N && iyT < N)
+            zT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
+    }
+    if (kPartials) {
+        double v2[2] = {num, den};
+        block_sum<2>(v2, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+            partials[2 * blk] = v2[0];
+            partials[2 * blk + 1] = v2[1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restrict__ partials,
+                                                           int nparts, SolveState *st)
+{
+    if (st->done)
+        return;
+    __shared__ double red[2][kRedThreads];
+    double v2[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
+        v2[0] += partials[2 * q];
+        v2[1] += partials[2 * q + 1];
+    }
+    block_sum<2>(v2, red);
+    if (threadIdx.x == 0) {
+        const double rho = v2[1] > 0.0 ? sqrt(v2[0] / v2[1]) : -1.0;
+        const int t = st->t + 1;
+        st->rho = rho;
+        st->t = t;
+        if (st->tol > 0.0 && rho >= 0.0 && rho <= st->tol) {
+            st->converged = 1;
+            st->done = 1;
+        } else if (t >= st->max_iters) {
+            st->done = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,
+                                                      const float *__restrict__ u, long d,
+                                                      double *__restrict__ partials)
+{
+    __shared__ double red[3][kRedThreads];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (long i = blockIdx.x * (long)kRedThreads + threadIdx.x; i < d;
+         i += (long)gridDim.x * kRedThreads) {
+        const double vv = v[i], uu = u[i];
+        a[0] = fma(vv, uu, a[0]);
+        a[1] = fma(vv, vv, a[1]);
+        a[2] = fma(uu, uu, a[2]);
+    }
+    block_sum<3>(a, red);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = a[0];
+        partials[3 * blockIdx.x + 1] = a[1];
+        partials[3 * blockIdx.x + 2] = a[2];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_dot3_finish(const double *__restrict__ partials,
+                                                             int nparts, SolveState *st)
+{
+    __shared__ double red[3][kRedThreads];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
+        a[0] += partials[3 * q];
+        a[1] += partials[3 * q + 1];
+        a[2] += partials[3 * q + 2];
+    }
+    block_sum<3>(a, red);
+    if (threadIdx.x == 0) {
+        st->lam = a[1] > 0.0 ? a[0] / a[1] : 0.0;
+        st->unorm = sqrt(a[2]);
+    }
+}
+
+__global__ __launch_bounds__(kTile * 8) void k_normalize(const float *__restrict__ u,
+                                                         float *__restrict__ v,
+                                                         float *__restrict__ vT, int N,
+                                                         const SolveState *__restrict__ st)
+{
+    __shared__ float tile[kTile][kTile + 1];
+    const double nrm = st->unorm;
+    const float inv = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
+    const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int iy = by + rr, ix = bx + threadIdx.x;
+        if (iy < N && ix < N) {
+            const size_t p = (size_t)iy * N + ix;
+            const float zv = u[p] * inv;
+            v[p] = zv;
+            tile[rr][threadIdx.x] = zv;
+        }
+    }
+    __syncthreads();
+    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
+        const int ixT = bx + rr, iyT = by + threadIdx.x;
+        if (ixT < N && iyT < N)
+            vT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
+    }
+}
+
+inline dim3 tile_grid(int N)
+{
+    const int t = (N + kTile - 1) / kTile;
+    return dim3(t, t);
+}
+
+inline int dot_blocks(long d)
+{
+    long b = (d + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+}  // namespace
+
+int num_tiles(int N)
+{
+    const int t = (N + kTile - 1) / kTile;
+    return t * t;
+}
+
+int num_dot_parts(long d) { return dot_blocks(d); }
+
+int num_count_parts(const Geo &g) { return ((g.B + kFwdThreads - 1) / kFwdThreads) * g.V; }
+
+hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st)
+{
+    dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
+    hipLaunchKernelGGL(k_count_nnz, grid, dim3(kFwdThreads), 0, st, g.views, g.N, g.B, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_transpose, tile_grid(N), dim3(kTile, 8), 0, st, x, xT, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *x, float value, long count, hipStream_t st)
+{
+    long blocks = (count + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, x, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const Geo &g, const float *x, const float *xT, float *s,
+                          const int32_t *skip, hipStream_t st)
+{
+    SpecArg none;
+    none.K = 0;
+    dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
+    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads), 0, st, g.views, g.N, g.B,
+                       x, xT, nullptr, none, s, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT,
+                                   const float *Y, const SpecArg &sp, float *r,
+                                   const int32_t *skip, hipStream_t st)
+{
+    dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
+    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads), 0, st, g.views, g.N, g.B,
+                       x, xT, Y, sp, r, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
+                       const int32_t *skip, hipStream_t st)
+{
+    dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
+    hipLaunchKernelGGL(k_back, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V, g.B, r,
+                       img, scale, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_sum(const float *y, int Wn, long n, float *Y, int32_t *bad,
+                             hipStream_t st)
+{
+    long blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_window_sum, dim3((unsigned)blocks), dim3(256), 0, st, y, Wn, n, Y, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_bad(const float *x, long count, int32_t *bad, hipStream_t st)
+{
+    long blocks = (count + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_count_bad, dim3((unsigned)blocks), dim3(256), 0, st, x, count, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_init(SolveState *state, double tol, int max_iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, state, tol, max_iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_eg_update(const float *x, const float *g, float gamma, float *z, float *zT,
+                            int N, double *partials, const int32_t *skip, hipStream_t st)
+{
+    if (partials)
+        hipLaunchKernelGGL(k_eg_update<true>, tile_grid(N), dim3(kTile, 8), 0, st, x, g, gamma,
+                           z, zT, N, partials, skip);
+    else
+        hipLaunchKernelGGL(k_eg_update<false>, tile_grid(N), dim3(kTile, 8), 0, st, x, g, gamma,
+                           z, zT, N, partials, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *state,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_eg_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot3(const float *v, const float *u, int N, double *partials, hipStream_t st)
+{
+    const long d = (long)N * N;
+    hipLaunchKernelGGL(k_dot3, dim3(dot_blocks(d)), dim3(kRedThreads), 0, st, v, u, d, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *state,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dot3_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const float *u, float *v, float *vT, int N, const SolveState *state,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_normalize, tile_grid(N), dim3(kTile, 8), 0, st, u, v, vT, N, state);
+    return hipGetLastError();
+}
+
+}  // namespace exact

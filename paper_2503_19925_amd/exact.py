@@ -1,0 +1,291 @@
+"""Python binding of libexact (include/exact.h): argument marshalling only.
+
+Every computation happens in the HIP library; torch supplies device memory
+and the current stream.  The module fails loudly if the compiled library is
+missing: there is no fallback path.
+
+Functions keep the C names:
+
+    g = exact_geometry_create(n_pix, n_views, n_bins, pixel_cm, bin_cm, half_turns=1)
+    exact_forward(g, x, s)              s = A x
+    exact_backproject(g, r, img)        img = A^T r
+    exact_operator(g, mu, weight, y, x, F, r=None)
+    lam, gamma = exact_step_size(g, mu, weight, max_iters=100, gamma_scale=0.25)
+    info = exact_solve(g, mu, weight, y, x, **opts)
+    exact_geometry_destroy(g)
+
+Tensors are float32 CUDA (HIP) tensors, contiguous, with the layouts of
+include/exact.h: images [N*N] (or [N, N]), sinograms [V*B], counts
+[Wn*V*B].  mu and weight are host float64 arrays ([K], [Wn*K]).
+"""
+import ctypes as C
+import errno
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexact.so")
+_LIB = None
+
+EXACT_ENOTCONV = 1
+
+EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_create",
+           "exact_geometry_destroy", "exact_forward", "exact_backproject",
+           "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
+           "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
+           "exact_count_nonzeros")
+
+
+class ExactError(RuntimeError):
+    """A libexact call returned an error code."""
+
+    def __init__(self, fn, code, msg):
+        name = errno.errorcode.get(-code, str(code)) if code < 0 else str(code)
+        super().__init__("%s failed (%s): %s" % (fn, name, msg))
+        self.code = code
+
+
+class Spectrum(C.Structure):
+    _fields_ = [("n_energies", C.c_int32), ("n_windows", C.c_int32),
+                ("mu", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double))]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("gamma_scale", C.c_double),
+                ("max_iters", C.c_int32), ("tol", C.c_double), ("stop_mode", C.c_int32),
+                ("check_every", C.c_int32), ("power_iters", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("resid", C.c_double), ("gamma", C.c_double),
+                ("lambda_hat", C.c_double), ("ms", C.c_double)]
+
+
+def load():
+    """Loads libexact.so (built by paper_2503_19925_amd.build)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libexact.so is not built (%s); run "
+                          "`python -m paper_2503_19925_amd.build`" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    sig = {
+        "exact_solve_opts_default": ([C.POINTER(SolveOpts)], None),
+        "exact_last_error": ([], C.c_char_p),
+        "exact_geometry_create": ([i32, i32, i32, i32, dbl, dbl, C.POINTER(vp)], C.c_int),
+        "exact_geometry_destroy": ([vp], C.c_int),
+        "exact_forward": ([vp, vp, vp, vp], C.c_int),
+        "exact_backproject": ([vp, vp, vp, vp], C.c_int),
+        "exact_operator": ([vp, C.POINTER(Spectrum), vp, vp, vp, vp, vp], C.c_int),
+        "exact_step_size": ([vp, C.POINTER(Spectrum), i32, dbl, C.POINTER(dbl),
+                             C.POINTER(dbl), vp], C.c_int),
+        "exact_solve": ([vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts),
+                         C.POINTER(SolveInfo), vp], C.c_int),
+        "exact_solver_create": ([vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts),
+                                 C.POINTER(vp), vp], C.c_int),
+        "exact_solver_step": ([vp, i32, vp], C.c_int),
+        "exact_solver_poll": ([vp, C.POINTER(SolveInfo)], C.c_int),
+        "exact_solver_destroy": ([vp], C.c_int),
+        "exact_count_nonzeros": ([vp, C.POINTER(C.c_int64), vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(fn, code):
+    if code < 0:
+        raise ExactError(fn, code, load().exact_last_error().decode())
+    return code
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("%s must be contiguous float32" % name)
+    if t.numel() != numel:
+        raise ValueError("%s must hold %d values, has %d" % (name, numel, t.numel()))
+    return C.c_void_p(t.data_ptr())
+
+
+class Geometry:
+    """Owns an exact_geometry handle."""
+
+    def __init__(self, n_pix, n_views, n_bins, pixel_cm=None, bin_cm=None, half_turns=1):
+        self.n_pix, self.n_views, self.n_bins = int(n_pix), int(n_views), int(n_bins)
+        self.pixel_cm = 10.0 / self.n_pix if pixel_cm is None else float(pixel_cm)
+        self.bin_cm = self.pixel_cm if bin_cm is None else float(bin_cm)
+        self.half_turns = int(half_turns)
+        h = C.c_void_p()
+        _check("exact_geometry_create", load().exact_geometry_create(
+            self.n_pix, self.n_views, self.n_bins, self.half_turns, self.pixel_cm,
+            self.bin_cm, C.byref(h)))
+        self.handle = h
+
+    @property
+    def d(self):
+        return self.n_pix * self.n_pix
+
+    @property
+    def n(self):
+        return self.n_views * self.n_bins
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check("exact_geometry_destroy", load().exact_geometry_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Spec:
+    """Keeps the host arrays alive while a call uses them."""
+
+    def __init__(self, mu, weight):
+        self.mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).ravel())
+        self.w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).ravel())
+        K = self.mu.size
+        Wn = self.w.size // K if K else 0
+        if K == 0 or Wn * K != self.w.size:
+            raise ValueError("weight must hold n_windows * n_energies values")
+        self.K, self.Wn = K, Wn
+        self.s = Spectrum(K, Wn, self.mu.ctypes.data_as(C.POINTER(C.c_double)),
+                          self.w.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def exact_geometry_create(n_pix, n_views, n_bins, pixel_cm=None, bin_cm=None, half_turns=1):
+    return Geometry(n_pix, n_views, n_bins, pixel_cm, bin_cm, half_turns)
+
+
+def exact_geometry_destroy(g):
+    g.close()
+
+
+def exact_forward(g, x, s, stream=None):
+    _check("exact_forward", load().exact_forward(
+        g.handle, _dev(x, g.d, "x"), _dev(s, g.n, "s"), _stream(stream)))
+    return s
+
+
+def exact_backproject(g, r, img, stream=None):
+    _check("exact_backproject", load().exact_backproject(
+        g.handle, _dev(r, g.n, "r"), _dev(img, g.d, "img"), _stream(stream)))
+    return img
+
+
+def exact_operator(g, mu, weight, y, x, F, r=None, stream=None):
+    sp = _Spec(mu, weight)
+    _check("exact_operator", load().exact_operator(
+        g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),
+        _dev(F, g.d, "F"), None if r is None else _dev(r, g.n, "r"), _stream(stream)))
+    return F
+
+
+def exact_step_size(g, mu=None, weight=None, max_iters=100, gamma_scale=0.25, stream=None):
+    sp = _Spec(mu, weight) if mu is not None else None
+    lam, gam = C.c_double(), C.c_double()
+    _check("exact_step_size", load().exact_step_size(
+        g.handle, C.byref(sp.s) if sp else None, int(max_iters), float(gamma_scale),
+        C.byref(lam), C.byref(gam), _stream(stream)))
+    return lam.value, gam.value
+
+
+def _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters):
+    o = SolveOpts()
+    load().exact_solve_opts_default(C.byref(o))
+    o.gamma, o.gamma_scale, o.max_iters, o.tol = float(gamma), float(gamma_scale), int(max_iters), float(tol)
+    o.check_every, o.power_iters = int(check_every), int(power_iters)
+    return o
+
+
+def _info_dict(info):
+    return dict(iters=info.iters, resid=info.resid, gamma=info.gamma,
+                lambda_hat=info.lambda_hat, ms=info.ms)
+
+
+def exact_count_nonzeros(g, stream=None):
+    out = C.c_int64()
+    _check("exact_count_nonzeros", load().exact_count_nonzeros(g.handle, C.byref(out), _stream(stream)))
+    return out.value
+
+
+class Solver:
+    """A resident run (exact_solver_*): state stays on the device and
+    step(n) enqueues n full extragradient steps on the stream."""
+
+    def __init__(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
+                 check_every=16, power_iters=100, stream=None):
+        sp = _Spec(mu, weight)
+        self.g, self.x = g, x
+        o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
+        h = C.c_void_p()
+        _check("exact_solver_create", load().exact_solver_create(
+            g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),
+            C.byref(h), _stream(stream)))
+        self.handle = h
+
+    def step(self, n_steps=1, stream=None):
+        _check("exact_solver_step", load().exact_solver_step(self.handle, int(n_steps), _stream(stream)))
+
+    def poll(self):
+        """(done, info dict); waits for the enqueued steps."""
+        info = SolveInfo()
+        done = _check("exact_solver_poll", load().exact_solver_poll(self.handle, C.byref(info)))
+        return bool(done), _info_dict(info)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check("exact_solver_destroy", load().exact_solver_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exact_solve(g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
+                check_every=16, power_iters=100, stream=None):
+    """Runs EXACT in place on x.  Returns a dict with iters, resid, gamma,
+    lambda_hat, ms and converged (True/False, or None when tol == 0)."""
+    sp = _Spec(mu, weight)
+    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
+    info = SolveInfo()
+    code = _check("exact_solve", load().exact_solve(
+        g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),
+        C.byref(info), _stream(stream)))
+    d = _info_dict(info)
+    d["converged"] = (code == 0) if tol > 0 else None
+    return d

@@ -1,0 +1,349 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (float32 path vs float64 oracle):
+  * forward, per ray:  |s - s_ora| <= 1e-5 * (A|x|)_i   (= 1e-5 s_ora for x >= 0)
+  * back-projection, per pixel: |g - g_ora| <= 1e-5 * (A^T |r|)_p
+  * operator, per pixel: |F - F_ora| <= 1e-5 * (1/n) (A^T (Y + m))_p, m the
+    model counts, since r = Y - m is a difference of two large terms
+  * iterates after T steps: ||x - x_ora|| / ||x_ora|| <= 1e-4.
+Each case prints its name and shape before touching the GPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2503_19925_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def t32(a):
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel()),
+                           device=DEV)
+
+
+def np64(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64).ravel()
+
+
+@pytest.fixture(scope="module")
+def ex():
+    from paper_2503_19925_amd import exact
+    exact.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return exact
+
+
+# (name, N, V, B, bin/pixel ratio, half_turns)
+SMALL_SHAPES = [
+    ("small_64", 64, 60, 92, 1.0, 1),
+    ("ragged", 77, 33, 109, 1.0, 1),
+    ("full_turn", 48, 50, 70, 1.0, 2),
+    ("wide_bins", 40, 36, 45, 1.3, 1),
+    ("narrow_bins", 40, 36, 81, 0.7, 1),
+    ("mostly_missed", 16, 8, 200, 1.0, 1),
+    ("one_pixel", 1, 3, 3, 1.0, 1),
+    ("two_pixels", 2, 5, 4, 1.0, 1),
+    ("one_view", 33, 1, 47, 1.0, 1),
+]
+
+
+def geoms(ex, ora, N, V, B, ratio, turns):
+    pc = 10.0 / N
+    return (ex.Geometry(N, V, B, pixel_cm=pc, bin_cm=pc * ratio, half_turns=turns),
+            ora.Geom(N, V, B, pixel_cm=pc, bin_cm=pc * ratio, half_turns=turns))
+
+
+@pytest.mark.parametrize("case", SMALL_SHAPES, ids=[c[0] for c in SMALL_SHAPES])
+def test_forward_backward_per_element(ex, ora, case):
+    name, N, V, B, ratio, turns = case
+    say("forward/back", name, N, V, B, ratio, turns)
+    g, go = geoms(ex, ora, N, V, B, ratio, turns)
+    rng = np.random.default_rng(20)
+    x = rng.uniform(0, 2, g.d).astype(np.float32)
+    s = torch.empty(g.n, device=DEV)
+    ex.exact_forward(g, t32(x), s)
+    s_ora = ora.forward(go, x)
+    scale = ora.forward(go, np.abs(x))
+    err = np.abs(np64(s) - s_ora)
+    assert (err <= 1e-5 * scale + 1e-30).all(), err.max()
+    # signed image: scale by A|x|
+    xs = rng.normal(size=g.d).astype(np.float32)
+    ex.exact_forward(g, t32(xs), s)
+    err = np.abs(np64(s) - ora.forward(go, xs))
+    assert (err <= 1e-5 * ora.forward(go, np.abs(xs)) + 1e-30).all()
+    # back-projection of a signed sinogram
+    r = rng.normal(size=g.n).astype(np.float32)
+    img = torch.empty(g.d, device=DEV)
+    ex.exact_backproject(g, t32(r), img)
+    err = np.abs(np64(img) - ora.back(go, r))
+    assert (err <= 1e-5 * ora.back(go, np.abs(r)) + 1e-30).all(), err.max()
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["solve_512", "large_1024"])
+def test_projectors_sampled_full_size(ex, ora, name):
+    """Full workload sizes, the launch shapes the benchmark times: sampled rays
+    and pixels computed one by one by the oracle."""
+    P = synth.config_problem(name, with_truth=True)
+    say("sampled projectors", name, P.n_pix, P.n_views, P.n_bins)
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    rng = np.random.default_rng(21)
+    x = P.x_true.astype(np.float32)
+    s = torch.empty(g.n, device=DEV)
+    ex.exact_forward(g, t32(x), s)
+    rays = np.unique(np.concatenate([rng.integers(0, g.n, 3000),
+                                     np.arange(0, P.n_bins), g.n - 1 - np.arange(P.n_bins)]))
+    s_ora = ora.forward_rays(go, x, rays)
+    err = np.abs(np64(s)[rays] - s_ora)
+    assert (err <= 1e-5 * s_ora + 1e-30).all(), (err / np.maximum(s_ora, 1e-30)).max()
+    r = rng.normal(size=g.n).astype(np.float32)
+    img = torch.empty(g.d, device=DEV)
+    ex.exact_backproject(g, t32(r), img)
+    pix = np.unique(np.concatenate([rng.integers(0, g.d, 48), [0, P.n_pix - 1, g.d - 1,
+                                                               g.d // 2 + P.n_pix // 2]]))
+    g_ora = ora.back_pixels(go, r, pix)
+    scale = ora.back_pixels(go, np.abs(r), pix)
+    err = np.abs(np64(img)[pix] - g_ora)
+    assert (err <= 1e-5 * scale).all(), (err / scale).max()
+    g.close()
+
+
+def test_adjoint_identity_on_gpu(ex):
+    """<A x, y> = <x, A^T y> with the GPU's own projector pair: the weights are
+    identical, so only float32 summation order separates the two."""
+    N, V, B = 256, 90, 363
+    say("adjoint", N, V, B)
+    g = ex.Geometry(N, V, B)
+    rng = np.random.default_rng(22)
+    x = rng.uniform(0, 1, g.d).astype(np.float32)
+    y = rng.uniform(0, 1, g.n).astype(np.float32)
+    s = torch.empty(g.n, device=DEV)
+    img = torch.empty(g.d, device=DEV)
+    ex.exact_forward(g, t32(x), s)
+    ex.exact_backproject(g, t32(y), img)
+    lhs = np.dot(np64(s), y.astype(np.float64))
+    rhs = np.dot(x.astype(np.float64), np64(img))
+    assert abs(lhs - rhs) <= 2e-7 * abs(lhs)
+    g.close()
+
+
+def test_determinism(ex):
+    N, V, B = 128, 45, 182
+    say("determinism", N, V, B)
+    g = ex.Geometry(N, V, B)
+    rng = np.random.default_rng(23)
+    x = t32(rng.uniform(0, 1, g.d))
+    r = t32(rng.normal(size=g.n))
+    s1, s2 = torch.empty(g.n, device=DEV), torch.empty(g.n, device=DEV)
+    i1, i2 = torch.empty(g.d, device=DEV), torch.empty(g.d, device=DEV)
+    ex.exact_forward(g, x, s1)
+    ex.exact_forward(g, x, s2)
+    ex.exact_backproject(g, r, i1)
+    ex.exact_backproject(g, r, i2)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2) and torch.equal(i1, i2)
+    g.close()
+
+
+def _problem(ex, ora, name, **over):
+    P = synth.config_problem(name, **over)
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    return P, g, go
+
+
+@pytest.mark.parametrize("name", ["small_64", "solve_512"])
+def test_operator_parity(ex, ora, name):
+    P, g, go = _problem(ex, ora, name)
+    say("operator", name, P.n_pix, P.n_views, P.n_bins, P.K, P.Wn)
+    y64 = P.y.astype(np.float64)
+    x = (0.9 * P.x_true).astype(np.float32)
+    F = torch.empty(g.d, device=DEV)
+    r = torch.empty(g.n, device=DEV)
+    ex.exact_operator(g, P.mu, P.I, t32(P.y), t32(x), F, r)
+    F_ora, s_ora, r_ora = ora.operator(go, P.mu, P.I, y64, x, want_sr=True)
+    _, m = ora.residual(s_ora, P.mu, P.I, y64)
+    Y = y64.reshape(P.Wn, -1).sum(0)
+    scale = ora.back(go, Y + m) / g.n
+    err = np.abs(np64(F) - F_ora)
+    assert (err <= 1e-5 * scale + 1e-30).all(), (err / np.maximum(scale, 1e-30)).max()
+    rerr = np.abs(np64(r) - r_ora)
+    assert (rerr <= 1e-5 * (Y + m)).all()
+    g.close()
+
+
+def test_operator_at_zero_and_monotone(ex, ora):
+    """F(0) = (1/n) A^T (Y - I0) (h(0) = 1) and <F(x)-F(z), x-z> >= 0 on the GPU."""
+    P, g, go = _problem(ex, ora, "small_64")
+    say("operator closed form + monotone", P.n_pix)
+    F0 = torch.empty(g.d, device=DEV)
+    ex.exact_operator(g, P.mu, P.I, t32(P.y), torch.zeros(g.d, device=DEV), F0)
+    Y = P.y.astype(np.float64).reshape(P.Wn, -1).sum(0)
+    expect = ora.back(go, Y - P.I0) / g.n
+    scale = ora.back(go, Y + P.I0) / g.n
+    assert (np.abs(np64(F0) - expect) <= 1e-5 * scale).all()
+    rng = np.random.default_rng(24)
+    Fx, Fz = torch.empty(g.d, device=DEV), torch.empty(g.d, device=DEV)
+    for _ in range(3):
+        x = np.maximum(0, P.x_true + rng.normal(scale=0.2, size=g.d)).astype(np.float32)
+        z = rng.uniform(0, 1.5, g.d).astype(np.float32)
+        ex.exact_operator(g, P.mu, P.I, t32(P.y), t32(x), Fx)
+        ex.exact_operator(g, P.mu, P.I, t32(P.y), t32(z), Fz)
+        assert np.dot(np64(Fx) - np64(Fz), x.astype(np.float64) - z) >= 0
+    g.close()
+
+
+def test_step_size_matches_oracle(ex, ora):
+    P, g, go = _problem(ex, ora, "small_64")
+    say("power iteration", P.n_pix)
+    lam, gamma = ex.exact_step_size(g, P.mu, P.I, max_iters=300)
+    lam_ora, _ = ora.power(go, 3000, 1e-11)
+    assert abs(lam - lam_ora) <= 1e-4 * lam_ora
+    assert abs(gamma - ora.step_size(lam, P.mu, P.I)) <= 1e-12 * gamma
+    g.close()
+
+
+def oracle_gamma(ora, go, P, power=True):
+    """Step size from the oracle: Theorem 2's gamma with lambda_max from power
+    iteration, or (cheap, for full-size problems) with the upper bound
+    lambda_max(A^T A) <= max row sum * max column sum of A."""
+    if power:
+        lam, _ = ora.power(go, 1000, 1e-9)
+    else:
+        rows = ora.forward(go, np.ones(go.d))
+        cols = ora.back(go, np.ones(go.n))
+        lam = rows.max() * cols.max() / go.n
+    return ora.step_size(lam, P.mu, P.I)
+
+
+def _solve_case(ex, ora, name, T, power=True, **over):
+    P, g, go = _problem(ex, ora, name, **over)
+    say("solve", name, P.n_pix, P.n_views, P.n_bins, "T =", T)
+    gamma = oracle_gamma(ora, go, P, power)
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=gamma, max_iters=T)
+    assert info["iters"] == T
+    x_ora, t, _ = ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d), gamma, T)
+    rel = np.linalg.norm(np64(x) - x_ora) / np.linalg.norm(x_ora)
+    print("  rel L2 vs oracle after %d steps: %.3e" % (T, rel), flush=True)
+    g.close()
+    return rel
+
+
+def test_solve_parity_small_64(ex, ora):
+    assert _solve_case(ex, ora, "small_64", 100) <= 1e-4
+
+
+def test_solve_parity_mid_128(ex, ora):
+    rel = _solve_case(ex, ora, "small_64", 200, power=False, n_pix=128, n_views=90, n_bins=182,
+                      K=30, Wn=3)
+    assert rel <= 1e-4
+
+
+def test_solve_parity_full_512_two_steps(ex, ora):
+    """The benchmark's workload at full size, two full steps (8 projector
+    passes on the oracle)."""
+    assert _solve_case(ex, ora, "solve_512", 2, power=False) <= 1e-5
+
+
+def test_solve_stop_rule(ex, ora):
+    P, g, go = _problem(ex, ora, "small_64")
+    say("solve stop rule", P.n_pix)
+    gamma = oracle_gamma(ora, go, P)
+    tol = 2e-3
+    x_ora, t_ora, hist = ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d), gamma,
+                                5000, tol=tol)
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=gamma, max_iters=5000, tol=tol,
+                          check_every=7)
+    assert info["converged"]
+    assert info["resid"] <= tol
+    assert abs(info["iters"] - t_ora) <= 1, (info["iters"], t_ora)
+    if info["iters"] == t_ora:
+        assert np.linalg.norm(np64(x) - x_ora) <= 1e-4 * np.linalg.norm(x_ora)
+    # a cap below the stopping step reports non-convergence
+    x2 = torch.zeros(g.d, device=DEV)
+    info2 = ex.exact_solve(g, P.mu, P.I, t32(P.y), x2, gamma=gamma, max_iters=5, tol=tol)
+    assert info2["converged"] is False and info2["iters"] == 5
+    g.close()
+
+
+def test_solve_is_deterministic(ex):
+    P = synth.config_problem("small_64")
+    say("solve determinism")
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    x1, x2 = torch.zeros(g.d, device=DEV), torch.zeros(g.d, device=DEV)
+    i1 = ex.exact_solve(g, P.mu, P.I, t32(P.y), x1, max_iters=50)
+    i2 = ex.exact_solve(g, P.mu, P.I, t32(P.y), x2, max_iters=50)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2) and i1["gamma"] == i2["gamma"]
+    g.close()
+
+
+def test_scalar_worked_example_on_gpu(ex):
+    """The hand-worked one-pixel example (tests/golden/eg_scalar.txt)."""
+    say("scalar EG example")
+    golden = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "eg_scalar.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            golden[k.strip()] = float(v)
+    g = ex.Geometry(1, 1, 1, pixel_cm=1.0, bin_cm=1.0)
+    s = torch.empty(1, device=DEV)
+    ex.exact_forward(g, t32([2.5]), s)
+    assert np64(s)[0] == 2.5
+    x = torch.zeros(1, device=DEV)
+    y = t32([math.exp(-1.0)])
+    ex.exact_solve(g, [1.0], [1.0], y, x, gamma=0.5, max_iters=1)
+    assert abs(np64(x)[0] - golden["x_2"]) <= 2e-7
+    ex.exact_solve(g, [1.0], [1.0], y, x, gamma=0.5, max_iters=1)
+    assert abs(np64(x)[0] - golden["x_3"]) <= 4e-7
+    x0 = torch.zeros(1, device=DEV)
+    ex.exact_solve(g, [1.0], [1.0], t32([1.5]), x0, gamma=0.5, max_iters=3)
+    assert np64(x0)[0] == 0.0
+    g.close()
+
+
+def test_error_paths(ex):
+    say("error paths")
+    g = ex.Geometry(16, 10, 23)
+    x = torch.zeros(g.d, device=DEV)
+    y = torch.ones(2 * g.n, device=DEV)
+    F = torch.empty(g.d, device=DEV)
+    with pytest.raises(ex.ExactError):
+        ex.exact_operator(g, [0.2, -1.0], [1.0, 1.0, 1.0, 1.0], y, x, F)      # mu <= 0
+    with pytest.raises(ex.ExactError):
+        ex.exact_operator(g, [0.2, 0.3], [0.0, 0.0, 1.0, 1.0], y, x, F)       # empty window
+    with pytest.raises(ex.ExactError):
+        ex.exact_operator(g, np.ones(200), np.ones(400), torch.ones(2 * g.n, device=DEV), x, F)
+    bad = torch.ones(2 * g.n, device=DEV)
+    bad[5] = -1.0
+    with pytest.raises(ex.ExactError):
+        ex.exact_solve(g, [0.2, 0.3], [1.0, 1.0, 1.0, 1.0], bad, x, max_iters=3)
+    bad[5] = float("nan")
+    with pytest.raises(ex.ExactError):
+        ex.exact_solve(g, [0.2, 0.3], [1.0, 1.0, 1.0, 1.0], bad, x, max_iters=3)
+    xneg = torch.zeros(g.d, device=DEV)
+    xneg[3] = -0.5
+    with pytest.raises(ex.ExactError):
+        ex.exact_solve(g, [0.2, 0.3], [1.0, 1.0, 1.0, 1.0], y, xneg, max_iters=3)
+    assert np64(xneg)[3] == -0.5
+    # zero steps leave x unchanged
+    x1 = torch.full((g.d,), 0.25, device=DEV)
+    info = ex.exact_solve(g, [0.2, 0.3], [1.0, 1.0, 1.0, 1.0], y, x1, gamma=1e-3, max_iters=0)
+    assert info["iters"] == 0 and (np64(x1) == 0.25).all()
+    g.close()

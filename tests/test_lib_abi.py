@@ -1,0 +1,84 @@
+"""CPU-only checks of the C ABI: the library loads, exports everything the
+public header declares, and rejects bad arguments before touching a GPU."""
+import ctypes as C
+import errno
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exact.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exact_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2503_19925_amd import build, exact
+    if not os.path.exists(exact.LIB_PATH):
+        build.build()
+    return exact.load()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("exact_geometry_create", "exact_geometry_destroy", "exact_forward",
+              "exact_backproject", "exact_operator", "exact_solve", "exact_step_size",
+              "exact_last_error", "exact_solve_opts_default"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2503_19925_amd import exact
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(exact.EXPORTS) == set(declared_functions())
+
+
+def test_opts_defaults(lib):
+    from paper_2503_19925_amd.exact import SolveOpts
+    o = SolveOpts()
+    lib.exact_solve_opts_default(C.byref(o))
+    assert o.gamma == 0.0 and o.gamma_scale == 0.25 and o.max_iters == 500
+    assert o.tol == 0.0 and o.stop_mode == 0 and o.check_every == 16 and o.power_iters == 100
+
+
+@pytest.mark.parametrize("args", [
+    (0, 10, 10, 1, 0.1, 0.1),          # no pixels
+    (16, 0, 10, 1, 0.1, 0.1),          # no views
+    (16, 10, 0, 1, 0.1, 0.1),          # no bins
+    (16, 10, 10, 3, 0.1, 0.1),         # neither 180 nor 360 degrees
+    (16, 10, 10, 1, 0.0, 0.1),         # zero pixel size
+    (16, 10, 10, 1, 0.1, float("nan")),
+    (20000, 10, 10, 1, 0.1, 0.1),      # image too large
+    (16, 65536, 65536, 1, 0.1, 0.1),   # too many rays
+])
+def test_geometry_create_rejects(lib, args):
+    h = C.c_void_p()
+    assert lib.exact_geometry_create(*args, C.byref(h)) == -errno.EINVAL
+    assert not h.value
+    assert lib.exact_last_error().decode()
+
+
+def test_null_handles_rejected(lib):
+    assert lib.exact_forward(None, None, None, None) == -errno.EINVAL
+    assert lib.exact_backproject(None, None, None, None) == -errno.EINVAL
+    assert lib.exact_operator(None, None, None, None, None, None, None) == -errno.EINVAL
+    assert lib.exact_solve(None, None, None, None, None, None, None) == -errno.EINVAL
+    lam = C.c_double()
+    assert lib.exact_step_size(None, None, 10, 0.25, C.byref(lam), None, None) == -errno.EINVAL
+    assert lib.exact_geometry_destroy(None) == 0
+    assert "NULL" in lib.exact_last_error().decode() or lib.exact_last_error() == b""
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2503_19925_amd import exact
+    monkeypatch.setattr(exact, "_LIB", None)
+    monkeypatch.setattr(exact, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        exact.load()
