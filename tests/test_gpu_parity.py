@@ -6,6 +6,10 @@ Tolerances (float32 path vs float64 oracle):
   * operator, per pixel: |F - F_ora| <= 1e-5 * (1/n) (A^T (Y + m))_p, m the
     model counts, since r = Y - m is a difference of two large terms
   * iterates after T steps: ||x - x_ora|| / ||x_ora|| <= 1e-4.
+The per-element bounds carry an absolute floor of 1e-9 of the largest
+element's scale: a ray that passes exactly one pixel outside the image (or a
+pixel that such a ray grazes) has true weight 0, which both sides compute in
+double as a rounding-level tent value (~1e-14) with no relative accuracy.
 Each case prints its name and shape before touching the GPU.
 """
 import math
@@ -35,6 +39,16 @@ def t32(a):
 def np64(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy().astype(np.float64).ravel()
+
+
+def within(got, want, scale, rel=1e-5):
+    """|got - want| <= rel * scale + 1e-9 * max(scale), element by element."""
+    scale = np.asarray(scale, dtype=np.float64)
+    tol = rel * scale + 1e-9 * float(scale.max(initial=0.0)) + 1e-30
+    err = np.abs(np.asarray(got, dtype=np.float64) - want)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, "%d elements out of tolerance; worst %s: got %r want %r scale %r" % (
+        bad.size, bad[np.argmax((err / tol)[bad])], got[bad[0]], want[bad[0]], scale[bad[0]])
 
 
 @pytest.fixture(scope="module")
@@ -76,19 +90,16 @@ def test_forward_backward_per_element(ex, ora, case):
     ex.exact_forward(g, t32(x), s)
     s_ora = ora.forward(go, x)
     scale = ora.forward(go, np.abs(x))
-    err = np.abs(np64(s) - s_ora)
-    assert (err <= 1e-5 * scale + 1e-30).all(), err.max()
+    within(np64(s), s_ora, scale)
     # signed image: scale by A|x|
     xs = rng.normal(size=g.d).astype(np.float32)
     ex.exact_forward(g, t32(xs), s)
-    err = np.abs(np64(s) - ora.forward(go, xs))
-    assert (err <= 1e-5 * ora.forward(go, np.abs(xs)) + 1e-30).all()
+    within(np64(s), ora.forward(go, xs), ora.forward(go, np.abs(xs)))
     # back-projection of a signed sinogram
     r = rng.normal(size=g.n).astype(np.float32)
     img = torch.empty(g.d, device=DEV)
     ex.exact_backproject(g, t32(r), img)
-    err = np.abs(np64(img) - ora.back(go, r))
-    assert (err <= 1e-5 * ora.back(go, np.abs(r)) + 1e-30).all(), err.max()
+    within(np64(img), ora.back(go, r), ora.back(go, np.abs(r)))
     g.close()
 
 
@@ -107,8 +118,7 @@ def test_projectors_sampled_full_size(ex, ora, name):
     rays = np.unique(np.concatenate([rng.integers(0, g.n, 3000),
                                      np.arange(0, P.n_bins), g.n - 1 - np.arange(P.n_bins)]))
     s_ora = ora.forward_rays(go, x, rays)
-    err = np.abs(np64(s)[rays] - s_ora)
-    assert (err <= 1e-5 * s_ora + 1e-30).all(), (err / np.maximum(s_ora, 1e-30)).max()
+    within(np64(s)[rays], s_ora, s_ora)
     r = rng.normal(size=g.n).astype(np.float32)
     img = torch.empty(g.d, device=DEV)
     ex.exact_backproject(g, t32(r), img)
@@ -116,8 +126,7 @@ def test_projectors_sampled_full_size(ex, ora, name):
                                                                g.d // 2 + P.n_pix // 2]]))
     g_ora = ora.back_pixels(go, r, pix)
     scale = ora.back_pixels(go, np.abs(r), pix)
-    err = np.abs(np64(img)[pix] - g_ora)
-    assert (err <= 1e-5 * scale).all(), (err / scale).max()
+    within(np64(img)[pix], g_ora, scale)
     g.close()
 
 
@@ -178,10 +187,8 @@ def test_operator_parity(ex, ora, name):
     _, m = ora.residual(s_ora, P.mu, P.I, y64)
     Y = y64.reshape(P.Wn, -1).sum(0)
     scale = ora.back(go, Y + m) / g.n
-    err = np.abs(np64(F) - F_ora)
-    assert (err <= 1e-5 * scale + 1e-30).all(), (err / np.maximum(scale, 1e-30)).max()
-    rerr = np.abs(np64(r) - r_ora)
-    assert (rerr <= 1e-5 * (Y + m)).all()
+    within(np64(F), F_ora, scale)
+    within(np64(r), r_ora, Y + m)
     g.close()
 
 
@@ -194,7 +201,7 @@ def test_operator_at_zero_and_monotone(ex, ora):
     Y = P.y.astype(np.float64).reshape(P.Wn, -1).sum(0)
     expect = ora.back(go, Y - P.I0) / g.n
     scale = ora.back(go, Y + P.I0) / g.n
-    assert (np.abs(np64(F0) - expect) <= 1e-5 * scale).all()
+    within(np64(F0), expect, scale)
     rng = np.random.default_rng(24)
     Fx, Fz = torch.empty(g.d, device=DEV), torch.empty(g.d, device=DEV)
     for _ in range(3):
