@@ -22,7 +22,7 @@ using exact::SpecArg;
 using exact::ViewGeom;
 
 struct exact_geometry_s {
-    int N, V, B, half_turns;
+    int N, V, B, half_turns, reach;
     double pixel_cm, bin_cm;
     int device;
     ViewGeom *d_views;
@@ -65,7 +65,7 @@ int guarded(F &&body)
     }
 }
 
-Geo geo_of(const exact_geometry_s *g) { return Geo{g->d_views, g->N, g->V, g->B}; }
+Geo geo_of(const exact_geometry_s *g) { return Geo{g->d_views, g->N, g->V, g->B, g->reach}; }
 
 void check_geometry(const exact_geometry_s *g)
 {
@@ -119,16 +119,22 @@ SpecArg make_spec(const exact_spectrum *sp, double *sum_J_mu)
     return a;
 }
 
-// Per-view parameters of the Joseph projector.  Computed in long double and
-// rounded once, so that the crossings are accurate to double rounding.
+// Rounds to the nearest multiple of 2^-32.
+long double fixed32(long double v) { return roundl(ldexpl(v, 32)) / 4294967296.0L; }
+
+// Per-view parameters of the Joseph projector (see ViewGeom).  Computed in
+// long double; A, P, Q are rounded once to multiples of 2^-32 pixel, which
+// moves any crossing by at most (1 + b + k) 2^-33 pixel.  Sets *reach for the
+// back-projector and fails if a crossing could leave the exact range.
 std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pixel_cm,
-                                  double bin_cm)
+                                  double bin_cm, int *reach)
 {
     const long double pi = 3.14159265358979323846264338327950288L;
     const long double c = (N - 1) / 2.0L;
     const long double half = (B - 1) / 2.0L;
     const long double ratio = (long double)bin_cm / (long double)pixel_cm;
     std::vector<ViewGeom> out((size_t)V);
+    long double pmin = 1e30L;
     for (int v = 0; v < V; ++v) {
         const long q = ((long)half_turns * v) % V;
         const bool row = 4 * q <= V || 4 * q >= 3L * V;
@@ -136,25 +142,32 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         const long double ct = cosl(th), st = sinl(th);
         const long double cs = row ? ct : st;       // cosine along the stepping axis
         const long double sn = row ? st : ct;
-        const long double P = ratio / cs;
-        const long double Q = -sn / cs;
-        const long double A = c + c * sn / cs - half * P;
+        const long double P = fixed32(ratio / cs);
+        const long double Q = fixed32(-sn / cs);
+        const long double A = fixed32(c + c * sn / cs - half * ratio / cs);
+        // largest crossing the kernels form: b up to B + 64 (candidate bins
+        // beyond the detector are formed, then discarded), k up to N
+        const long double span = fabsl(A) + (B + 64) * fabsl(P) + N * fabsl(Q) + 2.0L;
+        if (!(span < 1048576.0L))
+            fail(-EINVAL, "geometry too large for exact crossing arithmetic (|crossing| >= 2^20)");
         ViewGeom G;
         std::memset(&G, 0, sizeof(G));
         G.A = (double)A;
         G.P = (double)P;
         G.Q = (double)Q;
-        G.cbpix = (float)(1.0L / P);
-        G.cbk = (float)(-Q / P);
-        G.cb0 = (float)(-A / P);
-        // float error of the bin estimate: a few roundings of terms of the
-        // size of |cb0| + N|cbk| + N|cbpix|
-        const long double mag = fabsl(A / P) + (long double)N * (fabsl(Q / P) + fabsl(1.0L / P));
-        G.halfw = (float)(1.0L / fabsl(P) + 1e-3L + 8.0L * mag / 16777216.0L);
+        G.cbpix = (double)(1.0L / P);
+        G.cbk = (double)(-Q / P);
+        G.cb0 = (double)(-A / P);
         G.wstep = (float)((long double)pixel_cm / fabsl(cs));
         G.col = row ? 0 : 1;
         out[(size_t)v] = G;
+        pmin = std::min(pmin, fabsl(P));
     }
+    // Bins within one pixel of a pixel's crossing satisfy |b - b*| < 1/|P|;
+    // the nearest bin b0 is within 1/2 (+ rounding) of b*.
+    *reach = pmin >= 1.0L ? 0 : (int)floorl(1.0L / pmin + 0.5L + 0.01L);
+    if (*reach > 32)
+        fail(-EINVAL, "bins narrower than 1/32 of a pixel are not supported");
     return out;
 }
 
@@ -308,7 +321,7 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         g->d_views = nullptr;
         try {
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
-            g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm);
+            g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm, &g->reach);
             const size_t bytes = sizeof(ViewGeom) * (size_t)n_views;
             hip_check(hipMalloc((void **)&g->d_views, bytes), "hipMalloc");
             hip_check(hipMemcpy(g->d_views, g->h_views.data(), bytes, hipMemcpyHostToDevice),

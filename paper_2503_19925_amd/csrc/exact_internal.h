@@ -15,21 +15,25 @@ constexpr int kMaxEnergies = 128;
 //
 // A ray (v, b) crosses stepping line k (row iy for row-stepping views,
 // column ix otherwise) at the fractional pixel index
-//     f(b, k) = fma(k, Q, fma(b, P, A))            (double, exactly this form)
+//     f(b, k) = A + b P + k Q
 // and puts weight wstep * (float)(1 - |f - j|) on pixel j of that line when
-// positive.  Forward and back-projection evaluate this same expression, so
-// both apply bit-identical matrix entries.
+// positive.  A, P and Q are rounded to multiples of 2^-32 and every crossing
+// stays below 2^20 in magnitude, so f and f - j are integers times 2^-32 with
+// at most 53 significant bits: double arithmetic on them is exact in any
+// order (incremental stepping in the forward, direct evaluation in the
+// back-projector).  Both kernels therefore apply bit-identical weights.
 //
-// The back-projector finds the bins whose crossing on line k falls within
-// one pixel of pixel j from the float estimate fb = fmaf(j, cbpix,
-// fmaf(k, cbk, cb0)), scanning every b with |b - fb| <= halfw.
+// The back-projector starts from the bin nearest to a pixel,
+// b0 = rint(j * cbpix + k * cbk + cb0) (= the exact solution of f(b, k) = j
+// to within double rounding), and examines only the bins that can lie
+// within one pixel of it.
 struct alignas(16) ViewGeom {
     double A, P, Q;
-    float cb0, cbpix, cbk, halfw;
+    double cb0, cbpix, cbk;
     float wstep;
     int32_t col;     // 0: row-stepping (k = iy, j = ix); 1: column (k = ix, j = iy)
 };
-static_assert(sizeof(ViewGeom) == 48, "ViewGeom layout");
+static_assert(sizeof(ViewGeom) == 56 || sizeof(ViewGeom) == 64, "ViewGeom layout");
 
 // Spectrum collapsed over windows, passed to kernels by value.
 struct SpecArg {
@@ -53,6 +57,10 @@ struct SolveState {
 struct Geo {
     const ViewGeom *views;
     int N, V, B;
+    // Bins examined on each side of the nearest one in the back-projector;
+    // 1 (with the exact two-candidate rule) whenever every |P| >= 1, i.e.
+    // bins at least as wide as pixels.
+    int reach;
 };
 
 // Partial sums produced per workgroup by the update and dot kernels.

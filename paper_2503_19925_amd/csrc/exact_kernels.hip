@@ -58,53 +58,84 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThr
 
 // ---------------------------------------------------------------- forward
 
-// One lane per ray (v, b).  The ray walks its stepping lines k in increasing
-// order; on each it interpolates between the two pixels around the crossing.
-// Column-stepping views read the transposed image so that the lanes of a
-// wave touch neighbouring addresses on every line.
+constexpr int kSegs = 4;   // waves per forward workgroup, each a quarter of the lines
+
+// Lines k (of the N) on which ray base + k Q can have a tap inside the image,
+// i.e. floor(f) in [-1, N-1]; conservative by one line at each end (the
+// per-line test stays authoritative).
+__device__ __forceinline__ void ray_lines(double base, double Q, int N, int &k0, int &k1)
+{
+    double lo = 0.0, hi = (double)(N - 1);
+    if (Q != 0.0) {
+        const double ka = (-1.0 - base) / Q, kb = ((double)N - base) / Q;
+        lo = fmax(lo, floor(fmin(ka, kb)) - 1.0);
+        hi = fmin(hi, ceil(fmax(ka, kb)) + 1.0);
+    } else if (!(base > -1.0 && base < (double)N)) {
+        hi = -1.0;
+    }
+    k0 = (int)lo;
+    k1 = (int)hi;
+}
+
+// One lane per ray (v, b); the four waves of a workgroup take the same 64
+// rays and split the image lines into quarters, and their Kahan partial
+// sums are combined in a fixed order.  The crossing advances exactly by Q
+// per line.  Column-stepping views read the transposed image so that the
+// lanes of a wave touch neighbouring addresses on every line.
 template <bool kResid>
-__global__ __launch_bounds__(kFwdThreads) void k_forward(
+__global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     const ViewGeom *__restrict__ views, int N, int B, const float *__restrict__ x,
     const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
     float *__restrict__ out, const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
+    __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
+    const int lane = threadIdx.x % kFwdThreads;
+    const int seg = threadIdx.x / kFwdThreads;
     const int v = blockIdx.y;
-    const int b = blockIdx.x * kFwdThreads + threadIdx.x;
-    if (b >= B)
-        return;
+    const int b = blockIdx.x * kFwdThreads + lane;
     const ViewGeom G = views[v];
     const float *__restrict__ img = G.col ? xT : x;
     const double base = fma((double)b, G.P, G.A);
 
-    // Lines whose crossing lies in (-1, N); outside that range no tap is in
-    // the image.  The per-line bounds test below stays authoritative.
-    double lo = 0.0, hi = (double)(N - 1);
-    if (G.Q != 0.0) {
-        const double ka = (-1.0 - base) / G.Q, kb = ((double)N - base) / G.Q;
-        lo = fmax(lo, floor(fmin(ka, kb)));
-        hi = fmin(hi, ceil(fmax(ka, kb)));
-    } else if (!(base > -1.0 && base < (double)N)) {
-        hi = -1.0;
-    }
-    const int k0 = (int)lo, k1 = (int)hi;
+    int k0, k1;
+    ray_lines(base, G.Q, N, k0, k1);
+    const int per = (N + kSegs - 1) / kSegs;
+    k0 = max(k0, seg * per);
+    k1 = min(k1, min(N, (seg + 1) * per) - 1);
+    if (b >= B)
+        k1 = k0 - 1;
 
     Kahan acc;
+    double f = fma((double)k0, G.Q, base);
+#pragma unroll 4
     for (int k = k0; k <= k1; ++k) {
-        const double f = fma((double)k, G.Q, base);
         const double fl = floor(f);
+        const double e0 = f - fl;                 // exact, in [0, 1)
+        f += G.Q;                                 // exact
         if (fl < -1.0 || fl > (double)(N - 1))
             continue;
         const int j0 = (int)fl;
-        const float w0 = (float)(1.0 - fabs(f - fl));
-        const float w1 = (float)(1.0 - fabs(f - (fl + 1.0)));
+        const float w0 = (float)(1.0 - e0);       // pixel j0
+        const float w1 = (float)e0;               // pixel j0 + 1: 1 - |f - (j0+1)| = e0
         const float *row = img + (size_t)k * N;
         const float v0 = j0 >= 0 ? row[j0] : 0.f;
         const float v1 = j0 + 1 <= N - 1 ? row[j0 + 1] : 0.f;
         acc.add(fmaf(w1, v1, w0 * v0));
     }
-    const float s = acc.value() * G.wstep;
+    part_s[seg][lane] = acc.s;
+    part_c[seg][lane] = acc.c;
+    __syncthreads();
+    if (seg != 0 || b >= B)
+        return;
+    Kahan tot;
+#pragma unroll
+    for (int q = 0; q < kSegs; ++q) {
+        tot.add(part_s[q][lane]);
+        tot.add(-part_c[q][lane]);
+    }
+    const float s = tot.value() * G.wstep;
     const size_t i = (size_t)v * B + b;
     if (kResid) {
         // r_i = Y_i - sum_k J_k exp(-mu_k max(s_i, 0))
@@ -119,7 +150,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_forward(
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
-// the forward walk with the same weight expression, counting w > 0.
+// the forward walk with the same weights, counting w > 0.
 __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__restrict__ views,
                                                            int N, int B,
                                                            long long *__restrict__ parts)
@@ -130,17 +161,16 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
     long long cnt = 0;
     if (b < B) {
         const ViewGeom G = views[v];
-        const double base = fma((double)b, G.P, G.A);
+        double f = fma((double)b, G.P, G.A);
         for (int k = 0; k < N; ++k) {
-            const double f = fma((double)k, G.Q, base);
             const double fl = floor(f);
+            const double e0 = f - fl;
+            f += G.Q;
             if (fl < -1.0 || fl > (double)(N - 1))
                 continue;
             const int j0 = (int)fl;
-            const float w0 = (float)(1.0 - fabs(f - fl));
-            const float w1 = (float)(1.0 - fabs(f - (fl + 1.0)));
-            cnt += (j0 >= 0 && w0 > 0.f) ? 1 : 0;
-            cnt += (j0 + 1 <= N - 1 && w1 > 0.f) ? 1 : 0;
+            cnt += (j0 >= 0 && (float)(1.0 - e0) > 0.f) ? 1 : 0;
+            cnt += (j0 + 1 <= N - 1 && (float)e0 > 0.f) ? 1 : 0;
         }
     }
     red[threadIdx.x] = cnt;
@@ -156,12 +186,55 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 
 // ------------------------------------------------------------------- back
 
-// One lane per pixel; for every view it gathers the (at most three for
-// bins of pixel width) rays whose crossing on the pixel's stepping line is
-// within one pixel, with the forward kernel's own weight expression.
+// Contribution of view G to pixel (k, j) of its stepping line (without the
+// path-length factor): sum over bins b within one pixel of
+// (float)(1 - |f(b, k) - j|) * r[b].  Two-candidate rule (all |P| >= 1): the
+// nearest bin b0 has |d0| <= (1/2 + tiny)|P| with d0 = f(b0, k) - j; moving
+// away from the pixel adds |P| >= 1 to |d|, moving two bins towards it
+// leaves |d| >= (3/2 - tiny)|P| >= 1, so only b0 and its neighbour on the
+// pixel's side can have positive weight.
+template <bool kTwo>
+__device__ __forceinline__ float gather_view(const ViewGeom &G, int k, int j, int B, int reach,
+                                             const float *__restrict__ rv)
+{
+    const double kd = (double)k, jd = (double)j;
+    const double fb = fma(jd, G.cbpix, fma(kd, G.cbk, G.cb0));
+    const double b0d = fmin(fmax(rint(fb), -2.0 - reach), (double)(B + 1 + reach));
+    const int b0 = (int)b0d;
+    const double d0 = fma(b0d, G.P, fma(kd, G.Q, G.A)) - jd;     // exact
+    if (kTwo) {
+        const bool up = (d0 > 0.0) != (G.P > 0.0);   // neighbour towards the pixel
+        const int b1 = up ? b0 + 1 : b0 - 1;
+        const double d1 = up ? d0 + G.P : d0 - G.P;  // exact
+        const float w0 = (float)(1.0 - fabs(d0));
+        const float w1 = (float)(1.0 - fabs(d1));
+        const bool ok0 = w0 > 0.f && b0 >= 0 && b0 < B;
+        const bool ok1 = w1 > 0.f && b1 >= 0 && b1 < B;
+        const float r0 = ok0 ? rv[b0] : 0.f;
+        const float r1 = ok1 ? rv[b1] : 0.f;
+        // ascending bin order, as the general rule below sums
+        return up ? fmaf(ok1 ? w1 : 0.f, r1, (ok0 ? w0 : 0.f) * r0)
+                  : fmaf(ok0 ? w0 : 0.f, r0, (ok1 ? w1 : 0.f) * r1);
+    } else {
+        float sv = 0.f;
+        for (int m = -reach; m <= reach; ++m) {
+            const int bb = b0 + m;
+            const double d = fma((double)m, G.P, d0);    // exact
+            const float w = (float)(1.0 - fabs(d));
+            if (w > 0.f && bb >= 0 && bb < B)
+                sv = fmaf(w, rv[bb], sv);
+        }
+        return sv;
+    }
+}
+
+// One lane per pixel, views in order, Kahan-compensated across views.  The
+// view loop is unrolled so that several views' loads are in flight.
+template <bool kTwo>
 __global__ __launch_bounds__(kBackX *kBackY) void k_back(
-    const ViewGeom *__restrict__ views, int N, int V, int B, const float *__restrict__ r,
-    float *__restrict__ img, float scale, const int32_t *__restrict__ skip)
+    const ViewGeom *__restrict__ views, int N, int V, int B, int reach,
+    const float *__restrict__ r, float *__restrict__ img, float scale,
+    const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
@@ -170,22 +243,12 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
     if (ix >= N || iy >= N)
         return;
     Kahan acc;
+#pragma unroll 4
     for (int v = 0; v < V; ++v) {
         const ViewGeom G = views[v];
         const int k = G.col ? ix : iy;
         const int j = G.col ? iy : ix;
-        const double kd = (double)k, jd = (double)j;
-        const float fb = fmaf((float)j, G.cbpix, fmaf((float)k, G.cbk, G.cb0));
-        const int blo = max((int)ceilf(fb - G.halfw), 0);
-        const int bhi = min((int)floorf(fb + G.halfw), B - 1);
-        const float *rv = r + (size_t)v * B;
-        float sv = 0.f;
-        for (int b = blo; b <= bhi; ++b) {
-            const double f = fma(kd, G.Q, fma((double)b, G.P, G.A));
-            const float w = (float)(1.0 - fabs(f - jd));
-            if (w > 0.f)
-                sv = fmaf(w, rv[b], sv);
-        }
+        const float sv = gather_view<kTwo>(G, k, j, B, reach, r + (size_t)v * B);
         acc.add(sv * G.wstep);
     }
     img[(size_t)iy * N + ix] = acc.value() * scale;
@@ -449,8 +512,8 @@ hipError_t launch_forward(const Geo &g, const float *x, const float *xT, float *
     SpecArg none;
     none.K = 0;
     dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
-    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads), 0, st, g.views, g.N, g.B,
-                       x, xT, nullptr, none, s, skip);
+    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
+                       g.B, x, xT, nullptr, none, s, skip);
     return hipGetLastError();
 }
 
@@ -459,8 +522,8 @@ hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT
                                    const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
-    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads), 0, st, g.views, g.N, g.B,
-                       x, xT, Y, sp, r, skip);
+    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
+                       g.B, x, xT, Y, sp, r, skip);
     return hipGetLastError();
 }
 
@@ -468,8 +531,12 @@ hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
                        const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
-    hipLaunchKernelGGL(k_back, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V, g.B, r,
-                       img, scale, skip);
+    if (g.reach == 0)
+        hipLaunchKernelGGL(k_back<true>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
+                           g.B, 0, r, img, scale, skip);
+    else
+        hipLaunchKernelGGL(k_back<false>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
+                           g.B, g.reach, r, img, scale, skip);
     return hipGetLastError();
 }
 
