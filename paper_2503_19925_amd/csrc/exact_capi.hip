@@ -22,7 +22,7 @@ using exact::SpecArg;
 using exact::ViewGeom;
 
 struct exact_geometry_s {
-    int N, V, B, half_turns, reach;
+    int N, V, B, half_turns, reach, nrow;
     double pixel_cm, bin_cm;
     int device;
     ViewGeom *d_views;
@@ -65,7 +65,10 @@ int guarded(F &&body)
     }
 }
 
-Geo geo_of(const exact_geometry_s *g) { return Geo{g->d_views, g->N, g->V, g->B, g->reach}; }
+Geo geo_of(const exact_geometry_s *g)
+{
+    return Geo{g->d_views, g->N, g->V, g->B, g->nrow, g->reach};
+}
 
 void check_geometry(const exact_geometry_s *g)
 {
@@ -127,13 +130,13 @@ long double fixed32(long double v) { return roundl(ldexpl(v, 32)) / 4294967296.0
 // moves any crossing by at most (1 + b + k) 2^-33 pixel.  Sets *reach for the
 // back-projector and fails if a crossing could leave the exact range.
 std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pixel_cm,
-                                  double bin_cm, int *reach)
+                                  double bin_cm, int *reach, int *nrow)
 {
     const long double pi = 3.14159265358979323846264338327950288L;
     const long double c = (N - 1) / 2.0L;
     const long double half = (B - 1) / 2.0L;
     const long double ratio = (long double)bin_cm / (long double)pixel_cm;
-    std::vector<ViewGeom> out((size_t)V);
+    std::vector<ViewGeom> rows, cols;
     long double pmin = 1e30L;
     for (int v = 0; v < V; ++v) {
         const long q = ((long)half_turns * v) % V;
@@ -155,14 +158,16 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         G.A = (double)A;
         G.P = (double)P;
         G.Q = (double)Q;
-        G.cbpix = (double)(1.0L / P);
-        G.cbk = (double)(-Q / P);
-        G.cb0 = (double)(-A / P);
+        G.invP = (double)(1.0L / P);
+        G.absP = (double)fabsl(P);
         G.wstep = (float)((long double)pixel_cm / fabsl(cs));
-        G.col = row ? 0 : 1;
-        out[(size_t)v] = G;
+        G.vidx = v;
+        (row ? rows : cols).push_back(G);
         pmin = std::min(pmin, fabsl(P));
     }
+    *nrow = (int)rows.size();
+    std::vector<ViewGeom> out(rows);
+    out.insert(out.end(), cols.begin(), cols.end());
     // Bins within one pixel of a pixel's crossing satisfy |b - b*| < 1/|P|;
     // the nearest bin b0 is within 1/2 (+ rounding) of b*.
     *reach = pmin >= 1.0L ? 0 : (int)floorl(1.0L / pmin + 0.5L + 0.01L);
@@ -321,7 +326,8 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         g->d_views = nullptr;
         try {
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
-            g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm, &g->reach);
+            g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm,
+                                     &g->reach, &g->nrow);
             const size_t bytes = sizeof(ViewGeom) * (size_t)n_views;
             hip_check(hipMalloc((void **)&g->d_views, bytes), "hipMalloc");
             hip_check(hipMemcpy(g->d_views, g->h_views.data(), bytes, hipMemcpyHostToDevice),

@@ -24,16 +24,19 @@ constexpr int kMaxEnergies = 128;
 // back-projector).  Both kernels therefore apply bit-identical weights.
 //
 // The back-projector starts from the bin nearest to a pixel,
-// b0 = rint(j * cbpix + k * cbk + cb0) (= the exact solution of f(b, k) = j
-// to within double rounding), and examines only the bins that can lie
-// within one pixel of it.
+// b0 = rint((j - (A + k Q)) * invP) (the solution of f(b, k) = j to within
+// double rounding), and examines only the bins that can lie within one
+// pixel of it.
+//
+// The geometry's table lists the row-stepping views first and the
+// column-stepping views after them (Geo::nrow of each); vidx is the view's
+// index v in the sinogram.
 struct alignas(16) ViewGeom {
-    double A, P, Q;
-    double cb0, cbpix, cbk;
+    double A, P, Q, invP, absP;
     float wstep;
-    int32_t col;     // 0: row-stepping (k = iy, j = ix); 1: column (k = ix, j = iy)
+    int32_t vidx;
 };
-static_assert(sizeof(ViewGeom) == 56 || sizeof(ViewGeom) == 64, "ViewGeom layout");
+static_assert(sizeof(ViewGeom) == 48, "ViewGeom layout");
 
 // Spectrum collapsed over windows, passed to kernels by value.
 struct SpecArg {
@@ -57,6 +60,7 @@ struct SolveState {
 struct Geo {
     const ViewGeom *views;
     int N, V, B;
+    int nrow;        // views[0, nrow) step along rows, views[nrow, V) along columns
     // Bins examined on each side of the nearest one in the back-projector;
     // 1 (with the exact two-candidate rule) whenever every |P| >= 1, i.e.
     // bins at least as wide as pixels.

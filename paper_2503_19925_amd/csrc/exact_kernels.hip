@@ -77,14 +77,53 @@ __device__ __forceinline__ void ray_lines(double base, double Q, int N, int &k0,
     k1 = (int)hi;
 }
 
+constexpr int kLineBatch = 4;    // lines whose loads are in flight together
+constexpr int kViewBatch = 4;    // views likewise in the back-projector
+
+// The two taps of a ray on one line: crossing f (advanced by Q, exactly),
+// weights of pixels floor(f) and floor(f) + 1 (zero outside the image) and
+// their values, read from `row` at in-bounds indices.
+__device__ __forceinline__ void tap_pair(double &f, double Q, int N, const float *__restrict__ row,
+                                         float &w0, float &w1, float &v0, float &v1)
+{
+    const double fl = floor(f);
+    const double e0 = f - fl;                 // exact, in [0, 1)
+    f += Q;                                   // exact
+    const int j0 = (int)fl;                   // |f| < 2^20 by construction
+    const bool in0 = (unsigned)j0 < (unsigned)N;
+    const bool in1 = (unsigned)(j0 + 1) < (unsigned)N;
+    w0 = in0 ? (float)(1.0 - e0) : 0.f;       // pixel j0
+    w1 = in1 ? (float)e0 : 0.f;               // pixel j0 + 1: 1 - |f - (j0+1)| = e0 exactly
+    v0 = row[in0 ? (unsigned)j0 : 0u];
+    v1 = row[in1 ? (unsigned)(j0 + 1) : 0u];
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v = min(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v = max(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 // One lane per ray (v, b); the four waves of a workgroup take the same 64
 // rays and split the image lines into quarters, and their Kahan partial
-// sums are combined in a fixed order.  The crossing advances exactly by Q
-// per line.  Column-stepping views read the transposed image so that the
-// lanes of a wave touch neighbouring addresses on every line.
+// sums are combined in a fixed order.  A wave walks the lines any of its
+// rays needs (a wave-uniform loop, so the line's address is scalar); on a
+// line a ray does not reach both weights are zero.  The crossing advances
+// exactly by Q per line.  Column-stepping views read the transposed image
+// so that the lanes of a wave touch neighbouring addresses on every line.
+// Within a batch of lines the contributions are summed in float before the
+// Kahan step.
 template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
-    const ViewGeom *__restrict__ views, int N, int B, const float *__restrict__ x,
+    const ViewGeom *__restrict__ views, int N, int B, int nrow, const float *__restrict__ x,
     const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
     float *__restrict__ out, const int32_t *__restrict__ skip)
 {
@@ -92,36 +131,39 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
         return;
     __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
     const int lane = threadIdx.x % kFwdThreads;
-    const int seg = threadIdx.x / kFwdThreads;
-    const int v = blockIdx.y;
+    const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);  // wave-uniform
     const int b = blockIdx.x * kFwdThreads + lane;
-    const ViewGeom G = views[v];
-    const float *__restrict__ img = G.col ? xT : x;
+    const ViewGeom G = views[blockIdx.y];
+    const float *__restrict__ img = (int)blockIdx.y < nrow ? x : xT;
     const double base = fma((double)b, G.P, G.A);
 
     int k0, k1;
     ray_lines(base, G.Q, N, k0, k1);
+    if (b >= B) {
+        k0 = N;
+        k1 = -1;
+    }
     const int per = (N + kSegs - 1) / kSegs;
-    k0 = max(k0, seg * per);
-    k1 = min(k1, min(N, (seg + 1) * per) - 1);
-    if (b >= B)
-        k1 = k0 - 1;
+    const int kw0 = max(wave_min(k0), seg * per);
+    const int kw1 = min(wave_max(k1), min(N, (seg + 1) * per) - 1);
 
     Kahan acc;
-    double f = fma((double)k0, G.Q, base);
-#pragma unroll 4
-    for (int k = k0; k <= k1; ++k) {
-        const double fl = floor(f);
-        const double e0 = f - fl;                 // exact, in [0, 1)
-        f += G.Q;                                 // exact
-        if (fl < -1.0 || fl > (double)(N - 1))
-            continue;
-        const int j0 = (int)fl;
-        const float w0 = (float)(1.0 - e0);       // pixel j0
-        const float w1 = (float)e0;               // pixel j0 + 1: 1 - |f - (j0+1)| = e0
-        const float *row = img + (size_t)k * N;
-        const float v0 = j0 >= 0 ? row[j0] : 0.f;
-        const float v1 = j0 + 1 <= N - 1 ? row[j0 + 1] : 0.f;
+    double f = fma((double)kw0, G.Q, base);
+    int k = kw0;
+    for (; k + kLineBatch - 1 <= kw1; k += kLineBatch) {
+        float w0[kLineBatch], w1[kLineBatch], v0[kLineBatch], v1[kLineBatch];
+#pragma unroll
+        for (int q = 0; q < kLineBatch; ++q)
+            tap_pair(f, G.Q, N, img + (size_t)(k + q) * N, w0[q], w1[q], v0[q], v1[q]);
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < kLineBatch; ++q)
+            t = fmaf(w1[q], v1[q], fmaf(w0[q], v0[q], t));
+        acc.add(t);
+    }
+    for (; k <= kw1; ++k) {
+        float w0, w1, v0, v1;
+        tap_pair(f, G.Q, N, img + (size_t)k * N, w0, w1, v0, v1);
         acc.add(fmaf(w1, v1, w0 * v0));
     }
     part_s[seg][lane] = acc.s;
@@ -136,7 +178,7 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
         tot.add(-part_c[q][lane]);
     }
     const float s = tot.value() * G.wstep;
-    const size_t i = (size_t)v * B + b;
+    const size_t i = (size_t)G.vidx * B + b;
     if (kResid) {
         // r_i = Y_i - sum_k J_k exp(-mu_k max(s_i, 0))
         const float sp0 = fmaxf(s, 0.f);
@@ -193,46 +235,87 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 // away from the pixel adds |P| >= 1 to |d|, moving two bins towards it
 // leaves |d| >= (3/2 - tiny)|P| >= 1, so only b0 and its neighbour on the
 // pixel's side can have positive weight.
-template <bool kTwo>
-__device__ __forceinline__ float gather_view(const ViewGeom &G, int k, int j, int B, int reach,
-                                             const float *__restrict__ rv)
+// Two-candidate rule (every |P| >= 1): the nearest bin b0 has
+// |d0| <= (1/2 + tiny)|P| with d0 = f(b0, k) - j; moving away from the pixel
+// adds |P| >= 1 to |d|, and two bins towards it leaves |d| >= (3/2 - tiny)|P|
+// >= 1, so only b0 and its neighbour on the pixel's side, b1, can have
+// positive weight.  Returns w0 r[b0] + w1 r[b1] for pixel j on line k (the
+// path-length factor left out); out-of-range bins get weight 0 and an
+// in-bounds address.
+__device__ __forceinline__ float taps_two(const ViewGeom &G, double kd, double jd, int B,
+                                          const float *__restrict__ rv)
 {
-    const double kd = (double)k, jd = (double)j;
-    const double fb = fma(jd, G.cbpix, fma(kd, G.cbk, G.cb0));
-    const double b0d = fmin(fmax(rint(fb), -2.0 - reach), (double)(B + 1 + reach));
+    const double Kv = fma(kd, G.Q, G.A);                           // exact
+    const double b0d = rint((jd - Kv) * G.invP);                   // |b0 P| < 2^20
     const int b0 = (int)b0d;
-    const double d0 = fma(b0d, G.P, fma(kd, G.Q, G.A)) - jd;     // exact
-    if (kTwo) {
-        const bool up = (d0 > 0.0) != (G.P > 0.0);   // neighbour towards the pixel
-        const int b1 = up ? b0 + 1 : b0 - 1;
-        const double d1 = up ? d0 + G.P : d0 - G.P;  // exact
-        const float w0 = (float)(1.0 - fabs(d0));
-        const float w1 = (float)(1.0 - fabs(d1));
-        const bool ok0 = w0 > 0.f && b0 >= 0 && b0 < B;
-        const bool ok1 = w1 > 0.f && b1 >= 0 && b1 < B;
-        const float r0 = ok0 ? rv[b0] : 0.f;
-        const float r1 = ok1 ? rv[b1] : 0.f;
-        // ascending bin order, as the general rule below sums
-        return up ? fmaf(ok1 ? w1 : 0.f, r1, (ok0 ? w0 : 0.f) * r0)
-                  : fmaf(ok0 ? w0 : 0.f, r0, (ok1 ? w1 : 0.f) * r1);
-    } else {
-        float sv = 0.f;
-        for (int m = -reach; m <= reach; ++m) {
-            const int bb = b0 + m;
-            const double d = fma((double)m, G.P, d0);    // exact
-            const float w = (float)(1.0 - fabs(d));
-            if (w > 0.f && bb >= 0 && bb < B)
-                sv = fmaf(w, rv[bb], sv);
+    const double d0 = fma(b0d, G.P, Kv) - jd;                      // exact
+    const double d1 = d0 - copysign(G.absP, d0);                   // exact: towards the pixel
+    const int b1 = b0 + (((d0 > 0.0) == (G.P > 0.0)) ? -1 : 1);
+    const float u0 = (float)(1.0 - fabs(d0));
+    const float u1 = (float)(1.0 - fabs(d1));
+    const bool ok0 = u0 > 0.f && (unsigned)b0 < (unsigned)B;
+    const bool ok1 = u1 > 0.f && (unsigned)b1 < (unsigned)B;
+    const float r0 = rv[ok0 ? (unsigned)b0 : 0u];
+    const float r1 = rv[ok1 ? (unsigned)b1 : 0u];
+    return fmaf(ok1 ? u1 : 0.f, r1, (ok0 ? u0 : 0.f) * r0);
+}
+
+// General rule (bins narrower than pixels): every bin within `reach` of b0.
+__device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double jd, int B,
+                                            int reach, const float *__restrict__ rv)
+{
+    const double Kv = fma(kd, G.Q, G.A);                           // exact
+    const double b0d = fmin(fmax(rint((jd - Kv) * G.invP), -2.0 - reach),
+                            (double)(B + 1 + reach));
+    const int b0 = (int)b0d;
+    const double d0 = fma(b0d, G.P, Kv) - jd;                      // exact
+    float s = 0.f;
+    for (int m = -reach; m <= reach; ++m) {
+        const int bb = b0 + m;
+        const float u = (float)(1.0 - fabs(fma((double)m, G.P, d0)));   // exact distance
+        const bool ok = u > 0.f && (unsigned)bb < (unsigned)B;
+        s = fmaf(ok ? u : 0.f, rv[ok ? (unsigned)bb : 0u], s);
+    }
+    return s;
+}
+
+// Sum over views [v0, v1) of wstep * taps for pixel (kd, jd) of each view's
+// stepping line.  Batches of views: parameters and loads first, then a
+// float sum of the batch, then one Kahan step.
+template <bool kTwo>
+__device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views, int v0, int v1,
+                                             double kd, double jd, int B, int reach,
+                                             const float *__restrict__ r, Kahan &acc)
+{
+    int v = v0;
+    for (; v + kViewBatch <= v1; v += kViewBatch) {
+        float t[kViewBatch];
+#pragma unroll
+        for (int q = 0; q < kViewBatch; ++q) {
+            const ViewGeom G = views[v + q];
+            const float *rv = r + (size_t)G.vidx * B;
+            t[q] = (kTwo ? taps_two(G, kd, jd, B, rv) : taps_reach(G, kd, jd, B, reach, rv)) *
+                   G.wstep;
         }
-        return sv;
+        float sb = 0.f;
+#pragma unroll
+        for (int q = 0; q < kViewBatch; ++q)
+            sb += t[q];
+        acc.add(sb);
+    }
+    for (; v < v1; ++v) {
+        const ViewGeom G = views[v];
+        const float *rv = r + (size_t)G.vidx * B;
+        acc.add((kTwo ? taps_two(G, kd, jd, B, rv) : taps_reach(G, kd, jd, B, reach, rv)) *
+                G.wstep);
     }
 }
 
-// One lane per pixel, views in order, Kahan-compensated across views.  The
-// view loop is unrolled so that several views' loads are in flight.
+// One lane per pixel: the row-stepping views (line k = iy, pixel j = ix)
+// then the column-stepping views (k = ix, j = iy), Kahan-compensated.
 template <bool kTwo>
 __global__ __launch_bounds__(kBackX *kBackY) void k_back(
-    const ViewGeom *__restrict__ views, int N, int V, int B, int reach,
+    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float *__restrict__ img, float scale,
     const int32_t *__restrict__ skip)
 {
@@ -242,15 +325,10 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     if (ix >= N || iy >= N)
         return;
+    const double dx = (double)ix, dy = (double)iy;
     Kahan acc;
-#pragma unroll 4
-    for (int v = 0; v < V; ++v) {
-        const ViewGeom G = views[v];
-        const int k = G.col ? ix : iy;
-        const int j = G.col ? iy : ix;
-        const float sv = gather_view<kTwo>(G, k, j, B, reach, r + (size_t)v * B);
-        acc.add(sv * G.wstep);
-    }
+    gather_views<kTwo>(views, 0, nrow, dy, dx, B, reach, r, acc);
+    gather_views<kTwo>(views, nrow, V, dx, dy, B, reach, r, acc);
     img[(size_t)iy * N + ix] = acc.value() * scale;
 }
 
@@ -513,7 +591,7 @@ hipError_t launch_forward(const Geo &g, const float *x, const float *xT, float *
     none.K = 0;
     dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.B, x, xT, nullptr, none, s, skip);
+                       g.B, g.nrow, x, xT, nullptr, none, s, skip);
     return hipGetLastError();
 }
 
@@ -523,7 +601,7 @@ hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT
 {
     dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.B, x, xT, Y, sp, r, skip);
+                       g.B, g.nrow, x, xT, Y, sp, r, skip);
     return hipGetLastError();
 }
 
@@ -533,10 +611,10 @@ hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
     if (g.reach == 0)
         hipLaunchKernelGGL(k_back<true>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
-                           g.B, 0, r, img, scale, skip);
+                           g.B, g.nrow, 0, r, img, scale, skip);
     else
         hipLaunchKernelGGL(k_back<false>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
-                           g.B, g.reach, r, img, scale, skip);
+                           g.B, g.nrow, g.reach, r, img, scale, skip);
     return hipGetLastError();
 }
 
