@@ -12,7 +12,18 @@ all state resident in HBM.
 
 Prints one JSON line: EG iterations/s (value), projector rays/s, the
 back-projector's algorithmic-bytes roofline fraction (HIP events), and the
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  Two more legs
+report reconstructions/s and time-to-tolerance percentiles:
+
+* batched: 64 uneven scans (N in {128..768}, 30-360 views, 10-64 energy
+  bins, 2-4 windows; seed 401), each to natural residual 1e-4 (cap 5000
+  steps), once one at a time with exact_solve and once in one batch;
+  results are bitwise equal, so the accuracy is equal;
+* served: the first --served requests of a seeded Poisson stream at 20
+  requests/s (N in {256, 512, 1024}, 90/180/360 views, K = 30, Wn = 3,
+  I0 in {1e3, 1e4}, tolerance 1e-3 or 1e-4), admitted by HBM footprint and
+  batched continuously; time-to-tolerance runs from arrival to the result on
+  the host.
 """
 import argparse
 import json
@@ -64,6 +75,86 @@ def cpu_baseline(P, gamma, steps):
                       "%.1f s)" % (steps, dt)}
 
 
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
+
+
+def batched_leg(count, torch, exact, synth):
+    """Same scans, one at a time and batched; wall time includes each scan's
+    set-up (validation, power iteration) on both sides."""
+    tol, cap = 1e-4, 5000
+    Ps = [synth.make_problem("batch%d" % i, with_truth=False, **d)
+          for i, d in enumerate(synth.batch_draws(count, 401))]
+    geos = [exact.Geometry(P.n_pix, P.n_views, P.n_bins) for P in Ps]
+    ys = [torch.as_tensor(P.y, device="cuda") for P in Ps]
+    torch.cuda.synchronize()
+    log("batched leg: %d scans generated" % count)
+    xs_serial, iters_serial, done_serial = [], [], []
+    t0 = time.perf_counter()
+    for P, g, y in zip(Ps, geos, ys):
+        x = torch.zeros(g.d, device="cuda")
+        info = exact.exact_solve(g, P.mu, P.I, y, x, max_iters=cap, tol=tol, check_every=32)
+        if len(xs_serial) % 16 == 15:
+            log("serial: %d scans done" % (len(xs_serial) + 1))
+        xs_serial.append(x)
+        iters_serial.append(info["iters"])
+        done_serial.append(time.perf_counter() - t0)
+    t_serial = time.perf_counter() - t0
+    log("serial: %.2f s" % t_serial)
+    footprint = sum(exact.exact_run_footprint(P.n_pix, P.n_views, P.n_bins) for P in Ps)
+    xs = [torch.zeros(g.d, device="cuda") for g in geos]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = exact.Batch(footprint + (1 << 20), capacity=count)
+    slots = [b.add(g, P.mu, P.I, y, x, max_iters=cap, tol=tol) for P, g, y, x in zip(Ps, geos, ys, xs)]
+    done_at = {}
+    while len(done_at) < count:
+        b.step(32)
+        b.sync()
+        now = time.perf_counter() - t0
+        for s in slots:
+            if s not in done_at and b.poll(s)[0] != exact.RUNNING:
+                done_at[s] = now
+    t_batch = time.perf_counter() - t0
+    stats = [b.poll(s) for s in slots]
+    b.close()
+    log("batched: %.2f s" % t_batch)
+    same = all(st[1]["iters"] == it for st, it in zip(stats, iters_serial)) and \
+        all(torch.equal(a, c) for a, c in zip(xs, xs_serial))
+    capped = sum(1 for st in stats if st[0] == exact.CAPPED)
+    for g in geos:
+        g.close()
+    t_done = [done_at[s] for s in slots]
+    return {"scans": count, "tol": tol, "max_iters": cap,
+            "serial_recon_per_s": count / t_serial, "batched_recon_per_s": count / t_batch,
+            "speedup": t_serial / t_batch, "bitwise_equal_to_serial": bool(same),
+            "capped": capped, "mean_iters": sum(iters_serial) / count,
+            "batched_p50_s": pct(t_done, 50), "batched_p99_s": pct(t_done, 99),
+            "serial_p50_s": pct(done_serial, 50), "serial_p99_s": pct(done_serial, 99)}
+
+
+def served_leg(count, torch, exact, synth):
+    from paper_2503_19925_amd.serve import GpuBackend, Request, Server, summarize
+    stream = synth.served_stream(300, 20.0, 501)[:count]
+    reqs = [Request(q, s["arrival"], synth.make_problem("req%d" % q, with_truth=False,
+                                                        **s["params"]), s["tol"], 20000)
+            for q, s in enumerate(stream)]
+    log("served leg: %d requests generated" % count)
+    budget = 64 << 30
+    be = GpuBackend(budget, capacity=max(8, count), keep_x=False)
+    def progress(r):
+        log("served: request %d done (%d steps, %.2f s after arrival)" % (r.rid, r.iters, r.latency))
+
+    srv = Server(be, budget, chunk_steps=16, on_done=progress)
+    res = srv.run(reqs)
+    be.close()
+    s = summarize(res)
+    s["offered_req_per_s"] = (count - 1) / (reqs[-1].arrival - reqs[0].arrival)
+    s["peak_running"] = srv.peak_running
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +163,9 @@ def main():
     ap.add_argument("--proj-reps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
+    ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
+    ap.add_argument("--served", type=int, default=40,
+                    help="requests in the served leg (0 to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -129,6 +223,12 @@ def main():
     achieved = bytes_back / (t_back * 1e-3) / 1e9
     log("nnz %d; back %.4f ms, forward(+transpose) %.4f ms" % (nnz, t_back, t_fwd))
 
+    batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
+    served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
+    if served:
+        log("served: p50 %.2f s, p99 %.2f s, %.2f recon/s" % (served["p50_s"], served["p99_s"],
+                                                             served["recon_per_s"]))
+
     base = None
     if args.cpu_steps > 0:
         log("cpu baseline: %d oracle EG steps" % args.cpu_steps)
@@ -160,6 +260,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None},
         "cpu_baseline": base,
+        "batched": batched,
+        "served": served,
     }
     g.close()
     print(json.dumps(out), flush=True)

@@ -40,7 +40,8 @@
  *  streams at once.
  *
  *  Errors.  0 on success; a negative errno value on failure (-EINVAL bad
- *  argument, -ENOMEM out of memory, -EIO a HIP runtime error); see
+ *  argument, -ENOMEM out of memory, -ENOSPC a batch's budget or slots
+ *  exhausted, -EIO a HIP runtime error); see
  *  exact_last_error() for a message.  exact_solve returns EXACT_ENOTCONV
  *  (+1) when max_iters ends the run before the tolerance is met.  No C++
  *  exception crosses this interface.
@@ -211,6 +212,49 @@ int exact_solver_destroy(exact_solver s);
  * expression.  Blocks until done.
  */
 int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream);
+
+/*
+ * Batched and served extragradient (many independent reconstructions of
+ * different shapes at once).  A batch holds runs in slots; every
+ * exact_batch_step advances all running runs by whole extragradient steps
+ * with one captured graph of seven phase kernels, whose workgroups take
+ * (run, tile) items from device lists, heaviest runs first.  The per-item
+ * arithmetic is exact_solve's own, so each run's iterates are bitwise the
+ * same alone and in any batch.  A run that has stopped costs nothing further
+ * (its items return at once) until it is removed; runs may join or leave
+ * between steps (the lists and the graph are then rebuilt).
+ *
+ * exact_run_footprint: device bytes one run allocates inside the library
+ *   (the caller's x and y are extra); 0 for invalid sizes.
+ * exact_batch_create: hbm_budget_bytes caps the sum of the runs'
+ *   footprints; capacity is the number of slots (1..65536).
+ * exact_batch_add: validates and sets up one run as exact_solver_create
+ *   does (blocking; ordered after `stream`), and returns its slot.  x_dev is
+ *   the run's iterate, updated in place by every step: it must stay valid
+ *   and unwritten by the caller until exact_batch_remove.  -ENOSPC when the
+ *   budget or the slots are exhausted.
+ * exact_batch_step: enqueues n_steps steps of every run on `stream`
+ *   (asynchronous).
+ * exact_batch_sync: waits for the enqueued steps and refreshes the host copy
+ *   of every run's state; returns the number of runs still running.
+ * exact_batch_poll: from the last sync: 0 running, 1 finished (tolerance
+ *   met, or all max_iters steps run when tol = 0), 2 stopped at max_iters
+ *   without meeting tol > 0; info (nullable) is filled.
+ * exact_batch_remove: waits for the batch's work and frees the slot.
+ * exact_batch_destroy: waits and frees everything.
+ */
+typedef struct exact_batch_s *exact_batch;
+
+size_t exact_run_footprint(int32_t n_pix, int32_t n_views, int32_t n_bins);
+int exact_batch_create(size_t hbm_budget_bytes, int32_t capacity, exact_batch *out);
+int exact_batch_add(exact_batch b, exact_geometry g, const exact_spectrum *sp,
+                    const float *y_dev, float *x_dev, const exact_solve_opts *opts,
+                    int32_t *slot_out, void *stream);
+int exact_batch_step(exact_batch b, int32_t n_steps, void *stream);
+int exact_batch_sync(exact_batch b);
+int exact_batch_poll(exact_batch b, int32_t slot, exact_solve_info *info);
+int exact_batch_remove(exact_batch b, int32_t slot);
+int exact_batch_destroy(exact_batch b);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *exact_last_error(void);

@@ -454,35 +454,59 @@ int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream)
 
 }  // extern "C"
 
-// A resident extragradient run: the spectrum, the window sums of y, the
-// iterate's transpose, the half-step iterate, the gradient buffer, the
-// partial sums and the device state stay allocated, and one full step is a
-// captured graph replayed on a private stream.
-struct exact_solver_s {
+// One extragradient run's device state: the spectrum, the window sums of
+// y, the iterate's transpose, the half-step iterate and its transpose, the
+// gradient and residual buffers, the update partials.  The iterate itself
+// is the caller's buffer.  `state` points at the run's SolveState (owned by
+// the solver or the batch).
+struct Problem {
     const exact_geometry_s *g = nullptr;
     SpecArg spec;
     double gamma = 0.0, lam = 0.0;
     int max_iters = 0;
     float *x = nullptr;
-    std::unique_ptr<OwnStream> own;
-    std::unique_ptr<DevBuf> Y, r, gr, xT, xh, xhT, parts, state;
-    std::unique_ptr<PinnedState> hs;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::chrono::steady_clock::time_point t0;
+    std::unique_ptr<DevBuf> Y, r, gr, xT, xh, xhT, parts, specd;
+    SolveState *state = nullptr;
+    size_t footprint = 0;
 
-    ~exact_solver_s()
+    exact::BatchProb desc() const
     {
-        if (own && own->st)
-            (void)hipStreamSynchronize(own->st);
-        if (exec)
-            (void)hipGraphExecDestroy(exec);
-        if (graph)
-            (void)hipGraphDestroy(graph);
+        exact::BatchProb d;
+        std::memset(&d, 0, sizeof(d));
+        d.views = g->d_views;
+        d.N = g->N;
+        d.V = g->V;
+        d.B = g->B;
+        d.nrow = g->nrow;
+        d.reach = g->reach;
+        d.K = spec.K;
+        d.ntiles = exact::num_tiles(g->N);
+        d.Y = Y->as<float>();
+        d.J = specd->as<float>();
+        d.mu = specd->as<float>() + exact::kMaxEnergies;
+        d.x = x;
+        d.xT = xT->as<float>();
+        d.xh = xh->as<float>();
+        d.xhT = xhT->as<float>();
+        d.g = gr->as<float>();
+        d.r = r->as<float>();
+        d.parts = parts->as<double>();
+        d.state = state;
+        d.gamma = (float)gamma;
+        d.inv_n = (float)(1.0 / ((double)g->V * g->B));
+        return d;
     }
 };
 
 namespace {
+
+// Device bytes one run allocates (besides the caller's x and y).
+size_t run_footprint(int N, int V, int B)
+{
+    const size_t d = (size_t)N * N, n = (size_t)V * B;
+    return 4 * (2 * n + 5 * d) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
+           sizeof(SolveState);
+}
 
 void validate_opts(exact_solve_opts &o)
 {
@@ -502,75 +526,43 @@ void validate_opts(exact_solve_opts &o)
         o.power_iters = 1;
 }
 
-// Enqueue order of one extragradient step (paper Sec. 1.2, eq.
-// extragrad-method): F at x_t, half-step from x_t, F at x_{t+1/2}, full step
-// again from x_t, then the fixed-order residual reduction and stop test.
-void capture_step(exact_solver_s *s)
-{
-    const exact_geometry_s *g = s->g;
-    const Geo G = geo_of(g);
-    const long n = (long)g->V * g->B;
-    const int ntiles = exact::num_tiles(g->N);
-    const float gf = (float)s->gamma;
-    const float inv_n = (float)(1.0 / (double)n);
-    hipStream_t st = s->own->st;
-    SolveState *S = s->state->as<SolveState>();
-    const int32_t *skip = &S->done;
-    float *Y = s->Y->as<float>(), *r = s->r->as<float>(), *gr = s->gr->as<float>();
-    float *xT = s->xT->as<float>(), *xh = s->xh->as<float>(), *xhT = s->xhT->as<float>();
-    double *parts = s->parts->as<double>();
-
-    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t ce = hipSuccess;
-    auto cap = [&](hipError_t e) {
-        if (ce == hipSuccess && e != hipSuccess)
-            ce = e;
-    };
-    cap(exact::launch_forward_residual(G, s->x, xT, Y, s->spec, r, skip, st));
-    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
-    cap(exact::launch_eg_update(s->x, gr, gf, xh, xhT, g->N, parts, skip, st));
-    cap(exact::launch_forward_residual(G, xh, xhT, Y, s->spec, r, skip, st));
-    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
-    cap(exact::launch_eg_update(s->x, gr, gf, s->x, xT, g->N, nullptr, skip, st));
-    cap(exact::launch_eg_finish(parts, ntiles, S, st));
-    hipError_t ee = hipStreamEndCapture(st, &s->graph);
-    hip_check(ce, "kernel launch during capture");
-    hip_check(ee, "hipStreamEndCapture");
-    hip_check(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-}
-
-exact_solver_s *solver_build(exact_geometry_s *g, const exact_spectrum *sp, const float *y_dev,
-                             float *x_dev, exact_solve_opts o, hipStream_t user)
+// Validates the inputs, sums the windows of y, checks y and x_1 on the
+// device, picks the step size (Theorem 2's rule by power iteration unless
+// given), writes x_1's transpose and initialises the device state.  Blocks.
+void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *sp,
+                  const float *y_dev, float *x_dev, exact_solve_opts o, SolveState *state,
+                  hipStream_t st)
 {
     check_geometry(g);
     if (!y_dev || !x_dev)
         fail(-EINVAL, "NULL buffer");
     validate_opts(o);
     double sjm = 0.0;
-    std::unique_ptr<exact_solver_s> s(new exact_solver_s());
-    s->t0 = std::chrono::steady_clock::now();
-    s->g = g;
-    s->spec = make_spec(sp, &sjm);
-    s->x = x_dev;
-    s->max_iters = o.max_iters;
+    p.g = g;
+    p.spec = make_spec(sp, &sjm);
+    p.x = x_dev;
+    p.max_iters = o.max_iters;
+    p.state = state;
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
-    s->own.reset(new OwnStream(user));
-    hipStream_t st = s->own->st;
-    s->Y.reset(new DevBuf(n * 4));
-    s->r.reset(new DevBuf(n * 4));
-    s->gr.reset(new DevBuf(d * 4));
-    s->xT.reset(new DevBuf(d * 4));
-    s->xh.reset(new DevBuf(d * 4));
-    s->xhT.reset(new DevBuf(d * 4));
-    s->parts.reset(new DevBuf((size_t)exact::num_tiles(g->N) * 2 * 8));
-    s->state.reset(new DevBuf(sizeof(SolveState)));
-    s->hs.reset(new PinnedState());
+    p.footprint = run_footprint(g->N, g->V, g->B);
+    p.Y.reset(new DevBuf(n * 4));
+    p.r.reset(new DevBuf(n * 4));
+    p.gr.reset(new DevBuf(d * 4));
+    p.xT.reset(new DevBuf(d * 4));
+    p.xh.reset(new DevBuf(d * 4));
+    p.xhT.reset(new DevBuf(d * 4));
+    p.parts.reset(new DevBuf((size_t)exact::num_tiles(g->N) * 2 * 8));
+    p.specd.reset(new DevBuf(2 * exact::kMaxEnergies * 4));
+    hip_check(hipMemcpyAsync(p.specd->p, p.spec.J, exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(p.specd->as<float>() + exact::kMaxEnergies, p.spec.mu,
+                             exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
 
-    // window sums of y and the domain checks on y and x_1
     DevBuf bad(8);
     int32_t *badp = bad.as<int32_t>();
     hip_check(hipMemsetAsync(bad.p, 0, 8, st), "hipMemsetAsync");
-    hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, s->Y->as<float>(), badp, st),
+    hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, p.Y->as<float>(), badp, st),
               "window_sum");
     hip_check(exact::launch_count_bad(x_dev, d, badp + 1, st), "count_bad");
     int32_t hbad[2] = {0, 0};
@@ -581,51 +573,248 @@ exact_solver_s *solver_build(exact_geometry_s *g, const exact_spectrum *sp, cons
     if (hbad[1])
         fail(-EINVAL, "x_1 contains negative or non-finite values");
 
-    s->gamma = o.gamma;
-    if (s->gamma <= 0.0) {
-        s->lam = power_iteration(g, o.power_iters, st, nullptr);
-        s->gamma = o.gamma_scale / (s->lam * sjm);
+    p.gamma = o.gamma;
+    if (p.gamma <= 0.0) {
+        p.lam = power_iteration(g, o.power_iters, st, nullptr);
+        p.gamma = o.gamma_scale / (p.lam * sjm);
     }
-    hip_check(exact::launch_transpose(x_dev, s->xT->as<float>(), g->N, st), "transpose");
-    hip_check(exact::launch_state_init(s->state->as<SolveState>(), o.tol, o.max_iters, st),
-              "state_init");
-    capture_step(s.get());
+    hip_check(exact::launch_transpose(x_dev, p.xT->as<float>(), g->N, st), "transpose");
+    hip_check(exact::launch_state_init(state, o.tol, o.max_iters, st), "state_init");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-    return s.release();
 }
 
-void solver_enqueue(exact_solver_s *s, int n_steps, hipStream_t user)
+void fill_info(const Problem &p, const SolveState &h, exact_solve_info *info,
+               std::chrono::steady_clock::time_point t0)
 {
-    hipStream_t st = s->own->st;
+    if (!info)
+        return;
+    info->iters = p.max_iters == 0 ? 0 : h.t;
+    info->resid = p.max_iters == 0 ? -1.0 : h.rho;
+    info->gamma = p.gamma;
+    info->lambda_hat = p.lam;
+    info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Enqueue `n` replays of `exec` on `own`, ordered after and before `user`.
+void replay(hipGraphExec_t exec, int n, hipStream_t own, hipStream_t user)
+{
     hipEvent_t ev;
     hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
     hipError_t e = hipEventRecord(ev, user);
     if (e == hipSuccess)
-        e = hipStreamWaitEvent(st, ev, 0);
-    for (int c = 0; c < n_steps && e == hipSuccess; ++c)
-        e = hipGraphLaunch(s->exec, st);
+        e = hipStreamWaitEvent(own, ev, 0);
+    for (int c = 0; c < n && e == hipSuccess; ++c)
+        e = hipGraphLaunch(exec, own);
     if (e == hipSuccess)
-        e = hipEventRecord(ev, st);
+        e = hipEventRecord(ev, own);
     if (e == hipSuccess)
         e = hipStreamWaitEvent(user, ev, 0);
     (void)hipEventDestroy(ev);
     hip_check(e, "graph replay");
 }
 
-// Reads the device state (blocking on the solver's stream).
+struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~Graph() { reset(); }
+    // Captures whatever `enqueue` launches on st.
+    template <class F>
+    void capture(hipStream_t st, F &&enqueue)
+    {
+        reset();
+        hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        const hipError_t ce = enqueue();
+        const hipError_t ee = hipStreamEndCapture(st, &graph);
+        hip_check(ce, "kernel launch during capture");
+        hip_check(ee, "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+};
+
+// Enqueue order of one extragradient step (paper Sec. 1.2, eq.
+// extragrad-method): F at x_t, half-step from x_t, F at x_{t+1/2}, full step
+// again from x_t, then the fixed-order residual reduction and stop test.
+hipError_t enqueue_step(const Problem &p, hipStream_t st)
+{
+    const exact_geometry_s *g = p.g;
+    const Geo G = geo_of(g);
+    const long n = (long)g->V * g->B;
+    const int ntiles = exact::num_tiles(g->N);
+    const float gf = (float)p.gamma;
+    const float inv_n = (float)(1.0 / (double)n);
+    SolveState *S = p.state;
+    const int32_t *skip = &S->done;
+    float *Y = p.Y->as<float>(), *r = p.r->as<float>(), *gr = p.gr->as<float>();
+    float *xT = p.xT->as<float>(), *xh = p.xh->as<float>(), *xhT = p.xhT->as<float>();
+    double *parts = p.parts->as<double>();
+    hipError_t e = hipSuccess;
+    auto cap = [&](hipError_t x) {
+        if (e == hipSuccess && x != hipSuccess)
+            e = x;
+    };
+    cap(exact::launch_forward_residual(G, p.x, xT, Y, p.spec, r, skip, st));
+    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
+    cap(exact::launch_eg_update(p.x, gr, gf, xh, xhT, g->N, parts, skip, st));
+    cap(exact::launch_forward_residual(G, xh, xhT, Y, p.spec, r, skip, st));
+    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
+    cap(exact::launch_eg_update(p.x, gr, gf, p.x, xT, g->N, nullptr, skip, st));
+    cap(exact::launch_eg_finish(parts, ntiles, S, st));
+    return e;
+}
+
+}  // namespace
+
+// A resident extragradient run: its Problem, its state, a private stream
+// and the captured step graph.
+struct exact_solver_s {
+    std::unique_ptr<OwnStream> own;
+    std::unique_ptr<DevBuf> state;
+    std::unique_ptr<PinnedState> hs;
+    Problem prob;
+    Graph step;
+    std::chrono::steady_clock::time_point t0;
+
+    ~exact_solver_s()
+    {
+        if (own && own->st)
+            (void)hipStreamSynchronize(own->st);
+        step.reset();
+    }
+};
+
+namespace {
+
+exact_solver_s *solver_build(exact_geometry_s *g, const exact_spectrum *sp, const float *y_dev,
+                             float *x_dev, const exact_solve_opts &o, hipStream_t user)
+{
+    std::unique_ptr<exact_solver_s> s(new exact_solver_s());
+    s->t0 = std::chrono::steady_clock::now();
+    check_geometry(g);
+    s->own.reset(new OwnStream(user));
+    s->state.reset(new DevBuf(sizeof(SolveState)));
+    s->hs.reset(new PinnedState());
+    problem_init(s->prob, g, sp, y_dev, x_dev, o, s->state->as<SolveState>(), s->own->st);
+    const Problem &p = s->prob;
+    s->step.capture(s->own->st, [&]() { return enqueue_step(p, s->own->st); });
+    return s.release();
+}
+
 int solver_poll(exact_solver_s *s, exact_solve_info *info)
 {
-    read_state(s->state->as<SolveState>(), *s->hs, s->own->st);
-    const SolveState &h = *s->hs->h;
-    if (info) {
-        info->iters = s->max_iters == 0 ? 0 : h.t;
-        info->resid = s->max_iters == 0 ? -1.0 : h.rho;
-        info->gamma = s->gamma;
-        info->lambda_hat = s->lam;
-        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s->t0)
-                       .count();
+    read_state(s->prob.state, *s->hs, s->own->st);
+    fill_info(s->prob, *s->hs->h, info, s->t0);
+    return s->hs->h->done ? 1 : 0;
+}
+
+}  // namespace
+
+// A batch: many runs of different shapes advanced together, one captured
+// graph of seven batched phase kernels per step.  Runs occupy slots; the
+// device descriptors and item lists are rebuilt (and the graph recaptured)
+// at the next step after a run joins or leaves.
+struct exact_batch_s {
+    size_t budget = 0, used = 0;
+    int capacity = 0;
+    std::unique_ptr<OwnStream> own;
+    std::unique_ptr<DevBuf> states;                 // SolveState[capacity]
+    SolveState *hstates = nullptr;                   // pinned host copy
+    std::vector<std::unique_ptr<Problem>> slots;     // nullptr: free
+    std::vector<std::chrono::steady_clock::time_point> started;
+    std::vector<char> stopped;                       // host view, from the last sync
+    bool dirty = true;
+    std::unique_ptr<DevBuf> descs, fwd, back, upd;
+    int nprob = 0, nfwd = 0, nback = 0, nupd = 0;
+    Graph step;
+
+    ~exact_batch_s()
+    {
+        if (own && own->st)
+            (void)hipStreamSynchronize(own->st);
+        step.reset();
+        if (hstates)
+            (void)hipHostFree(hstates);
     }
-    return h.done ? 1 : 0;
+};
+
+namespace {
+
+// Item lists of the runs still running (as of the last sync), heaviest
+// first (work per item grows with N) so the long tiles start early.  A run
+// that stopped is left out: its workgroups would only return at once.
+void batch_rebuild(exact_batch_s *b)
+{
+    std::vector<int> order;
+    for (int i = 0; i < (int)b->slots.size(); ++i)
+        if (b->slots[(size_t)i] && !b->stopped[(size_t)i])
+            order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return b->slots[(size_t)a]->g->N > b->slots[(size_t)c]->g->N;
+    });
+    std::vector<exact::BatchProb> descs;
+    std::vector<exact::BatchItem> fwd, back, upd;
+    for (int slot : order) {
+        const Problem &p = *b->slots[(size_t)slot];
+        const int pi = (int)descs.size();
+        descs.push_back(p.desc());
+        const int nbb = exact::fwd_items_per_view(p.g->B);
+        for (int v = 0; v < p.g->V; ++v)
+            for (int bb = 0; bb < nbb; ++bb)
+                fwd.push_back(exact::BatchItem{pi, v, bb, 0});
+        const int bt = exact::back_tiles_per_side(p.g->N);
+        for (int ty = 0; ty < bt; ++ty)
+            for (int tx = 0; tx < bt; ++tx)
+                back.push_back(exact::BatchItem{pi, tx, ty, 0});
+        const int ut = exact::update_tiles_per_side(p.g->N);
+        for (int ty = 0; ty < ut; ++ty)
+            for (int tx = 0; tx < ut; ++tx)
+                upd.push_back(exact::BatchItem{pi, tx, ty, 0});
+    }
+    hipStream_t st = b->own->st;
+    auto upload = [&](std::unique_ptr<DevBuf> &buf, const void *src, size_t bytes) {
+        buf.reset(new DevBuf(bytes));
+        if (bytes)
+            hip_check(hipMemcpyAsync(buf->p, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    };
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    upload(b->descs, descs.data(), descs.size() * sizeof(exact::BatchProb));
+    upload(b->fwd, fwd.data(), fwd.size() * sizeof(exact::BatchItem));
+    upload(b->back, back.data(), back.size() * sizeof(exact::BatchItem));
+    upload(b->upd, upd.data(), upd.size() * sizeof(exact::BatchItem));
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    b->nprob = (int)descs.size();
+    b->nfwd = (int)fwd.size();
+    b->nback = (int)back.size();
+    b->nupd = (int)upd.size();
+    const exact::BatchProb *dp = b->descs->as<exact::BatchProb>();
+    const exact::BatchItem *f = b->fwd->as<exact::BatchItem>(), *bk = b->back->as<exact::BatchItem>(),
+                           *u = b->upd->as<exact::BatchItem>();
+    b->step.capture(st, [&]() {
+        return exact::launch_batch_step(dp, b->nprob, f, b->nfwd, bk, b->nback, u, b->nupd, st);
+    });
+    b->dirty = false;
+}
+
+exact_batch_s *batch_of(exact_batch b)
+{
+    if (!b)
+        fail(-EINVAL, "batch is NULL");
+    return b;
+}
+
+Problem &slot_of(exact_batch_s *b, int32_t slot)
+{
+    if (slot < 0 || slot >= (int)b->slots.size() || !b->slots[(size_t)slot])
+        fail(-EINVAL, "no run in slot " + std::to_string(slot));
+    return *b->slots[(size_t)slot];
 }
 
 }  // namespace
@@ -656,7 +845,7 @@ int exact_solver_step(exact_solver s, int32_t n_steps, void *stream)
             fail(-EINVAL, "solver is NULL");
         if (n_steps < 0)
             fail(-EINVAL, "n_steps must be >= 0");
-        solver_enqueue(s, n_steps, (hipStream_t)stream);
+        replay(s->step.exec, n_steps, s->own->st, (hipStream_t)stream);
         return 0;
     });
 }
@@ -693,7 +882,7 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev, 
         exact_solve_info local;
         while (launched < o.max_iters) {
             const int chunk = std::min(o.check_every, o.max_iters - launched);
-            solver_enqueue(s.get(), chunk, (hipStream_t)stream);
+            replay(s->step.exec, chunk, s->own->st, (hipStream_t)stream);
             launched += chunk;
             if (solver_poll(s.get(), &local))
                 break;
@@ -706,6 +895,155 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev, 
             *info = local;
         if (o.tol > 0.0 && !converged)
             return EXACT_ENOTCONV;
+        return 0;
+    });
+}
+
+size_t exact_run_footprint(int32_t n_pix, int32_t n_views, int32_t n_bins)
+{
+    if (n_pix < 1 || n_views < 1 || n_bins < 1)
+        return 0;
+    return run_footprint(n_pix, n_views, n_bins);
+}
+
+int exact_batch_create(size_t hbm_budget_bytes, int32_t capacity, exact_batch *out)
+{
+    return guarded([&]() -> int {
+        if (!out)
+            fail(-EINVAL, "out is NULL");
+        *out = nullptr;
+        if (capacity < 1 || capacity > 65536)
+            fail(-EINVAL, "capacity must be in [1, 65536]");
+        std::unique_ptr<exact_batch_s> b(new exact_batch_s());
+        b->budget = hbm_budget_bytes;
+        b->capacity = capacity;
+        b->own.reset(new OwnStream(nullptr));
+        b->states.reset(new DevBuf(sizeof(SolveState) * (size_t)capacity));
+        hip_check(hipHostMalloc((void **)&b->hstates, sizeof(SolveState) * (size_t)capacity,
+                                hipHostMallocDefault),
+                  "hipHostMalloc");
+        std::memset(b->hstates, 0, sizeof(SolveState) * (size_t)capacity);
+        b->slots.resize((size_t)capacity);
+        b->started.resize((size_t)capacity);
+        b->stopped.assign((size_t)capacity, 0);
+        *out = b.release();
+        return 0;
+    });
+}
+
+int exact_batch_add(exact_batch bh, exact_geometry g, const exact_spectrum *sp, const float *y_dev,
+                    float *x_dev, const exact_solve_opts *opts, int32_t *slot_out, void *stream)
+{
+    return guarded([&]() -> int {
+        exact_batch_s *b = batch_of(bh);
+        check_geometry(g);
+        if (!slot_out)
+            fail(-EINVAL, "slot_out is NULL");
+        *slot_out = -1;
+        const size_t need = run_footprint(g->N, g->V, g->B);
+        if (b->used + need > b->budget)
+            fail(-ENOSPC, "run needs " + std::to_string(need) + " bytes, " +
+                              std::to_string(b->budget - b->used) + " left in the batch budget");
+        int slot = -1;
+        for (int i = 0; i < b->capacity; ++i)
+            if (!b->slots[(size_t)i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0)
+            fail(-ENOSPC, "all " + std::to_string(b->capacity) + " slots are in use");
+        exact_solve_opts o;
+        exact_solve_opts_default(&o);
+        if (opts)
+            o = *opts;
+        std::unique_ptr<Problem> p(new Problem());
+        // set-up runs on the batch's stream, after the caller's stream
+        hip_check(hipStreamSynchronize(b->own->st), "hipStreamSynchronize");
+        hip_check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+        problem_init(*p, g, sp, y_dev, x_dev, o, b->states->as<SolveState>() + slot, b->own->st);
+        b->used += p->footprint;
+        b->slots[(size_t)slot] = std::move(p);
+        b->started[(size_t)slot] = std::chrono::steady_clock::now();
+        std::memset(&b->hstates[slot], 0, sizeof(SolveState));
+        b->stopped[(size_t)slot] = 0;
+        b->dirty = true;
+        *slot_out = slot;
+        return 0;
+    });
+}
+
+int exact_batch_step(exact_batch bh, int32_t n_steps, void *stream)
+{
+    return guarded([&]() -> int {
+        exact_batch_s *b = batch_of(bh);
+        if (n_steps < 0)
+            fail(-EINVAL, "n_steps must be >= 0");
+        if (b->dirty)
+            batch_rebuild(b);
+        if (b->nprob == 0 || n_steps == 0)
+            return 0;
+        replay(b->step.exec, n_steps, b->own->st, (hipStream_t)stream);
+        return 0;
+    });
+}
+
+int exact_batch_sync(exact_batch bh)
+{
+    return guarded([&]() -> int {
+        exact_batch_s *b = batch_of(bh);
+        hip_check(hipMemcpyAsync(b->hstates, b->states->p, sizeof(SolveState) * (size_t)b->capacity,
+                                 hipMemcpyDeviceToHost, b->own->st),
+                  "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(b->own->st), "hipStreamSynchronize");
+        int running = 0;
+        for (int i = 0; i < b->capacity; ++i) {
+            if (!b->slots[(size_t)i])
+                continue;
+            if (b->hstates[i].done) {
+                if (!b->stopped[(size_t)i]) {
+                    b->stopped[(size_t)i] = 1;
+                    b->dirty = true;        // drop its items at the next step
+                }
+            } else {
+                ++running;
+            }
+        }
+        return running;
+    });
+}
+
+int exact_batch_poll(exact_batch bh, int32_t slot, exact_solve_info *info)
+{
+    return guarded([&]() -> int {
+        exact_batch_s *b = batch_of(bh);
+        const Problem &p = slot_of(b, slot);
+        const SolveState &h = b->hstates[slot];
+        fill_info(p, h, info, b->started[(size_t)slot]);
+        if (!h.done)
+            return 0;
+        return (h.converged || p.max_iters == 0 || h.tol <= 0.0) ? 1 : 2;
+    });
+}
+
+int exact_batch_remove(exact_batch bh, int32_t slot)
+{
+    return guarded([&]() -> int {
+        exact_batch_s *b = batch_of(bh);
+        Problem &p = slot_of(b, slot);
+        hip_check(hipStreamSynchronize(b->own->st), "hipStreamSynchronize");
+        b->used -= p.footprint;
+        b->slots[(size_t)slot].reset();
+        if (!b->stopped[(size_t)slot])
+            b->dirty = true;
+        b->stopped[(size_t)slot] = 0;
+        return 0;
+    });
+}
+
+int exact_batch_destroy(exact_batch bh)
+{
+    return guarded([&]() -> int {
+        delete bh;
         return 0;
     });
 }

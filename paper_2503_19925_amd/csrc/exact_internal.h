@@ -67,6 +67,23 @@ struct Geo {
     int reach;
 };
 
+// One problem of a batch, as the batched kernels see it.
+struct BatchProb {
+    const ViewGeom *views;
+    int32_t N, V, B, nrow, reach, K, ntiles, pad;
+    const float *Y, *J, *mu;           // window sums of y; spectrum (device)
+    float *x, *xT, *xh, *xhT, *g, *r;  // iterate, half-step iterate (and transposes), gradient, residual
+    double *parts;                      // update partials, 2 per 32x32 tile
+    SolveState *state;
+    float gamma, inv_n;
+};
+
+// One workgroup's work: problem p and two coordinates (forward: table view
+// slot, bin block; back-projection and update: tile column, tile row).
+struct BatchItem {
+    int32_t p, a, b, pad;
+};
+
 // Partial sums produced per workgroup by the update and dot kernels.
 constexpr int kTile = 32;
 
@@ -75,6 +92,15 @@ int num_dot_parts(long d);
 int num_count_parts(const Geo &g);
 
 hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st);
+
+// Batched step: the seven phases of one extragradient step over the item
+// lists (forward items, back-projection tiles, update tiles).
+hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem *fwd, int nfwd,
+                             const BatchItem *back, int nback, const BatchItem *upd, int nupd,
+                             hipStream_t st);
+int fwd_items_per_view(int B);
+int back_tiles_per_side(int N);
+int update_tiles_per_side(int N);
 
 hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st);
 hipError_t launch_fill(float *x, float value, long count, hipStream_t st);

@@ -121,20 +121,29 @@ __device__ __forceinline__ int wave_max(int v)
 // so that the lanes of a wave touch neighbouring addresses on every line.
 // Within a batch of lines the contributions are summed in float before the
 // Kahan step.
-template <bool kResid>
-__global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
-    const ViewGeom *__restrict__ views, int N, int B, int nrow, const float *__restrict__ x,
-    const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
-    float *__restrict__ out, const int32_t *__restrict__ skip)
+// Spectrum read through device pointers (the batched kernels).
+struct SpecPtr {
+    int32_t K;
+    const float *__restrict__ J;
+    const float *__restrict__ mu;
+};
+
+// Forward projection of rays [64 bblock, 64 bblock + 64) of table view
+// `slot` by one workgroup of kFwdThreads * kSegs threads; with kResid the
+// spectral residual replaces the line integral in `out`.
+template <bool kResid, class Spec>
+__device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views, int N, int B,
+                                              int nrow, const float *__restrict__ x,
+                                              const float *__restrict__ xT,
+                                              const float *__restrict__ Y, const Spec &sp,
+                                              float *__restrict__ out, int slot, int bblock)
 {
-    if (skipped(skip))
-        return;
     __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
     const int lane = threadIdx.x % kFwdThreads;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);  // wave-uniform
-    const int b = blockIdx.x * kFwdThreads + lane;
-    const ViewGeom G = views[blockIdx.y];
-    const float *__restrict__ img = (int)blockIdx.y < nrow ? x : xT;
+    const int b = bblock * kFwdThreads + lane;
+    const ViewGeom G = views[slot];
+    const float *__restrict__ img = slot < nrow ? x : xT;
     const double base = fma((double)b, G.P, G.A);
 
     int k0, k1;
@@ -189,6 +198,17 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     } else {
         out[i] = s;
     }
+}
+
+template <bool kResid>
+__global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
+    const ViewGeom *__restrict__ views, int N, int B, int nrow, const float *__restrict__ x,
+    const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
+    float *__restrict__ out, const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    forward_block<kResid>(views, N, B, nrow, x, xT, Y, sp, out, blockIdx.y, blockIdx.x);
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -314,15 +334,12 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
 // One lane per pixel: the row-stepping views (line k = iy, pixel j = ix)
 // then the column-stepping views (k = ix, j = iy), Kahan-compensated.
 template <bool kTwo>
-__global__ __launch_bounds__(kBackX *kBackY) void k_back(
-    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
-    const float *__restrict__ r, float *__restrict__ img, float scale,
-    const int32_t *__restrict__ skip)
+__device__ __forceinline__ void back_tile(const ViewGeom *__restrict__ views, int N, int V, int B,
+                                          int nrow, int reach, const float *__restrict__ r,
+                                          float *__restrict__ img, float scale, int tx, int ty)
 {
-    if (skipped(skip))
-        return;
-    const int ix = blockIdx.x * kBackX + threadIdx.x;
-    const int iy = blockIdx.y * kBackY + threadIdx.y;
+    const int ix = tx * kBackX + threadIdx.x;
+    const int iy = ty * kBackY + threadIdx.y;
     if (ix >= N || iy >= N)
         return;
     const double dx = (double)ix, dy = (double)iy;
@@ -330,6 +347,17 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
     gather_views<kTwo>(views, 0, nrow, dy, dx, B, reach, r, acc);
     gather_views<kTwo>(views, nrow, V, dx, dy, B, reach, r, acc);
     img[(size_t)iy * N + ix] = acc.value() * scale;
+}
+
+template <bool kTwo>
+__global__ __launch_bounds__(kBackX *kBackY) void k_back(
+    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
+    const float *__restrict__ r, float *__restrict__ img, float scale,
+    const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    back_tile<kTwo>(views, N, V, B, nrow, reach, r, img, scale, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------ elementwise / tiles
@@ -401,18 +429,16 @@ __global__ void k_state_init(SolveState *st, double tol, int max_iters)
     }
 }
 
-// z = max(0, x - gamma g); z and its transpose; optional partials.
+// z = max(0, x - gamma g) on one 32x32 tile; z and its transpose; with
+// kPartials the tile's double sums of (z - x)^2 and x^2 go to part2[0..1].
 template <bool kPartials>
-__global__ __launch_bounds__(kTile * 8) void k_eg_update(
-    const float *x, const float *__restrict__ g, float gamma, float *z,
-    float *__restrict__ zT, int N, double *__restrict__ partials,
-    const int32_t *__restrict__ skip)
+__device__ __forceinline__ void update_tile(const float *x, const float *__restrict__ g,
+                                            float gamma, float *z, float *__restrict__ zT, int N,
+                                            double *__restrict__ part2, int tx, int ty)
 {
-    if (skipped(skip))
-        return;
     __shared__ float tile[kTile][kTile + 1];
     __shared__ double red[2][kRedThreads];
-    const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+    const int bx = tx * kTile, by = ty * kTile;
     double num = 0.0, den = 0.0;
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int iy = by + rr, ix = bx + threadIdx.x;
@@ -439,15 +465,28 @@ __global__ __launch_bounds__(kTile * 8) void k_eg_update(
         double v2[2] = {num, den};
         block_sum<2>(v2, red);
         if (threadIdx.x == 0 && threadIdx.y == 0) {
-            const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-            partials[2 * blk] = v2[0];
-            partials[2 * blk + 1] = v2[1];
+            part2[0] = v2[0];
+            part2[1] = v2[1];
         }
     }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restrict__ partials,
-                                                           int nparts, SolveState *st)
+template <bool kPartials>
+__global__ __launch_bounds__(kTile * 8) void k_eg_update(
+    const float *x, const float *__restrict__ g, float gamma, float *z,
+    float *__restrict__ zT, int N, double *__restrict__ partials,
+    const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    update_tile<kPartials>(x, g, gamma, z, zT, N, kPartials ? partials + 2 * blk : nullptr,
+                           blockIdx.x, blockIdx.y);
+}
+
+// Fixed-order reduction of a run's update partials, rho_t, and the stop test.
+__device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
+                                             SolveState *st)
 {
     if (st->done)
         return;
@@ -470,6 +509,69 @@ __global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restr
             st->done = 1;
         }
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restrict__ partials,
+                                                           int nparts, SolveState *st)
+{
+    finish_block(partials, nparts, st);
+}
+
+// ------------------------------------------------------------- batched
+
+// One phase of the extragradient step for every problem of a batch: each
+// workgroup takes one item (problem, a, b) of the phase's list; the
+// problem's own buffers and parameters come from its descriptor.  Items of
+// problems that have stopped return at once.  The per-item work is the
+// single-problem kernels' own device code, so a problem gets bit-identical
+// results alone and in a batch.
+template <bool kAtHalf>
+__global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb *__restrict__ probs,
+                                                                 const BatchItem *__restrict__ items)
+{
+    const BatchItem it = items[blockIdx.x];
+    const BatchProb &P = probs[it.p];
+    if (P.state->done)
+        return;
+    const SpecPtr sp{P.K, P.J, P.mu};
+    forward_block<true>(P.views, P.N, P.B, P.nrow, kAtHalf ? P.xh : P.x, kAtHalf ? P.xhT : P.xT,
+                        P.Y, sp, P.r, it.a, it.b);
+}
+
+__global__ __launch_bounds__(kBackX *kBackY) void kb_back(const BatchProb *__restrict__ probs,
+                                                          const BatchItem *__restrict__ items)
+{
+    const BatchItem it = items[blockIdx.x];
+    const BatchProb &P = probs[it.p];
+    if (P.state->done)
+        return;
+    if (P.reach == 0)
+        back_tile<true>(P.views, P.N, P.V, P.B, P.nrow, 0, P.r, P.g, P.inv_n, it.a, it.b);
+    else
+        back_tile<false>(P.views, P.N, P.V, P.B, P.nrow, P.reach, P.r, P.g, P.inv_n, it.a, it.b);
+}
+
+template <bool kHalf>
+__global__ __launch_bounds__(kTile * 8) void kb_update(const BatchProb *__restrict__ probs,
+                                                       const BatchItem *__restrict__ items)
+{
+    const BatchItem it = items[blockIdx.x];
+    const BatchProb &P = probs[it.p];
+    if (P.state->done)
+        return;
+    if (kHalf) {
+        const int ntx = (P.N + kTile - 1) / kTile;
+        update_tile<true>(P.x, P.g, P.gamma, P.xh, P.xhT, P.N, P.parts + 2 * (it.b * ntx + it.a),
+                          it.a, it.b);
+    } else {
+        update_tile<false>(P.x, P.g, P.gamma, P.x, P.xT, P.N, nullptr, it.a, it.b);
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
+{
+    const BatchProb &P = probs[blockIdx.x];
+    finish_block(P.parts, P.ntiles, P.state);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,
@@ -665,6 +767,27 @@ hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *stat
     hipLaunchKernelGGL(k_eg_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state);
     return hipGetLastError();
 }
+
+hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem *fwd, int nfwd,
+                             const BatchItem *back, int nback, const BatchItem *upd, int nupd,
+                             hipStream_t st)
+{
+    if (nprobs == 0)
+        return hipSuccess;
+    const dim3 fb(kFwdThreads * kSegs), bb(kBackX, kBackY), ub(kTile, 8), rb(kRedThreads);
+    hipLaunchKernelGGL(kb_forward<false>, dim3(nfwd), fb, 0, st, probs, fwd);
+    hipLaunchKernelGGL(kb_back, dim3(nback), bb, 0, st, probs, back);
+    hipLaunchKernelGGL(kb_update<true>, dim3(nupd), ub, 0, st, probs, upd);
+    hipLaunchKernelGGL(kb_forward<true>, dim3(nfwd), fb, 0, st, probs, fwd);
+    hipLaunchKernelGGL(kb_back, dim3(nback), bb, 0, st, probs, back);
+    hipLaunchKernelGGL(kb_update<false>, dim3(nupd), ub, 0, st, probs, upd);
+    hipLaunchKernelGGL(kb_finish, dim3(nprobs), rb, 0, st, probs);
+    return hipGetLastError();
+}
+
+int fwd_items_per_view(int B) { return (B + kFwdThreads - 1) / kFwdThreads; }
+int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }
+int update_tiles_per_side(int N) { return (N + kTile - 1) / kTile; }
 
 hipError_t launch_dot3(const float *v, const float *u, int N, double *partials, hipStream_t st)
 {

@@ -34,7 +34,12 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
            "exact_geometry_destroy", "exact_forward", "exact_backproject",
            "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
-           "exact_count_nonzeros")
+           "exact_count_nonzeros", "exact_run_footprint", "exact_batch_create",
+           "exact_batch_add", "exact_batch_step", "exact_batch_sync", "exact_batch_poll",
+           "exact_batch_remove", "exact_batch_destroy")
+
+# exact_batch_poll results
+RUNNING, FINISHED, CAPPED = 0, 1, 2
 
 
 class ExactError(RuntimeError):
@@ -90,6 +95,15 @@ def load():
         "exact_solver_poll": ([vp, C.POINTER(SolveInfo)], C.c_int),
         "exact_solver_destroy": ([vp], C.c_int),
         "exact_count_nonzeros": ([vp, C.POINTER(C.c_int64), vp], C.c_int),
+        "exact_run_footprint": ([i32, i32, i32], C.c_size_t),
+        "exact_batch_create": ([C.c_size_t, i32, C.POINTER(vp)], C.c_int),
+        "exact_batch_add": ([vp, vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts),
+                             C.POINTER(i32), vp], C.c_int),
+        "exact_batch_step": ([vp, i32, vp], C.c_int),
+        "exact_batch_sync": ([vp], C.c_int),
+        "exact_batch_poll": ([vp, i32, C.POINTER(SolveInfo)], C.c_int),
+        "exact_batch_remove": ([vp, i32], C.c_int),
+        "exact_batch_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -289,3 +303,67 @@ def exact_solve(g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500,
     d = _info_dict(info)
     d["converged"] = (code == 0) if tol > 0 else None
     return d
+
+
+def exact_run_footprint(n_pix, n_views, n_bins):
+    """Device bytes the library allocates for one run (x and y not included)."""
+    return int(load().exact_run_footprint(int(n_pix), int(n_views), int(n_bins)))
+
+
+class Batch:
+    """exact_batch_*: many runs of different shapes advanced together.
+
+    add() returns a slot; step(n) enqueues n steps of every run; sync()
+    waits and returns how many runs are still running; poll(slot) gives
+    (status, info) with status RUNNING, FINISHED or CAPPED."""
+
+    def __init__(self, hbm_budget_bytes, capacity=256):
+        h = C.c_void_p()
+        _check("exact_batch_create", load().exact_batch_create(
+            C.c_size_t(int(hbm_budget_bytes)), int(capacity), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def add(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
+            power_iters=100, stream=None):
+        sp = _Spec(mu, weight)
+        o = _opts(gamma, gamma_scale, max_iters, tol, 1, power_iters)
+        slot = C.c_int32(-1)
+        _check("exact_batch_add", load().exact_batch_add(
+            self.handle, g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),
+            C.byref(o), C.byref(slot), _stream(stream)))
+        self._keep[slot.value] = (g, x)
+        return slot.value
+
+    def step(self, n_steps=1, stream=None):
+        _check("exact_batch_step", load().exact_batch_step(self.handle, int(n_steps), _stream(stream)))
+
+    def sync(self):
+        return _check("exact_batch_sync", load().exact_batch_sync(self.handle))
+
+    def poll(self, slot):
+        info = SolveInfo()
+        st = _check("exact_batch_poll", load().exact_batch_poll(self.handle, int(slot), C.byref(info)))
+        return st, _info_dict(info)
+
+    def remove(self, slot):
+        _check("exact_batch_remove", load().exact_batch_remove(self.handle, int(slot)))
+        self._keep.pop(slot, None)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check("exact_batch_destroy", load().exact_batch_destroy(self.handle))
+        self.handle = None
+        self._keep = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,197 @@
+"""Continuous-batching request loop for EXACT reconstructions.
+
+Requests (scans with their own geometry, spectrum, counts and tolerance)
+arrive over time.  The loop admits them in arrival order while the sum of
+their device footprints (library state + the iterate and the counts) stays
+within an HBM budget, keeps every admitted scan's counts and iterate
+resident on the device, and advances all admitted scans together, a few
+extragradient steps at a time, in one exact_batch.  Between those chunks it
+retires scans that have stopped (copying the reconstruction to the host and
+freeing their memory) and admits new arrivals, so work of requests that
+arrive while others run overlaps on the device.
+
+Each scan's step size is Theorem 2's rule (paper Sec. 2.1) with
+lambda_max(A^T A / n) computed once per geometry and cached; its iterates are
+bitwise those of a solo exact_solve with the same step size.
+
+The scheduler is host logic over a small backend interface (GpuBackend
+below); tests drive it with a fake backend on the CPU.
+"""
+from dataclasses import dataclass, field
+import time
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the stream starts
+    problem: object         # synth.Problem: sizes, mu, I, y (host)
+    tol: float
+    max_iters: int = 20000
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    iters: int
+    resid: float
+    status: int             # 1 finished, 2 stopped at max_iters
+    gamma: float
+    x: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+    @property
+    def queued(self):
+        return self.admitted - self.arrival
+
+
+class GpuBackend:
+    """exact_batch on the current HIP device; owns the scans' x and y."""
+
+    def __init__(self, hbm_budget_bytes, capacity=256, power_iters=100, keep_x=True):
+        import torch
+        from . import exact
+        self.torch, self.exact = torch, exact
+        self.batch = exact.Batch(hbm_budget_bytes, capacity)
+        self.power_iters = power_iters
+        self.keep_x = keep_x
+        self.geoms, self.lams, self.live = {}, {}, {}
+
+    def _geometry(self, P):
+        key = (P.n_pix, P.n_views, P.n_bins, P.pixel_cm, P.bin_cm, P.half_turns)
+        if key not in self.geoms:
+            g = self.exact.Geometry(P.n_pix, P.n_views, P.n_bins, P.pixel_cm, P.bin_cm, P.half_turns)
+            self.geoms[key] = g
+            self.lams[key], _ = self.exact.exact_step_size(g, None, None, self.power_iters)
+        return self.geoms[key], self.lams[key]
+
+    def footprint(self, P):
+        return (self.exact.exact_run_footprint(P.n_pix, P.n_views, P.n_bins)
+                + 4 * P.d + 4 * P.Wn * P.n)
+
+    def gamma(self, P, lam):
+        J = np.asarray(P.I, dtype=np.float64).reshape(-1, len(P.mu)).sum(axis=0)
+        return 0.25 / (lam * float(np.dot(J, P.mu)))
+
+    def add(self, req):
+        P = req.problem
+        g, lam = self._geometry(P)
+        dev = self.torch.device("cuda")
+        y = self.torch.as_tensor(np.ascontiguousarray(P.y, dtype=np.float32), device=dev)
+        x = self.torch.zeros(P.d, device=dev)
+        gamma = self.gamma(P, lam)
+        slot = self.batch.add(g, P.mu, P.I, y, x, gamma=gamma, max_iters=req.max_iters, tol=req.tol)
+        self.live[slot] = (x, y)
+        return slot, gamma
+
+    def step(self, n):
+        self.batch.step(n)
+        return self.batch.sync()
+
+    def poll(self, slot):
+        return self.batch.poll(slot)
+
+    def retire(self, slot):
+        x, _ = self.live.pop(slot)
+        out = x.cpu().numpy() if self.keep_x else None
+        self.batch.remove(slot)
+        return out
+
+    def close(self):
+        self.batch.close()
+        for g in self.geoms.values():
+            g.close()
+        self.geoms.clear()
+
+
+class Server:
+    """Admission by footprint, continuous batching, retirement.
+
+    run(requests) plays the arrival times against `clock` (seconds); with
+    realtime=False the clock jumps to the next arrival when the device is
+    idle instead of sleeping."""
+
+    def __init__(self, backend, hbm_budget_bytes, chunk_steps=8, realtime=True,
+                 clock=time.perf_counter, on_done=None):
+        self.on_done = on_done      # called with each Result as it completes
+        self.backend = backend
+        self.budget = int(hbm_budget_bytes)
+        self.chunk = int(chunk_steps)
+        self.realtime = realtime
+        self.clock = clock
+
+    def run(self, requests):
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in reqs:
+            if self.backend.footprint(r.problem) > self.budget:
+                raise ValueError("request %d alone exceeds the HBM budget" % r.rid)
+        pending, running, results = [], {}, []
+        used, nxt = 0, 0
+        t0 = self.clock()
+        skew = 0.0                                    # simulated-time advance
+        now = lambda: self.clock() - t0 + skew        # noqa: E731
+        self.peak_running = 0
+        while nxt < len(reqs) or pending or running:
+            t = now()
+            while nxt < len(reqs) and reqs[nxt].arrival <= t:
+                pending.append(reqs[nxt])
+                nxt += 1
+            # admit in arrival order while memory allows (no overtaking)
+            while pending:
+                fp = self.backend.footprint(pending[0].problem)
+                if used + fp > self.budget:
+                    break
+                r = pending.pop(0)
+                slot, gamma = self.backend.add(r)
+                running[slot] = (r, now(), fp, gamma)
+                used += fp
+            self.peak_running = max(self.peak_running, len(running))
+            if not running:
+                if nxt < len(reqs):
+                    wait = reqs[nxt].arrival - now()
+                    if wait > 0:
+                        if self.realtime:
+                            time.sleep(wait)
+                        else:
+                            skew += wait
+                continue
+            self.backend.step(self.chunk)
+            for slot in list(running):
+                status, info = self.backend.poll(slot)
+                if status == 0:
+                    continue
+                r, admitted, fp, gamma = running.pop(slot)
+                x = self.backend.retire(slot)
+                used -= fp
+                results.append(Result(r.rid, r.arrival, admitted, now(), info["iters"],
+                                       info["resid"], status, gamma, x))
+                if self.on_done:
+                    self.on_done(results[-1])
+        return sorted(results, key=lambda z: z.rid)
+
+
+def summarize(results, duration=None):
+    """p50/p99 time-to-tolerance (arrival to result on the host), the
+    queueing share, and reconstructions per second over the stream."""
+    lat = np.array([r.latency for r in results])
+    q = np.array([r.queued for r in results])
+    first = min(r.arrival for r in results)
+    last = max(r.finished for r in results)
+    span = duration if duration is not None else last - first
+    i99 = int(np.argsort(lat)[min(len(lat) - 1, int(np.ceil(0.99 * len(lat))) - 1)])
+    return {"requests": len(results),
+            "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)),
+            "mean_queue_s": float(q.mean()),
+            "p99_queue_share": float(q[i99] / lat[i99]) if lat[i99] > 0 else 0.0,
+            "recon_per_s": len(results) / span if span > 0 else float("inf"),
+            "capped": int(sum(1 for r in results if r.status == 2)),
+            "mean_iters": float(np.mean([r.iters for r in results]))}

@@ -220,3 +220,22 @@ def batch_draws(count=64, seed=401):
                  K=int(Ks[p]), Wn=int(Ws[p]), I0=1e4, n_ell=20,
                  seed_phantom=1000 + p, seed_noise=2000 + p)
             for p in range(count)]
+
+
+def served_stream(count=300, rate=20.0, seed=501):
+    """Request parameters of the served stream: Poisson arrivals at `rate`
+    per second; per request, independent uniform draws of N in
+    {256, 512, 1024}, V in {90, 180, 360}, I0 in {1e3, 1e4} and tolerance in
+    {1e-3, 1e-4}; K = 30, Wn = 3, 20 ellipses, seeds 3000+q / 4000+q."""
+    rng = np.random.default_rng(int(seed))
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    Ns = rng.choice([256, 512, 1024], size=count)
+    Vs = rng.choice([90, 180, 360], size=count)
+    I0s = rng.choice([1e3, 1e4], size=count)
+    tols = rng.choice([1e-3, 1e-4], size=count)
+    return [dict(arrival=float(arrivals[q]), tol=float(tols[q]),
+                 params=dict(n_pix=int(Ns[q]), n_views=int(Vs[q]), n_bins=bins_for(int(Ns[q])),
+                             K=30, Wn=3, I0=float(I0s[q]), n_ell=20, seed_phantom=3000 + q,
+                             seed_noise=4000 + q))
+            for q in range(count)]

@@ -1,0 +1,134 @@
+"""Batched runs (exact_batch_*): every run's iterates are bitwise equal to
+its solo exact_solve, whatever else shares the batch and whenever it joins;
+budget and slot refusals.  The solo path itself is pinned to the oracle in
+test_gpu_parity.py."""
+import errno
+
+import numpy as np
+import pytest
+
+from paper_2503_19925_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ex():
+    from paper_2503_19925_amd import exact
+    exact.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return exact
+
+
+# uneven shapes: (N, V, B, K, Wn, seed)
+SHAPES = [(64, 40, 92, 10, 2, 11), (48, 33, 69, 23, 3, 12), (96, 25, 137, 40, 4, 13),
+          (32, 60, 46, 64, 2, 14), (80, 17, 114, 12, 3, 15), (56, 71, 80, 31, 4, 16)]
+
+
+def problems():
+    out = []
+    for N, V, B, K, Wn, seed in SHAPES:
+        P = synth.make_problem("batch", N, V, B, K, Wn, 1e4, 6, seed, seed + 100, with_truth=False)
+        out.append(P)
+    return out
+
+
+def solo(ex, P, **opts):
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, torch.as_tensor(P.y, device=DEV), x, **opts)
+    torch.cuda.synchronize()
+    g.close()
+    return x, info
+
+
+def run_batch(ex, Ps, join_late=(), chunk=7, **opts):
+    b = ex.Batch(1 << 34, capacity=len(Ps))
+    geos, xs, ys, slots = [], [], [], {}
+    for i, P in enumerate(Ps):
+        geos.append(ex.Geometry(P.n_pix, P.n_views, P.n_bins))
+        xs.append(torch.zeros(P.d, device=DEV))
+        ys.append(torch.as_tensor(P.y, device=DEV))
+    for i, P in enumerate(Ps):
+        if i not in join_late:
+            slots[i] = b.add(geos[i], P.mu, P.I, ys[i], xs[i], **opts)
+    rounds = 0
+    while True:
+        b.step(chunk)
+        running = b.sync()
+        rounds += 1
+        if rounds == 2:
+            for i in join_late:
+                slots[i] = b.add(geos[i], Ps[i].mu, Ps[i].I, ys[i], xs[i], **opts)
+            continue
+        if running == 0 and len(slots) == len(Ps):
+            break
+        assert rounds < 10000
+    infos = {i: b.poll(s) for i, s in slots.items()}
+    b.close()
+    torch.cuda.synchronize()
+    for g in geos:
+        g.close()
+    return xs, infos
+
+
+def test_batch_equals_solo_bitwise(ex):
+    Ps = problems()
+    say("batch vs solo", [(P.n_pix, P.n_views, P.n_bins, P.K, P.Wn) for P in Ps])
+    opts = dict(max_iters=120, tol=2e-3)
+    xs, infos = run_batch(ex, Ps, **opts)
+    for i, P in enumerate(Ps):
+        xs_solo, info = solo(ex, P, **opts)
+        status, binfo = infos[i]
+        assert status in (ex.FINISHED, ex.CAPPED)
+        assert binfo["iters"] == info["iters"], (i, binfo["iters"], info["iters"])
+        assert binfo["gamma"] == info["gamma"]
+        assert torch.equal(xs[i], xs_solo), i
+
+
+def test_batch_join_late_and_fixed_steps(ex):
+    """Runs that join after others have advanced, fixed step counts (tol 0)."""
+    Ps = problems()[:4]
+    say("batch join late")
+    opts = dict(max_iters=40)
+    xs, infos = run_batch(ex, Ps, join_late=(1, 3), chunk=5, **opts)
+    for i, P in enumerate(Ps):
+        xs_solo, info = solo(ex, P, **opts)
+        assert infos[i][0] == ex.FINISHED and infos[i][1]["iters"] == 40
+        assert torch.equal(xs[i], xs_solo), i
+
+
+def test_batch_budget_and_slots(ex):
+    P = problems()[0]
+    say("batch budget")
+    need = ex.exact_run_footprint(P.n_pix, P.n_views, P.n_bins)
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    y = torch.as_tensor(P.y, device=DEV)
+    x1, x2 = torch.zeros(g.d, device=DEV), torch.zeros(g.d, device=DEV)
+    b = ex.Batch(need + need // 2, capacity=4)
+    s1 = b.add(g, P.mu, P.I, y, x1, max_iters=3)
+    with pytest.raises(ex.ExactError) as e:
+        b.add(g, P.mu, P.I, y, x2, max_iters=3)
+    assert e.value.code == -errno.ENOSPC
+    b.step(3)
+    assert b.sync() == 0
+    b.remove(s1)
+    s2 = b.add(g, P.mu, P.I, y, x2, max_iters=3)
+    b.step(5)
+    assert b.sync() == 0 and b.poll(s2)[1]["iters"] == 3
+    b.close()
+    b1 = ex.Batch(1 << 30, capacity=1)
+    b1.add(g, P.mu, P.I, y, torch.zeros(g.d, device=DEV), max_iters=1)
+    with pytest.raises(ex.ExactError) as e:
+        b1.add(g, P.mu, P.I, y, torch.zeros(g.d, device=DEV), max_iters=1)
+    assert e.value.code == -errno.ENOSPC
+    b1.close()
+    g.close()

@@ -82,3 +82,21 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(exact, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         exact.load()
+
+
+def test_run_footprint_is_host_arithmetic(lib):
+    from paper_2503_19925_amd import exact
+    # 2 sinogram-sized and 5 image-sized float buffers plus small tables
+    f = exact.exact_run_footprint(512, 180, 725)
+    assert 4 * (2 * 180 * 725 + 5 * 512 * 512) < f < 4 * (2 * 180 * 725 + 5 * 512 * 512) + 65536
+    assert exact.exact_run_footprint(0, 10, 10) == 0
+
+
+def test_batch_null_handles(lib):
+    assert lib.exact_batch_step(None, 1, None) == -errno.EINVAL
+    assert lib.exact_batch_sync(None) == -errno.EINVAL
+    assert lib.exact_batch_poll(None, 0, None) == -errno.EINVAL
+    assert lib.exact_batch_remove(None, 0) == -errno.EINVAL
+    assert lib.exact_batch_destroy(None) == 0
+    h = C.c_void_p()
+    assert lib.exact_batch_create(1 << 20, 0, C.byref(h)) == -errno.EINVAL
