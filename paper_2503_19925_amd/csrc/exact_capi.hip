@@ -2,6 +2,7 @@
 // per-view geometry tables, and the host drivers of the operator, the power
 // iteration and the extragradient solve.  All arithmetic of the path runs
 // in the kernels of exact_kernels.hip.
+#define EXACT_HOST_SIDE 1
 #include "exact.h"
 #include "exact_internal.h"
 

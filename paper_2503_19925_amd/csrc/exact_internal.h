@@ -67,14 +67,31 @@ struct Geo {
     int reach;
 };
 
+// Device code sees the descriptor's pointers as global-memory pointers
+// (otherwise pointers loaded from memory are generic and every access
+// through them becomes a flat load); host code (and exact_capi.hip, which
+// defines EXACT_HOST_SIDE) sees plain pointers.  The layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(EXACT_HOST_SIDE)
+#define EXACT_GLOBAL __attribute__((address_space(1)))
+#else
+#define EXACT_GLOBAL
+#endif
+
 // One problem of a batch, as the batched kernels see it.
 struct BatchProb {
-    const ViewGeom *views;
+    const ViewGeom EXACT_GLOBAL *views;
     int32_t N, V, B, nrow, reach, K, ntiles, pad;
-    const float *Y, *J, *mu;           // window sums of y; spectrum (device)
-    float *x, *xT, *xh, *xhT, *g, *r;  // iterate, half-step iterate (and transposes), gradient, residual
-    double *parts;                      // update partials, 2 per 32x32 tile
-    SolveState *state;
+    const float EXACT_GLOBAL *Y;       // window sums of y
+    const float EXACT_GLOBAL *J;       // spectrum (device copies)
+    const float EXACT_GLOBAL *mu;
+    float EXACT_GLOBAL *x;             // iterate and its transpose
+    float EXACT_GLOBAL *xT;
+    float EXACT_GLOBAL *xh;            // half-step iterate and its transpose
+    float EXACT_GLOBAL *xhT;
+    float EXACT_GLOBAL *g;             // gradient
+    float EXACT_GLOBAL *r;             // residual
+    double EXACT_GLOBAL *parts;        // update partials, 2 per 32x32 tile
+    SolveState EXACT_GLOBAL *state;
     float gamma, inv_n;
 };
 

@@ -519,6 +519,14 @@ __global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restr
 
 // ------------------------------------------------------------- batched
 
+// A descriptor's global-memory pointer as the generic pointer the shared
+// device code takes (an address-space cast the compiler sees through).
+template <class T>
+__device__ __forceinline__ T *glob(T EXACT_GLOBAL *p)
+{
+    return (T *)p;
+}
+
 // One phase of the extragradient step for every problem of a batch: each
 // workgroup takes one item (problem, a, b) of the phase's list; the
 // problem's own buffers and parameters come from its descriptor.  Items of
@@ -531,11 +539,11 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
 {
     const BatchItem it = items[blockIdx.x];
     const BatchProb &P = probs[it.p];
-    if (P.state->done)
+    if (glob(P.state)->done)
         return;
-    const SpecPtr sp{P.K, P.J, P.mu};
-    forward_block<true>(P.views, P.N, P.B, P.nrow, kAtHalf ? P.xh : P.x, kAtHalf ? P.xhT : P.xT,
-                        P.Y, sp, P.r, it.a, it.b);
+    const SpecPtr sp{P.K, glob(P.J), glob(P.mu)};
+    forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xh : P.x),
+                        glob(kAtHalf ? P.xhT : P.xT), glob(P.Y), sp, glob(P.r), it.a, it.b);
 }
 
 __global__ __launch_bounds__(kBackX *kBackY) void kb_back(const BatchProb *__restrict__ probs,
@@ -543,12 +551,14 @@ __global__ __launch_bounds__(kBackX *kBackY) void kb_back(const BatchProb *__res
 {
     const BatchItem it = items[blockIdx.x];
     const BatchProb &P = probs[it.p];
-    if (P.state->done)
+    if (glob(P.state)->done)
         return;
     if (P.reach == 0)
-        back_tile<true>(P.views, P.N, P.V, P.B, P.nrow, 0, P.r, P.g, P.inv_n, it.a, it.b);
+        back_tile<true>(glob(P.views), P.N, P.V, P.B, P.nrow, 0, glob(P.r), glob(P.g), P.inv_n,
+                        it.a, it.b);
     else
-        back_tile<false>(P.views, P.N, P.V, P.B, P.nrow, P.reach, P.r, P.g, P.inv_n, it.a, it.b);
+        back_tile<false>(glob(P.views), P.N, P.V, P.B, P.nrow, P.reach, glob(P.r), glob(P.g),
+                         P.inv_n, it.a, it.b);
 }
 
 template <bool kHalf>
@@ -557,21 +567,22 @@ __global__ __launch_bounds__(kTile * 8) void kb_update(const BatchProb *__restri
 {
     const BatchItem it = items[blockIdx.x];
     const BatchProb &P = probs[it.p];
-    if (P.state->done)
+    if (glob(P.state)->done)
         return;
     if (kHalf) {
         const int ntx = (P.N + kTile - 1) / kTile;
-        update_tile<true>(P.x, P.g, P.gamma, P.xh, P.xhT, P.N, P.parts + 2 * (it.b * ntx + it.a),
-                          it.a, it.b);
+        update_tile<true>(glob(P.x), glob(P.g), P.gamma, glob(P.xh), glob(P.xhT), P.N,
+                          glob(P.parts) + 2 * (it.b * ntx + it.a), it.a, it.b);
     } else {
-        update_tile<false>(P.x, P.g, P.gamma, P.x, P.xT, P.N, nullptr, it.a, it.b);
+        update_tile<false>(glob(P.x), glob(P.g), P.gamma, glob(P.x), glob(P.xT), P.N, nullptr,
+                           it.a, it.b);
     }
 }
 
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
 {
     const BatchProb &P = probs[blockIdx.x];
-    finish_block(P.parts, P.ntiles, P.state);
+    finish_block(glob(P.parts), P.ntiles, glob(P.state));
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,

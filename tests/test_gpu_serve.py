@@ -28,12 +28,16 @@ def test_served_results_equal_solo():
         reqs.append(Request(q, 0.002 * q, P, tol=tol, max_iters=3000))
     say("served stream", [(r.problem.n_pix, r.problem.n_views, r.tol) for r in reqs])
     be = GpuBackend(1 << 40, capacity=8)
-    # room for about three of these scans at a time: later ones must queue
-    budget = 3 * max(be.footprint(r.problem) for r in reqs)
+    # room for three of the largest scans at a time: later ones must queue
+    fps = [be.footprint(r.problem) for r in reqs]
+    budget = 3 * max(fps)
     srv = Server(be, budget, chunk_steps=8)
     res = srv.run(reqs)
     be.close()
-    assert srv.peak_running <= 3
+    most = 0                                 # most scans that fit together
+    while most < len(fps) and sum(sorted(fps)[:most + 1]) <= budget:
+        most += 1
+    assert 3 <= srv.peak_running <= most < len(reqs)
     assert any(r.queued > 0 for r in res)
     s = summarize(res)
     print("  summary", s, flush=True)
