@@ -36,6 +36,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "EG iters/s + projector Grays/s @512²×180 views; batched p50/p99 time-to-tol"
+WORKLOADS = {
+    "solve_512": "solve_512: 512x512 image (20 random ellipses), 180 views over 180 deg, "
+                 "725 bins, 30 energy bins, 3 windows, I0=1e4 Poisson",
+    "large_1024": "large_1024: 1024x1024 image (40 random ellipses), 720 views over 180 deg, "
+                  "1448 bins, 64 energy bins, 4 windows, I0=1e3 Poisson",
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -71,8 +77,26 @@ def cpu_baseline(P, gamma, steps):
     ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(P.d), gamma, steps)
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "EG iters/s", "cores": 1, "kind": "oracle",
-            "sample": "%d EG steps of solve_512 from x=0 (float64 C oracle, one thread, "
-                      "%.1f s)" % (steps, dt)}
+            "sample": "%d EG steps of %s from x=0 (float64 C oracle, one thread, "
+                      "%.1f s)" % (steps, P.name, dt)}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic.json: rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
+    plain copy's reading), or None when the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2503_19925_amd", "csrc", "exact_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha1") != sha:
+            return None
+        return rec["workloads"][workload][kernel]["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def pct(v, q):
@@ -166,6 +190,12 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
     ap.add_argument("--served", type=int, default=40,
                     help="requests in the served leg (0 to skip)")
+    ap.add_argument("--workload", default="solve_512", choices=sorted(WORKLOADS),
+                    help="single-scan workload of the main line")
+    ap.add_argument("--to-tol", type=float, default=0.0,
+                    help="also solve the workload from x=0 to this natural residual")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -178,8 +208,16 @@ def main():
     exact.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    P = synth.config_problem("solve_512", with_truth=False)
-    log("workload solve_512: N=%d V=%d B=%d K=%d Wn=%d" % (P.n_pix, P.n_views, P.n_bins, P.K, P.Wn))
+    P = synth.config_problem(args.workload, with_truth=False)
+    log("workload %s: N=%d V=%d B=%d K=%d Wn=%d" % (P.name, P.n_pix, P.n_views, P.n_bins, P.K, P.Wn))
+    if args.calibrate_copy_mb > 0:
+        src = torch.ones(args.calibrate_copy_mb << 18, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d MiB" % args.calibrate_copy_mb)
+        del src, dst
     g = exact.Geometry(P.n_pix, P.n_views, P.n_bins)
     y = torch.as_tensor(P.y, device=dev)
     x = torch.zeros(g.d, device=dev)
@@ -223,6 +261,15 @@ def main():
     achieved = bytes_back / (t_back * 1e-3) / 1e9
     log("nnz %d; back %.4f ms, forward(+transpose) %.4f ms" % (nnz, t_back, t_fwd))
 
+    to_tol = None
+    if args.to_tol > 0:
+        xt = torch.zeros(g.d, device=dev)
+        info_t = exact.exact_solve(g, P.mu, P.I, y, xt, max_iters=20000, tol=args.to_tol,
+                                   check_every=32)
+        to_tol = {"tol": args.to_tol, "iters": info_t["iters"], "resid": info_t["resid"],
+                  "converged": info_t["converged"], "seconds": info_t["ms"] / 1e3}
+        log("to tolerance %.0e: %d steps, %.2f s" % (args.to_tol, info_t["iters"], info_t["ms"] / 1e3))
+
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
     served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
     if served:
@@ -247,8 +294,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "solve_512: 512x512 image (20 random ellipses), 180 views over "
-                               "180 deg, 725 bins, 30 energy bins, 3 windows, I0=1e4 Poisson",
+        "config": {"workload": WORKLOADS[args.workload],
                    "n_pix": P.n_pix, "n_views": P.n_views, "n_bins": P.n_bins,
                    "n_energies": P.K, "n_windows": P.Wn, "parallelism": "single GPU"},
         "forward_grays": g.n / (t_fwd * 1e-3) / 1e9,
@@ -258,7 +304,8 @@ def main():
         "nnz": nnz,
         "roofline": {"kernel": "k_back", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(args.workload, "k_back")},
+        "to_tol": to_tol,
         "cpu_baseline": base,
         "batched": batched,
         "served": served,
