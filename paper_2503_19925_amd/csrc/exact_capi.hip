@@ -749,8 +749,9 @@ struct exact_batch_s {
 namespace {
 
 // Item lists of the runs still running (as of the last sync), heaviest
-// first (work per item grows with N) so the long tiles start early.  A run
-// that stopped is left out: its workgroups would only return at once.
+// first so the long tiles start early: runs by decreasing N, and each run's
+// forward items centre-out (central bin blocks hold the longest chords).
+// A run that stopped is left out: its workgroups would only return at once.
 void batch_rebuild(exact_batch_s *b)
 {
     std::vector<int> order;
@@ -767,9 +768,9 @@ void batch_rebuild(exact_batch_s *b)
         const int pi = (int)descs.size();
         descs.push_back(p.desc());
         const int nbb = exact::fwd_items_per_view(p.g->B);
-        for (int v = 0; v < p.g->V; ++v)
-            for (int bb = 0; bb < nbb; ++bb)
-                fwd.push_back(exact::BatchItem{pi, v, bb, 0});
+        for (int rk = 0; rk < nbb; ++rk)
+            for (int v = 0; v < p.g->V; ++v)
+                fwd.push_back(exact::BatchItem{pi, v, exact::fwd_block_centre_out(rk, nbb), 0});
         const int bt = exact::back_tiles_per_side(p.g->N);
         for (int ty = 0; ty < bt; ++ty)
             for (int tx = 0; tx < bt; ++tx)

@@ -116,6 +116,7 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
                              const BatchItem *back, int nback, const BatchItem *upd, int nupd,
                              hipStream_t st);
 int fwd_items_per_view(int B);
+int fwd_block_centre_out(int r, int nbb);
 int back_tiles_per_side(int N);
 int update_tiles_per_side(int N);
 

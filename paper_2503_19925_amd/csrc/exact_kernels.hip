@@ -58,7 +58,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThr
 
 // ---------------------------------------------------------------- forward
 
-constexpr int kSegs = 4;   // waves per forward workgroup, each a quarter of the lines
+#ifndef EXACT_FWD_SEGS
+#define EXACT_FWD_SEGS 4
+#endif
+constexpr int kSegs = EXACT_FWD_SEGS;   // waves per forward workgroup, each a share of the lines
+
+// Bin block of rank r when the blocks of a view are taken centre-out (the
+// central blocks hold the longest chords): c, c-1, c+1, c-2, ... with
+// c = nbb / 2.  A bijection of [0, nbb).
+__device__ __host__ __forceinline__ int centre_out(int r, int nbb)
+{
+    const int c = nbb / 2;
+    return (r % 2 == 0) ? c + r / 2 : c - (r + 1) / 2;
+}
 
 // Lines k (of the N) on which ray base + k Q can have a tap inside the image,
 // i.e. floor(f) in [-1, N-1]; conservative by one line at each end (the
@@ -77,8 +89,21 @@ __device__ __forceinline__ void ray_lines(double base, double Q, int N, int &k0,
     k1 = (int)hi;
 }
 
-constexpr int kLineBatch = 4;    // lines whose loads are in flight together
-constexpr int kViewBatch = 4;    // views likewise in the back-projector
+#ifndef EXACT_LINE_BATCH
+#define EXACT_LINE_BATCH 4
+#endif
+#ifndef EXACT_VIEW_BATCH
+#define EXACT_VIEW_BATCH 4
+#endif
+constexpr int kLineBatch = EXACT_LINE_BATCH;   // lines whose loads are in flight together
+constexpr int kViewBatch = EXACT_VIEW_BATCH;   // views likewise in the back-projector
+
+// Element i of a float array through a 32-bit byte offset: with a
+// wave-uniform base this is a scalar-base + vector-offset load.
+__device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
+{
+    return *(const float *)((const char *)base + (i << 2));
+}
 
 // The two taps of a ray on one line: crossing f (advanced by Q, exactly),
 // weights of pixels floor(f) and floor(f) + 1 (zero outside the image) and
@@ -94,8 +119,8 @@ __device__ __forceinline__ void tap_pair(double &f, double Q, int N, const float
     const bool in1 = (unsigned)(j0 + 1) < (unsigned)N;
     w0 = in0 ? (float)(1.0 - e0) : 0.f;       // pixel j0
     w1 = in1 ? (float)e0 : 0.f;               // pixel j0 + 1: 1 - |f - (j0+1)| = e0 exactly
-    v0 = row[in0 ? (unsigned)j0 : 0u];
-    v1 = row[in1 ? (unsigned)(j0 + 1) : 0u];
+    v0 = at(row, in0 ? (unsigned)j0 : 0u);
+    v1 = at(row, in1 ? (unsigned)(j0 + 1) : 0u);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -200,15 +225,19 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     }
 }
 
+// Workgroup i takes view i % V and the (i / V)-th bin block centre-out, so
+// the heaviest blocks of every view are dispatched first.
 template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
-    const ViewGeom *__restrict__ views, int N, int B, int nrow, const float *__restrict__ x,
-    const float *__restrict__ xT, const float *__restrict__ Y, SpecArg sp,
-    float *__restrict__ out, const int32_t *__restrict__ skip)
+    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow,
+    const float *__restrict__ x, const float *__restrict__ xT, const float *__restrict__ Y,
+    SpecArg sp, float *__restrict__ out, const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
-    forward_block<kResid>(views, N, B, nrow, x, xT, Y, sp, out, blockIdx.y, blockIdx.x);
+    const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
+    forward_block<kResid>(views, N, B, nrow, x, xT, Y, sp, out, blockIdx.x % V,
+                          centre_out(blockIdx.x / V, nbb));
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -275,8 +304,8 @@ __device__ __forceinline__ float taps_two(const ViewGeom &G, double kd, double j
     const float u1 = (float)(1.0 - fabs(d1));
     const bool ok0 = u0 > 0.f && (unsigned)b0 < (unsigned)B;
     const bool ok1 = u1 > 0.f && (unsigned)b1 < (unsigned)B;
-    const float r0 = rv[ok0 ? (unsigned)b0 : 0u];
-    const float r1 = rv[ok1 ? (unsigned)b1 : 0u];
+    const float r0 = at(rv, ok0 ? (unsigned)b0 : 0u);
+    const float r1 = at(rv, ok1 ? (unsigned)b1 : 0u);
     return fmaf(ok1 ? u1 : 0.f, r1, (ok0 ? u0 : 0.f) * r0);
 }
 
@@ -702,9 +731,9 @@ hipError_t launch_forward(const Geo &g, const float *x, const float *xT, float *
 {
     SpecArg none;
     none.K = 0;
-    dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
+    dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.B, g.nrow, x, xT, nullptr, none, s, skip);
+                       g.V, g.B, g.nrow, x, xT, nullptr, none, s, skip);
     return hipGetLastError();
 }
 
@@ -712,9 +741,9 @@ hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT
                                    const float *Y, const SpecArg &sp, float *r,
                                    const int32_t *skip, hipStream_t st)
 {
-    dim3 grid((g.B + kFwdThreads - 1) / kFwdThreads, g.V);
+    dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.B, g.nrow, x, xT, Y, sp, r, skip);
+                       g.V, g.B, g.nrow, x, xT, Y, sp, r, skip);
     return hipGetLastError();
 }
 
@@ -797,6 +826,7 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
 }
 
 int fwd_items_per_view(int B) { return (B + kFwdThreads - 1) / kFwdThreads; }
+int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }
 int update_tiles_per_side(int N) { return (N + kTile - 1) / kTile; }
 

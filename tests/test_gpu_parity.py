@@ -354,3 +354,38 @@ def test_error_paths(ex):
     info = ex.exact_solve(g, [0.2, 0.3], [1.0, 1.0, 1.0, 1.0], y, x1, gamma=1e-3, max_iters=0)
     assert info["iters"] == 0 and (np64(x1) == 0.25).all()
     g.close()
+
+
+def test_solve_parity_full_512_500_steps(ex):
+    """The benchmark's workload at full size for 500 steps against the oracle's
+    run stored in tests/golden/trajectory_solve_512.txt (written by
+    make_trajectory_512.py from the oracle alone): relative L2 over 4096
+    sampled pixels and the iterate's norm within 1e-4."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "trajectory_solve_512.txt")
+    head, pix, val = {}, [], []
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        if "=" in line:
+            k, v = line.split("=")
+            head[k.strip()] = float(v)
+        else:
+            p, v = line.split()
+            pix.append(int(p))
+            val.append(float(v))
+    pix, val = np.array(pix), np.array(val)
+    P = synth.config_problem("solve_512", with_truth=False)
+    assert float(P.y.astype(np.float64).sum()) == head["y_sum"]
+    say("solve 512 x 500 vs stored oracle run")
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=head["gamma"], max_iters=int(head["steps"]))
+    assert info["iters"] == int(head["steps"])
+    xs = np64(x)
+    rel = np.linalg.norm(xs[pix] - val) / np.linalg.norm(val)
+    nrm = abs(np.linalg.norm(xs) - head["x_norm"]) / head["x_norm"]
+    print("  sampled rel L2 %.3e, norm rel %.3e (oracle float build drift %.3e)"
+          % (rel, nrm, head["f32_rel_l2"]), flush=True)
+    assert rel <= 1e-4 and nrm <= 1e-4
+    g.close()
