@@ -457,7 +457,7 @@ int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream)
 
 // One extragradient run's device state: the spectrum, the window sums of
 // y, the iterate's transpose, the half-step iterate and its transpose, the
-// gradient and residual buffers, the update partials.  The iterate itself
+// residual buffer, the update partials.  The iterate itself
 // is the caller's buffer.  `state` points at the run's SolveState (owned by
 // the solver or the batch).
 struct Problem {
@@ -466,7 +466,7 @@ struct Problem {
     double gamma = 0.0, lam = 0.0;
     int max_iters = 0;
     float *x = nullptr;
-    std::unique_ptr<DevBuf> Y, r, gr, xT, xh, xhT, parts, specd;
+    std::unique_ptr<DevBuf> Y, r, xT, xh, xhT, parts, specd;
     SolveState *state = nullptr;
     size_t footprint = 0;
 
@@ -489,7 +489,6 @@ struct Problem {
         d.xT = xT->as<float>();
         d.xh = xh->as<float>();
         d.xhT = xhT->as<float>();
-        d.g = gr->as<float>();
         d.r = r->as<float>();
         d.parts = parts->as<double>();
         d.state = state;
@@ -505,7 +504,7 @@ namespace {
 size_t run_footprint(int N, int V, int B)
 {
     const size_t d = (size_t)N * N, n = (size_t)V * B;
-    return 4 * (2 * n + 5 * d) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
+    return 4 * (2 * n + 4 * d) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
            sizeof(SolveState);
 }
 
@@ -548,7 +547,6 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.footprint = run_footprint(g->N, g->V, g->B);
     p.Y.reset(new DevBuf(n * 4));
     p.r.reset(new DevBuf(n * 4));
-    p.gr.reset(new DevBuf(d * 4));
     p.xT.reset(new DevBuf(d * 4));
     p.xh.reset(new DevBuf(d * 4));
     p.xhT.reset(new DevBuf(d * 4));
@@ -654,7 +652,7 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
     const float inv_n = (float)(1.0 / (double)n);
     SolveState *S = p.state;
     const int32_t *skip = &S->done;
-    float *Y = p.Y->as<float>(), *r = p.r->as<float>(), *gr = p.gr->as<float>();
+    float *Y = p.Y->as<float>(), *r = p.r->as<float>();
     float *xT = p.xT->as<float>(), *xh = p.xh->as<float>(), *xhT = p.xhT->as<float>();
     double *parts = p.parts->as<double>();
     hipError_t e = hipSuccess;
@@ -663,11 +661,9 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
             e = x;
     };
     cap(exact::launch_forward_residual(G, p.x, xT, Y, p.spec, r, skip, st));
-    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
-    cap(exact::launch_eg_update(p.x, gr, gf, xh, xhT, g->N, parts, skip, st));
+    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, xh, xhT, parts, skip, st));
     cap(exact::launch_forward_residual(G, xh, xhT, Y, p.spec, r, skip, st));
-    cap(exact::launch_back(G, r, gr, inv_n, skip, st));
-    cap(exact::launch_eg_update(p.x, gr, gf, p.x, xT, g->N, nullptr, skip, st));
+    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xT, nullptr, skip, st));
     cap(exact::launch_eg_finish(parts, ntiles, S, st));
     return e;
 }
@@ -732,8 +728,8 @@ struct exact_batch_s {
     std::vector<std::chrono::steady_clock::time_point> started;
     std::vector<char> stopped;                       // host view, from the last sync
     bool dirty = true;
-    std::unique_ptr<DevBuf> descs, fwd, back, upd;
-    int nprob = 0, nfwd = 0, nback = 0, nupd = 0;
+    std::unique_ptr<DevBuf> descs, fwd, back;
+    int nprob = 0, nfwd = 0, nback = 0;
     Graph step;
 
     ~exact_batch_s()
@@ -762,7 +758,7 @@ void batch_rebuild(exact_batch_s *b)
         return b->slots[(size_t)a]->g->N > b->slots[(size_t)c]->g->N;
     });
     std::vector<exact::BatchProb> descs;
-    std::vector<exact::BatchItem> fwd, back, upd;
+    std::vector<exact::BatchItem> fwd, back;
     for (int slot : order) {
         const Problem &p = *b->slots[(size_t)slot];
         const int pi = (int)descs.size();
@@ -775,10 +771,6 @@ void batch_rebuild(exact_batch_s *b)
         for (int ty = 0; ty < bt; ++ty)
             for (int tx = 0; tx < bt; ++tx)
                 back.push_back(exact::BatchItem{pi, tx, ty, 0});
-        const int ut = exact::update_tiles_per_side(p.g->N);
-        for (int ty = 0; ty < ut; ++ty)
-            for (int tx = 0; tx < ut; ++tx)
-                upd.push_back(exact::BatchItem{pi, tx, ty, 0});
     }
     hipStream_t st = b->own->st;
     auto upload = [&](std::unique_ptr<DevBuf> &buf, const void *src, size_t bytes) {
@@ -790,17 +782,14 @@ void batch_rebuild(exact_batch_s *b)
     upload(b->descs, descs.data(), descs.size() * sizeof(exact::BatchProb));
     upload(b->fwd, fwd.data(), fwd.size() * sizeof(exact::BatchItem));
     upload(b->back, back.data(), back.size() * sizeof(exact::BatchItem));
-    upload(b->upd, upd.data(), upd.size() * sizeof(exact::BatchItem));
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     b->nprob = (int)descs.size();
     b->nfwd = (int)fwd.size();
     b->nback = (int)back.size();
-    b->nupd = (int)upd.size();
     const exact::BatchProb *dp = b->descs->as<exact::BatchProb>();
-    const exact::BatchItem *f = b->fwd->as<exact::BatchItem>(), *bk = b->back->as<exact::BatchItem>(),
-                           *u = b->upd->as<exact::BatchItem>();
+    const exact::BatchItem *f = b->fwd->as<exact::BatchItem>(), *bk = b->back->as<exact::BatchItem>();
     b->step.capture(st, [&]() {
-        return exact::launch_batch_step(dp, b->nprob, f, b->nfwd, bk, b->nback, u, b->nupd, st);
+        return exact::launch_batch_step(dp, b->nprob, f, b->nfwd, bk, b->nback, st);
     });
     b->dirty = false;
 }

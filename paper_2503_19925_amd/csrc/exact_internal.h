@@ -88,9 +88,8 @@ struct BatchProb {
     float EXACT_GLOBAL *xT;
     float EXACT_GLOBAL *xh;            // half-step iterate and its transpose
     float EXACT_GLOBAL *xhT;
-    float EXACT_GLOBAL *g;             // gradient
     float EXACT_GLOBAL *r;             // residual
-    double EXACT_GLOBAL *parts;        // update partials, 2 per 32x32 tile
+    double EXACT_GLOBAL *parts;        // update partials, 2 per 16x16 tile
     SolveState EXACT_GLOBAL *state;
     float gamma, inv_n;
 };
@@ -101,24 +100,23 @@ struct BatchItem {
     int32_t p, a, b, pad;
 };
 
-// Partial sums produced per workgroup by the update and dot kernels.
+// Tile side of the transpose and normalisation kernels.
 constexpr int kTile = 32;
 
+// 16 x 16 tiles of an N x N image (the update partials are per tile).
 int num_tiles(int N);
 int num_dot_parts(long d);
 int num_count_parts(const Geo &g);
 
 hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st);
 
-// Batched step: the seven phases of one extragradient step over the item
-// lists (forward items, back-projection tiles, update tiles).
+// Batched step: the five phases of one extragradient step over the item
+// lists (forward items; back-projection + update tiles).
 hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem *fwd, int nfwd,
-                             const BatchItem *back, int nback, const BatchItem *upd, int nupd,
-                             hipStream_t st);
+                             const BatchItem *back, int nback, hipStream_t st);
 int fwd_items_per_view(int B);
 int fwd_block_centre_out(int r, int nbb);
 int back_tiles_per_side(int N);
-int update_tiles_per_side(int N);
 
 hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st);
 hipError_t launch_fill(float *x, float value, long count, hipStream_t st);
@@ -135,12 +133,14 @@ hipError_t launch_count_bad(const float *x, long count, int32_t *bad,
                             hipStream_t st);
 hipError_t launch_state_init(SolveState *state, double tol, int max_iters,
                              hipStream_t st);
+// Back-projection fused with the update: g = scale A^T r and
 // z = max(0, x - gamma g) for every pixel, written to z and (transposed) zT.
 // With partials != nullptr also writes per-tile double partial sums of
-// ||z - x||^2 and ||x||^2 (2 per tile).  z may alias x.
-hipError_t launch_eg_update(const float *x, const float *g, float gamma, float *z,
-                            float *zT, int N, double *partials,
-                            const int32_t *skip, hipStream_t st);
+// ||z - x||^2 and ||x||^2 (2 per 16x16 tile, num_tiles of them).  z may
+// alias x.
+hipError_t launch_back_update(const Geo &g, const float *r, float scale, const float *x,
+                              float gamma, float *z, float *zT, double *partials,
+                              const int32_t *skip, hipStream_t st);
 // Fixed-order reduction of the update partials; sets rho_t, advances t and
 // raises done when rho_t <= tol or t reaches max_iters.
 hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *state,

@@ -360,22 +360,18 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
     }
 }
 
-// One lane per pixel: the row-stepping views (line k = iy, pixel j = ix)
-// then the column-stepping views (k = ix, j = iy), Kahan-compensated.
+// (A^T r) at pixel (ix, iy): the row-stepping views (line k = iy, pixel
+// j = ix) then the column-stepping views (k = ix, j = iy), Kahan-compensated.
 template <bool kTwo>
-__device__ __forceinline__ void back_tile(const ViewGeom *__restrict__ views, int N, int V, int B,
-                                          int nrow, int reach, const float *__restrict__ r,
-                                          float *__restrict__ img, float scale, int tx, int ty)
+__device__ __forceinline__ float back_pixel(const ViewGeom *__restrict__ views, int V, int B,
+                                            int nrow, int reach, const float *__restrict__ r,
+                                            int ix, int iy)
 {
-    const int ix = tx * kBackX + threadIdx.x;
-    const int iy = ty * kBackY + threadIdx.y;
-    if (ix >= N || iy >= N)
-        return;
     const double dx = (double)ix, dy = (double)iy;
     Kahan acc;
     gather_views<kTwo>(views, 0, nrow, dy, dx, B, reach, r, acc);
     gather_views<kTwo>(views, nrow, V, dx, dy, B, reach, r, acc);
-    img[(size_t)iy * N + ix] = acc.value() * scale;
+    return acc.value();
 }
 
 template <bool kTwo>
@@ -386,7 +382,75 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
 {
     if (skipped(skip))
         return;
-    back_tile<kTwo>(views, N, V, B, nrow, reach, r, img, scale, blockIdx.x, blockIdx.y);
+    const int ix = blockIdx.x * kBackX + threadIdx.x;
+    const int iy = blockIdx.y * kBackY + threadIdx.y;
+    if (ix >= N || iy >= N)
+        return;
+    img[(size_t)iy * N + ix] = back_pixel<kTwo>(views, V, B, nrow, reach, r, ix, iy) * scale;
+}
+
+// The projected update on one 16 x 16 tile once g = scale (A^T r) is known
+// for the lane's pixel (paper Sec. 1.2, eq. extragrad-method, with the
+// orthant projection of Sec. 3.1): z = max(0, x_p - gamma g); z and, through
+// an LDS tile, its transpose are written; with kPartials the tile's double
+// sums of (z - x)^2 and x^2 go to part2[0..1].  z may alias x (each lane
+// reads and writes only its own pixel of x).  Every lane of the block calls
+// this (it holds barriers); lanes outside the image pass inside = false.
+template <bool kPartials>
+__device__ __forceinline__ void update_epilogue(bool inside, float g, int N, const float *x,
+                                                float gamma, float *z, float *__restrict__ zT,
+                                                double *__restrict__ part2, int tx, int ty)
+{
+    __shared__ float tile[kBackY][kBackX + 1];
+    __shared__ double red[2][kRedThreads];
+    const int ix = tx * kBackX + threadIdx.x;
+    const int iy = ty * kBackY + threadIdx.y;
+    double num = 0.0, den = 0.0;
+    if (inside) {
+        const size_t p = (size_t)iy * N + ix;
+        const float xv = x[p];
+        const float zv = fmaxf(0.f, fmaf(-gamma, g, xv));
+        z[p] = zv;
+        tile[threadIdx.y][threadIdx.x] = zv;
+        if (kPartials) {
+            const double dz = (double)zv - (double)xv;
+            num = dz * dz;
+            den = (double)xv * (double)xv;
+        }
+    }
+    __syncthreads();
+    const int ixT = tx * kBackX + threadIdx.y, iyT = ty * kBackY + threadIdx.x;
+    if (ixT < N && iyT < N)
+        zT[(size_t)ixT * N + iyT] = tile[threadIdx.x][threadIdx.y];
+    if (kPartials) {
+        double v2[2] = {num, den};
+        block_sum<2>(v2, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            part2[0] = v2[0];
+            part2[1] = v2[1];
+        }
+    }
+}
+
+// Back-projection fused with the update: each lane gathers its pixel's
+// gradient, then the tile runs the update epilogue.
+template <bool kTwo, bool kPartials>
+__global__ __launch_bounds__(kBackX *kBackY) void k_back_update(
+    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
+    const float *__restrict__ r, float scale, const float *x, float gamma, float *z,
+    float *__restrict__ zT, double *__restrict__ partials, const int32_t *__restrict__ skip)
+{
+    if (skipped(skip))
+        return;
+    const int ix = blockIdx.x * kBackX + threadIdx.x;
+    const int iy = blockIdx.y * kBackY + threadIdx.y;
+    const bool inside = ix < N && iy < N;
+    float g = 0.f;
+    if (inside)
+        g = back_pixel<kTwo>(views, V, B, nrow, reach, r, ix, iy) * scale;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    update_epilogue<kPartials>(inside, g, N, x, gamma, z, zT,
+                               kPartials ? partials + 2 * blk : nullptr, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------ elementwise / tiles
@@ -458,61 +522,6 @@ __global__ void k_state_init(SolveState *st, double tol, int max_iters)
     }
 }
 
-// z = max(0, x - gamma g) on one 32x32 tile; z and its transpose; with
-// kPartials the tile's double sums of (z - x)^2 and x^2 go to part2[0..1].
-template <bool kPartials>
-__device__ __forceinline__ void update_tile(const float *x, const float *__restrict__ g,
-                                            float gamma, float *z, float *__restrict__ zT, int N,
-                                            double *__restrict__ part2, int tx, int ty)
-{
-    __shared__ float tile[kTile][kTile + 1];
-    __shared__ double red[2][kRedThreads];
-    const int bx = tx * kTile, by = ty * kTile;
-    double num = 0.0, den = 0.0;
-    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
-        const int iy = by + rr, ix = bx + threadIdx.x;
-        if (iy < N && ix < N) {
-            const size_t p = (size_t)iy * N + ix;
-            const float xv = x[p];
-            const float zv = fmaxf(0.f, fmaf(-gamma, g[p], xv));
-            z[p] = zv;
-            tile[rr][threadIdx.x] = zv;
-            if (kPartials) {
-                const double dz = (double)zv - (double)xv;
-                num = fma(dz, dz, num);
-                den = fma((double)xv, (double)xv, den);
-            }
-        }
-    }
-    __syncthreads();
-    for (int rr = threadIdx.y; rr < kTile; rr += 8) {
-        const int ixT = bx + rr, iyT = by + threadIdx.x;
-        if (ixT < N && iyT < N)
-            zT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
-    }
-    if (kPartials) {
-        double v2[2] = {num, den};
-        block_sum<2>(v2, red);
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
-            part2[0] = v2[0];
-            part2[1] = v2[1];
-        }
-    }
-}
-
-template <bool kPartials>
-__global__ __launch_bounds__(kTile * 8) void k_eg_update(
-    const float *x, const float *__restrict__ g, float gamma, float *z,
-    float *__restrict__ zT, int N, double *__restrict__ partials,
-    const int32_t *__restrict__ skip)
-{
-    if (skipped(skip))
-        return;
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    update_tile<kPartials>(x, g, gamma, z, zT, N, kPartials ? partials + 2 * blk : nullptr,
-                           blockIdx.x, blockIdx.y);
-}
-
 // Fixed-order reduction of a run's update partials, rho_t, and the stop test.
 __device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
                                              SolveState *st)
@@ -575,37 +584,31 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
                         glob(kAtHalf ? P.xhT : P.xT), glob(P.Y), sp, glob(P.r), it.a, it.b);
 }
 
-__global__ __launch_bounds__(kBackX *kBackY) void kb_back(const BatchProb *__restrict__ probs,
-                                                          const BatchItem *__restrict__ items)
-{
-    const BatchItem it = items[blockIdx.x];
-    const BatchProb &P = probs[it.p];
-    if (glob(P.state)->done)
-        return;
-    if (P.reach == 0)
-        back_tile<true>(glob(P.views), P.N, P.V, P.B, P.nrow, 0, glob(P.r), glob(P.g), P.inv_n,
-                        it.a, it.b);
-    else
-        back_tile<false>(glob(P.views), P.N, P.V, P.B, P.nrow, P.reach, glob(P.r), glob(P.g),
-                         P.inv_n, it.a, it.b);
-}
-
 template <bool kHalf>
-__global__ __launch_bounds__(kTile * 8) void kb_update(const BatchProb *__restrict__ probs,
-                                                       const BatchItem *__restrict__ items)
+__global__ __launch_bounds__(kBackX *kBackY) void kb_back_update(
+    const BatchProb *__restrict__ probs, const BatchItem *__restrict__ items)
 {
     const BatchItem it = items[blockIdx.x];
     const BatchProb &P = probs[it.p];
     if (glob(P.state)->done)
         return;
-    if (kHalf) {
-        const int ntx = (P.N + kTile - 1) / kTile;
-        update_tile<true>(glob(P.x), glob(P.g), P.gamma, glob(P.xh), glob(P.xhT), P.N,
-                          glob(P.parts) + 2 * (it.b * ntx + it.a), it.a, it.b);
-    } else {
-        update_tile<false>(glob(P.x), glob(P.g), P.gamma, glob(P.x), glob(P.xT), P.N, nullptr,
-                           it.a, it.b);
+    const int ix = it.a * kBackX + threadIdx.x;
+    const int iy = it.b * kBackY + threadIdx.y;
+    const bool inside = ix < P.N && iy < P.N;
+    // the gather of either projector variant comes before any store or
+    // barrier of the epilogue, so its view-table loads stay scalar
+    float g = 0.f;
+    if (inside) {
+        if (P.reach == 0)
+            g = back_pixel<true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy);
+        else
+            g = back_pixel<false>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix, iy);
+        g *= P.inv_n;
     }
+    const int ntx = (P.N + kBackX - 1) / kBackX;
+    double *part2 = kHalf ? glob(P.parts) + 2 * (it.b * ntx + it.a) : nullptr;
+    update_epilogue<kHalf>(inside, g, P.N, glob(P.x), P.gamma, glob(kHalf ? P.xh : P.x),
+                           glob(kHalf ? P.xhT : P.xT), part2, it.a, it.b);
 }
 
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
@@ -694,7 +697,7 @@ inline int dot_blocks(long d)
 
 int num_tiles(int N)
 {
-    const int t = (N + kTile - 1) / kTile;
+    const int t = (N + kBackX - 1) / kBackX;
     return t * t;
 }
 
@@ -789,15 +792,28 @@ hipError_t launch_state_init(SolveState *state, double tol, int max_iters, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_eg_update(const float *x, const float *g, float gamma, float *z, float *zT,
-                            int N, double *partials, const int32_t *skip, hipStream_t st)
+hipError_t launch_back_update(const Geo &g, const float *r, float scale, const float *x,
+                              float gamma, float *z, float *zT, double *partials,
+                              const int32_t *skip, hipStream_t st)
 {
-    if (partials)
-        hipLaunchKernelGGL(k_eg_update<true>, tile_grid(N), dim3(kTile, 8), 0, st, x, g, gamma,
-                           z, zT, N, partials, skip);
-    else
-        hipLaunchKernelGGL(k_eg_update<false>, tile_grid(N), dim3(kTile, 8), 0, st, x, g, gamma,
-                           z, zT, N, partials, skip);
+    dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
+    dim3 blk(kBackX, kBackY);
+    if (g.reach == 0) {
+        if (partials)
+            hipLaunchKernelGGL((k_back_update<true, true>), grid, blk, 0, st, g.views, g.N, g.V,
+                               g.B, g.nrow, 0, r, scale, x, gamma, z, zT, partials, skip);
+        else
+            hipLaunchKernelGGL((k_back_update<true, false>), grid, blk, 0, st, g.views, g.N, g.V,
+                               g.B, g.nrow, 0, r, scale, x, gamma, z, zT, partials, skip);
+    } else {
+        if (partials)
+            hipLaunchKernelGGL((k_back_update<false, true>), grid, blk, 0, st, g.views, g.N, g.V,
+                               g.B, g.nrow, g.reach, r, scale, x, gamma, z, zT, partials, skip);
+        else
+            hipLaunchKernelGGL((k_back_update<false, false>), grid, blk, 0, st, g.views, g.N,
+                               g.V, g.B, g.nrow, g.reach, r, scale, x, gamma, z, zT, partials,
+                               skip);
+    }
     return hipGetLastError();
 }
 
@@ -809,18 +825,15 @@ hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *stat
 }
 
 hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem *fwd, int nfwd,
-                             const BatchItem *back, int nback, const BatchItem *upd, int nupd,
-                             hipStream_t st)
+                             const BatchItem *back, int nback, hipStream_t st)
 {
     if (nprobs == 0)
         return hipSuccess;
-    const dim3 fb(kFwdThreads * kSegs), bb(kBackX, kBackY), ub(kTile, 8), rb(kRedThreads);
+    const dim3 fb(kFwdThreads * kSegs), bb(kBackX, kBackY), rb(kRedThreads);
     hipLaunchKernelGGL(kb_forward<false>, dim3(nfwd), fb, 0, st, probs, fwd);
-    hipLaunchKernelGGL(kb_back, dim3(nback), bb, 0, st, probs, back);
-    hipLaunchKernelGGL(kb_update<true>, dim3(nupd), ub, 0, st, probs, upd);
+    hipLaunchKernelGGL(kb_back_update<true>, dim3(nback), bb, 0, st, probs, back);
     hipLaunchKernelGGL(kb_forward<true>, dim3(nfwd), fb, 0, st, probs, fwd);
-    hipLaunchKernelGGL(kb_back, dim3(nback), bb, 0, st, probs, back);
-    hipLaunchKernelGGL(kb_update<false>, dim3(nupd), ub, 0, st, probs, upd);
+    hipLaunchKernelGGL(kb_back_update<false>, dim3(nback), bb, 0, st, probs, back);
     hipLaunchKernelGGL(kb_finish, dim3(nprobs), rb, 0, st, probs);
     return hipGetLastError();
 }
@@ -828,7 +841,6 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
 int fwd_items_per_view(int B) { return (B + kFwdThreads - 1) / kFwdThreads; }
 int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }
-int update_tiles_per_side(int N) { return (N + kTile - 1) / kTile; }
 
 hipError_t launch_dot3(const float *v, const float *u, int N, double *partials, hipStream_t st)
 {

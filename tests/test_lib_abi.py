@@ -86,9 +86,9 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def test_run_footprint_is_host_arithmetic(lib):
     from paper_2503_19925_amd import exact
-    # 2 sinogram-sized and 5 image-sized float buffers plus small tables
+    # 2 sinogram-sized and 4 image-sized float buffers plus small tables
     f = exact.exact_run_footprint(512, 180, 725)
-    assert 4 * (2 * 180 * 725 + 5 * 512 * 512) < f < 4 * (2 * 180 * 725 + 5 * 512 * 512) + 65536
+    assert 4 * (2 * 180 * 725 + 4 * 512 * 512) < f < 4 * (2 * 180 * 725 + 4 * 512 * 512) + 65536
     assert exact.exact_run_footprint(0, 10, 10) == 0
 
 
