@@ -39,6 +39,11 @@
  *  projection onto the nonnegative orthant of Sec. 3.1 (keep positive
  *  entries, zero the rest).  Both half-steps start from x_t.
  *
+ *  Averaged iterate and stopping rule of the experiments (Sec. 5,
+ *  comparison of methods): xbar_s is the mean of x_j over the last half of
+ *  the indices, j = floor(s/2)+1 .. s; the run stops at the first s with
+ *  ||xbar_s - xbar_{s-1}||_2 <= tol and reports xbar_s.
+ *
  *  Step size (Theorem 2, Sec. 2.1; Lipschitz bound in Sec. 4.2):
  *  L <= lambda_max(Sigma) * sum_k J_k mu_k with Sigma = A^T A / n and
  *  J_k = sum_j I[j][k]; gamma = c / L.  lambda_max comes from ora_power.

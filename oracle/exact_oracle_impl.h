@@ -377,6 +377,97 @@ int FN(ora_eg)(const ora_geom *g, int K, int Wn, const double *mu,
 }
 
 /*
+ * Averaged iterate of the paper's experiments (Sec. 5, comparison of
+ * methods): at index s the mean of the last half of the iterates,
+ *   xbar_s = (1 / (s - floor(s/2))) * sum_{j = floor(s/2)+1}^{s} x_j,
+ * taken here from traj, whose row j-1 holds x_j (x_1 the starting point).
+ */
+static void FN(window_mean)(const REAL *traj, long d, int s, REAL *out)
+{
+    int first = s / 2 + 1;
+    for (long p = 0; p < d; ++p)
+        out[p] = 0;
+    for (int j = first; j <= s; ++j)
+        for (long p = 0; p < d; ++p)
+            out[p] += traj[(size_t)(j - 1) * (size_t)d + (size_t)p];
+    for (long p = 0; p < d; ++p)
+        out[p] /= (REAL)(s - first + 1);
+}
+
+/* window_mean on a caller-supplied trajectory (rows x_1 .. x_s). */
+void FN(ora_window_mean)(const double *traj, long d, int s, double *out)
+{
+    REAL *tr = FN(to_real)(traj, (long)s * d);
+    REAL *o = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    FN(window_mean)(tr, d, s, o);
+    FN(to_double)(o, d, out);
+    free(tr); free(o);
+}
+
+/*
+ * Projected extragradient with the paper's averaged-iterate stopping rule
+ * (Sec. 5): the iterates are those of ora_eg; after step t the averaged
+ * iterates at s = t+1 and s-1 = t are compared and the loop stops once
+ * ||xbar_{t+1} - xbar_t||_2 <= tol (tol > 0; an absolute bound, as in the
+ * paper).  On exit x holds xbar at the last index reached and x_last
+ * (nullable) the last iterate x_{t+1}; crit_hist (nullable, length
+ * max_iters) receives ||xbar_{t+1} - xbar_t||.  Keeps the whole trajectory
+ * (max_iters + 1 images): small problems only.  Returns the steps taken.
+ */
+int FN(ora_eg_avg)(const ora_geom *g, int K, int Wn, const double *mu,
+                   const double *Iwk, const double *y, double *x, double gamma,
+                   int max_iters, double tol, double *crit_hist, double *x_last)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    REAL *traj = (REAL *)malloc(sizeof(REAL) * (size_t)(max_iters + 1) * (size_t)d);
+    REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *prev = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *cur = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL gm = (REAL)gamma;
+    for (long p = 0; p < d; ++p)
+        traj[p] = (REAL)x[p];
+    FN(window_mean)(traj, d, 1, cur);
+    int t;
+    for (t = 1; t <= max_iters; ++t) {
+        const REAL *xt = traj + (size_t)(t - 1) * (size_t)d;
+        REAL *xn = traj + (size_t)t * (size_t)d;
+        FN(apply_F)(g, &sp, xt, F, s, r);
+        for (long p = 0; p < d; ++p) {
+            REAL z = xt[p] - gm * F[p];
+            xh[p] = z > 0 ? z : 0;
+        }
+        FN(apply_F)(g, &sp, xh, F, s, r);
+        for (long p = 0; p < d; ++p) {
+            REAL z = xt[p] - gm * F[p];
+            xn[p] = z > 0 ? z : 0;
+        }
+        for (long p = 0; p < d; ++p)
+            prev[p] = cur[p];
+        FN(window_mean)(traj, d, t + 1, cur);
+        REAL sq = 0;
+        for (long p = 0; p < d; ++p)
+            sq += (cur[p] - prev[p]) * (cur[p] - prev[p]);
+        double crit = (double)sqrt(sq);
+        if (crit_hist)
+            crit_hist[t - 1] = crit;
+        if (tol > 0 && crit <= tol)
+            break;
+    }
+    if (t > max_iters)
+        t = max_iters;
+    FN(to_double)(cur, d, x);
+    if (x_last)
+        FN(to_double)(traj + (size_t)t * (size_t)d, d, x_last);
+    FN(free_spec)(&sp);
+    free(traj); free(xh); free(F); free(s); free(r); free(prev); free(cur);
+    return t;
+}
+
+/*
  * Largest eigenvalue of Sigma = A^T A / n by power iteration from the
  * constant unit vector, with Rayleigh quotients; stops when the quotient
  * changes by less than rel_tol (relative) or after max_iters products.

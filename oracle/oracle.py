@@ -87,6 +87,13 @@ def _lib():
             f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_double,
                           C.c_int, C.c_double, C.c_void_p]
             f.restype = C.c_int
+            f = getattr(_LIB, "ora_eg_avg_" + p)
+            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_double,
+                          C.c_int, C.c_double, C.c_void_p, C.c_void_p]
+            f.restype = C.c_int
+            f = getattr(_LIB, "ora_window_mean_" + p)
+            f.argtypes = [_dp, C.c_long, C.c_int, _dp]
+            f.restype = None
             f = getattr(_LIB, "ora_power_" + p)
             f.argtypes = [_gp, C.c_int, C.c_double, C.POINTER(C.c_int)]
             f.restype = C.c_double
@@ -192,6 +199,34 @@ def eg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
     t = _fn("eg", prec)(C.byref(g), K, Wn, mu, I, y, x, float(gamma),
                         int(max_iters), float(tol), _ptr(hist))
     return x, int(t), hist[:t]
+
+
+def eg_avg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
+    """Projected extragradient with the averaged-iterate stopping rule.
+    Returns (xbar, steps, crit_hist, x_last): xbar at index steps+1, the
+    history of ||xbar_{t+1} - xbar_t|| and the last iterate x_{steps+1}."""
+    mu = _f64(mu)
+    K = mu.size
+    I = _f64(I)
+    Wn = I.size // K
+    y = _f64(y, Wn * g.n)
+    x = _f64(x1, g.d).copy()
+    last = np.empty(g.d)
+    hist = np.full(max(int(max_iters), 1), np.nan)
+    t = _fn("eg_avg", prec)(C.byref(g), K, Wn, mu, I, y, x, float(gamma),
+                            int(max_iters), float(tol), _ptr(hist), _ptr(last))
+    return x, int(t), hist[:t], last
+
+
+def window_mean(traj, s, prec="f64"):
+    """Mean of rows floor(s/2)+1 .. s (1-based) of traj [>= s, d]."""
+    traj = np.ascontiguousarray(np.asarray(traj, dtype=np.float64))
+    d = traj.shape[1]
+    if traj.shape[0] < s or s < 1:
+        raise ValueError("need 1 <= s <= rows")
+    out = np.empty(d)
+    _fn("window_mean", prec)(np.ascontiguousarray(traj[:s]).ravel(), d, int(s), out)
+    return out
 
 
 def power(g, max_iters=10000, rel_tol=1e-12, prec="f64"):

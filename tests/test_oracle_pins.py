@@ -324,10 +324,12 @@ def test_noiseless_fixed_point_and_recovery(ora):
     assert np.linalg.norm(x - x_star) <= 1e-8 * np.linalg.norm(x_star), t
 
 
-def test_linear_rate_bound(ora):
-    """Theorem 1 with zero noise: ||x_{t+1} - x*|| <= (1 - nu/8L)^{t/2} ||x_1 - x*||,
-    L = lambda_max * sum J mu, nu >= lambda_min * sum_k J_k mu_k exp(-mu_k M)
-    where M bounds a_i . x over the points visited (Sec. 2.1 / 4.2)."""
+def _rate_run(ora, steps=300):
+    """The noiseless problem's EG trajectory from 0 at gamma = 1/(4L), one
+    step at a time, with Theorem 1's contraction factor per step:
+    ||x_{t+1} - x*|| <= q^{t/2} ||x_1 - x*||, q = 1 - nu/8L, L = lambda_max *
+    sum J mu, nu >= lambda_min * sum_k J_k mu_k exp(-mu_k M) where M bounds
+    a_i . x over the points visited (Sec. 2.1 / 4.2)."""
     g, mu, I, y, x_star = _noiseless(ora)
     A = dense_A(g.n_pix, g.n_views, g.n_bins, g.pixel_cm, g.bin_cm)
     ev = np.linalg.eigvalsh(A.T @ A / g.n)
@@ -336,7 +338,7 @@ def test_linear_rate_bound(ora):
     gamma = 1.0 / (4.0 * L)
     xs = [np.zeros(g.d)]
     pts = [x_star]
-    for _ in range(300):
+    for _ in range(steps):
         xt = xs[-1]
         xh = np.maximum(0, xt - gamma * ora.operator(g, mu, I, y, xt))
         pts += [xt, xh]
@@ -344,10 +346,81 @@ def test_linear_rate_bound(ora):
         xs.append(xn)
     M = max(float((A @ p).max()) for p in pts)
     nu = ev[0] * float(np.dot(J * mu, np.exp(-mu * M)))
+    return g, mu, I, y, x_star, gamma, 1 - nu / (8 * L), xs
+
+
+def test_linear_rate_bound(ora):
+    """Theorem 1 with zero noise: ||x_{t+1} - x*|| <= q^{t/2} ||x_1 - x*||."""
+    g, mu, I, y, x_star, gamma, q, xs = _rate_run(ora)
     e0 = np.linalg.norm(xs[0] - x_star)
     for t in range(1, len(xs)):
-        bound = (1 - nu / (8 * L)) ** (t / 2) * e0
+        bound = q ** (t / 2) * e0
         assert np.linalg.norm(xs[t] - x_star) <= bound * (1 + 1e-9) + 1e-12, t
+
+
+# --------------------------------------- averaged iterate (Sec. 5 stop rule)
+
+def test_window_mean_closed_forms(ora):
+    """xbar_s averages x_j over j = floor(s/2)+1 .. s (the last half of the
+    iterates): on the sequences x_j = j, j^2 and (-1)^j the means are
+    arithmetic-series closed forms."""
+    S = 41
+    j = np.arange(1, S + 1, dtype=np.float64)
+    traj = np.stack([j, j * j, (-1.0) ** j, np.full(S, 2.5)], axis=1)
+    for s in range(1, S + 1):
+        a, b = s // 2 + 1, s
+        c = b - a + 1
+        assert c == (s + 1) // 2                 # ceil(s/2) iterates
+        sq = (b * (b + 1) * (2 * b + 1) - (a - 1) * a * (2 * a - 1)) / 6.0
+        alt = 0.0 if c % 2 == 0 else (-1.0) ** a
+        want = [(a + b) / 2.0, sq / c, alt / c, 2.5]
+        got = ora.window_mean(traj, s)
+        np.testing.assert_allclose(got, want, rtol=1e-15, atol=1e-15, err_msg=str(s))
+
+
+def test_averaged_iterate_inherits_rate(ora):
+    """The average at index s obeys the linear-rate bound of iterate
+    floor(s/2)+1, the first one it averages (the convexity remark on the
+    averaged iterate in Sec. 5, with Theorem 1): ||xbar_s - x*|| <=
+    q^{floor(s/2)/2} ||x_1 - x*||.  The last iterate equals plain EG's."""
+    g, mu, I, y, x_star, gamma, q, xs = _rate_run(ora, steps=120)
+    e0 = np.linalg.norm(xs[0] - x_star)
+    for T in (1, 2, 7, 40, 119, 120):
+        xbar, t, crit, last = ora.eg_avg(g, mu, I, y, np.zeros(g.d), gamma, T)
+        assert t == T and crit.size == T
+        np.testing.assert_array_equal(last, xs[T])
+        s = T + 1
+        bound = q ** ((s // 2) / 2) * e0
+        assert np.linalg.norm(xbar - x_star) <= bound * (1 + 1e-9) + 1e-12, T
+        # an average of iterates that all lie within the bound of the first
+        assert np.linalg.norm(xbar - np.mean(xs[s // 2:s], axis=0)) <= 1e-13 * np.linalg.norm(x_star)
+
+
+def test_averaged_stop_at_fixed_point(ora):
+    """Started at the noiseless solution the iterates stay there (F(x*) = 0),
+    so every average is x*: the rule stops after the first step."""
+    g, mu, I, y, x_star = _noiseless(ora)
+    lam, _ = ora.power(g, 2000, 1e-12)
+    gamma = ora.step_size(lam, mu, I)
+    xbar, t, crit, last = ora.eg_avg(g, mu, I, y, x_star, gamma, 50, tol=1e-9)
+    assert t == 1 and crit[0] <= 1e-9
+    assert np.linalg.norm(xbar - x_star) <= 1e-10 * np.linalg.norm(x_star)
+
+
+def test_averaged_stop_rule(ora):
+    """The loop stops at the first step whose ||xbar_{t+1} - xbar_t|| is at
+    most tol; the criterion alternates between the two kinds of window move
+    (one iterate added, or one added and one dropped)."""
+    g, mu, I, y, _ = _small_problem(ora, N=16, V=20, B=24)
+    lam, _ = ora.power(g, 2000, 1e-10)
+    gamma = ora.step_size(lam, mu, I)
+    xbar, t, hist, last = ora.eg_avg(g, mu, I, y, np.zeros(g.d), gamma, 3000, tol=1e-4)
+    assert 1 < t < 3000
+    assert hist[-1] <= 1e-4 and (hist[:-1] > 1e-4).all()
+    x2, t2, _, last2 = ora.eg_avg(g, mu, I, y, np.zeros(g.d), gamma, t)
+    np.testing.assert_array_equal(xbar, x2)
+    x3, _, _ = ora.eg(g, mu, I, y, np.zeros(g.d), gamma, t)
+    np.testing.assert_array_equal(last, x3)
 
 
 def test_vi_solution_at_convergence(ora):
