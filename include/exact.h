@@ -76,8 +76,18 @@ typedef struct {
     const double *weight;   /* [Wn][K]  */
 } exact_spectrum;
 
-/* Stop rules for exact_solve. */
+/* Stop rules for exact_solve.
+ * NATURAL_RESIDUAL: stop after the first step t with
+ *   rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| <= tol (relative); returns x_{t+1}.
+ * AVERAGED_ITERATE (the rule of the paper's experiments, Sec. 5, comparison
+ *   of methods): with xbar_s the mean of the iterates x_j, j = floor(s/2)+1
+ *   .. s (x_1 the starting point), stop after the first step t with
+ *   ||xbar_{t+1} - xbar_t|| <= tol (absolute, as in the paper); returns
+ *   xbar_{t+1}.  Keeps floor(J/2)+2 images of iterates, J =
+ *   floor((max_iters+1)/2), plus a double running sum: bound max_iters
+ *   accordingly.  exact_solve only; the solver and batch calls reject it. */
 #define EXACT_STOP_NATURAL_RESIDUAL 0
+#define EXACT_STOP_AVERAGED_ITERATE 1
 
 typedef struct {
     double gamma;        /* step size; <= 0 selects gamma_scale / L (below)  */
@@ -85,8 +95,8 @@ typedef struct {
                             sum_k J_k mu_k), J_k = sum_j weight[j][k];
                             Theorem 2 uses c = 1/4 (default)                */
     int32_t max_iters;   /* full extragradient steps (two F evaluations each) */
-    double tol;          /* stop after step t once rho_t <= tol; 0 = run all */
-    int32_t stop_mode;   /* EXACT_STOP_NATURAL_RESIDUAL                      */
+    double tol;          /* stop tolerance of the stop rule; 0 = run all     */
+    int32_t stop_mode;   /* EXACT_STOP_NATURAL_RESIDUAL or _AVERAGED_ITERATE */
     int32_t check_every; /* steps between host reads of the device stop flag */
     int32_t power_iters; /* cap on power-iteration steps for lambda_max     */
 } exact_solve_opts;
@@ -94,7 +104,8 @@ typedef struct {
 typedef struct {
     int32_t iters;       /* steps taken                                      */
     double resid;        /* last rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| (-1 if
-                            undefined, i.e. x_t = 0)                         */
+                            undefined, i.e. x_t = 0); with the averaged rule
+                            the last ||xbar_{t+1} - xbar_t||                 */
     double gamma;        /* step size used                                   */
     double lambda_hat;   /* lambda_max estimate (0 if gamma was given)       */
     double ms;           /* wall time of the call                            */
@@ -162,12 +173,14 @@ int exact_step_size(exact_geometry g, const exact_spectrum *sp,
  * X = {x >= 0} (the orthant projection of Sec. 3.1):
  *     x_{t+1/2} = max(0, x_t - gamma F(x_t)),
  *     x_{t+1}   = max(0, x_t - gamma F(x_{t+1/2})),   t = 1, 2, ...
- * x_dev holds x_1 >= 0 on entry and the last iterate on return.  With
- * tol > 0 the run stops after the first step t with
- * rho_t = ||x_{t+1/2} - x_t|| / ||x_t|| <= tol (norms in double), returning
- * x_{t+1}; otherwise it runs max_iters steps.  Blocks until done; info
- * (nullable) receives the summary.  Returns EXACT_ENOTCONV if tol > 0 and
- * max_iters steps did not reach it (x_dev then holds the last iterate).
+ * x_dev holds x_1 >= 0 on entry and, on return, the last iterate (or, with
+ * EXACT_STOP_AVERAGED_ITERATE, the averaged iterate at the last index).
+ * With tol > 0 the run stops after the first step t that meets the stop
+ * rule (norms in double; see the stop rules above); otherwise it runs
+ * max_iters steps.  Blocks until done; info (nullable) receives the
+ * summary.  Returns EXACT_ENOTCONV if tol > 0 and max_iters steps did not
+ * reach it (x_dev then holds the last iterate or average).  -ENOMEM if the
+ * averaged rule's iterate ring does not fit.
  * Checks on the device that y is finite and >= 0 and x_1 finite and >= 0
  * (-EINVAL otherwise, x_dev unchanged).
  */

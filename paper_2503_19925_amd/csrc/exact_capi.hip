@@ -259,7 +259,7 @@ double power_iteration(const exact_geometry_s *g, int max_iters, hipStream_t st,
     PinnedState hs;
     hip_check(exact::launch_fill(v.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st), "fill");
     hip_check(exact::launch_fill(vT.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st), "fill");
-    hip_check(exact::launch_state_init(state.as<SolveState>(), 0.0, 0, st), "state_init");
+    hip_check(exact::launch_state_init(state.as<SolveState>(), 0.0, 0, 0, st), "state_init");
     double lam = 0.0;
     int it = 0;
     for (it = 1; it <= max_iters; ++it) {
@@ -465,6 +465,9 @@ struct Problem {
     SpecArg spec;
     double gamma = 0.0, lam = 0.0;
     int max_iters = 0;
+    int stop_mode = EXACT_STOP_NATURAL_RESIDUAL;
+    int avg_R = 0, avg_J = 0;                       // averaged-iterate ring (stop_mode 1)
+    std::unique_ptr<DevBuf> avg_ring, avg_S, avg_parts;
     float *x = nullptr;
     std::unique_ptr<DevBuf> Y, r, xT, xh, xhT, parts, specd;
     SolveState *state = nullptr;
@@ -514,7 +517,7 @@ void validate_opts(exact_solve_opts &o)
         fail(-EINVAL, "max_iters must be >= 0");
     if (!(std::isfinite(o.tol) && o.tol >= 0.0))
         fail(-EINVAL, "tol must be finite and >= 0");
-    if (o.stop_mode != EXACT_STOP_NATURAL_RESIDUAL)
+    if (o.stop_mode != EXACT_STOP_NATURAL_RESIDUAL && o.stop_mode != EXACT_STOP_AVERAGED_ITERATE)
         fail(-EINVAL, "unsupported stop_mode");
     if (!std::isfinite(o.gamma))
         fail(-EINVAL, "gamma must be finite");
@@ -542,6 +545,7 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.spec = make_spec(sp, &sjm);
     p.x = x_dev;
     p.max_iters = o.max_iters;
+    p.stop_mode = o.stop_mode;
     p.state = state;
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
     p.footprint = run_footprint(g->N, g->V, g->B);
@@ -578,7 +582,17 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
         p.gamma = o.gamma_scale / (p.lam * sjm);
     }
     hip_check(exact::launch_transpose(x_dev, p.xT->as<float>(), g->N, st), "transpose");
-    hip_check(exact::launch_state_init(state, o.tol, o.max_iters, st), "state_init");
+    hip_check(exact::launch_state_init(state, o.tol, o.max_iters, o.stop_mode, st), "state_init");
+    if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
+        p.avg_J = exact::avg_last_kept(o.max_iters);
+        p.avg_R = exact::avg_ring_slots(o.max_iters);
+        p.avg_ring.reset(new DevBuf((size_t)p.avg_R * (size_t)d * 4));
+        p.avg_S.reset(new DevBuf((size_t)d * 8));
+        p.avg_parts.reset(new DevBuf((size_t)exact::num_avg_parts(d) * 8));
+        hip_check(exact::launch_avg_init(x_dev, p.avg_ring->as<float>(), p.avg_R, p.avg_J,
+                                         p.avg_S->as<double>(), d, st),
+                  "avg_init");
+    }
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
@@ -588,7 +602,9 @@ void fill_info(const Problem &p, const SolveState &h, exact_solve_info *info,
     if (!info)
         return;
     info->iters = p.max_iters == 0 ? 0 : h.t;
-    info->resid = p.max_iters == 0 ? -1.0 : h.rho;
+    info->resid = p.max_iters == 0 ? -1.0
+                  : p.stop_mode == EXACT_STOP_AVERAGED_ITERATE ? h.crit
+                                                                : h.rho;
     info->gamma = p.gamma;
     info->lambda_hat = p.lam;
     info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -664,7 +680,15 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, xh, xhT, parts, skip, st));
     cap(exact::launch_forward_residual(G, xh, xhT, Y, p.spec, r, skip, st));
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xT, nullptr, skip, st));
-    cap(exact::launch_eg_finish(parts, ntiles, S, st));
+    if (p.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
+        const long d = (long)g->N * g->N;
+        double *ap = p.avg_parts->as<double>();
+        cap(exact::launch_avg_step(p.x, p.avg_ring->as<float>(), p.avg_R, p.avg_J,
+                                   p.avg_S->as<double>(), d, ap, S, st));
+        cap(exact::launch_eg_finish(parts, ntiles, ap, exact::num_avg_parts(d), S, st));
+    } else {
+        cap(exact::launch_eg_finish(parts, ntiles, nullptr, 0, S, st));
+    }
     return e;
 }
 
@@ -824,6 +848,8 @@ int exact_solver_create(exact_geometry g, const exact_spectrum *sp, const float 
         exact_solve_opts_default(&o);
         if (opts)
             o = *opts;
+        if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE)
+            fail(-EINVAL, "the averaged-iterate stop rule is available in exact_solve only");
         *out = solver_build(g, sp, y_dev, x_dev, o, (hipStream_t)stream);
         return 0;
     });
@@ -877,6 +903,12 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev, 
             launched += chunk;
             if (solver_poll(s.get(), &local))
                 break;
+        }
+        if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
+            const Problem &p = s->prob;
+            hip_check(exact::launch_avg_output(p.avg_S->as<double>(), p.x,
+                                               (long)p.g->N * p.g->N, p.state, s->own->st),
+                      "avg_output");
         }
         solver_poll(s.get(), &local);
         const bool converged = s->hs->h->converged != 0;
@@ -947,6 +979,8 @@ int exact_batch_add(exact_batch bh, exact_geometry g, const exact_spectrum *sp, 
         exact_solve_opts_default(&o);
         if (opts)
             o = *opts;
+        if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE)
+            fail(-EINVAL, "the averaged-iterate stop rule is available in exact_solve only");
         std::unique_ptr<Problem> p(new Problem());
         // set-up runs on the batch's stream, after the caller's stream
         hip_check(hipStreamSynchronize(b->own->st), "hipStreamSynchronize");

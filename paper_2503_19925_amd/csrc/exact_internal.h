@@ -55,6 +55,9 @@ struct SolveState {
     int32_t done;        // nonzero: every later kernel of the run is a no-op
     int32_t converged;
     int32_t max_iters;
+    int32_t stop_mode;   // 0: natural residual rho; 1: averaged iterate
+    int32_t pad_;
+    double crit;         // stop_mode 1: last ||xbar_s - xbar_{s-1}|| (-1 if none)
 };
 
 struct Geo {
@@ -131,7 +134,7 @@ hipError_t launch_window_sum(const float *y, int Wn, long n, float *Y,
                              int32_t *bad, hipStream_t st);
 hipError_t launch_count_bad(const float *x, long count, int32_t *bad,
                             hipStream_t st);
-hipError_t launch_state_init(SolveState *state, double tol, int max_iters,
+hipError_t launch_state_init(SolveState *state, double tol, int max_iters, int stop_mode,
                              hipStream_t st);
 // Back-projection fused with the update: g = scale A^T r and
 // z = max(0, x - gamma g) for every pixel, written to z and (transposed) zT.
@@ -142,9 +145,32 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
                               float gamma, float *z, float *zT, double *partials,
                               const int32_t *skip, hipStream_t st);
 // Fixed-order reduction of the update partials; sets rho_t, advances t and
-// raises done when rho_t <= tol or t reaches max_iters.
-hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *state,
-                            hipStream_t st);
+// raises done when t reaches max_iters or the run's stop rule holds: rho_t
+// <= tol (stop_mode 0), or, from the averaged-iterate partials (n_avg of
+// them), ||xbar_s - xbar_{s-1}|| <= tol (stop_mode 1).
+hipError_t launch_eg_finish(const double *partials, int nparts, const double *avg_parts,
+                            int n_avg, SolveState *state, hipStream_t st);
+
+// Averaged iterate xbar_s = mean of x_j, j = floor(s/2)+1 .. s, kept as the
+// double running sum S of its window.  Iterates that a later window move
+// drops are kept in a ring of R image slots (slot j mod R holds x_j for
+// j <= J = floor((max_iters+1)/2), the largest index ever dropped);
+// R = floor(J/2) + 2 slots suffice.
+int avg_ring_slots(int max_iters);
+int avg_last_kept(int max_iters);
+int num_avg_parts(long d);
+// s = 1: S = x_1 and x_1 into its ring slot.
+hipError_t launch_avg_init(const float *x, float *ring, int R, int J, double *S, long d,
+                           hipStream_t st);
+// After the step that produced x_s (s = t + 2 with t the steps completed
+// before it): moves the window, S += x_s (- x_{s/2} for even s), stores x_s
+// if it will be dropped later, and writes per-block partials of
+// (S_new/c_s - S_old/c_{s-1})^2.  No-op once the run is done.
+hipError_t launch_avg_step(const float *x, float *ring, int R, int J, double *S, long d,
+                           double *partials, const SolveState *state, hipStream_t st);
+// x = xbar at the last index reached (s = t + 1).
+hipError_t launch_avg_output(const double *S, float *x, long d, const SolveState *state,
+                             hipStream_t st);
 // Power iteration helpers: partials of <v,u>, <v,v>, <u,u>; reduction into
 // state->lam and state->unorm; v = u / unorm (and its transpose).
 hipError_t launch_dot3(const float *v, const float *u, int N, double *partials,

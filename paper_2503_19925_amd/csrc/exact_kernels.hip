@@ -508,7 +508,7 @@ __global__ void k_count_bad(const float *__restrict__ x, long count, int32_t *__
     }
 }
 
-__global__ void k_state_init(SolveState *st, double tol, int max_iters)
+__global__ void k_state_init(SolveState *st, double tol, int max_iters, int stop_mode)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->rho = -1.0;
@@ -519,28 +519,43 @@ __global__ void k_state_init(SolveState *st, double tol, int max_iters)
         st->done = max_iters <= 0 ? 1 : 0;
         st->converged = 0;
         st->max_iters = max_iters;
+        st->stop_mode = stop_mode;
+        st->pad_ = 0;
+        st->crit = -1.0;
     }
 }
 
-// Fixed-order reduction of a run's update partials, rho_t, and the stop test.
+// Fixed-order reduction of a run's update partials, rho_t, and the stop test
+// (with stop_mode 1 also the averaged-iterate partials and their criterion).
 __device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
+                                             const double *__restrict__ avg_parts, int n_avg,
                                              SolveState *st)
 {
     if (st->done)
         return;
-    __shared__ double red[2][kRedThreads];
-    double v2[2] = {0.0, 0.0};
+    __shared__ double red[3][kRedThreads];
+    double v3[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
-        v2[0] += partials[2 * q];
-        v2[1] += partials[2 * q + 1];
+        v3[0] += partials[2 * q];
+        v3[1] += partials[2 * q + 1];
     }
-    block_sum<2>(v2, red);
+    for (int q = threadIdx.x; q < n_avg; q += kRedThreads)
+        v3[2] += avg_parts[q];
+    block_sum<3>(v3, red);
     if (threadIdx.x == 0) {
-        const double rho = v2[1] > 0.0 ? sqrt(v2[0] / v2[1]) : -1.0;
+        const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
         const int t = st->t + 1;
         st->rho = rho;
         st->t = t;
-        if (st->tol > 0.0 && rho >= 0.0 && rho <= st->tol) {
+        bool met;
+        if (st->stop_mode == 1) {
+            const double crit = sqrt(v3[2]);
+            st->crit = crit;
+            met = crit <= st->tol;
+        } else {
+            met = rho >= 0.0 && rho <= st->tol;
+        }
+        if (st->tol > 0.0 && met) {
             st->converged = 1;
             st->done = 1;
         } else if (t >= st->max_iters) {
@@ -550,9 +565,71 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restrict__ partials,
-                                                           int nparts, SolveState *st)
+                                                           int nparts,
+                                                           const double *__restrict__ avg_parts,
+                                                           int n_avg, SolveState *st)
 {
-    finish_block(partials, nparts, st);
+    finish_block(partials, nparts, avg_parts, n_avg, st);
+}
+
+// ------------------------------------------------------ averaged iterate
+
+constexpr int kAvgThreads = 256;
+
+__global__ __launch_bounds__(kAvgThreads) void k_avg_init(const float *__restrict__ x,
+                                                          float *__restrict__ ring, int R, int J,
+                                                          double *__restrict__ S, long d)
+{
+    const long p = (long)blockIdx.x * kAvgThreads + threadIdx.x;
+    if (p >= d)
+        return;
+    const float v = x[p];
+    S[p] = (double)v;
+    if (J >= 1)
+        ring[(size_t)(1 % R) * (size_t)d + (size_t)p] = v;
+}
+
+// One pixel per lane.  Window of index s: j = floor(s/2)+1 .. s, c_s =
+// s - floor(s/2) iterates.  Odd s adds x_s; even s adds x_s and drops
+// x_{s/2}.
+__global__ __launch_bounds__(kAvgThreads) void k_avg_step(
+    const float *__restrict__ x, float *__restrict__ ring, int R, int J, double *__restrict__ S,
+    long d, double *__restrict__ partials, const SolveState *__restrict__ st)
+{
+    if (st->done)
+        return;
+    __shared__ double red[1][kRedThreads];
+    const int s = st->t + 2;
+    const double c_new = (double)(s - s / 2), c_old = (double)((s - 1) - (s - 1) / 2);
+    const long p = (long)blockIdx.x * kAvgThreads + threadIdx.x;
+    double sq = 0.0;
+    if (p < d) {
+        const float xs = x[p];
+        const double so = S[p];
+        double sn = so + (double)xs;
+        if ((s & 1) == 0)
+            sn -= (double)ring[(size_t)((s / 2) % R) * (size_t)d + (size_t)p];
+        const double diff = sn / c_new - so / c_old;
+        sq = diff * diff;
+        S[p] = sn;
+        if (s <= J)
+            ring[(size_t)(s % R) * (size_t)d + (size_t)p] = xs;
+    }
+    double v1[1] = {sq};
+    block_sum<1>(v1, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = v1[0];
+}
+
+__global__ __launch_bounds__(kAvgThreads) void k_avg_output(const double *__restrict__ S,
+                                                            float *__restrict__ x, long d,
+                                                            const SolveState *__restrict__ st)
+{
+    const int s = st->t + 1;
+    const double c = (double)(s - s / 2);
+    const long p = (long)blockIdx.x * kAvgThreads + threadIdx.x;
+    if (p < d)
+        x[p] = (float)(S[p] / c);
 }
 
 // ------------------------------------------------------------- batched
@@ -614,7 +691,7 @@ __global__ __launch_bounds__(kBackX *kBackY) void kb_back_update(
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
 {
     const BatchProb &P = probs[blockIdx.x];
-    finish_block(glob(P.parts), P.ntiles, glob(P.state));
+    finish_block(glob(P.parts), P.ntiles, nullptr, 0, glob(P.state));
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,
@@ -786,9 +863,40 @@ hipError_t launch_count_bad(const float *x, long count, int32_t *bad, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(SolveState *state, double tol, int max_iters, hipStream_t st)
+hipError_t launch_state_init(SolveState *state, double tol, int max_iters, int stop_mode,
+                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, state, tol, max_iters);
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, state, tol, max_iters, stop_mode);
+    return hipGetLastError();
+}
+
+int avg_last_kept(int max_iters) { return max_iters < 0 ? 0 : (int)(((long)max_iters + 1) / 2); }
+int avg_ring_slots(int max_iters) { return avg_last_kept(max_iters) / 2 + 2; }
+int num_avg_parts(long d) { return (int)((d + kAvgThreads - 1) / kAvgThreads); }
+
+hipError_t launch_avg_init(const float *x, float *ring, int R, int J, double *S, long d,
+                           hipStream_t st)
+{
+    if (d <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_avg_init, dim3(num_avg_parts(d)), dim3(kAvgThreads), 0, st, x, ring, R,
+                       J, S, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_avg_step(const float *x, float *ring, int R, int J, double *S, long d,
+                           double *partials, const SolveState *state, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_avg_step, dim3(num_avg_parts(d)), dim3(kAvgThreads), 0, st, x, ring, R,
+                       J, S, d, partials, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_avg_output(const double *S, float *x, long d, const SolveState *state,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_avg_output, dim3(num_avg_parts(d)), dim3(kAvgThreads), 0, st, S, x, d,
+                       state);
     return hipGetLastError();
 }
 
@@ -817,10 +925,11 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
     return hipGetLastError();
 }
 
-hipError_t launch_eg_finish(const double *partials, int nparts, SolveState *state,
-                            hipStream_t st)
+hipError_t launch_eg_finish(const double *partials, int nparts, const double *avg_parts,
+                            int n_avg, SolveState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_eg_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state);
+    hipLaunchKernelGGL(k_eg_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts,
+                       avg_parts, n_avg, state);
     return hipGetLastError();
 }
 

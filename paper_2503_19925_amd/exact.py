@@ -40,6 +40,7 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
 
 # exact_batch_poll results
 RUNNING, FINISHED, CAPPED = 0, 1, 2
+STOP_NATURAL_RESIDUAL, STOP_AVERAGED_ITERATE = 0, 1
 
 
 class ExactError(RuntimeError):
@@ -229,11 +230,13 @@ def exact_step_size(g, mu=None, weight=None, max_iters=100, gamma_scale=0.25, st
     return lam.value, gam.value
 
 
-def _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters):
+def _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters,
+          stop_mode=STOP_NATURAL_RESIDUAL):
     o = SolveOpts()
     load().exact_solve_opts_default(C.byref(o))
     o.gamma, o.gamma_scale, o.max_iters, o.tol = float(gamma), float(gamma_scale), int(max_iters), float(tol)
     o.check_every, o.power_iters = int(check_every), int(power_iters)
+    o.stop_mode = int(stop_mode)
     return o
 
 
@@ -291,11 +294,13 @@ class Solver:
 
 
 def exact_solve(g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-                check_every=16, power_iters=100, stream=None):
+                check_every=16, power_iters=100, stream=None, stop_mode=STOP_NATURAL_RESIDUAL):
     """Runs EXACT in place on x.  Returns a dict with iters, resid, gamma,
-    lambda_hat, ms and converged (True/False, or None when tol == 0)."""
+    lambda_hat, ms and converged (True/False, or None when tol == 0).  With
+    stop_mode=STOP_AVERAGED_ITERATE x receives the averaged iterate and tol
+    bounds ||xbar_{t+1} - xbar_t|| (absolute)."""
     sp = _Spec(mu, weight)
-    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
+    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters, stop_mode)
     info = SolveInfo()
     code = _check("exact_solve", load().exact_solve(
         g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),

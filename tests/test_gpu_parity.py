@@ -288,6 +288,61 @@ def test_solve_stop_rule(ex, ora):
     g.close()
 
 
+@pytest.fixture(scope="module")
+def small_gamma(ora):
+    P = synth.config_problem("small_64")
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    return oracle_gamma(ora, go, P)
+
+
+@pytest.mark.parametrize("T,start", [(0, "half"), (1, "zero"), (2, "half"), (9, "zero"),
+                                     (100, "zero"), (101, "half")])
+def test_solve_averaged_iterate_parity(ex, ora, small_gamma, T, start):
+    """The averaged iterate (mean of x_j, j = floor(s/2)+1 .. s) after T fixed
+    steps, against the oracle's direct mean of its stored trajectory.  At
+    T = 100 the device keeps 27 ring slots for the 50 iterates a window ever
+    drops, so the ring wraps."""
+    P, g, go = _problem(ex, ora, "small_64")
+    say("averaged iterate", P.n_pix, "T =", T, "start", start)
+    x1 = np.zeros(g.d) if start == "zero" else (0.5 * P.x_true).astype(np.float32).astype(np.float64)
+    x = t32(x1)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=small_gamma, max_iters=T,
+                          stop_mode=ex.STOP_AVERAGED_ITERATE, check_every=8)
+    xb_ora, t, crit, _ = ora.eg_avg(go, P.mu, P.I, P.y.astype(np.float64), x1, small_gamma, T)
+    assert info["iters"] == T == t
+    got = np64(x)
+    if T == 0:
+        np.testing.assert_array_equal(got, x1)
+    else:
+        rel = np.linalg.norm(got - xb_ora) / np.linalg.norm(xb_ora)
+        print("  averaged iterate rel L2 %.3e; criterion %.6e vs %.6e" % (
+            rel, info["resid"], crit[-1]), flush=True)
+        assert rel <= 1e-4
+        assert abs(info["resid"] - crit[-1]) <= 1e-3 * crit[-1]
+    g.close()
+
+
+def test_solve_averaged_stop_rule(ex, ora, small_gamma):
+    """The averaged rule stops at the first step with ||xbar_{t+1} - xbar_t||
+    <= tol (absolute).  The criterion alternates between window moves that
+    only add an iterate and moves that also drop one, so a marginal float
+    difference can move the stop by two steps."""
+    P, g, go = _problem(ex, ora, "small_64")
+    say("averaged stop rule", P.n_pix)
+    tol = 0.02
+    xb_ora, t_ora, crit, _ = ora.eg_avg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d),
+                                        small_gamma, 1000, tol=tol)
+    assert t_ora < 1000
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=small_gamma, max_iters=1000, tol=tol,
+                          stop_mode=ex.STOP_AVERAGED_ITERATE, check_every=5)
+    assert info["converged"] and info["resid"] <= tol
+    assert abs(info["iters"] - t_ora) <= 2, (info["iters"], t_ora)
+    if info["iters"] == t_ora:
+        assert np.linalg.norm(np64(x) - xb_ora) <= 1e-4 * np.linalg.norm(xb_ora)
+    g.close()
+
+
 def test_solve_is_deterministic(ex):
     P = synth.config_problem("small_64")
     say("solve determinism")

@@ -100,3 +100,17 @@ def test_batch_null_handles(lib):
     assert lib.exact_batch_destroy(None) == 0
     h = C.c_void_p()
     assert lib.exact_batch_create(1 << 20, 0, C.byref(h)) == -errno.EINVAL
+
+
+def test_averaged_rule_is_exact_solve_only(lib):
+    """The resident solver and the batch keep one live iterate and no ring of
+    past iterates: they refuse the averaged-iterate stop rule."""
+    from paper_2503_19925_amd.exact import SolveOpts, STOP_AVERAGED_ITERATE
+    o = SolveOpts()
+    lib.exact_solve_opts_default(C.byref(o))
+    o.stop_mode = STOP_AVERAGED_ITERATE
+    h = C.c_void_p()
+    assert lib.exact_solver_create(None, None, None, None, C.byref(o), C.byref(h), None) == -errno.EINVAL
+    assert "averaged" in lib.exact_last_error().decode()
+    o.stop_mode = 7
+    assert lib.exact_solve(None, None, None, None, C.byref(o), None, None) == -errno.EINVAL
