@@ -151,16 +151,17 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         const long double A = fixed32(c + c * sn / cs - half * ratio / cs);
         // largest crossing the kernels form: b up to B + 64 (candidate bins
         // beyond the detector are formed, then discarded), k up to N
-        const long double span = fabsl(A) + (B + 64) * fabsl(P) + N * fabsl(Q) + 2.0L;
+        const long double span = fabsl(A) + (B + 64) * fabsl(P) + N * fabsl(Q) + 4.0L;
         if (!(span < 1048576.0L))
             fail(-EINVAL, "geometry too large for exact crossing arithmetic (|crossing| >= 2^20)");
         ViewGeom G;
         std::memset(&G, 0, sizeof(G));
         G.A = (double)A;
+        G.Ab = (double)(A - (long double)exact::kPadB * P);   // exact: multiples of 2^-32
         G.P = (double)P;
         G.Q = (double)Q;
         G.invP = (double)(1.0L / P);
-        G.absP = (double)fabsl(P);
+        G.sPhi = P < 0 ? -1 : 0;
         G.wstep = (float)((long double)pixel_cm / fabsl(cs));
         G.vidx = v;
         (row ? rows : cols).push_back(G);
@@ -255,20 +256,32 @@ double power_iteration(const exact_geometry_s *g, int max_iters, hipStream_t st,
     const Geo G = geo_of(g);
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
     const int nparts = exact::num_dot_parts(d);
-    DevBuf v(d * 4), vT(d * 4), u(d * 4), s(n * 4), parts(nparts * 3 * 8), state(sizeof(SolveState));
+    const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+    const size_t np = (size_t)g->V * exact::padded_bins(g->B);
+    DevBuf v(d * 4), vp(dp * 4), vTp(dp * 4), u(d * 4), s(np * 4), parts(nparts * 3 * 8),
+        state(sizeof(SolveState));
     PinnedState hs;
+    hip_check(hipMemsetAsync(vp.p, 0, dp * 4, st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(vTp.p, 0, dp * 4, st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(s.p, 0, np * 4, st), "hipMemsetAsync");
     hip_check(exact::launch_fill(v.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st), "fill");
-    hip_check(exact::launch_fill(vT.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st), "fill");
+    hip_check(exact::launch_pad_pair(v.as<float>(), vp.as<float>(), vTp.as<float>(), g->N, st),
+              "pad_pair");
     hip_check(exact::launch_state_init(state.as<SolveState>(), 0.0, 0, 0, st), "state_init");
     double lam = 0.0;
     int it = 0;
     for (it = 1; it <= max_iters; ++it) {
-        hip_check(exact::launch_forward(G, v.as<float>(), vT.as<float>(), s.as<float>(), nullptr, st), "forward");
-        hip_check(exact::launch_back(G, s.as<float>(), u.as<float>(), (float)(1.0 / (double)n), nullptr, st), "back");
+        hip_check(exact::launch_forward(G, vp.as<float>(), vTp.as<float>(), s.as<float>(),
+                                        exact::padded_bins(g->B), exact::kPadB, nullptr, st),
+                  "forward");
+        hip_check(exact::launch_back(G, s.as<float>(), true, u.as<float>(), (float)(1.0 / (double)n),
+                                     nullptr, st),
+                  "back");
         hip_check(exact::launch_dot3(v.as<float>(), u.as<float>(), g->N, parts.as<double>(), st), "dot3");
         hip_check(exact::launch_dot3_finish(parts.as<double>(), nparts, state.as<SolveState>(), st), "dot3_finish");
-        hip_check(exact::launch_normalize(u.as<float>(), v.as<float>(), vT.as<float>(), g->N,
-                                          state.as<SolveState>(), st), "normalize");
+        hip_check(exact::launch_normalize(u.as<float>(), v.as<float>(), vp.as<float>(), vTp.as<float>(),
+                                          g->N, state.as<SolveState>(), st),
+                  "normalize");
         read_state(state.as<SolveState>(), hs, st);
         const double lam_new = hs.h->lam;
         if (!(std::isfinite(lam_new) && lam_new > 0.0))
@@ -364,10 +377,14 @@ int exact_forward(exact_geometry g, const float *x_dev, float *s_dev, void *stre
         if (!x_dev || !s_dev)
             fail(-EINVAL, "NULL buffer");
         hipStream_t st = (hipStream_t)stream;
-        const long d = (long)g->N * g->N;
-        AsyncBuf xT(d * sizeof(float), st);
-        hip_check(exact::launch_transpose(x_dev, xT.as<float>(), g->N, st), "transpose");
-        hip_check(exact::launch_forward(geo_of(g), x_dev, xT.as<float>(), s_dev, nullptr, st),
+        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        AsyncBuf xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st);
+        hip_check(hipMemsetAsync(xp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(xTp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        hip_check(exact::launch_pad_pair(x_dev, xp.as<float>(), xTp.as<float>(), g->N, st),
+                  "pad_pair");
+        hip_check(exact::launch_forward(geo_of(g), xp.as<float>(), xTp.as<float>(), s_dev, g->B, 0,
+                                        nullptr, st),
                   "forward");
         return 0;
     });
@@ -379,7 +396,8 @@ int exact_backproject(exact_geometry g, const float *r_dev, float *img_dev, void
         check_geometry(g);
         if (!r_dev || !img_dev)
             fail(-EINVAL, "NULL buffer");
-        hip_check(exact::launch_back(geo_of(g), r_dev, img_dev, 1.0f, nullptr, (hipStream_t)stream),
+        hip_check(exact::launch_back(geo_of(g), r_dev, false, img_dev, 1.0f, nullptr,
+                                     (hipStream_t)stream),
                   "back");
         return 0;
     });
@@ -394,18 +412,31 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp, const float *y_de
             fail(-EINVAL, "NULL buffer");
         const SpecArg a = make_spec(sp, nullptr);
         hipStream_t st = (hipStream_t)stream;
-        const long d = (long)g->N * g->N, n = (long)g->V * g->B;
-        AsyncBuf Y(n * sizeof(float), st), xT(d * sizeof(float), st);
-        AsyncBuf rs(r_dev ? 0 : n * sizeof(float), st);
-        float *r = r_dev ? r_dev : rs.as<float>();
+        const long n = (long)g->V * g->B;
+        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t np = (size_t)g->V * exact::padded_bins(g->B);
+        AsyncBuf Y(n * sizeof(float), st), xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st),
+            rp(np * sizeof(float), st);
+        hip_check(hipMemsetAsync(xp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(xTp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(rp.p, 0, np * sizeof(float), st), "hipMemsetAsync");
         hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, Y.as<float>(), nullptr, st),
                   "window_sum");
-        hip_check(exact::launch_transpose(x_dev, xT.as<float>(), g->N, st), "transpose");
-        hip_check(exact::launch_forward_residual(geo_of(g), x_dev, xT.as<float>(), Y.as<float>(),
-                                                 a, r, nullptr, st),
+        hip_check(exact::launch_pad_pair(x_dev, xp.as<float>(), xTp.as<float>(), g->N, st),
+                  "pad_pair");
+        hip_check(exact::launch_forward_residual(geo_of(g), xp.as<float>(), xTp.as<float>(),
+                                                 Y.as<float>(), a, rp.as<float>(), nullptr, st),
                   "forward_residual");
-        hip_check(exact::launch_back(geo_of(g), r, F_dev, (float)(1.0 / (double)n), nullptr, st),
+        hip_check(exact::launch_back(geo_of(g), rp.as<float>(), true, F_dev, (float)(1.0 / (double)n),
+                                     nullptr, st),
                   "back");
+        if (r_dev)
+            hip_check(hipMemcpy2DAsync(r_dev, (size_t)g->B * sizeof(float),
+                                       rp.as<float>() + exact::kPadB,
+                                       (size_t)exact::padded_bins(g->B) * sizeof(float),
+                                       (size_t)g->B * sizeof(float), (size_t)g->V,
+                                       hipMemcpyDeviceToDevice, st),
+                      "hipMemcpy2DAsync");
         return 0;
     });
 }
@@ -456,8 +487,9 @@ int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream)
 }  // extern "C"
 
 // One extragradient run's device state: the spectrum, the window sums of
-// y, the iterate's transpose, the half-step iterate and its transpose, the
-// residual buffer, the update partials.  The iterate itself
+// y, the iterate and the half-step iterate with their transposes in the
+// projectors' padded layout, the padded residual, the update partials.  The
+// iterate itself
 // is the caller's buffer.  `state` points at the run's SolveState (owned by
 // the solver or the batch).
 struct Problem {
@@ -469,7 +501,7 @@ struct Problem {
     int avg_R = 0, avg_J = 0;                       // averaged-iterate ring (stop_mode 1)
     std::unique_ptr<DevBuf> avg_ring, avg_S, avg_parts;
     float *x = nullptr;
-    std::unique_ptr<DevBuf> Y, r, xT, xh, xhT, parts, specd;
+    std::unique_ptr<DevBuf> Y, r, xp, xTp, xhp, xhTp, parts, specd;
     SolveState *state = nullptr;
     size_t footprint = 0;
 
@@ -489,9 +521,10 @@ struct Problem {
         d.J = specd->as<float>();
         d.mu = specd->as<float>() + exact::kMaxEnergies;
         d.x = x;
-        d.xT = xT->as<float>();
-        d.xh = xh->as<float>();
-        d.xhT = xhT->as<float>();
+        d.xp = xp->as<float>();
+        d.xTp = xTp->as<float>();
+        d.xhp = xhp->as<float>();
+        d.xhTp = xhTp->as<float>();
         d.r = r->as<float>();
         d.parts = parts->as<double>();
         d.state = state;
@@ -506,8 +539,9 @@ namespace {
 // Device bytes one run allocates (besides the caller's x and y).
 size_t run_footprint(int N, int V, int B)
 {
-    const size_t d = (size_t)N * N, n = (size_t)V * B;
-    return 4 * (2 * n + 4 * d) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
+    const size_t n = (size_t)V * B;
+    const size_t dp = (size_t)N * exact::padded_cols(N), np = (size_t)V * exact::padded_bins(B);
+    return 4 * (n + np + 4 * dp) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
            sizeof(SolveState);
 }
 
@@ -549,11 +583,17 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.state = state;
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
     p.footprint = run_footprint(g->N, g->V, g->B);
+    const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+    const size_t np = (size_t)g->V * exact::padded_bins(g->B);
     p.Y.reset(new DevBuf(n * 4));
-    p.r.reset(new DevBuf(n * 4));
-    p.xT.reset(new DevBuf(d * 4));
-    p.xh.reset(new DevBuf(d * 4));
-    p.xhT.reset(new DevBuf(d * 4));
+    p.r.reset(new DevBuf(np * 4));
+    p.xp.reset(new DevBuf(dp * 4));
+    p.xTp.reset(new DevBuf(dp * 4));
+    p.xhp.reset(new DevBuf(dp * 4));
+    p.xhTp.reset(new DevBuf(dp * 4));
+    // the padding of these buffers must read zero; kernels never write it
+    for (DevBuf *b : {p.r.get(), p.xp.get(), p.xTp.get(), p.xhp.get(), p.xhTp.get()})
+        hip_check(hipMemsetAsync(b->p, 0, (b == p.r.get() ? np : dp) * 4, st), "hipMemsetAsync");
     p.parts.reset(new DevBuf((size_t)exact::num_tiles(g->N) * 2 * 8));
     p.specd.reset(new DevBuf(2 * exact::kMaxEnergies * 4));
     hip_check(hipMemcpyAsync(p.specd->p, p.spec.J, exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
@@ -581,7 +621,8 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
         p.lam = power_iteration(g, o.power_iters, st, nullptr);
         p.gamma = o.gamma_scale / (p.lam * sjm);
     }
-    hip_check(exact::launch_transpose(x_dev, p.xT->as<float>(), g->N, st), "transpose");
+    hip_check(exact::launch_pad_pair(x_dev, p.xp->as<float>(), p.xTp->as<float>(), g->N, st),
+              "pad_pair");
     hip_check(exact::launch_state_init(state, o.tol, o.max_iters, o.stop_mode, st), "state_init");
     if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
         p.avg_J = exact::avg_last_kept(o.max_iters);
@@ -669,17 +710,18 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
     SolveState *S = p.state;
     const int32_t *skip = &S->done;
     float *Y = p.Y->as<float>(), *r = p.r->as<float>();
-    float *xT = p.xT->as<float>(), *xh = p.xh->as<float>(), *xhT = p.xhT->as<float>();
+    float *xp = p.xp->as<float>(), *xTp = p.xTp->as<float>();
+    float *xhp = p.xhp->as<float>(), *xhTp = p.xhTp->as<float>();
     double *parts = p.parts->as<double>();
     hipError_t e = hipSuccess;
     auto cap = [&](hipError_t x) {
         if (e == hipSuccess && x != hipSuccess)
             e = x;
     };
-    cap(exact::launch_forward_residual(G, p.x, xT, Y, p.spec, r, skip, st));
-    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, xh, xhT, parts, skip, st));
-    cap(exact::launch_forward_residual(G, xh, xhT, Y, p.spec, r, skip, st));
-    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xT, nullptr, skip, st));
+    cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, skip, st));
+    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, nullptr, xhp, xhTp, parts, skip, st));
+    cap(exact::launch_forward_residual(G, xhp, xhTp, Y, p.spec, r, skip, st));
+    cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xp, xTp, nullptr, skip, st));
     if (p.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
         const long d = (long)g->N * g->N;
         double *ap = p.avg_parts->as<double>();

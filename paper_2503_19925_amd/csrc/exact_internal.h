@@ -23,20 +23,34 @@ constexpr int kMaxEnergies = 128;
 // order (incremental stepping in the forward, direct evaluation in the
 // back-projector).  Both kernels therefore apply bit-identical weights.
 //
-// The back-projector starts from the bin nearest to a pixel,
-// b0 = rint((j - (A + k Q)) * invP) (the solution of f(b, k) = j to within
-// double rounding), and examines only the bins that can lie within one
-// pixel of it.
+// The back-projector starts from the bin nearest to a pixel (the solution of
+// f(b, k) = j rounded to an integer) and examines only the bins that can lie
+// within one pixel of it.  Ab = A - kPadB P is A in padded-bin coordinates
+// (bin b of a padded sinogram row sits at index b + kPadB); sPhi is -1 when
+// P < 0 and 0 otherwise (a sign mask).
 //
 // The geometry's table lists the row-stepping views first and the
 // column-stepping views after them (Geo::nrow of each); vidx is the view's
 // index v in the sinogram.
-struct alignas(16) ViewGeom {
-    double A, P, Q, invP, absP;
+struct alignas(8) ViewGeom {
+    double A, Ab, P, Q, invP;
     float wstep;
     int32_t vidx;
+    int32_t sPhi;
+    int32_t pad_;
 };
-static_assert(sizeof(ViewGeom) == 48, "ViewGeom layout");
+static_assert(sizeof(ViewGeom) == 56, "ViewGeom layout");
+
+// Padded layouts read by the projectors.  An image row (or a row of the
+// transposed image) holds kPadX zeros, the N pixels, kPadX zeros; a
+// sinogram row holds kPadB zero bins, the B bins, kPadB zero bins.  Taps
+// that fall outside the image or the detector then read zeros at in-bounds
+// addresses, so the inner loops need no range tests.  The padding is zeroed
+// when a buffer is created and never written afterwards.
+constexpr int kPadX = 2;
+constexpr int kPadB = 2;
+__host__ __device__ inline int padded_cols(int N) { return N + 2 * kPadX; }
+__host__ __device__ inline int padded_bins(int B) { return B + 2 * kPadB; }
 
 // Spectrum collapsed over windows, passed to kernels by value.
 struct SpecArg {
@@ -87,11 +101,12 @@ struct BatchProb {
     const float EXACT_GLOBAL *Y;       // window sums of y
     const float EXACT_GLOBAL *J;       // spectrum (device copies)
     const float EXACT_GLOBAL *mu;
-    float EXACT_GLOBAL *x;             // iterate and its transpose
-    float EXACT_GLOBAL *xT;
-    float EXACT_GLOBAL *xh;            // half-step iterate and its transpose
-    float EXACT_GLOBAL *xhT;
-    float EXACT_GLOBAL *r;             // residual
+    float EXACT_GLOBAL *x;             // iterate (the caller's buffer)
+    float EXACT_GLOBAL *xp;            // iterate and its transpose, padded rows
+    float EXACT_GLOBAL *xTp;
+    float EXACT_GLOBAL *xhp;           // half-step iterate and its transpose, padded
+    float EXACT_GLOBAL *xhTp;
+    float EXACT_GLOBAL *r;             // residual, padded rows
     double EXACT_GLOBAL *parts;        // update partials, 2 per 16x16 tile
     SolveState EXACT_GLOBAL *state;
     float gamma, inv_n;
@@ -103,7 +118,7 @@ struct BatchItem {
     int32_t p, a, b, pad;
 };
 
-// Tile side of the transpose and normalisation kernels.
+// Tile side of the padding/transposition and normalisation kernels.
 constexpr int kTile = 32;
 
 // 16 x 16 tiles of an N x N image (the update partials are per tile).
@@ -121,14 +136,18 @@ int fwd_items_per_view(int B);
 int fwd_block_centre_out(int r, int nbb);
 int back_tiles_per_side(int N);
 
-hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st);
+// xp, xTp (padded, padding already zero) <- x and its transpose.
+hipError_t launch_pad_pair(const float *x, float *xp, float *xTp, int N, hipStream_t st);
 hipError_t launch_fill(float *x, float value, long count, hipStream_t st);
-hipError_t launch_forward(const Geo &g, const float *x, const float *xT,
-                          float *s, const int32_t *skip, hipStream_t st);
-hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT,
+// s = A x from the padded pair; s[vidx * s_stride + s_off + b].
+hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float *s,
+                          int s_stride, int s_off, const int32_t *skip, hipStream_t st);
+// r = Y - sum_k J_k exp(-mu_k (A x)_+) into a padded residual.
+hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
                                    const float *Y, const SpecArg &sp, float *r,
                                    const int32_t *skip, hipStream_t st);
-hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
+// img = scale A^T r; r padded (r_padded) or the plain [V][B] layout.
+hipError_t launch_back(const Geo &g, const float *r, bool r_padded, float *img, float scale,
                        const int32_t *skip, hipStream_t st);
 hipError_t launch_window_sum(const float *y, int Wn, long n, float *Y,
                              int32_t *bad, hipStream_t st);
@@ -136,13 +155,14 @@ hipError_t launch_count_bad(const float *x, long count, int32_t *bad,
                             hipStream_t st);
 hipError_t launch_state_init(SolveState *state, double tol, int max_iters, int stop_mode,
                              hipStream_t st);
-// Back-projection fused with the update: g = scale A^T r and
-// z = max(0, x - gamma g) for every pixel, written to z and (transposed) zT.
-// With partials != nullptr also writes per-tile double partial sums of
+// Back-projection fused with the update: g = scale A^T r (r padded) and
+// z = max(0, x - gamma g) for every pixel, written to zp and (transposed)
+// zTp in the padded layout and, when z is not null, to z.  With
+// partials != nullptr also writes per-tile double partial sums of
 // ||z - x||^2 and ||x||^2 (2 per 16x16 tile, num_tiles of them).  z may
 // alias x.
 hipError_t launch_back_update(const Geo &g, const float *r, float scale, const float *x,
-                              float gamma, float *z, float *zT, double *partials,
+                              float gamma, float *z, float *zp, float *zTp, double *partials,
                               const int32_t *skip, hipStream_t st);
 // Fixed-order reduction of the update partials; sets rho_t, advances t and
 // raises done when t reaches max_iters or the run's stop rule holds: rho_t
@@ -177,7 +197,8 @@ hipError_t launch_dot3(const float *v, const float *u, int N, double *partials,
                        hipStream_t st);
 hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *state,
                               hipStream_t st);
-hipError_t launch_normalize(const float *u, float *v, float *vT, int N,
+// v = u / ||u|| (the norm from the state), also into the padded pair.
+hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int N,
                             const SolveState *state, hipStream_t st);
 
 }  // namespace exact

@@ -56,6 +56,32 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThr
         v[q] = lds[q][0];
 }
 
+// 1.5 * 2^52: adding it to a double x with |x| < 2^31 rounds x to the
+// nearest integer (ties to even) and leaves that integer, in two's
+// complement, in the low 32 bits of the sum.
+constexpr double kRoundMagic = 6755399441055744.0;
+
+__device__ __forceinline__ int low_int(double m)
+{
+    return __double2loint(m);
+}
+
+// min(max(v, kLo), hi) for kLo <= hi in one instruction (the compiler
+// forms v_med3_i32 only for constant bounds).
+template <int kLo>
+__device__ __forceinline__ int clamp_int(int v, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "n"(kLo), "v"(hi));
+    return r;
+}
+
+// (float)(1 - |d|) clamped below at 0 (it never exceeds 1).
+__device__ __forceinline__ float tent(double d)
+{
+    return __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
+}
+
 // ---------------------------------------------------------------- forward
 
 #ifndef EXACT_FWD_SEGS
@@ -105,22 +131,23 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
     return *(const float *)((const char *)base + (i << 2));
 }
 
-// The two taps of a ray on one line: crossing f (advanced by Q, exactly),
-// weights of pixels floor(f) and floor(f) + 1 (zero outside the image) and
-// their values, read from `row` at in-bounds indices.
-__device__ __forceinline__ void tap_pair(double &f, double Q, int N, const float *__restrict__ row,
-                                         float &w0, float &w1, float &v0, float &v1)
+// The two taps of a ray on one padded image line: crossing f in padded
+// column coordinates (advanced by Q, exactly), weights (float)(1 - e0) and
+// (float)e0 of columns floor(f) and floor(f) + 1, and their values.  A tap
+// outside the image reads a padding zero; the column is clamped to the
+// padded row so that lines the ray does not reach read zeros too.
+__device__ __forceinline__ void tap_pair(double &f, int N, double Q,
+                                         const float *__restrict__ row, float &w0, float &w1,
+                                         float &v0, float &v1)
 {
     const double fl = floor(f);
     const double e0 = f - fl;                 // exact, in [0, 1)
     f += Q;                                   // exact
-    const int j0 = (int)fl;                   // |f| < 2^20 by construction
-    const bool in0 = (unsigned)j0 < (unsigned)N;
-    const bool in1 = (unsigned)(j0 + 1) < (unsigned)N;
-    w0 = in0 ? (float)(1.0 - e0) : 0.f;       // pixel j0
-    w1 = in1 ? (float)e0 : 0.f;               // pixel j0 + 1: 1 - |f - (j0+1)| = e0 exactly
-    v0 = at(row, in0 ? (unsigned)j0 : 0u);
-    v1 = at(row, in1 ? (unsigned)(j0 + 1) : 0u);
+    const int c = clamp_int<0>((int)fl, N + 2 * kPadX - 2);
+    w0 = (float)(1.0 - e0);                   // pixel floor(f)
+    w1 = (float)e0;                           // pixel floor(f) + 1: 1 - |f - (j0+1)| = e0
+    v0 = at(row, (unsigned)c);
+    v1 = at(row + 1, (unsigned)c);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -154,21 +181,24 @@ struct SpecPtr {
 };
 
 // Forward projection of rays [64 bblock, 64 bblock + 64) of table view
-// `slot` by one workgroup of kFwdThreads * kSegs threads; with kResid the
-// spectral residual replaces the line integral in `out`.
+// `slot` by one workgroup of kFwdThreads * kSegs threads, reading the padded
+// image pair; with kResid the spectral residual replaces the line integral.
+// Ray i = vidx B + b goes to out[vidx * ostride + ooff + b].
 template <bool kResid, class Spec>
 __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views, int N, int B,
-                                              int nrow, const float *__restrict__ x,
-                                              const float *__restrict__ xT,
+                                              int nrow, const float *__restrict__ xp,
+                                              const float *__restrict__ xTp,
                                               const float *__restrict__ Y, const Spec &sp,
-                                              float *__restrict__ out, int slot, int bblock)
+                                              float *__restrict__ out, int ostride, int ooff,
+                                              int slot, int bblock)
 {
     __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
     const int lane = threadIdx.x % kFwdThreads;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);  // wave-uniform
     const int b = bblock * kFwdThreads + lane;
     const ViewGeom G = views[slot];
-    const float *__restrict__ img = slot < nrow ? x : xT;
+    const float *__restrict__ img = slot < nrow ? xp : xTp;
+    const int Np = padded_cols(N);
     const double base = fma((double)b, G.P, G.A);
 
     int k0, k1;
@@ -182,13 +212,13 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     const int kw1 = min(wave_max(k1), min(N, (seg + 1) * per) - 1);
 
     Kahan acc;
-    double f = fma((double)kw0, G.Q, base);
+    double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
     int k = kw0;
     for (; k + kLineBatch - 1 <= kw1; k += kLineBatch) {
         float w0[kLineBatch], w1[kLineBatch], v0[kLineBatch], v1[kLineBatch];
 #pragma unroll
         for (int q = 0; q < kLineBatch; ++q)
-            tap_pair(f, G.Q, N, img + (size_t)(k + q) * N, w0[q], w1[q], v0[q], v1[q]);
+            tap_pair(f, N, G.Q, img + (size_t)(k + q) * Np, w0[q], w1[q], v0[q], v1[q]);
         float t = 0.f;
 #pragma unroll
         for (int q = 0; q < kLineBatch; ++q)
@@ -197,7 +227,7 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     }
     for (; k <= kw1; ++k) {
         float w0, w1, v0, v1;
-        tap_pair(f, G.Q, N, img + (size_t)k * N, w0, w1, v0, v1);
+        tap_pair(f, N, G.Q, img + (size_t)k * Np, w0, w1, v0, v1);
         acc.add(fmaf(w1, v1, w0 * v0));
     }
     part_s[seg][lane] = acc.s;
@@ -212,16 +242,16 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         tot.add(-part_c[q][lane]);
     }
     const float s = tot.value() * G.wstep;
-    const size_t i = (size_t)G.vidx * B + b;
+    const size_t o = (size_t)G.vidx * ostride + ooff + b;
     if (kResid) {
         // r_i = Y_i - sum_k J_k exp(-mu_k max(s_i, 0))
         const float sp0 = fmaxf(s, 0.f);
         float m = 0.f;
         for (int q = 0; q < sp.K; ++q)
             m = fmaf(sp.J[q], expf(-sp.mu[q] * sp0), m);
-        out[i] = Y[i] - m;
+        out[o] = Y[(size_t)G.vidx * B + b] - m;
     } else {
-        out[i] = s;
+        out[o] = s;
     }
 }
 
@@ -230,13 +260,13 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
 template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow,
-    const float *__restrict__ x, const float *__restrict__ xT, const float *__restrict__ Y,
-    SpecArg sp, float *__restrict__ out, const int32_t *__restrict__ skip)
+    const float *__restrict__ xp, const float *__restrict__ xTp, const float *__restrict__ Y,
+    SpecArg sp, float *__restrict__ out, int ostride, int ooff, const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
-    forward_block<kResid>(views, N, B, nrow, x, xT, Y, sp, out, blockIdx.x % V,
+    forward_block<kResid>(views, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff, blockIdx.x % V,
                           centre_out(blockIdx.x / V, nbb));
 }
 
@@ -277,104 +307,120 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 
 // ------------------------------------------------------------------- back
 
-// Contribution of view G to pixel (k, j) of its stepping line (without the
-// path-length factor): sum over bins b within one pixel of
-// (float)(1 - |f(b, k) - j|) * r[b].  Two-candidate rule (all |P| >= 1): the
-// nearest bin b0 has |d0| <= (1/2 + tiny)|P| with d0 = f(b0, k) - j; moving
-// away from the pixel adds |P| >= 1 to |d|, moving two bins towards it
-// leaves |d| >= (3/2 - tiny)|P| >= 1, so only b0 and its neighbour on the
-// pixel's side can have positive weight.
+// Taps of view G for pixel (line k, pixel j of that line), the path-length
+// factor left out: sum over bins b within one pixel of
+// (float)(1 - |f(b, k) - j|) * r[b].
+//
 // Two-candidate rule (every |P| >= 1): the nearest bin b0 has
 // |d0| <= (1/2 + tiny)|P| with d0 = f(b0, k) - j; moving away from the pixel
-// adds |P| >= 1 to |d|, and two bins towards it leaves |d| >= (3/2 - tiny)|P|
-// >= 1, so only b0 and its neighbour on the pixel's side, b1, can have
-// positive weight.  Returns w0 r[b0] + w1 r[b1] for pixel j on line k (the
-// path-length factor left out); out-of-range bins get weight 0 and an
-// in-bounds address.
+// adds |P| >= 1 to |d|, and two bins towards it leave |d| >= (3/2 - tiny)|P|
+// >= 1, so only b0 and its neighbour on the pixel's side, b1 = b0 + delta,
+// can have positive weight (delta = -1 when d0 and P have the same sign,
+// +1 otherwise; either neighbour has weight 0 when d0 = 0).  b0 comes from
+// one rounding fma (kRoundMagic); d0 and d1 are exact.
+//
+// kPad: rv is a padded residual row (bin b at index b + kPadB); b0 is
+// clamped to [-1, B] so both taps index the row, and bins off the detector
+// read padding zeros.  Otherwise rv is a plain row and out-of-range taps get
+// weight 0 and an in-bounds address.
+template <bool kPad>
 __device__ __forceinline__ float taps_two(const ViewGeom &G, double kd, double jd, int B,
                                           const float *__restrict__ rv)
 {
-    const double Kv = fma(kd, G.Q, G.A);                           // exact
-    const double b0d = rint((jd - Kv) * G.invP);                   // |b0 P| < 2^20
-    const int b0 = (int)b0d;
-    const double d0 = fma(b0d, G.P, Kv) - jd;                      // exact
-    const double d1 = d0 - copysign(G.absP, d0);                   // exact: towards the pixel
-    const int b1 = b0 + (((d0 > 0.0) == (G.P > 0.0)) ? -1 : 1);
-    const float u0 = (float)(1.0 - fabs(d0));
-    const float u1 = (float)(1.0 - fabs(d1));
-    const bool ok0 = u0 > 0.f && (unsigned)b0 < (unsigned)B;
-    const bool ok1 = u1 > 0.f && (unsigned)b1 < (unsigned)B;
-    const float r0 = at(rv, ok0 ? (unsigned)b0 : 0u);
-    const float r1 = at(rv, ok1 ? (unsigned)b1 : 0u);
-    return fmaf(ok1 ? u1 : 0.f, r1, (ok0 ? u0 : 0.f) * r0);
+    const double T = fma(kd, G.Q, (kPad ? G.Ab : G.A) - jd);        // f(0, k) - j, exact
+    const double m = fma(-T, G.invP, kRoundMagic);                  // rint((j - f(0,k)) / P)
+    const int b0 = clamp_int<kPad ? 1 : -1>(low_int(m), kPad ? B + 2 : B);
+    const double d0 = fma((double)b0, G.P, T);                      // exact
+    // sign bit of `agree` set iff d0 and P have the same sign
+    const int agree = ~(__double2hiint(d0) ^ G.sPhi);
+    const int delta = ((agree >> 31) * 2) | 1;                      // -1 or +1
+    const int b1 = b0 + delta;
+    const double d1 = fma((double)delta, G.P, d0);                  // exact
+    float u0 = tent(d0), u1 = tent(d1);
+    unsigned i0 = (unsigned)b0, i1 = (unsigned)b1;
+    if (!kPad) {
+        const bool ok0 = i0 < (unsigned)B, ok1 = i1 < (unsigned)B;
+        u0 = ok0 ? u0 : 0.f;
+        u1 = ok1 ? u1 : 0.f;
+        i0 = ok0 ? i0 : 0u;
+        i1 = ok1 ? i1 : 0u;
+    }
+    return fmaf(u1, at(rv, i1), u0 * at(rv, i0));
 }
 
 // General rule (bins narrower than pixels): every bin within `reach` of b0.
+// Works in true bin numbers with explicit range tests (the padding is too
+// narrow for the reach); rv points at bin 0 of the row.
 __device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double jd, int B,
                                             int reach, const float *__restrict__ rv)
 {
-    const double Kv = fma(kd, G.Q, G.A);                           // exact
-    const double b0d = fmin(fmax(rint((jd - Kv) * G.invP), -2.0 - reach),
-                            (double)(B + 1 + reach));
-    const int b0 = (int)b0d;
-    const double d0 = fma(b0d, G.P, Kv) - jd;                      // exact
+    const double T = fma(kd, G.Q, G.A) - jd;                        // exact
+    const double m = fma(-T, G.invP, kRoundMagic);
+    const int b0 = min(max(low_int(m), -2 - reach), B + 1 + reach);
+    const double d0 = fma((double)b0, G.P, T);                      // exact
     float s = 0.f;
-    for (int m = -reach; m <= reach; ++m) {
-        const int bb = b0 + m;
-        const float u = (float)(1.0 - fabs(fma((double)m, G.P, d0)));   // exact distance
+    for (int q = -reach; q <= reach; ++q) {
+        const int bb = b0 + q;
+        const float u = (float)(1.0 - fabs(fma((double)q, G.P, d0)));   // exact distance
         const bool ok = u > 0.f && (unsigned)bb < (unsigned)B;
-        s = fmaf(ok ? u : 0.f, rv[ok ? (unsigned)bb : 0u], s);
+        s = fmaf(ok ? u : 0.f, rv[ok ? bb : 0], s);
     }
     return s;
 }
 
 // Sum over views [v0, v1) of wstep * taps for pixel (kd, jd) of each view's
-// stepping line.  Batches of views: parameters and loads first, then a
-// float sum of the batch, then one Kahan step.
-template <bool kTwo>
+// stepping line; r has rows of rstride floats (padded or plain).  Batches
+// of views: parameters and loads first, then a float sum of the batch
+// (wstep applied by fma), then one Kahan step.
+template <bool kTwo, bool kPad>
 __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views, int v0, int v1,
                                              double kd, double jd, int B, int reach,
-                                             const float *__restrict__ r, Kahan &acc)
+                                             const float *__restrict__ r, int rstride,
+                                             Kahan &acc)
 {
+    const int roff = kPad ? kPadB : 0;
     int v = v0;
     for (; v + kViewBatch <= v1; v += kViewBatch) {
-        float t[kViewBatch];
+        float t[kViewBatch], w[kViewBatch];
 #pragma unroll
         for (int q = 0; q < kViewBatch; ++q) {
             const ViewGeom G = views[v + q];
-            const float *rv = r + (size_t)G.vidx * B;
-            t[q] = (kTwo ? taps_two(G, kd, jd, B, rv) : taps_reach(G, kd, jd, B, reach, rv)) *
-                   G.wstep;
+            const float *rv = r + (size_t)G.vidx * rstride;
+            t[q] = kTwo ? taps_two<kPad>(G, kd, jd, B, rv)
+                        : taps_reach(G, kd, jd, B, reach, rv + roff);
+            w[q] = G.wstep;
         }
         float sb = 0.f;
 #pragma unroll
         for (int q = 0; q < kViewBatch; ++q)
-            sb += t[q];
+            sb = fmaf(w[q], t[q], sb);
         acc.add(sb);
     }
     for (; v < v1; ++v) {
         const ViewGeom G = views[v];
-        const float *rv = r + (size_t)G.vidx * B;
-        acc.add((kTwo ? taps_two(G, kd, jd, B, rv) : taps_reach(G, kd, jd, B, reach, rv)) *
+        const float *rv = r + (size_t)G.vidx * rstride;
+        acc.add((kTwo ? taps_two<kPad>(G, kd, jd, B, rv)
+                      : taps_reach(G, kd, jd, B, reach, rv + roff)) *
                 G.wstep);
     }
 }
 
 // (A^T r) at pixel (ix, iy): the row-stepping views (line k = iy, pixel
 // j = ix) then the column-stepping views (k = ix, j = iy), Kahan-compensated.
-template <bool kTwo>
+template <bool kTwo, bool kPad>
 __device__ __forceinline__ float back_pixel(const ViewGeom *__restrict__ views, int V, int B,
                                             int nrow, int reach, const float *__restrict__ r,
                                             int ix, int iy)
 {
     const double dx = (double)ix, dy = (double)iy;
+    const int rstride = kPad ? padded_bins(B) : B;
     Kahan acc;
-    gather_views<kTwo>(views, 0, nrow, dy, dx, B, reach, r, acc);
-    gather_views<kTwo>(views, nrow, V, dx, dy, B, reach, r, acc);
+    gather_views<kTwo, kPad>(views, 0, nrow, dy, dx, B, reach, r, rstride, acc);
+    gather_views<kTwo, kPad>(views, nrow, V, dx, dy, B, reach, r, rstride, acc);
     return acc.value();
 }
 
-template <bool kTwo>
+template <bool kTwo, bool kPad>
 __global__ __launch_bounds__(kBackX *kBackY) void k_back(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float *__restrict__ img, float scale,
@@ -386,23 +432,27 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     if (ix >= N || iy >= N)
         return;
-    img[(size_t)iy * N + ix] = back_pixel<kTwo>(views, V, B, nrow, reach, r, ix, iy) * scale;
+    img[(size_t)iy * N + ix] =
+        back_pixel<kTwo, kPad>(views, V, B, nrow, reach, r, ix, iy) * scale;
 }
 
 // The projected update on one 16 x 16 tile once g = scale (A^T r) is known
 // for the lane's pixel (paper Sec. 1.2, eq. extragrad-method, with the
-// orthant projection of Sec. 3.1): z = max(0, x_p - gamma g); z and, through
-// an LDS tile, its transpose are written; with kPartials the tile's double
-// sums of (z - x)^2 and x^2 go to part2[0..1].  z may alias x (each lane
-// reads and writes only its own pixel of x).  Every lane of the block calls
-// this (it holds barriers); lanes outside the image pass inside = false.
+// orthant projection of Sec. 3.1): z = max(0, x_p - gamma g), written to
+// the padded pair (zp and, through an LDS tile, zTp) and, when z is not
+// null, to z; with kPartials the tile's double sums of (z - x)^2 and x^2 go
+// to part2[0..1].  z may alias x (each lane reads and writes only its own
+// pixel of x).  Every lane of the block calls this (it holds barriers);
+// lanes outside the image pass inside = false.
 template <bool kPartials>
 __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, const float *x,
-                                                float gamma, float *z, float *__restrict__ zT,
+                                                float gamma, float *z, float *__restrict__ zp,
+                                                float *__restrict__ zTp,
                                                 double *__restrict__ part2, int tx, int ty)
 {
     __shared__ float tile[kBackY][kBackX + 1];
     __shared__ double red[2][kRedThreads];
+    const int Np = padded_cols(N);
     const int ix = tx * kBackX + threadIdx.x;
     const int iy = ty * kBackY + threadIdx.y;
     double num = 0.0, den = 0.0;
@@ -410,7 +460,9 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
         const size_t p = (size_t)iy * N + ix;
         const float xv = x[p];
         const float zv = fmaxf(0.f, fmaf(-gamma, g, xv));
-        z[p] = zv;
+        if (z)
+            z[p] = zv;
+        zp[(size_t)iy * Np + kPadX + ix] = zv;
         tile[threadIdx.y][threadIdx.x] = zv;
         if (kPartials) {
             const double dz = (double)zv - (double)xv;
@@ -421,7 +473,7 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
     __syncthreads();
     const int ixT = tx * kBackX + threadIdx.y, iyT = ty * kBackY + threadIdx.x;
     if (ixT < N && iyT < N)
-        zT[(size_t)ixT * N + iyT] = tile[threadIdx.x][threadIdx.y];
+        zTp[(size_t)ixT * Np + kPadX + iyT] = tile[threadIdx.x][threadIdx.y];
     if (kPartials) {
         double v2[2] = {num, den};
         block_sum<2>(v2, red);
@@ -433,12 +485,13 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
 }
 
 // Back-projection fused with the update: each lane gathers its pixel's
-// gradient, then the tile runs the update epilogue.
+// gradient from the padded residual, then the tile runs the update epilogue.
 template <bool kTwo, bool kPartials>
 __global__ __launch_bounds__(kBackX *kBackY) void k_back_update(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float scale, const float *x, float gamma, float *z,
-    float *__restrict__ zT, double *__restrict__ partials, const int32_t *__restrict__ skip)
+    float *__restrict__ zp, float *__restrict__ zTp, double *__restrict__ partials,
+    const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
@@ -447,29 +500,36 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back_update(
     const bool inside = ix < N && iy < N;
     float g = 0.f;
     if (inside)
-        g = back_pixel<kTwo>(views, V, B, nrow, reach, r, ix, iy) * scale;
+        g = back_pixel<kTwo, true>(views, V, B, nrow, reach, r, ix, iy) * scale;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    update_epilogue<kPartials>(inside, g, N, x, gamma, z, zT,
+    update_epilogue<kPartials>(inside, g, N, x, gamma, z, zp, zTp,
                                kPartials ? partials + 2 * blk : nullptr, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------ elementwise / tiles
 
-__global__ __launch_bounds__(kTile * 8) void k_transpose(const float *__restrict__ x,
-                                                         float *__restrict__ xT, int N)
+// x into the padded pair: row-major copy xp and transpose xTp (interiors;
+// the padding is zero already), the transpose through an LDS tile.
+__global__ __launch_bounds__(kTile * 8) void k_pad_pair(const float *__restrict__ x,
+                                                        float *__restrict__ xp,
+                                                        float *__restrict__ xTp, int N)
 {
     __shared__ float tile[kTile][kTile + 1];
+    const int Np = padded_cols(N);
     const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int iy = by + rr, ix = bx + threadIdx.x;
-        if (iy < N && ix < N)
-            tile[rr][threadIdx.x] = x[(size_t)iy * N + ix];
+        if (iy < N && ix < N) {
+            const float v = x[(size_t)iy * N + ix];
+            xp[(size_t)iy * Np + kPadX + ix] = v;
+            tile[rr][threadIdx.x] = v;
+        }
     }
     __syncthreads();
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int ixT = bx + rr, iyT = by + threadIdx.x;
         if (ixT < N && iyT < N)
-            xT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
+            xTp[(size_t)ixT * Np + kPadX + iyT] = tile[threadIdx.x][rr];
     }
 }
 
@@ -657,8 +717,9 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
     if (glob(P.state)->done)
         return;
     const SpecPtr sp{P.K, glob(P.J), glob(P.mu)};
-    forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xh : P.x),
-                        glob(kAtHalf ? P.xhT : P.xT), glob(P.Y), sp, glob(P.r), it.a, it.b);
+    forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xhp : P.xp),
+                        glob(kAtHalf ? P.xhTp : P.xTp), glob(P.Y), sp, glob(P.r),
+                        padded_bins(P.B), kPadB, it.a, it.b);
 }
 
 template <bool kHalf>
@@ -677,15 +738,17 @@ __global__ __launch_bounds__(kBackX *kBackY) void kb_back_update(
     float g = 0.f;
     if (inside) {
         if (P.reach == 0)
-            g = back_pixel<true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy);
+            g = back_pixel<true, true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy);
         else
-            g = back_pixel<false>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix, iy);
+            g = back_pixel<false, true>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
+                                        iy);
         g *= P.inv_n;
     }
     const int ntx = (P.N + kBackX - 1) / kBackX;
     double *part2 = kHalf ? glob(P.parts) + 2 * (it.b * ntx + it.a) : nullptr;
-    update_epilogue<kHalf>(inside, g, P.N, glob(P.x), P.gamma, glob(kHalf ? P.xh : P.x),
-                           glob(kHalf ? P.xhT : P.xT), part2, it.a, it.b);
+    update_epilogue<kHalf>(inside, g, P.N, glob(P.x), P.gamma, kHalf ? nullptr : glob(P.x),
+                           glob(kHalf ? P.xhp : P.xp), glob(kHalf ? P.xhTp : P.xTp), part2, it.a,
+                           it.b);
 }
 
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
@@ -734,19 +797,21 @@ __global__ __launch_bounds__(kRedThreads) void k_dot3_finish(const double *__res
 
 __global__ __launch_bounds__(kTile * 8) void k_normalize(const float *__restrict__ u,
                                                          float *__restrict__ v,
-                                                         float *__restrict__ vT, int N,
+                                                         float *__restrict__ vp,
+                                                         float *__restrict__ vTp, int N,
                                                          const SolveState *__restrict__ st)
 {
     __shared__ float tile[kTile][kTile + 1];
     const double nrm = st->unorm;
     const float inv = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
+    const int Np = padded_cols(N);
     const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int iy = by + rr, ix = bx + threadIdx.x;
         if (iy < N && ix < N) {
-            const size_t p = (size_t)iy * N + ix;
-            const float zv = u[p] * inv;
-            v[p] = zv;
+            const float zv = u[(size_t)iy * N + ix] * inv;
+            v[(size_t)iy * N + ix] = zv;
+            vp[(size_t)iy * Np + kPadX + ix] = zv;
             tile[rr][threadIdx.x] = zv;
         }
     }
@@ -754,7 +819,7 @@ __global__ __launch_bounds__(kTile * 8) void k_normalize(const float *__restrict
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int ixT = bx + rr, iyT = by + threadIdx.x;
         if (ixT < N && iyT < N)
-            vT[(size_t)ixT * N + iyT] = tile[threadIdx.x][rr];
+            vTp[(size_t)ixT * Np + kPadX + iyT] = tile[threadIdx.x][rr];
     }
 }
 
@@ -789,9 +854,9 @@ hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float *x, float *xT, int N, hipStream_t st)
+hipError_t launch_pad_pair(const float *x, float *xp, float *xTp, int N, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_transpose, tile_grid(N), dim3(kTile, 8), 0, st, x, xT, N);
+    hipLaunchKernelGGL(k_pad_pair, tile_grid(N), dim3(kTile, 8), 0, st, x, xp, xTp, N);
     return hipGetLastError();
 }
 
@@ -806,37 +871,47 @@ hipError_t launch_fill(float *x, float value, long count, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const Geo &g, const float *x, const float *xT, float *s,
-                          const int32_t *skip, hipStream_t st)
+hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float *s,
+                          int s_stride, int s_off, const int32_t *skip, hipStream_t st)
 {
     SpecArg none;
     none.K = 0;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, x, xT, nullptr, none, s, skip);
+                       g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_forward_residual(const Geo &g, const float *x, const float *xT,
+hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
                                    const float *Y, const SpecArg &sp, float *r,
                                    const int32_t *skip, hipStream_t st)
 {
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, x, xT, Y, sp, r, skip);
+                       g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_back(const Geo &g, const float *r, float *img, float scale,
+hipError_t launch_back(const Geo &g, const float *r, bool r_padded, float *img, float scale,
                        const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
-    if (g.reach == 0)
-        hipLaunchKernelGGL(k_back<true>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
-                           g.B, g.nrow, 0, r, img, scale, skip);
-    else
-        hipLaunchKernelGGL(k_back<false>, grid, dim3(kBackX, kBackY), 0, st, g.views, g.N, g.V,
-                           g.B, g.nrow, g.reach, r, img, scale, skip);
+    dim3 blk(kBackX, kBackY);
+    if (g.reach == 0) {
+        if (r_padded)
+            hipLaunchKernelGGL((k_back<true, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                               g.nrow, 0, r, img, scale, skip);
+        else
+            hipLaunchKernelGGL((k_back<true, false>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                               g.nrow, 0, r, img, scale, skip);
+    } else {
+        if (r_padded)
+            hipLaunchKernelGGL((k_back<false, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                               g.nrow, g.reach, r, img, scale, skip);
+        else
+            hipLaunchKernelGGL((k_back<false, false>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                               g.nrow, g.reach, r, img, scale, skip);
+    }
     return hipGetLastError();
 }
 
@@ -901,7 +976,7 @@ hipError_t launch_avg_output(const double *S, float *x, long d, const SolveState
 }
 
 hipError_t launch_back_update(const Geo &g, const float *r, float scale, const float *x,
-                              float gamma, float *z, float *zT, double *partials,
+                              float gamma, float *z, float *zp, float *zTp, double *partials,
                               const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
@@ -909,18 +984,19 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
     if (g.reach == 0) {
         if (partials)
             hipLaunchKernelGGL((k_back_update<true, true>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, 0, r, scale, x, gamma, z, zT, partials, skip);
+                               g.B, g.nrow, 0, r, scale, x, gamma, z, zp, zTp, partials, skip);
         else
             hipLaunchKernelGGL((k_back_update<true, false>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, 0, r, scale, x, gamma, z, zT, partials, skip);
+                               g.B, g.nrow, 0, r, scale, x, gamma, z, zp, zTp, partials, skip);
     } else {
         if (partials)
             hipLaunchKernelGGL((k_back_update<false, true>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, g.reach, r, scale, x, gamma, z, zT, partials, skip);
+                               g.B, g.nrow, g.reach, r, scale, x, gamma, z, zp, zTp, partials,
+                               skip);
         else
             hipLaunchKernelGGL((k_back_update<false, false>), grid, blk, 0, st, g.views, g.N,
-                               g.V, g.B, g.nrow, g.reach, r, scale, x, gamma, z, zT, partials,
-                               skip);
+                               g.V, g.B, g.nrow, g.reach, r, scale, x, gamma, z, zp, zTp,
+                               partials, skip);
     }
     return hipGetLastError();
 }
@@ -965,10 +1041,10 @@ hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *st
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(const float *u, float *v, float *vT, int N, const SolveState *state,
-                            hipStream_t st)
+hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int N,
+                            const SolveState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_normalize, tile_grid(N), dim3(kTile, 8), 0, st, u, v, vT, N, state);
+    hipLaunchKernelGGL(k_normalize, tile_grid(N), dim3(kTile, 8), 0, st, u, v, vp, vTp, N, state);
     return hipGetLastError();
 }
 
