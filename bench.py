@@ -11,8 +11,10 @@ residual reduction and stop test), replayed from a captured HIP graph with
 all state resident in HBM.
 
 Prints one JSON line: EG iterations/s (value), projector rays/s, the
-back-projector's algorithmic-bytes roofline fraction (HIP events), and the
-CPU oracle timed on a bounded sample of the same workload.  Two more legs
+roofline fraction of the step's dominant kernel (back-projection fused with
+the update) on algorithmic bytes, from HIP events around each kernel of a
+few further steps launched one kernel at a time, and the CPU oracle timed on
+a bounded sample of the same workload.  Two more legs
 report reconstructions/s and time-to-tolerance percentiles:
 
 * batched: 64 uneven scans (N in {128..768}, 30-360 views, 10-64 energy
@@ -185,7 +187,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--proj-reps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--profile-steps", type=int, default=50,
+                    help="extra steps launched kernel by kernel for per-phase times")
+    ap.add_argument("--cpu-steps", type=int, default=8,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
     ap.add_argument("--served", type=int, default=40,
@@ -223,7 +227,8 @@ def main():
     x = torch.zeros(g.d, device=dev)
 
     # set-up (untimed): step size by power iteration, resident state, graph
-    solver = exact.Solver(g, P.mu, P.I, y, x, max_iters=args.warmup + args.steps, tol=0.0)
+    solver = exact.Solver(g, P.mu, P.I, y, x,
+                          max_iters=args.warmup + args.steps + args.profile_steps, tol=0.0)
     solver.step(args.warmup)
     torch.cuda.synchronize()
     _, info_w = solver.poll()
@@ -243,11 +248,18 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
     done, info = solver.poll()
-    solver.close()
     if info["iters"] != args.warmup + args.steps:
         raise RuntimeError("solver ran %d steps, expected %d" % (info["iters"], args.warmup + args.steps))
     log("timed %d steps: %.4f ms/step (events), %.4f ms/step (wall)" % (
         args.steps, ms_step, 1e3 * wall / args.steps))
+    # the same step kernel by kernel, HIP events around each phase on the
+    # solver's stream: per-kernel durations for the roofline
+    phase_ms = solver.profile(args.profile_steps)
+    _, info_p = solver.poll()
+    solver.close()
+    if info_p["iters"] != args.warmup + args.steps + args.profile_steps:
+        raise RuntimeError("profiled steps did not run")
+    log("per-phase ms: " + ", ".join("%s %.4f" % (n, t) for n, t in zip(exact.PHASE_NAMES, phase_ms)))
 
     # projector throughput and the back-projector's roofline
     nnz = exact.exact_count_nonzeros(g)
@@ -257,9 +269,16 @@ def main():
     xb = torch.rand(g.d, device=dev)
     t_back = event_time_ms(lambda: exact.exact_backproject(g, r, img), args.proj_reps, torch)
     t_fwd = event_time_ms(lambda: exact.exact_forward(g, xb, s), args.proj_reps, torch)
-    bytes_back = 4.0 * nnz + 4.0 * g.n + 4.0 * g.d
-    achieved = bytes_back / (t_back * 1e-3) / 1e9
-    log("nnz %d; back %.4f ms, forward(+transpose) %.4f ms" % (nnz, t_back, t_fwd))
+    log("nnz %d; exact_backproject %.4f ms, exact_forward (with padding copy) %.4f ms" % (
+        nnz, t_back, t_fwd))
+    # algorithmic bytes (4 B per nonzero of A plus compulsory I/O) of the
+    # step's back-projection + update kernel: r gathered per nonzero, r read
+    # once, x read, z written to the padded pair (and to x in the full step)
+    bytes_bu = [4.0 * nnz + 4.0 * g.n + 12.0 * g.d, 4.0 * nnz + 4.0 * g.n + 16.0 * g.d]
+    t_bu = [phase_ms[1], phase_ms[3]]
+    achieved = sum(bytes_bu) / (sum(t_bu) * 1e-3) / 1e9
+    bytes_fwd = 4.0 * nnz + 8.0 * g.d + 8.0 * g.n        # x operands, Y in, r out
+    fwd_achieved = 2 * bytes_fwd / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9
 
     to_tol = None
     if args.to_tol > 0:
@@ -302,9 +321,16 @@ def main():
         "forward_ms": t_fwd,
         "back_ms": t_back,
         "nnz": nnz,
-        "roofline": {"kernel": "k_back", "bound": "hbm", "achieved": achieved,
+        "step_phase_ms": dict(zip(exact.PHASE_NAMES, phase_ms)),
+        "step_forward_grays": 2 * g.n / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9,
+        "step_back_grays": 2 * g.n / (sum(t_bu) * 1e-3) / 1e9,
+        "roofline": {"kernel": "k_back_update", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, "k_back")},
+                     "traffic": measured_traffic(args.workload, "k_back_update"),
+                     "bytes_per_launch": sum(bytes_bu) / 2, "ms_per_launch": sum(t_bu) / 2},
+        "roofline_forward": {"kernel": "k_forward<true>", "bound": "hbm",
+                             "achieved": fwd_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": fwd_achieved / HBM_PEAK_GBS},
         "to_tol": to_tol,
         "cpu_baseline": base,
         "batched": batched,

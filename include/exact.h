@@ -209,8 +209,24 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
  * and returns 1 once the run has stopped, 0 while it is still running.
  *
  * exact_solver_destroy waits for the run's work and frees its state.
+ *
+ * exact_solver_profile (for measurement) runs n_steps (1..4096) further
+ * steps launched one kernel at a time instead of through the captured
+ * graph, with HIP events recorded on the solver's stream around each of the
+ * step's EXACT_STEP_PHASES kernels, and writes the average milliseconds of
+ * each phase to phase_ms[EXACT_STEP_PHASES]:
+ *   [0] forward projection + spectral residual at x_t,
+ *   [1] back-projection + half-step update and residual partials,
+ *   [2] forward projection + spectral residual at x_{t+1/2},
+ *   [3] back-projection + full-step update,
+ *   [4] reduction of rho_t and the stop test.
+ * The steps advance the run exactly as exact_solver_step's would (after the
+ * stop they are no-ops and time as such).  Ordered on `stream` like
+ * exact_solver_step; blocks until the steps are done.
  */
 typedef struct exact_solver_s *exact_solver;
+
+#define EXACT_STEP_PHASES 5
 
 int exact_solver_create(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
                         float *x_dev, const exact_solve_opts *opts, exact_solver *out,
@@ -218,6 +234,7 @@ int exact_solver_create(exact_geometry g, const exact_spectrum *sp, const float 
 int exact_solver_step(exact_solver s, int32_t n_steps, void *stream);
 int exact_solver_poll(exact_solver s, exact_solve_info *info);
 int exact_solver_destroy(exact_solver s);
+int exact_solver_profile(exact_solver s, int32_t n_steps, double *phase_ms, void *stream);
 
 /*
  * Exact number of positive entries of A (the tent weights that round to a

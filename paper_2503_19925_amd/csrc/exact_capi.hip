@@ -699,7 +699,7 @@ struct Graph {
 // Enqueue order of one extragradient step (paper Sec. 1.2, eq.
 // extragrad-method): F at x_t, half-step from x_t, F at x_{t+1/2}, full step
 // again from x_t, then the fixed-order residual reduction and stop test.
-hipError_t enqueue_step(const Problem &p, hipStream_t st)
+hipError_t enqueue_step(const Problem &p, hipStream_t st, hipEvent_t *marks = nullptr)
 {
     const exact_geometry_s *g = p.g;
     const Geo G = geo_of(g);
@@ -718,10 +718,21 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
         if (e == hipSuccess && x != hipSuccess)
             e = x;
     };
+    int phase = 0;
+    auto mark = [&]() {           // event before phase `phase` (and after the last)
+        if (marks)
+            cap(hipEventRecord(marks[phase], st));
+        ++phase;
+    };
+    mark();
     cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, skip, st));
+    mark();
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, nullptr, xhp, xhTp, parts, skip, st));
+    mark();
     cap(exact::launch_forward_residual(G, xhp, xhTp, Y, p.spec, r, skip, st));
+    mark();
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xp, xTp, nullptr, skip, st));
+    mark();
     if (p.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
         const long d = (long)g->N * g->N;
         double *ap = p.avg_parts->as<double>();
@@ -731,6 +742,7 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st)
     } else {
         cap(exact::launch_eg_finish(parts, ntiles, nullptr, 0, S, st));
     }
+    mark();
     return e;
 }
 
@@ -893,6 +905,59 @@ int exact_solver_create(exact_geometry g, const exact_spectrum *sp, const float 
         if (o.stop_mode == EXACT_STOP_AVERAGED_ITERATE)
             fail(-EINVAL, "the averaged-iterate stop rule is available in exact_solve only");
         *out = solver_build(g, sp, y_dev, x_dev, o, (hipStream_t)stream);
+        return 0;
+    });
+}
+
+int exact_solver_profile(exact_solver s, int32_t n_steps, double *phase_ms, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!s)
+            fail(-EINVAL, "solver is NULL");
+        if (!phase_ms)
+            fail(-EINVAL, "phase_ms is NULL");
+        if (n_steps < 1 || n_steps > 4096)
+            fail(-EINVAL, "n_steps must be in [1, 4096]");
+        constexpr int kMarks = EXACT_STEP_PHASES + 1;
+        std::vector<hipEvent_t> ev((size_t)n_steps * kMarks, nullptr);
+        struct Events {
+            std::vector<hipEvent_t> &v;
+            ~Events()
+            {
+                for (hipEvent_t e : v)
+                    if (e)
+                        (void)hipEventDestroy(e);
+            }
+        } guard{ev};
+        for (hipEvent_t &e : ev)
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+        hipStream_t own = s->own->st, user = (hipStream_t)stream;
+        hipEvent_t order;
+        hip_check(hipEventCreateWithFlags(&order, hipEventDisableTiming), "hipEventCreate");
+        hipError_t e = hipEventRecord(order, user);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(own, order, 0);
+        for (int t = 0; t < n_steps && e == hipSuccess; ++t)
+            e = enqueue_step(s->prob, own, ev.data() + (size_t)t * kMarks);
+        if (e == hipSuccess)
+            e = hipEventRecord(order, own);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(user, order, 0);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(own);
+        (void)hipEventDestroy(order);
+        hip_check(e, "profiled steps");
+        for (int q = 0; q < EXACT_STEP_PHASES; ++q) {
+            double sum = 0.0;
+            for (int t = 0; t < n_steps; ++t) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, ev[(size_t)t * kMarks + q],
+                                              ev[(size_t)t * kMarks + q + 1]),
+                          "hipEventElapsedTime");
+                sum += ms;
+            }
+            phase_ms[q] = sum / n_steps;
+        }
         return 0;
     });
 }

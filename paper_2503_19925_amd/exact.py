@@ -34,6 +34,7 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
            "exact_geometry_destroy", "exact_forward", "exact_backproject",
            "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
+           "exact_solver_profile",
            "exact_count_nonzeros", "exact_run_footprint", "exact_batch_create",
            "exact_batch_add", "exact_batch_step", "exact_batch_sync", "exact_batch_poll",
            "exact_batch_remove", "exact_batch_destroy")
@@ -41,6 +42,10 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
 # exact_batch_poll results
 RUNNING, FINISHED, CAPPED = 0, 1, 2
 STOP_NATURAL_RESIDUAL, STOP_AVERAGED_ITERATE = 0, 1
+# phases of exact_solver_profile
+STEP_PHASES = 5
+PHASE_NAMES = ("forward_residual_x", "back_update_half", "forward_residual_xh",
+               "back_update_full", "finish")
 
 
 class ExactError(RuntimeError):
@@ -95,6 +100,7 @@ def load():
         "exact_solver_step": ([vp, i32, vp], C.c_int),
         "exact_solver_poll": ([vp, C.POINTER(SolveInfo)], C.c_int),
         "exact_solver_destroy": ([vp], C.c_int),
+        "exact_solver_profile": ([vp, C.c_int32, C.POINTER(C.c_double), vp], C.c_int),
         "exact_count_nonzeros": ([vp, C.POINTER(C.c_int64), vp], C.c_int),
         "exact_run_footprint": ([i32, i32, i32], C.c_size_t),
         "exact_batch_create": ([C.c_size_t, i32, C.POINTER(vp)], C.c_int),
@@ -274,6 +280,14 @@ class Solver:
         info = SolveInfo()
         done = _check("exact_solver_poll", load().exact_solver_poll(self.handle, C.byref(info)))
         return bool(done), _info_dict(info)
+
+    def profile(self, n_steps, stream=None):
+        """Runs n_steps more steps kernel by kernel with HIP events around
+        each phase; returns the average ms of the STEP_PHASES phases."""
+        out = (C.c_double * STEP_PHASES)()
+        _check("exact_solver_profile", load().exact_solver_profile(
+            self.handle, int(n_steps), out, _stream(stream)))
+        return list(out)
 
     def close(self):
         if self.handle is not None and self.handle.value:

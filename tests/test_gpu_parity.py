@@ -355,6 +355,30 @@ def test_solve_is_deterministic(ex):
     g.close()
 
 
+def test_solver_profile_steps_equal_graph_steps(ex):
+    """exact_solver_profile launches the step's kernels one by one with
+    events between them: the iterates equal those of graph replays and the
+    five phase times are positive."""
+    P = synth.config_problem("small_64")
+    say("solver profile vs graph steps")
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    y = t32(P.y)
+    xa, xb = torch.zeros(g.d, device=DEV), torch.zeros(g.d, device=DEV)
+    sa = ex.Solver(g, P.mu, P.I, y, xa, max_iters=10)
+    sa.step(10)
+    _, ia = sa.poll()
+    sb = ex.Solver(g, P.mu, P.I, y, xb, max_iters=10)
+    sb.step(4)
+    ms = sb.profile(6)
+    _, ib = sb.poll()
+    assert ia["iters"] == ib["iters"] == 10
+    assert len(ms) == ex.STEP_PHASES and all(t > 0 for t in ms), ms
+    assert torch.equal(xa, xb)
+    sa.close()
+    sb.close()
+    g.close()
+
+
 def test_scalar_worked_example_on_gpu(ex):
     """The hand-worked one-pixel example (tests/golden/eg_scalar.txt)."""
     say("scalar EG example")

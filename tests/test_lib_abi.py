@@ -114,3 +114,9 @@ def test_averaged_rule_is_exact_solve_only(lib):
     assert "averaged" in lib.exact_last_error().decode()
     o.stop_mode = 7
     assert lib.exact_solve(None, None, None, None, C.byref(o), None, None) == -errno.EINVAL
+
+
+def test_solver_profile_rejects_bad_arguments(lib):
+    import ctypes
+    out = (ctypes.c_double * 5)()
+    assert lib.exact_solver_profile(None, 3, out, None) == -errno.EINVAL
