@@ -34,17 +34,22 @@ struct Kahan {
     __device__ __forceinline__ float value() const { return s - c; }
 };
 
-// Fixed-order sum of one double per thread over a kRedThreads block.
+// Fixed-order sum of one double per thread over kRedThreads threads (the
+// x-y plane of the block); threads with active = false (other z planes)
+// only take part in the barriers.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThreads])
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[kRedThreads],
+                                          bool active = true)
 {
     const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-        lds[q][t] = v[q];
+        for (int q = 0; q < NV; ++q)
+            lds[q][t] = v[q];
+    }
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if (t < w) {
+        if (active && t < w) {
 #pragma unroll
             for (int q = 0; q < NV; ++q)
                 lds[q][t] += lds[q][t + w];
@@ -165,12 +170,12 @@ __device__ __forceinline__ int wave_max(int v)
 }
 
 // One lane per ray (v, b); the four waves of a workgroup take the same 64
-// rays and split the image lines into quarters, and their Kahan partial
-// sums are combined in a fixed order.  A wave walks the lines any of its
-// rays needs (a wave-uniform loop, so the line's address is scalar); on a
-// line a ray does not reach both weights are zero.  The crossing advances
-// exactly by Q per line.  Column-stepping views read the transposed image
-// so that the lanes of a wave touch neighbouring addresses on every line.
+// rays and split the image lines those rays reach into four equal shares,
+// and their Kahan partial sums are combined in a fixed order.  A wave walks
+// its lines in a wave-uniform loop, so the line's address is scalar; a ray
+// on a line it does not reach reads padding zeros.  The crossing advances
+// exactly by Q per line.  Column-stepping views read the transposed image so
+// that the lanes of a wave touch neighbouring addresses on every line.
 // Within a batch of lines the contributions are summed in float before the
 // Kahan step.
 // Spectrum read through device pointers (the batched kernels).
@@ -207,9 +212,15 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         k0 = N;
         k1 = -1;
     }
-    const int per = (N + kSegs - 1) / kSegs;
-    const int kw0 = max(wave_min(k0), seg * per);
-    const int kw1 = min(wave_max(k1), min(N, (seg + 1) * per) - 1);
+    // the four waves hold the same 64 rays: split the lines any of them
+    // reaches into equal shares
+    const int kmin = wave_min(k0), kmax = wave_max(k1);
+    int kw0 = 0, kw1 = -1;
+    if (kmin <= kmax) {
+        const int per = (kmax - kmin + kSegs) / kSegs;
+        kw0 = kmin + seg * per;
+        kw1 = min(kmax, kw0 + per - 1);
+    }
 
     Kahan acc;
     double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
@@ -405,23 +416,39 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
     }
 }
 
-// (A^T r) at pixel (ix, iy): the row-stepping views (line k = iy, pixel
-// j = ix) then the column-stepping views (k = ix, j = iy), Kahan-compensated.
+// (A^T r) at pixel (ix, iy) with the views split over the block's two z
+// planes: plane 0 gathers the row-stepping views, plane 1 the
+// column-stepping views (each about half of them), so a 16 x 16 tile runs
+// as 8 waves.  Plane 1 hands its sum to plane 0 through LDS; the result
+// (row part + column part, a fixed order) is meaningful in plane 0.  Every
+// thread of the block calls this (it holds a barrier).
 template <bool kTwo, bool kPad>
-__device__ __forceinline__ float back_pixel(const ViewGeom *__restrict__ views, int V, int B,
-                                            int nrow, int reach, const float *__restrict__ r,
-                                            int ix, int iy)
+__device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ views, int V,
+                                                  int B, int nrow, int reach,
+                                                  const float *__restrict__ r, int ix, int iy,
+                                                  bool inside)
 {
-    const double dx = (double)ix, dy = (double)iy;
+    __shared__ float part[kBackY][kBackX];
     const int rstride = kPad ? padded_bins(B) : B;
-    Kahan acc;
-    gather_views<kTwo, kPad>(views, 0, nrow, dy, dx, B, reach, r, rstride, acc);
-    gather_views<kTwo, kPad>(views, nrow, V, dx, dy, B, reach, r, rstride, acc);
-    return acc.value();
+    float v = 0.f;
+    if (inside) {
+        Kahan acc;
+        if (threadIdx.z == 0)
+            gather_views<kTwo, kPad>(views, 0, nrow, (double)iy, (double)ix, B, reach, r,
+                                     rstride, acc);
+        else
+            gather_views<kTwo, kPad>(views, nrow, V, (double)ix, (double)iy, B, reach, r,
+                                     rstride, acc);
+        v = acc.value();
+    }
+    if (threadIdx.z == 1)
+        part[threadIdx.y][threadIdx.x] = v;
+    __syncthreads();
+    return threadIdx.z == 0 ? v + part[threadIdx.y][threadIdx.x] : 0.f;
 }
 
 template <bool kTwo, bool kPad>
-__global__ __launch_bounds__(kBackX *kBackY) void k_back(
+__global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float *__restrict__ img, float scale,
     const int32_t *__restrict__ skip)
@@ -430,10 +457,10 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
         return;
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
-    if (ix >= N || iy >= N)
-        return;
-    img[(size_t)iy * N + ix] =
-        back_pixel<kTwo, kPad>(views, V, B, nrow, reach, r, ix, iy) * scale;
+    const bool inside = ix < N && iy < N;
+    const float g = back_pixel_split<kTwo, kPad>(views, V, B, nrow, reach, r, ix, iy, inside);
+    if (inside && threadIdx.z == 0)
+        img[(size_t)iy * N + ix] = g * scale;
 }
 
 // The projected update on one 16 x 16 tile once g = scale (A^T r) is known
@@ -442,8 +469,9 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back(
 // the padded pair (zp and, through an LDS tile, zTp) and, when z is not
 // null, to z; with kPartials the tile's double sums of (z - x)^2 and x^2 go
 // to part2[0..1].  z may alias x (each lane reads and writes only its own
-// pixel of x).  Every lane of the block calls this (it holds barriers);
-// lanes outside the image pass inside = false.
+// pixel of x).  Every thread of the block calls this (it holds barriers);
+// the work is done by z plane 0, and lanes outside the image pass
+// inside = false.
 template <bool kPartials>
 __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, const float *x,
                                                 float gamma, float *z, float *__restrict__ zp,
@@ -452,11 +480,12 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
 {
     __shared__ float tile[kBackY][kBackX + 1];
     __shared__ double red[2][kRedThreads];
+    const bool plane0 = threadIdx.z == 0;
     const int Np = padded_cols(N);
     const int ix = tx * kBackX + threadIdx.x;
     const int iy = ty * kBackY + threadIdx.y;
     double num = 0.0, den = 0.0;
-    if (inside) {
+    if (inside && plane0) {
         const size_t p = (size_t)iy * N + ix;
         const float xv = x[p];
         const float zv = fmaxf(0.f, fmaf(-gamma, g, xv));
@@ -472,22 +501,23 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
     }
     __syncthreads();
     const int ixT = tx * kBackX + threadIdx.y, iyT = ty * kBackY + threadIdx.x;
-    if (ixT < N && iyT < N)
+    if (plane0 && ixT < N && iyT < N)
         zTp[(size_t)ixT * Np + kPadX + iyT] = tile[threadIdx.x][threadIdx.y];
     if (kPartials) {
         double v2[2] = {num, den};
-        block_sum<2>(v2, red);
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
+        block_sum<2>(v2, red, plane0);
+        if (plane0 && threadIdx.x == 0 && threadIdx.y == 0) {
             part2[0] = v2[0];
             part2[1] = v2[1];
         }
     }
 }
 
-// Back-projection fused with the update: each lane gathers its pixel's
-// gradient from the padded residual, then the tile runs the update epilogue.
+// Back-projection fused with the update: the block's two z planes gather
+// the pixel's gradient from the padded residual, then plane 0 runs the
+// update epilogue.
 template <bool kTwo, bool kPartials>
-__global__ __launch_bounds__(kBackX *kBackY) void k_back_update(
+__global__ __launch_bounds__(kBackX *kBackY * 2) void k_back_update(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float scale, const float *x, float gamma, float *z,
     float *__restrict__ zp, float *__restrict__ zTp, double *__restrict__ partials,
@@ -498,9 +528,8 @@ __global__ __launch_bounds__(kBackX *kBackY) void k_back_update(
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     const bool inside = ix < N && iy < N;
-    float g = 0.f;
-    if (inside)
-        g = back_pixel<kTwo, true>(views, V, B, nrow, reach, r, ix, iy) * scale;
+    const float g =
+        back_pixel_split<kTwo, true>(views, V, B, nrow, reach, r, ix, iy, inside) * scale;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     update_epilogue<kPartials>(inside, g, N, x, gamma, z, zp, zTp,
                                kPartials ? partials + 2 * blk : nullptr, blockIdx.x, blockIdx.y);
@@ -723,7 +752,7 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
 }
 
 template <bool kHalf>
-__global__ __launch_bounds__(kBackX *kBackY) void kb_back_update(
+__global__ __launch_bounds__(kBackX *kBackY * 2) void kb_back_update(
     const BatchProb *__restrict__ probs, const BatchItem *__restrict__ items)
 {
     const BatchItem it = items[blockIdx.x];
@@ -733,17 +762,16 @@ __global__ __launch_bounds__(kBackX *kBackY) void kb_back_update(
     const int ix = it.a * kBackX + threadIdx.x;
     const int iy = it.b * kBackY + threadIdx.y;
     const bool inside = ix < P.N && iy < P.N;
-    // the gather of either projector variant comes before any store or
-    // barrier of the epilogue, so its view-table loads stay scalar
-    float g = 0.f;
-    if (inside) {
-        if (P.reach == 0)
-            g = back_pixel<true, true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy);
-        else
-            g = back_pixel<false, true>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
-                                        iy);
-        g *= P.inv_n;
-    }
+    // the gather of either projector variant comes before the epilogue's
+    // stores, so its view-table loads stay scalar
+    float g;
+    if (P.reach == 0)
+        g = back_pixel_split<true, true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
+                                         inside);
+    else
+        g = back_pixel_split<false, true>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
+                                          iy, inside);
+    g *= P.inv_n;
     const int ntx = (P.N + kBackX - 1) / kBackX;
     double *part2 = kHalf ? glob(P.parts) + 2 * (it.b * ntx + it.a) : nullptr;
     update_epilogue<kHalf>(inside, g, P.N, glob(P.x), P.gamma, kHalf ? nullptr : glob(P.x),
@@ -896,7 +924,7 @@ hipError_t launch_back(const Geo &g, const float *r, bool r_padded, float *img, 
                        const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
-    dim3 blk(kBackX, kBackY);
+    dim3 blk(kBackX, kBackY, 2);
     if (g.reach == 0) {
         if (r_padded)
             hipLaunchKernelGGL((k_back<true, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
@@ -980,7 +1008,7 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
                               const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
-    dim3 blk(kBackX, kBackY);
+    dim3 blk(kBackX, kBackY, 2);
     if (g.reach == 0) {
         if (partials)
             hipLaunchKernelGGL((k_back_update<true, true>), grid, blk, 0, st, g.views, g.N, g.V,
@@ -1014,7 +1042,7 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
 {
     if (nprobs == 0)
         return hipSuccess;
-    const dim3 fb(kFwdThreads * kSegs), bb(kBackX, kBackY), rb(kRedThreads);
+    const dim3 fb(kFwdThreads * kSegs), bb(kBackX, kBackY, 2), rb(kRedThreads);
     hipLaunchKernelGGL(kb_forward<false>, dim3(nfwd), fb, 0, st, probs, fwd);
     hipLaunchKernelGGL(kb_back_update<true>, dim3(nback), bb, 0, st, probs, back);
     hipLaunchKernelGGL(kb_forward<true>, dim3(nfwd), fb, 0, st, probs, fwd);
