@@ -31,6 +31,13 @@
  *  (window j, energy bin k) the expected counts on ray i are
  *  sum_k I[j][k] exp(-mu_k max(<a_i,x>, 0)).
  *
+ *  Known materials (appendix, model underlying the experiment in the
+ *  introduction's figure): when the other materials of the scan are known,
+ *  with line integral bg_i on ray i, each ray gets the reparametrised window
+ *  spectrum Ibar'_ij = sum_k I[j][k] exp(-mu_k bg_i), s'_ijk = I[j][k]
+ *  exp(-mu_k bg_i) / Ibar'_ij, and the single-material model applies with
+ *  those.  Every entry point below takes bg as an optional argument.
+ *
  *  Operator (Sec. 1.2, eq. operator, summed over windows as in the
  *  multi-window model): F(x) = (1/n) sum_i [sum_j y[j][i] - sum_j sum_k
  *  I[j][k] exp(-mu_k <a_i,x>_+)] a_i = (1/n) A^T r, n = number of rays.

@@ -163,18 +163,39 @@ static void FN(back_pixels)(const ora_geom *g, const REAL *r, int nsel,
 /* ------------------------------------------------------- spectral model */
 
 /* Literal per-window residual: r_i = sum_j y[j][i] - sum_j sum_k
- * Iwk[j][k] exp(-mu_k max(s_i, 0)). */
+ * Iwk[j][k] exp(-mu_k max(s_i, 0)).
+ *
+ * With bg (nullable, [n]) the other materials of the scan are known and bg_i
+ * is their line integral on ray i.  The appendix's reparametrisation
+ * (multi-material model with known materials) then gives ray i its own
+ * window spectrum: per window j, Ibar'_ij = sum_k Iwk[j][k] exp(-mu_k bg_i)
+ * and s'_ijk = Iwk[j][k] exp(-mu_k bg_i) / Ibar'_ij, and the model counts
+ * are sum_j Ibar'_ij sum_k s'_ijk exp(-mu_k max(s_i, 0)). */
 static void FN(residual)(long n, int K, int Wn, const REAL *mu, const REAL *Iwk,
-                         const REAL *y, const REAL *s, REAL *r, REAL *model)
+                         const REAL *y, const REAL *s, const REAL *bg, REAL *r, REAL *model)
 {
     for (long i = 0; i < n; ++i) {
         REAL sp = s[i] > 0 ? s[i] : 0;
         REAL ysum = 0, m = 0;
         for (int j = 0; j < Wn; ++j)
             ysum += y[(long)j * n + i];
-        for (int j = 0; j < Wn; ++j)
+        for (int j = 0; j < Wn; ++j) {
+            if (!bg) {
+                for (int k = 0; k < K; ++k)
+                    m += Iwk[(long)j * K + k] * exp(-mu[k] * sp);
+                continue;
+            }
+            REAL ibar = 0, win = 0;
             for (int k = 0; k < K; ++k)
-                m += Iwk[(long)j * K + k] * exp(-mu[k] * sp);
+                ibar += Iwk[(long)j * K + k] * exp(-mu[k] * bg[i]);
+            if (ibar <= 0)
+                continue;
+            for (int k = 0; k < K; ++k) {
+                REAL sk = Iwk[(long)j * K + k] * exp(-mu[k] * bg[i]) / ibar;
+                win += sk * exp(-mu[k] * sp);
+            }
+            m += ibar * win;
+        }
         r[i] = ysum - m;
         if (model)
             model[i] = m;
@@ -183,7 +204,7 @@ static void FN(residual)(long n, int K, int Wn, const REAL *mu, const REAL *Iwk,
 
 typedef struct {
     int K, Wn;
-    REAL *mu, *Iwk, *y;      /* [K], [Wn*K], [Wn*n] */
+    REAL *mu, *Iwk, *y, *bg;   /* [K], [Wn*K], [Wn*n], [n] or NULL */
 } FN(spec);
 
 /* F(x) = (1/n) A^T (Y - model(Ax)), n = number of rays. */
@@ -192,7 +213,7 @@ static void FN(apply_F)(const ora_geom *g, const FN(spec) *sp, const REAL *x,
 {
     long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
     FN(forward_rays)(g, x, (int)n, 0, s);
-    FN(residual)(n, sp->K, sp->Wn, sp->mu, sp->Iwk, sp->y, s, r, 0);
+    FN(residual)(n, sp->K, sp->Wn, sp->mu, sp->Iwk, sp->y, s, sp->bg, r, 0);
     FN(back_scatter)(g, r, F);
     for (long p = 0; p < d; ++p)
         F[p] = F[p] / (REAL)n;
@@ -223,7 +244,7 @@ static REAL FN(dot)(const REAL *a, const REAL *b, long len)
 }
 
 static FN(spec) FN(load_spec)(const ora_geom *g, int K, int Wn, const double *mu,
-                              const double *Iwk, const double *y)
+                              const double *Iwk, const double *y, const double *bg)
 {
     FN(spec) sp;
     long n = (long)g->n_views * g->n_bins;
@@ -232,6 +253,7 @@ static FN(spec) FN(load_spec)(const ora_geom *g, int K, int Wn, const double *mu
     sp.mu = FN(to_real)(mu, K);
     sp.Iwk = FN(to_real)(Iwk, (long)Wn * K);
     sp.y = y ? FN(to_real)(y, (long)Wn * n) : 0;
+    sp.bg = bg ? FN(to_real)(bg, n) : 0;
     return sp;
 }
 
@@ -240,6 +262,7 @@ static void FN(free_spec)(FN(spec) *sp)
     free(sp->mu);
     free(sp->Iwk);
     free(sp->y);
+    free(sp->bg);
 }
 
 /* ------------------------------------------------------------ exported API */
@@ -291,26 +314,28 @@ void FN(ora_back_pixels)(const ora_geom *g, const double *r, int nsel,
 }
 
 void FN(ora_residual)(long n, int K, int Wn, const double *mu, const double *Iwk,
-                      const double *y, const double *s, double *r, double *model)
+                      const double *y, const double *s, const double *bg, double *r,
+                      double *model)
 {
     REAL *mur = FN(to_real)(mu, K), *Ir = FN(to_real)(Iwk, (long)Wn * K);
     REAL *yr = FN(to_real)(y, (long)Wn * n), *sr = FN(to_real)(s, n);
+    REAL *br = bg ? FN(to_real)(bg, n) : 0;
     REAL *rr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
     REAL *mr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
-    FN(residual)(n, K, Wn, mur, Ir, yr, sr, rr, mr);
+    FN(residual)(n, K, Wn, mur, Ir, yr, sr, br, rr, mr);
     FN(to_double)(rr, n, r);
     if (model)
         FN(to_double)(mr, n, model);
-    free(mur); free(Ir); free(yr); free(sr); free(rr); free(mr);
+    free(mur); free(Ir); free(yr); free(sr); free(br); free(rr); free(mr);
 }
 
 /* F(x); optionally also returns s = Ax and r (each may be NULL). */
 void FN(ora_operator)(const ora_geom *g, int K, int Wn, const double *mu,
-                      const double *Iwk, const double *y, const double *x,
+                      const double *Iwk, const double *y, const double *bg, const double *x,
                       double *F, double *s_out, double *r_out)
 {
     long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
-    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y, bg);
     REAL *xr = FN(to_real)(x, d);
     REAL *Fr = (REAL *)malloc(sizeof(REAL) * (size_t)d);
     REAL *sr = (REAL *)malloc(sizeof(REAL) * (size_t)n);
@@ -336,11 +361,11 @@ void FN(ora_operator)(const ora_geom *g, int K, int Wn, const double *mu,
  * (-1 where undefined).  Returns the number of steps taken.
  */
 int FN(ora_eg)(const ora_geom *g, int K, int Wn, const double *mu,
-               const double *Iwk, const double *y, double *x, double gamma,
+               const double *Iwk, const double *y, const double *bg, double *x, double gamma,
                int max_iters, double tol, double *rho_hist)
 {
     long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
-    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y, bg);
     REAL *xt = FN(to_real)(x, d);
     REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d);
     REAL *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);
@@ -415,11 +440,12 @@ void FN(ora_window_mean)(const double *traj, long d, int s, double *out)
  * (max_iters + 1 images): small problems only.  Returns the steps taken.
  */
 int FN(ora_eg_avg)(const ora_geom *g, int K, int Wn, const double *mu,
-                   const double *Iwk, const double *y, double *x, double gamma,
-                   int max_iters, double tol, double *crit_hist, double *x_last)
+                   const double *Iwk, const double *y, const double *bg, double *x,
+                   double gamma, int max_iters, double tol, double *crit_hist,
+                   double *x_last)
 {
     long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
-    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y);
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y, bg);
     REAL *traj = (REAL *)malloc(sizeof(REAL) * (size_t)(max_iters + 1) * (size_t)d);
     REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d);
     REAL *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);

@@ -77,18 +77,18 @@ def _lib():
             f.argtypes = [_gp, _dp, C.c_int, _lp, _dp]
             f.restype = None
             f = getattr(_LIB, "ora_residual_" + p)
-            f.argtypes = [C.c_long, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+            f.argtypes = [C.c_long, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, _dp, _dp]
             f.restype = None
             f = getattr(_LIB, "ora_operator_" + p)
-            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp,
+            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, C.c_void_p, _dp, _dp,
                           C.c_void_p, C.c_void_p]
             f.restype = None
             f = getattr(_LIB, "ora_eg_" + p)
-            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_double,
+            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, C.c_void_p, _dp, C.c_double,
                           C.c_int, C.c_double, C.c_void_p]
             f.restype = C.c_int
             f = getattr(_LIB, "ora_eg_avg_" + p)
-            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_double,
+            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, C.c_void_p, _dp, C.c_double,
                           C.c_int, C.c_double, C.c_void_p, C.c_void_p]
             f.restype = C.c_int
             f = getattr(_LIB, "ora_window_mean_" + p)
@@ -154,9 +154,14 @@ def back_pixels(g, r, pixels, prec="f64"):
     return out
 
 
-def residual(s, mu, I, y, prec="f64"):
+def _bg(bg, n):
+    return None if bg is None else _f64(bg, n)
+
+
+def residual(s, mu, I, y, prec="f64", bg=None):
     """Per-ray residual r = sum_j y_j - sum_j sum_k I_jk exp(-mu_k s_+);
-    returns (r, model)."""
+    returns (r, model).  bg (optional, per ray): line integrals of known
+    materials, entering through the reparametrised per-ray spectrum."""
     s = _f64(s)
     n = s.size
     mu = _f64(mu)
@@ -168,11 +173,12 @@ def residual(s, mu, I, y, prec="f64"):
     y = _f64(y, Wn * n)
     r = np.empty(n)
     m = np.empty(n)
-    _fn("residual", prec)(n, K, Wn, mu, I, y, s, r, m)
+    b = _bg(bg, n)
+    _fn("residual", prec)(n, K, Wn, mu, I, y, s, _ptr(b), r, m)
     return r, m
 
 
-def operator(g, mu, I, y, x, prec="f64", want_sr=False):
+def operator(g, mu, I, y, x, prec="f64", want_sr=False, bg=None):
     """F(x) = (1/n) A^T r.  With want_sr also returns s = Ax and r."""
     mu = _f64(mu)
     K = mu.size
@@ -183,11 +189,12 @@ def operator(g, mu, I, y, x, prec="f64", want_sr=False):
     F = np.empty(g.d)
     s = np.empty(g.n) if want_sr else None
     r = np.empty(g.n) if want_sr else None
-    _fn("operator", prec)(C.byref(g), K, Wn, mu, I, y, x, F, _ptr(s), _ptr(r))
+    b = _bg(bg, g.n)
+    _fn("operator", prec)(C.byref(g), K, Wn, mu, I, y, _ptr(b), x, F, _ptr(s), _ptr(r))
     return (F, s, r) if want_sr else F
 
 
-def eg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
+def eg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64", bg=None):
     """Projected extragradient from x1.  Returns (x_last, steps, rho_hist)."""
     mu = _f64(mu)
     K = mu.size
@@ -196,12 +203,13 @@ def eg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
     y = _f64(y, Wn * g.n)
     x = _f64(x1, g.d).copy()
     hist = np.full(max(int(max_iters), 1), np.nan)
-    t = _fn("eg", prec)(C.byref(g), K, Wn, mu, I, y, x, float(gamma),
+    b = _bg(bg, g.n)
+    t = _fn("eg", prec)(C.byref(g), K, Wn, mu, I, y, _ptr(b), x, float(gamma),
                         int(max_iters), float(tol), _ptr(hist))
     return x, int(t), hist[:t]
 
 
-def eg_avg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
+def eg_avg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64", bg=None):
     """Projected extragradient with the averaged-iterate stopping rule.
     Returns (xbar, steps, crit_hist, x_last): xbar at index steps+1, the
     history of ||xbar_{t+1} - xbar_t|| and the last iterate x_{steps+1}."""
@@ -213,7 +221,8 @@ def eg_avg(g, mu, I, y, x1, gamma, max_iters, tol=0.0, prec="f64"):
     x = _f64(x1, g.d).copy()
     last = np.empty(g.d)
     hist = np.full(max(int(max_iters), 1), np.nan)
-    t = _fn("eg_avg", prec)(C.byref(g), K, Wn, mu, I, y, x, float(gamma),
+    b = _bg(bg, g.n)
+    t = _fn("eg_avg", prec)(C.byref(g), K, Wn, mu, I, y, _ptr(b), x, float(gamma),
                             int(max_iters), float(tol), _ptr(hist), _ptr(last))
     return x, int(t), hist[:t], last
 

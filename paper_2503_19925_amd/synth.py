@@ -137,6 +137,32 @@ def poisson_counts(mean, seed):
     return y.astype(np.float32)
 
 
+# ------------------------------------------------------- known background
+
+def background_ellipses(radius_cm=FOV_CM / 2):
+    """Known materials of a scan (the multi-material setting of the paper's
+    appendix, in which all but one material are known): a water-like disc of
+    density 1.0 filling 85% of the field and a bone-like ring segment
+    (density 1.8) as an off-centre ellipse."""
+    R = float(radius_cm)
+    return np.array([[0.0, 0.0, 0.85 * R, 0.80 * R, 0.0, 1.0],
+                     [0.35 * R, -0.2 * R, 0.12 * R, 0.07 * R, 0.6, 1.8]])
+
+
+def with_background(P, bg_ell=None):
+    """A copy of problem P whose scan also holds known materials: their exact
+    line integrals bg (float64 [V*B]) and counts redrawn from the model with
+    the total line integral (the unknown material's plus the background's,
+    sharing the attenuation curve as in the reparametrised model)."""
+    import copy
+    ell = background_ellipses() if bg_ell is None else np.asarray(bg_ell, dtype=np.float64)
+    bg = analytic_sinogram(ell, P.n_views, P.n_bins, P.bin_cm, P.half_turns)
+    Q = copy.copy(P)
+    Q.bg = bg
+    Q.y = poisson_counts(expected_counts(P.line_int + bg, P.mu, P.I), P.seed_noise + 7)
+    return Q
+
+
 # ------------------------------------------------------------- configurations
 
 def bins_for(n_pix):
@@ -166,6 +192,7 @@ class Problem:
     line_int: np.ndarray = field(default=None, repr=False)
     y: np.ndarray = field(default=None, repr=False)
     x_true: np.ndarray = field(default=None, repr=False)
+    bg: np.ndarray = field(default=None, repr=False)     # known materials' line integrals
 
     @property
     def d(self):

@@ -455,6 +455,64 @@ def test_stop_rule(ora):
     np.testing.assert_array_equal(x, x2)
 
 
+# ------------------------------------------- known background (appendix)
+
+def test_background_zero_is_plain_model(ora):
+    """bg = 0: the reparametrised spectrum is the plain one."""
+    rng = np.random.default_rng(31)
+    mu, I = synth.spectrum(12, 3, 1e4)
+    n = 200
+    s = rng.uniform(-0.5, 8, n)
+    y = rng.poisson(3000, (3, n)).astype(np.float64).ravel()
+    r0, m0 = ora.residual(s, mu, I, y)
+    r1, m1 = ora.residual(s, mu, I, y, bg=np.zeros(n))
+    np.testing.assert_allclose(m1, m0, rtol=1e-14)
+    np.testing.assert_allclose(r1, r0, rtol=1e-12, atol=1e-9)
+
+
+def test_background_reparametrisation_is_multi_material_model(ora):
+    """The appendix's reparametrised single-material model reproduces the
+    expected counts of the full model with known materials, in which the
+    known line integral bg_i adds to the unknown one inside every
+    exponential: sum_j sum_k I_jk exp(-mu_k (bg_i + max(s_i, 0)))."""
+    rng = np.random.default_rng(32)
+    mu, I = synth.spectrum(17, 4, 1e4)
+    n = 300
+    s = rng.uniform(-0.5, 6, n)
+    bg = rng.uniform(0, 9, n)
+    y = np.zeros(4 * n)
+    _, m = ora.residual(s, mu, I, y, bg=bg)
+    Ij = I.reshape(4, 17)
+    want = np.exp(-np.outer(bg + np.maximum(s, 0), mu)) @ Ij.sum(0)
+    np.testing.assert_allclose(m, want, rtol=1e-13)
+    # K = Wn = 1: Beer-Lambert through the two layers
+    mu1, I1 = np.array([0.3]), np.array([5e3])
+    _, m1 = ora.residual(s, mu1, I1, np.zeros(n), bg=bg)
+    np.testing.assert_allclose(m1, 5e3 * np.exp(-0.3 * bg) * np.exp(-0.3 * np.maximum(s, 0)),
+                               rtol=1e-13)
+
+
+def test_background_noiseless_recovery(ora):
+    """Noiseless counts from the model with a known background: F(x*) = 0
+    and EG from 0 recovers x* (Theorem 2 applies to the reparametrised
+    model)."""
+    g, mu, I, _, x_star = _noiseless(ora)
+    rng = np.random.default_rng(33)
+    bg = rng.uniform(0, 2.0, g.n)
+    s = ora.forward(g, x_star)
+    Wn = I.size // mu.size
+    _, m = ora.residual(s, mu, I, np.zeros(Wn * g.n), bg=bg)
+    y = np.zeros(Wn * g.n)
+    y[:g.n] = m
+    F = ora.operator(g, mu, I, y, x_star, bg=bg)
+    assert np.abs(F).max() <= 1e-11 * np.abs(ora.operator(g, mu, I, y, 0 * x_star, bg=bg)).max()
+    A = dense_A(g.n_pix, g.n_views, g.n_bins, g.pixel_cm, g.bin_cm)
+    lam = np.linalg.eigvalsh(A.T @ A / g.n)[-1]
+    gamma = ora.step_size(lam, mu, I)
+    x, t, _ = ora.eg(g, mu, I, y, np.zeros(g.d), gamma, 20000, tol=1e-13, bg=bg)
+    assert np.linalg.norm(x - x_star) <= 1e-8 * np.linalg.norm(x_star), t
+
+
 # ------------------------------------------------- the oracle's own rounding
 
 def test_long_double_agreement(ora):
