@@ -65,15 +65,27 @@ typedef struct exact_geometry_s *exact_geometry;
  * model:multi-material with one material; Sec. 1.2, eq. function-h-plus):
  * expected counts in window j on ray i are
  *     sum_k weight[j*K + k] * exp(-mu[k] * max(<a_i, x>, 0)),
- * weight[j][k] = Ibar_j * s_{jk} >= 0.  Host pointers, copied by each call.
- * Requirements: K >= 1, Wn >= 1, every mu[k] > 0 and finite, every weight
- * finite and >= 0, each window's row sum > 0.
+ * weight[j][k] = Ibar_j * s_{jk} >= 0.  mu and weight are host pointers,
+ * copied by each call.  Requirements: K >= 1, Wn >= 1, every mu[k] > 0 and
+ * finite, every weight finite and >= 0, each window's row sum > 0.
+ *
+ * background (optional): when the scan's other materials are known (the
+ * multi-material model of the paper's appendix, reparametrised there into
+ * a single-material model with a per-ray spectrum), their line integrals
+ * bg_i, one per ray ([V][B] float32, device pointer), and the expected
+ * counts become sum_k weight[j*K + k] * exp(-mu[k] * (bg_i +
+ * max(<a_i, x>, 0))).  NULL means no known material.  Read during the call
+ * (the solvers keep a copy); must be finite and >= 0 (exact_solve, the
+ * solver and the batch check it: -EINVAL).  The step-size rule keeps
+ * Theorem 2's gamma for the unattenuated spectrum, which bounds every ray's
+ * reparametrised one.
  */
 typedef struct {
     int32_t n_energies;     /* K  */
     int32_t n_windows;      /* Wn */
     const double *mu;       /* [K]      */
     const double *weight;   /* [Wn][K]  */
+    const float *background;/* [V][B] device, or NULL */
 } exact_spectrum;
 
 /* Stop rules for exact_solve.
@@ -255,7 +267,8 @@ int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream);
  * between steps (the lists and the graph are then rebuilt).
  *
  * exact_run_footprint: device bytes one run allocates inside the library
- *   (the caller's x and y are extra); 0 for invalid sizes.
+ *   (the caller's x and y are extra; a run with a known background holds
+ *   4 V B bytes more for its copy); 0 for invalid sizes.
  * exact_batch_create: hbm_budget_bytes caps the sum of the runs'
  *   footprints; capacity is the number of slots (1..65536).
  * exact_batch_add: validates and sets up one run as exact_solver_create

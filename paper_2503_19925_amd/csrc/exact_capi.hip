@@ -120,6 +120,7 @@ SpecArg make_spec(const exact_spectrum *sp, double *sum_J_mu)
     }
     if (sum_J_mu)
         *sum_J_mu = sjm;
+    a.bg = sp->background;
     return a;
 }
 
@@ -501,7 +502,7 @@ struct Problem {
     int avg_R = 0, avg_J = 0;                       // averaged-iterate ring (stop_mode 1)
     std::unique_ptr<DevBuf> avg_ring, avg_S, avg_parts;
     float *x = nullptr;
-    std::unique_ptr<DevBuf> Y, r, xp, xTp, xhp, xhTp, parts, specd;
+    std::unique_ptr<DevBuf> Y, r, xp, xTp, xhp, xhTp, parts, specd, bg;
     SolveState *state = nullptr;
     size_t footprint = 0;
 
@@ -520,6 +521,7 @@ struct Problem {
         d.Y = Y->as<float>();
         d.J = specd->as<float>();
         d.mu = specd->as<float>() + exact::kMaxEnergies;
+        d.bg = bg ? bg->as<float>() : nullptr;
         d.x = x;
         d.xp = xp->as<float>();
         d.xTp = xTp->as<float>();
@@ -582,7 +584,7 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.stop_mode = o.stop_mode;
     p.state = state;
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
-    p.footprint = run_footprint(g->N, g->V, g->B);
+    p.footprint = run_footprint(g->N, g->V, g->B) + (sp->background ? (size_t)n * 4 : 0);
     const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
     const size_t np = (size_t)g->V * exact::padded_bins(g->B);
     p.Y.reset(new DevBuf(n * 4));
@@ -602,19 +604,31 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
                              exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
               "hipMemcpyAsync");
 
-    DevBuf bad(8);
+    // the run keeps its own copy of the known background
+    if (sp->background) {
+        p.bg.reset(new DevBuf(n * 4));
+        hip_check(hipMemcpyAsync(p.bg->p, sp->background, n * 4, hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync");
+        p.spec.bg = p.bg->as<float>();
+    }
+
+    DevBuf bad(12);
     int32_t *badp = bad.as<int32_t>();
-    hip_check(hipMemsetAsync(bad.p, 0, 8, st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(bad.p, 0, 12, st), "hipMemsetAsync");
     hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, p.Y->as<float>(), badp, st),
               "window_sum");
     hip_check(exact::launch_count_bad(x_dev, d, badp + 1, st), "count_bad");
-    int32_t hbad[2] = {0, 0};
-    hip_check(hipMemcpyAsync(hbad, badp, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    if (p.bg)
+        hip_check(exact::launch_count_bad(p.bg->as<float>(), n, badp + 2, st), "count_bad");
+    int32_t hbad[3] = {0, 0, 0};
+    hip_check(hipMemcpyAsync(hbad, badp, 12, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     if (hbad[0])
         fail(-EINVAL, "y contains negative or non-finite counts");
     if (hbad[1])
         fail(-EINVAL, "x_1 contains negative or non-finite values");
+    if (hbad[2])
+        fail(-EINVAL, "background contains negative or non-finite values");
 
     p.gamma = o.gamma;
     if (p.gamma <= 0.0) {
@@ -1070,7 +1084,8 @@ int exact_batch_add(exact_batch bh, exact_geometry g, const exact_spectrum *sp, 
         if (!slot_out)
             fail(-EINVAL, "slot_out is NULL");
         *slot_out = -1;
-        const size_t need = run_footprint(g->N, g->V, g->B);
+        const size_t need = run_footprint(g->N, g->V, g->B) +
+                            (sp && sp->background ? (size_t)g->V * g->B * 4 : 0);
         if (b->used + need > b->budget)
             fail(-ENOSPC, "run needs " + std::to_string(need) + " bytes, " +
                               std::to_string(b->budget - b->used) + " left in the batch budget");

@@ -52,11 +52,13 @@ constexpr int kPadB = 2;
 __host__ __device__ inline int padded_cols(int N) { return N + 2 * kPadX; }
 __host__ __device__ inline int padded_bins(int B) { return B + 2 * kPadB; }
 
-// Spectrum collapsed over windows, passed to kernels by value.
+// Spectrum collapsed over windows, passed to kernels by value; bg (device,
+// [V][B], or null) holds known materials' line integrals per ray.
 struct SpecArg {
     int32_t K;
     float J[kMaxEnergies];    // J_k = sum_j weight[j][k]
     float mu[kMaxEnergies];
+    const float *bg;
 };
 
 // Device-side state of one extragradient run.
@@ -101,6 +103,7 @@ struct BatchProb {
     const float EXACT_GLOBAL *Y;       // window sums of y
     const float EXACT_GLOBAL *J;       // spectrum (device copies)
     const float EXACT_GLOBAL *mu;
+    const float EXACT_GLOBAL *bg;      // known materials' line integrals, or null
     float EXACT_GLOBAL *x;             // iterate (the caller's buffer)
     float EXACT_GLOBAL *xp;            // iterate and its transpose, padded rows
     float EXACT_GLOBAL *xTp;

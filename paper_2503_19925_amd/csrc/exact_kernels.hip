@@ -183,6 +183,7 @@ struct SpecPtr {
     int32_t K;
     const float *__restrict__ J;
     const float *__restrict__ mu;
+    const float *__restrict__ bg;
 };
 
 // Forward projection of rays [64 bblock, 64 bblock + 64) of table view
@@ -255,12 +256,13 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     const float s = tot.value() * G.wstep;
     const size_t o = (size_t)G.vidx * ostride + ooff + b;
     if (kResid) {
-        // r_i = Y_i - sum_k J_k exp(-mu_k max(s_i, 0))
-        const float sp0 = fmaxf(s, 0.f);
+        // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0)))
+        const size_t i = (size_t)G.vidx * B + b;
+        const float sp0 = fmaxf(s, 0.f) + (sp.bg ? sp.bg[i] : 0.f);
         float m = 0.f;
         for (int q = 0; q < sp.K; ++q)
             m = fmaf(sp.J[q], expf(-sp.mu[q] * sp0), m);
-        out[o] = Y[(size_t)G.vidx * B + b] - m;
+        out[o] = Y[i] - m;
     } else {
         out[o] = s;
     }
@@ -745,7 +747,7 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
     const BatchProb &P = probs[it.p];
     if (glob(P.state)->done)
         return;
-    const SpecPtr sp{P.K, glob(P.J), glob(P.mu)};
+    const SpecPtr sp{P.K, glob(P.J), glob(P.mu), P.bg ? glob(P.bg) : nullptr};
     forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xhp : P.xp),
                         glob(kAtHalf ? P.xhTp : P.xTp), glob(P.Y), sp, glob(P.r),
                         padded_bins(P.B), kPadB, it.a, it.b);
@@ -904,6 +906,7 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
 {
     SpecArg none;
     none.K = 0;
+    none.bg = nullptr;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
                        g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off, skip);

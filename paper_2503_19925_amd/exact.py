@@ -59,7 +59,8 @@ class ExactError(RuntimeError):
 
 class Spectrum(C.Structure):
     _fields_ = [("n_energies", C.c_int32), ("n_windows", C.c_int32),
-                ("mu", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double))]
+                ("mu", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double)),
+                ("background", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -185,9 +186,11 @@ class Geometry:
 
 
 class _Spec:
-    """Keeps the host arrays alive while a call uses them."""
+    """Keeps the host arrays alive while a call uses them.  background: an
+    optional float32 device tensor [V*B] of known materials' line
+    integrals."""
 
-    def __init__(self, mu, weight):
+    def __init__(self, mu, weight, background=None, n=None):
         self.mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).ravel())
         self.w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).ravel())
         K = self.mu.size
@@ -195,8 +198,10 @@ class _Spec:
         if K == 0 or Wn * K != self.w.size:
             raise ValueError("weight must hold n_windows * n_energies values")
         self.K, self.Wn = K, Wn
+        self.bg = background
+        bgp = _dev(background, n, "background") if background is not None else None
         self.s = Spectrum(K, Wn, self.mu.ctypes.data_as(C.POINTER(C.c_double)),
-                          self.w.ctypes.data_as(C.POINTER(C.c_double)))
+                          self.w.ctypes.data_as(C.POINTER(C.c_double)), bgp)
 
 
 def exact_geometry_create(n_pix, n_views, n_bins, pixel_cm=None, bin_cm=None, half_turns=1):
@@ -219,8 +224,8 @@ def exact_backproject(g, r, img, stream=None):
     return img
 
 
-def exact_operator(g, mu, weight, y, x, F, r=None, stream=None):
-    sp = _Spec(mu, weight)
+def exact_operator(g, mu, weight, y, x, F, r=None, stream=None, background=None):
+    sp = _Spec(mu, weight, background, g.n)
     _check("exact_operator", load().exact_operator(
         g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),
         _dev(F, g.d, "F"), None if r is None else _dev(r, g.n, "r"), _stream(stream)))
@@ -262,8 +267,8 @@ class Solver:
     step(n) enqueues n full extragradient steps on the stream."""
 
     def __init__(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-                 check_every=16, power_iters=100, stream=None):
-        sp = _Spec(mu, weight)
+                 check_every=16, power_iters=100, stream=None, background=None):
+        sp = _Spec(mu, weight, background, g.n)
         self.g, self.x = g, x
         o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
         h = C.c_void_p()
@@ -308,12 +313,14 @@ class Solver:
 
 
 def exact_solve(g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-                check_every=16, power_iters=100, stream=None, stop_mode=STOP_NATURAL_RESIDUAL):
+                check_every=16, power_iters=100, stream=None, stop_mode=STOP_NATURAL_RESIDUAL,
+                background=None):
     """Runs EXACT in place on x.  Returns a dict with iters, resid, gamma,
     lambda_hat, ms and converged (True/False, or None when tol == 0).  With
     stop_mode=STOP_AVERAGED_ITERATE x receives the averaged iterate and tol
-    bounds ||xbar_{t+1} - xbar_t|| (absolute)."""
-    sp = _Spec(mu, weight)
+    bounds ||xbar_{t+1} - xbar_t|| (absolute).  background: known materials'
+    line integrals per ray (device float32 [V*B]) or None."""
+    sp = _Spec(mu, weight, background, g.n)
     o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters, stop_mode)
     info = SolveInfo()
     code = _check("exact_solve", load().exact_solve(
@@ -344,8 +351,8 @@ class Batch:
         self._keep = {}
 
     def add(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-            power_iters=100, stream=None):
-        sp = _Spec(mu, weight)
+            power_iters=100, stream=None, background=None):
+        sp = _Spec(mu, weight, background, g.n)
         o = _opts(gamma, gamma_scale, max_iters, tol, 1, power_iters)
         slot = C.c_int32(-1)
         _check("exact_batch_add", load().exact_batch_add(

@@ -132,3 +132,31 @@ def test_batch_budget_and_slots(ex):
     assert e.value.code == -errno.ENOSPC
     b1.close()
     g.close()
+
+
+def test_batch_with_background_equals_solo(ex):
+    """A scan with a known background shares a batch with plain scans; each
+    is bitwise equal to its solo run."""
+    Ps = problems()[:3]
+    Ps[1] = synth.with_background(Ps[1])
+    say("batch with background")
+    opts = dict(max_iters=30)
+    b = ex.Batch(1 << 34, capacity=3)
+    geos = [ex.Geometry(P.n_pix, P.n_views, P.n_bins) for P in Ps]
+    xs = [torch.zeros(P.d, device=DEV) for P in Ps]
+    bgs = [None if P.bg is None else torch.as_tensor(P.bg.astype(np.float32), device=DEV)
+           for P in Ps]
+    slots = [b.add(g, P.mu, P.I, torch.as_tensor(P.y, device=DEV), x, background=bg, **opts)
+             for P, g, x, bg in zip(Ps, geos, xs, bgs)]
+    b.step(30)
+    assert b.sync() == 0
+    for i, P in enumerate(Ps):
+        assert b.poll(slots[i])[1]["iters"] == 30
+        x = torch.zeros(P.d, device=DEV)
+        ex.exact_solve(geos[i], P.mu, P.I, torch.as_tensor(P.y, device=DEV), x,
+                       background=bgs[i], **opts)
+        torch.cuda.synchronize()
+        assert torch.equal(xs[i], x), i
+    b.close()
+    for g in geos:
+        g.close()

@@ -192,6 +192,52 @@ def test_operator_parity(ex, ora, name):
     g.close()
 
 
+def test_operator_with_known_background(ex, ora):
+    """Known materials (the appendix's reparametrised model): the GPU adds
+    bg_i inside every exponential; the oracle builds each ray's
+    reparametrised window spectrum."""
+    P = synth.with_background(synth.config_problem("small_64"))
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    say("operator with background", P.n_pix, P.n_views, P.n_bins)
+    y64 = P.y.astype(np.float64)
+    bg32 = P.bg.astype(np.float32)
+    x = (0.9 * P.x_true).astype(np.float32)
+    F = torch.empty(g.d, device=DEV)
+    r = torch.empty(g.n, device=DEV)
+    ex.exact_operator(g, P.mu, P.I, t32(P.y), t32(x), F, r, background=t32(bg32))
+    F_ora, s_ora, r_ora = ora.operator(go, P.mu, P.I, y64, x, want_sr=True, bg=bg32)
+    _, m = ora.residual(s_ora, P.mu, P.I, y64, bg=bg32)
+    Y = y64.reshape(P.Wn, -1).sum(0)
+    within(np64(F), F_ora, ora.back(go, Y + m) / g.n)
+    within(np64(r), r_ora, Y + m)
+    g.close()
+
+
+def test_solve_with_known_background(ex, ora):
+    P = synth.with_background(synth.config_problem("small_64"))
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    say("solve with background", P.n_pix, "T = 100")
+    gamma = oracle_gamma(ora, go, P)
+    bg32 = P.bg.astype(np.float32)
+    x = torch.zeros(g.d, device=DEV)
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=gamma, max_iters=100,
+                          background=t32(bg32))
+    assert info["iters"] == 100
+    x_ora, _, _ = ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d), gamma, 100,
+                         bg=bg32)
+    rel = np.linalg.norm(np64(x) - x_ora) / np.linalg.norm(x_ora)
+    print("  rel L2 vs oracle with background after 100 steps: %.3e" % rel, flush=True)
+    assert rel <= 1e-4
+    bad = bg32.copy()
+    bad[5] = -1.0
+    with pytest.raises(ex.ExactError):
+        ex.exact_solve(g, P.mu, P.I, t32(P.y), torch.zeros(g.d, device=DEV), gamma=gamma,
+                       max_iters=2, background=t32(bad))
+    g.close()
+
+
 def test_operator_at_zero_and_monotone(ex, ora):
     """F(0) = (1/n) A^T (Y - I0) (h(0) = 1) and <F(x)-F(z), x-z> >= 0 on the GPU."""
     P, g, go = _problem(ex, ora, "small_64")
