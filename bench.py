@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
+    ap.add_argument("--background-steps", type=int, default=100,
+                    help="timed steps of the workload with known materials (0 to skip)")
     ap.add_argument("--served", type=int, default=40,
                     help="requests in the served leg (0 to skip)")
     ap.add_argument("--workload", default="solve_512", choices=sorted(WORKLOADS),
@@ -289,6 +291,28 @@ def main():
                   "converged": info_t["converged"], "seconds": info_t["ms"] / 1e3}
         log("to tolerance %.0e: %d steps, %.2f s" % (args.to_tol, info_t["iters"], info_t["ms"] / 1e3))
 
+    # the same workload with known materials (the appendix's reparametrised
+    # model): one more per-ray input in the residual epilogue
+    background = None
+    if args.background_steps > 0:
+        Pb = synth.with_background(P)
+        bgt = torch.as_tensor(Pb.bg.astype("float32"), device=dev)
+        yb = torch.as_tensor(Pb.y, device=dev)
+        xb0 = torch.zeros(g.d, device=dev)
+        sb = exact.Solver(g, Pb.mu, Pb.I, yb, xb0, gamma=info["gamma"], tol=0.0,
+                          max_iters=10 + args.background_steps, background=bgt)
+        sb.step(10)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sb.step(args.background_steps)
+        e1.record(st)
+        e1.synchronize()
+        sb.close()
+        ms_bg = e0.elapsed_time(e1) / args.background_steps
+        background = {"ms_per_step": ms_bg, "EG_iters_per_s": 1000.0 / ms_bg,
+                      "relative_to_plain": ms_bg / ms_step}
+        log("known background: %.4f ms/step" % ms_bg)
+
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
     served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
     if served:
@@ -332,6 +356,7 @@ def main():
                              "achieved": fwd_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": fwd_achieved / HBM_PEAK_GBS},
         "to_tol": to_tol,
+        "background": background,
         "cpu_baseline": base,
         "batched": batched,
         "served": served,

@@ -51,6 +51,15 @@
  *  the indices, j = floor(s/2)+1 .. s; the run stops at the first s with
  *  ||xbar_s - xbar_{s-1}||_2 <= tol and reports xbar_s.
  *
+ *  Constraint set of the experiments (Sec. 5): X = TV ball intersected with
+ *  the orthant.  TV is the isotropic total variation with forward
+ *  differences; the TV-ball projection is approximated by the
+ *  TV-regularized point (eq. TV-regularization) whose weight is found by
+ *  binary search to |TV - tau| <= tv_tol, the regularized point itself by
+ *  the fast gradient projection method on the dual of TV denoising (Beck and
+ *  Teboulle 2009) with a fixed number of steps; the intersection by
+ *  Dykstra's algorithm (eq. projection-intersection).
+ *
  *  Step size (Theorem 2, Sec. 2.1; Lipschitz bound in Sec. 4.2):
  *  L <= lambda_max(Sigma) * sum_k J_k mu_k with Sigma = A^T A / n and
  *  J_k = sum_j I[j][k]; gamma = c / L.  lambda_max comes from ora_power.

@@ -493,6 +493,297 @@ int FN(ora_eg_avg)(const ora_geom *g, int K, int Wn, const double *mu,
     return t;
 }
 
+/* ------------------------------------------- TV ball and orthant (Sec. 5) */
+
+/*
+ * Isotropic total variation of an N x N image with forward differences and
+ * nothing across the last row or column:
+ *   TV(x) = sum_{iy,ix} sqrt(dx^2 + dy^2),
+ *   dx = x[iy][ix+1] - x[iy][ix] (0 when ix = N-1), dy = x[iy+1][ix] - x[iy][ix]
+ *   (0 when iy = N-1).
+ */
+static REAL FN(tv_norm)(int N, const REAL *x)
+{
+    REAL acc = 0;
+    for (int iy = 0; iy < N; ++iy)
+        for (int ix = 0; ix < N; ++ix) {
+            REAL c = x[(long)iy * N + ix];
+            REAL dx = ix + 1 < N ? x[(long)iy * N + ix + 1] - c : 0;
+            REAL dy = iy + 1 < N ? x[(long)(iy + 1) * N + ix] - c : 0;
+            acc += sqrt(dx * dx + dy * dy);
+        }
+    return acc;
+}
+
+/*
+ * TV proximal point xbar = argmin_x ||x - b||^2 + lam TV(x) (Sec. 5, eq.
+ * TV-regularization), by `iters` steps of the fast gradient projection
+ * method on the dual of TV denoising (Beck and Teboulle, IEEE TIP 2009),
+ * started from zero.  With l = lam / 2 the problem is min ||x - b||^2 +
+ * 2 l TV(x); the dual variable is a pair of fields (p, q) with each
+ * (p_ij, q_ij) in the unit disc, and
+ *   L(p, q)_ij = p_ij + q_ij - p_{i-1,j} - q_{i,j-1},
+ *   L^T(x)     = (x_ij - x_{i+1,j}, x_ij - x_{i,j+1})
+ * (terms outside the image are zero; p on the last row and q on the last
+ * column stay zero).  One step from (r, s) with momentum t:
+ *   x = b - l L(r, s);  (p', q') = P_disc((r, s) + L^T(x) / (8 l));
+ *   t' = (1 + sqrt(1 + 4 t^2)) / 2;  (r, s) = (p', q') + ((t - 1)/t') ((p', q') - (p, q)).
+ * The result is b - l L(p, q).  lam <= 0 returns b.
+ */
+static void FN(tv_prox)(int N, const REAL *b, REAL lam, int iters, REAL *x)
+{
+    long d = (long)N * N;
+    if (!(lam > 0)) {
+        for (long i = 0; i < d; ++i)
+            x[i] = b[i];
+        return;
+    }
+    REAL l = lam / 2;
+    REAL *p = (REAL *)calloc((size_t)d, sizeof(REAL)), *q = (REAL *)calloc((size_t)d, sizeof(REAL));
+    REAL *r = (REAL *)calloc((size_t)d, sizeof(REAL)), *sv = (REAL *)calloc((size_t)d, sizeof(REAL));
+    REAL *pn = (REAL *)calloc((size_t)d, sizeof(REAL)), *qn = (REAL *)calloc((size_t)d, sizeof(REAL));
+    REAL t = 1;
+    for (int k = 0; k < iters; ++k) {
+        /* x = b - l L(r, s) */
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                long c = (long)i * N + j;
+                REAL Lv = r[c] + sv[c] - (i > 0 ? r[c - N] : 0) - (j > 0 ? sv[c - 1] : 0);
+                x[c] = b[c] - l * Lv;
+            }
+        /* gradient step and projection onto the unit disc */
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                long c = (long)i * N + j;
+                REAL gp = i + 1 < N ? x[c] - x[c + N] : 0;
+                REAL gq = j + 1 < N ? x[c] - x[c + 1] : 0;
+                REAL a = r[c] + gp / (8 * l), bq = sv[c] + gq / (8 * l);
+                if (i + 1 >= N)
+                    a = 0;
+                if (j + 1 >= N)
+                    bq = 0;
+                REAL nrm = sqrt(a * a + bq * bq);
+                REAL den = nrm > 1 ? nrm : 1;
+                pn[c] = a / den;
+                qn[c] = bq / den;
+            }
+        REAL tn = (1 + sqrt(1 + 4 * t * t)) / 2;
+        REAL w = (t - 1) / tn;
+        for (long c = 0; c < d; ++c) {
+            r[c] = pn[c] + w * (pn[c] - p[c]);
+            sv[c] = qn[c] + w * (qn[c] - q[c]);
+            p[c] = pn[c];
+            q[c] = qn[c];
+        }
+        t = tn;
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            long c = (long)i * N + j;
+            REAL Lv = p[c] + q[c] - (i > 0 ? p[c - N] : 0) - (j > 0 ? q[c - 1] : 0);
+            x[c] = b[c] - l * Lv;
+        }
+    free(p); free(q); free(r); free(sv); free(pn); free(qn);
+}
+
+/*
+ * Approximate projection onto the TV ball {TV(x) <= tau} as in Sec. 5: the
+ * TV-regularized point for a lam found by binary search, until
+ * |TV(xbar) - tau| <= tv_tol.  If TV(v) <= tau the result is v.  Otherwise
+ * hi starts at 1 and doubles (at most 60 times) until TV(xbar(hi)) <= tau,
+ * lo being the previous value (0 first); then up to max_bisect midpoints
+ * mid = (lo + hi)/2: the first with |TV - tau| <= tv_tol is returned, else
+ * TV > tau moves lo to mid and TV <= tau moves hi to mid.  Without a hit the
+ * result is xbar(hi), the last point inside the ball.  Returns the number
+ * of proximal solves; *lam_out receives the lam of the result.
+ */
+static int FN(tv_ball)(int N, const REAL *v, REAL tau, REAL tv_tol, int iters, int max_bisect,
+                       REAL *out, REAL *lam_out)
+{
+    long d = (long)N * N;
+    if (FN(tv_norm)(N, v) <= tau) {
+        for (long i = 0; i < d; ++i)
+            out[i] = v[i];
+        *lam_out = 0;
+        return 0;
+    }
+    REAL *x = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL lo = 0, hi = 1;
+    int solves = 0;
+    FN(tv_prox)(N, v, hi, iters, x);
+    ++solves;
+    REAL t = FN(tv_norm)(N, x);
+    for (int grow = 0; t > tau && grow < 60; ++grow) {
+        lo = hi;
+        hi = 2 * hi;
+        FN(tv_prox)(N, v, hi, iters, x);
+        ++solves;
+        t = FN(tv_norm)(N, x);
+    }
+    for (long i = 0; i < d; ++i)
+        out[i] = x[i];
+    *lam_out = hi;
+    for (int it = 0; it < max_bisect; ++it) {
+        REAL mid = (lo + hi) / 2;
+        FN(tv_prox)(N, v, mid, iters, x);
+        ++solves;
+        t = FN(tv_norm)(N, x);
+        if (fabs(t - tau) <= tv_tol) {
+            for (long i = 0; i < d; ++i)
+                out[i] = x[i];
+            *lam_out = mid;
+            break;
+        }
+        if (t > tau) {
+            lo = mid;
+        } else {
+            hi = mid;
+            for (long i = 0; i < d; ++i)
+                out[i] = x[i];
+            *lam_out = mid;
+        }
+    }
+    free(x);
+    return solves;
+}
+
+/*
+ * Projection onto X = {TV(x) <= tau} intersected with the orthant by
+ * Dykstra's algorithm (Sec. 5, eq. projection-intersection): z_0 = z,
+ * p_0 = q_0 = 0; y_k = P_TV(z_k + p_k), p_{k+1} = z_k + p_k - y_k,
+ * z_{k+1} = max(0, y_k + q_k), q_{k+1} = y_k + q_k - z_{k+1}; stops once
+ * ||z_{k+1} - z_k||_2 <= tol or after max_outer rounds.  P_TV is tv_ball.
+ */
+static void FN(tv_dykstra)(int N, const REAL *z, REAL tau, REAL tv_tol, int iters,
+                           int max_bisect, REAL tol, int max_outer, REAL *out, int *rounds,
+                           int *solves)
+{
+    long d = (long)N * N;
+    REAL *p = (REAL *)calloc((size_t)d, sizeof(REAL)), *q = (REAL *)calloc((size_t)d, sizeof(REAL));
+    REAL *y = (REAL *)malloc(sizeof(REAL) * (size_t)d), *w = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    for (long i = 0; i < d; ++i)
+        out[i] = z[i];
+    int k, ns = 0;
+    for (k = 0; k < max_outer; ++k) {
+        REAL lam;
+        for (long i = 0; i < d; ++i)
+            w[i] = out[i] + p[i];
+        ns += FN(tv_ball)(N, w, tau, tv_tol, iters, max_bisect, y, &lam);
+        REAL sq = 0;
+        for (long i = 0; i < d; ++i) {
+            p[i] = w[i] - y[i];
+            REAL zn = y[i] + q[i] > 0 ? y[i] + q[i] : 0;
+            q[i] = y[i] + q[i] - zn;
+            sq += (zn - out[i]) * (zn - out[i]);
+            out[i] = zn;
+        }
+        if (sqrt(sq) <= tol) {
+            ++k;
+            break;
+        }
+    }
+    if (rounds)
+        *rounds = k;
+    if (solves)
+        *solves = ns;
+    free(p); free(q); free(y); free(w);
+}
+
+double FN(ora_tv_norm)(int N, const double *x)
+{
+    REAL *xr = FN(to_real)(x, (long)N * N);
+    REAL t = FN(tv_norm)(N, xr);
+    free(xr);
+    return (double)t;
+}
+
+void FN(ora_tv_prox)(int N, const double *b, double lam, int iters, double *x)
+{
+    long d = (long)N * N;
+    REAL *br = FN(to_real)(b, d), *xr = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    FN(tv_prox)(N, br, (REAL)lam, iters, xr);
+    FN(to_double)(xr, d, x);
+    free(br); free(xr);
+}
+
+int FN(ora_tv_ball)(int N, const double *v, double tau, double tv_tol, int iters,
+                    int max_bisect, double *out, double *lam_out)
+{
+    long d = (long)N * N;
+    REAL *vr = FN(to_real)(v, d), *o = (REAL *)malloc(sizeof(REAL) * (size_t)d), lam = 0;
+    int ns = FN(tv_ball)(N, vr, (REAL)tau, (REAL)tv_tol, iters, max_bisect, o, &lam);
+    FN(to_double)(o, d, out);
+    if (lam_out)
+        *lam_out = (double)lam;
+    free(vr); free(o);
+    return ns;
+}
+
+int FN(ora_project_tv)(int N, const double *z, double tau, double tv_tol, int iters,
+                       int max_bisect, double tol, int max_outer, double *out, int *solves)
+{
+    long d = (long)N * N;
+    REAL *zr = FN(to_real)(z, d), *o = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    int rounds = 0;
+    FN(tv_dykstra)(N, zr, (REAL)tau, (REAL)tv_tol, iters, max_bisect, (REAL)tol, max_outer, o,
+                   &rounds, solves);
+    FN(to_double)(o, d, out);
+    free(zr); free(o);
+    return rounds;
+}
+
+/*
+ * Projected extragradient over X = {TV(x) <= tau} intersected with the
+ * orthant, the constraint set of the paper's experiments (Sec. 5): as
+ * ora_eg, with both half-steps projected by tv_dykstra.  rho_hist as in
+ * ora_eg; tol > 0 stops on the natural residual.  Returns the steps taken.
+ */
+int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const double *Iwk,
+                  const double *y, const double *bg, double *x, double gamma, int max_iters,
+                  double tol, double tau, double tv_tol, int prox_iters, int max_bisect,
+                  double dyk_tol, int max_outer, double *rho_hist)
+{
+    long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
+    int N = g->n_pix;
+    FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y, bg);
+    REAL *xt = FN(to_real)(x, d);
+    REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *v = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL gm = (REAL)gamma;
+    int t;
+    for (t = 1; t <= max_iters; ++t) {
+        FN(apply_F)(g, &sp, xt, F, s, r);
+        for (long p = 0; p < d; ++p)
+            v[p] = xt[p] - gm * F[p];
+        FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
+                       max_outer, xh, 0, 0);
+        REAL num = 0, den = 0;
+        for (long p = 0; p < d; ++p) {
+            num += (xh[p] - xt[p]) * (xh[p] - xt[p]);
+            den += xt[p] * xt[p];
+        }
+        double rho = den > 0 ? (double)sqrt(num / den) : -1.0;
+        if (rho_hist)
+            rho_hist[t - 1] = rho;
+        FN(apply_F)(g, &sp, xh, F, s, r);
+        for (long p = 0; p < d; ++p)
+            v[p] = xt[p] - gm * F[p];
+        FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
+                       max_outer, xt, 0, 0);
+        if (tol > 0 && rho >= 0 && rho <= tol)
+            break;
+    }
+    if (t > max_iters)
+        t = max_iters;
+    FN(to_double)(xt, d, x);
+    FN(free_spec)(&sp);
+    free(xt); free(xh); free(v); free(F); free(s); free(r);
+    return t;
+}
+
 /*
  * Largest eigenvalue of Sigma = A^T A / n by power iteration from the
  * constant unit vector, with Rayleigh quotients; stops when the quotient

@@ -94,6 +94,25 @@ def _lib():
             f = getattr(_LIB, "ora_window_mean_" + p)
             f.argtypes = [_dp, C.c_long, C.c_int, _dp]
             f.restype = None
+            f = getattr(_LIB, "ora_tv_norm_" + p)
+            f.argtypes = [C.c_int, _dp]
+            f.restype = C.c_double
+            f = getattr(_LIB, "ora_tv_prox_" + p)
+            f.argtypes = [C.c_int, _dp, C.c_double, C.c_int, _dp]
+            f.restype = None
+            f = getattr(_LIB, "ora_tv_ball_" + p)
+            f.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp,
+                          C.POINTER(C.c_double)]
+            f.restype = C.c_int
+            f = getattr(_LIB, "ora_project_tv_" + p)
+            f.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                          C.c_int, _dp, C.POINTER(C.c_int)]
+            f.restype = C.c_int
+            f = getattr(_LIB, "ora_eg_tv_" + p)
+            f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, C.c_void_p, _dp, C.c_double,
+                          C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                          C.c_double, C.c_int, C.c_void_p]
+            f.restype = C.c_int
             f = getattr(_LIB, "ora_power_" + p)
             f.argtypes = [_gp, C.c_int, C.c_double, C.POINTER(C.c_int)]
             f.restype = C.c_double
@@ -236,6 +255,81 @@ def window_mean(traj, s, prec="f64"):
     out = np.empty(d)
     _fn("window_mean", prec)(np.ascontiguousarray(traj[:s]).ravel(), d, int(s), out)
     return out
+
+
+# TV-ball projection parameters: the paper's tolerances (|TV - tau| <= 0.01,
+# Dykstra ||z_{k+1} - z_k|| <= 1e-4) and this implementation's fixed
+# inner counts.
+TV_DEFAULTS = dict(tv_tol=0.01, prox_iters=100, max_bisect=40, dyk_tol=1e-4, max_outer=200)
+
+
+def _img(x, N=None):
+    x = _f64(x)
+    n = int(round(np.sqrt(x.size))) if N is None else int(N)
+    if n * n != x.size:
+        raise ValueError("image must be square")
+    return x, n
+
+
+def tv_norm(x, prec="f64"):
+    """Isotropic TV (forward differences) of a square image."""
+    x, N = _img(x)
+    return float(_fn("tv_norm", prec)(N, x))
+
+
+def tv_prox(b, lam, iters=TV_DEFAULTS["prox_iters"], prec="f64"):
+    """argmin_x ||x - b||^2 + lam TV(x) by `iters` fast-gradient-projection
+    steps on the dual, from zero."""
+    b, N = _img(b)
+    x = np.empty(N * N)
+    _fn("tv_prox", prec)(N, b, float(lam), int(iters), x)
+    return x
+
+
+def tv_ball(v, tau, tv_tol=TV_DEFAULTS["tv_tol"], prox_iters=TV_DEFAULTS["prox_iters"],
+            max_bisect=TV_DEFAULTS["max_bisect"], prec="f64"):
+    """Approximate projection onto {TV <= tau} by binary search on the TV
+    weight.  Returns (x, lam, proximal solves)."""
+    v, N = _img(v)
+    out = np.empty(N * N)
+    lam = C.c_double(0.0)
+    ns = _fn("tv_ball", prec)(N, v, float(tau), float(tv_tol), int(prox_iters),
+                              int(max_bisect), out, C.byref(lam))
+    return out, lam.value, int(ns)
+
+
+def project_tv(z, tau, tv_tol=TV_DEFAULTS["tv_tol"], prox_iters=TV_DEFAULTS["prox_iters"],
+               max_bisect=TV_DEFAULTS["max_bisect"], dyk_tol=TV_DEFAULTS["dyk_tol"],
+               max_outer=TV_DEFAULTS["max_outer"], prec="f64"):
+    """Projection onto {TV <= tau} intersected with x >= 0 by Dykstra's
+    algorithm.  Returns (x, rounds, proximal solves)."""
+    z, N = _img(z)
+    out = np.empty(N * N)
+    ns = C.c_int(0)
+    k = _fn("project_tv", prec)(N, z, float(tau), float(tv_tol), int(prox_iters),
+                                int(max_bisect), float(dyk_tol), int(max_outer), out,
+                                C.byref(ns))
+    return out, int(k), ns.value
+
+
+def eg_tv(g, mu, I, y, x1, gamma, max_iters, tau, tol=0.0, prec="f64", bg=None, **tvkw):
+    """Projected extragradient over TV ball intersected with the orthant.
+    Returns (x_last, steps, rho_hist)."""
+    kw = dict(TV_DEFAULTS)
+    kw.update(tvkw)
+    mu = _f64(mu)
+    K = mu.size
+    I = _f64(I)
+    Wn = I.size // K
+    y = _f64(y, Wn * g.n)
+    x = _f64(x1, g.d).copy()
+    hist = np.full(max(int(max_iters), 1), np.nan)
+    b = _bg(bg, g.n)
+    t = _fn("eg_tv", prec)(C.byref(g), K, Wn, mu, I, y, _ptr(b), x, float(gamma),
+                           int(max_iters), float(tol), float(tau), float(kw["tv_tol"]),
+                           int(kw["prox_iters"]), int(kw["max_bisect"]), float(kw["dyk_tol"]),
+                           int(kw["max_outer"]), _ptr(hist))
+    return x, int(t), hist[:t]
 
 
 def power(g, max_iters=10000, rel_tol=1e-12, prec="f64"):

@@ -513,6 +513,150 @@ def test_background_noiseless_recovery(ora):
     assert np.linalg.norm(x - x_star) <= 1e-8 * np.linalg.norm(x_star), t
 
 
+# ------------------------------------- TV ball and orthant (Sec. 5 set-up)
+
+def test_tv_norm_closed_forms(ora):
+    """Isotropic TV with forward differences: constant -> 0; a vertical step
+    of height h -> N h; a ramp c j -> N (N-1) |c|; the plane i + j ->
+    (N-1)^2 sqrt 2 + 2 (N-1)."""
+    N = 9
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    assert ora.tv_norm(np.full(N * N, 3.7)) == 0.0
+    step = np.where(j < 4, 1.0, 3.5)
+    assert abs(ora.tv_norm(step) - N * 2.5) <= 1e-12
+    assert abs(ora.tv_norm(-0.3 * j) - N * (N - 1) * 0.3) <= 1e-12
+    plane = (i + j).astype(np.float64)
+    assert abs(ora.tv_norm(plane) - ((N - 1) ** 2 * math.sqrt(2) + 2 * (N - 1))) <= 1e-11
+
+
+def _tv_np(x, N):
+    x = x.reshape(N, N)
+    dx = np.zeros_like(x)
+    dy = np.zeros_like(x)
+    dx[:, :-1] = x[:, 1:] - x[:, :-1]
+    dy[:-1, :] = x[1:, :] - x[:-1, :]
+    return np.sqrt(dx * dx + dy * dy).sum()
+
+
+def _tv_prox_pdhg(b, lam, N, iters):
+    """Reference TV proximal point by a different method: the primal-dual
+    hybrid gradient iteration (Chambolle and Pock 2011) on
+    min ||x - b||^2 + lam TV(x), with the gradient as forward differences
+    and the dual ball constraint |(u, v)| <= lam."""
+    b = b.reshape(N, N)
+    x = b.copy()
+    xb = x.copy()
+    u = np.zeros_like(b)
+    v = np.zeros_like(b)
+    tau = sigma = 1.0 / math.sqrt(8.0)
+    for _ in range(iters):
+        gx = np.zeros_like(b)
+        gy = np.zeros_like(b)
+        gx[:, :-1] = xb[:, 1:] - xb[:, :-1]
+        gy[:-1, :] = xb[1:, :] - xb[:-1, :]
+        u, v = u + sigma * gx, v + sigma * gy
+        nrm = np.maximum(1.0, np.sqrt(u * u + v * v) / lam)
+        u, v = u / nrm, v / nrm
+        div = np.zeros_like(b)          # div = -grad^T
+        div[:, :-1] += u[:, :-1]
+        div[:, 1:] -= u[:, :-1]
+        div[:-1, :] += v[:-1, :]
+        div[1:, :] -= v[:-1, :]
+        xn = (x + tau * div + 2 * tau * b) / (1 + 2 * tau)
+        xb = 2 * xn - x
+        x = xn
+    return x.ravel()
+
+
+def test_tv_prox_matches_independent_solver(ora):
+    """The FGP dual iteration and a primal-dual iteration converge to the same
+    TV proximal point, and the point beats nearby perturbations on the
+    objective ||x - b||^2 + lam TV(x)."""
+    N = 8
+    rng = np.random.default_rng(41)
+    b = rng.normal(size=N * N) + np.where(np.arange(N * N) % N < 4, 0.0, 2.0)
+    for lam in (0.05, 0.5, 2.0):
+        x = ora.tv_prox(b, lam, iters=4000)
+        ref = _tv_prox_pdhg(b, lam, N, 40000)
+        obj = lambda z: float(np.sum((z - b) ** 2) + lam * _tv_np(z, N))  # noqa: E731
+        assert np.abs(x - ref).max() <= 2e-6 * max(1.0, np.abs(b).max()), lam
+        for _ in range(20):
+            e = rng.normal(size=N * N) * 1e-3
+            assert obj(x + e) >= obj(x) - 1e-9
+    # special cases: lam <= 0 is the identity, a constant image is a fixed point
+    np.testing.assert_array_equal(ora.tv_prox(b, 0.0), b)
+    c = np.full(N * N, 1.25)
+    np.testing.assert_allclose(ora.tv_prox(c, 3.0, iters=50), c, atol=1e-14)
+
+
+def test_tv_ball_search(ora):
+    """Binary search on the TV weight: the result's TV is within tv_tol of tau
+    (or below tau), TV grows monotonically back towards v as tau grows, and a
+    point already in the ball is returned unchanged."""
+    N = 24
+    P = synth.make_problem("tv", N, 10, 35, 5, 1, 1e4, 5, 51, 52)
+    rng = np.random.default_rng(42)
+    v = P.x_true + rng.normal(scale=0.2, size=N * N)
+    tv_v = ora.tv_norm(v)
+    last = 0.0
+    for frac in (0.2, 0.5, 0.8):
+        tau = frac * tv_v
+        x, lam, ns = ora.tv_ball(v, tau)
+        t = ora.tv_norm(x)
+        assert lam > 0 and ns >= 2
+        assert t <= tau + 0.01
+        assert t >= last
+        last = t
+    x, lam, ns = ora.tv_ball(v, 1.01 * tv_v)
+    assert lam == 0 and ns == 0
+    np.testing.assert_array_equal(x, v)
+
+
+def test_tv_orthant_projection_properties(ora):
+    """Dykstra's projection onto {TV <= tau} and the orthant: the result is
+    feasible (x >= 0, TV <= tau + tv_tol) and satisfies the projection
+    inequality <z - x, w - x> <= eps for feasible w (scaled copies of x,
+    constants, zero); a feasible z is returned unchanged."""
+    N = 20
+    P = synth.make_problem("tv", N, 10, 29, 5, 1, 1e4, 5, 61, 62)
+    tau = ora.tv_norm(P.x_true)
+    rng = np.random.default_rng(43)
+    z = P.x_true + rng.normal(scale=0.3, size=N * N)
+    x, rounds, ns = ora.project_tv(z, tau)
+    assert rounds < 200 and x.min() >= 0
+    assert ora.tv_norm(x) <= tau + 0.011
+    scale = np.linalg.norm(z - x) * np.linalg.norm(z)
+    for w in [0.0 * x, 0.5 * x, 0.9 * x, np.full(N * N, x.mean()), np.full(N * N, 0.1)]:
+        assert np.dot(z - x, w - x) <= 2e-3 * scale
+    x2, rounds2, ns2 = ora.project_tv(P.x_true, tau + 1.0)
+    assert rounds2 == 1 and ns2 == 0
+    np.testing.assert_array_equal(x2, P.x_true)
+
+
+def test_eg_tv_reduces_to_orthant_for_a_loose_ball(ora):
+    """With a TV bound no iterate reaches, the projection is the orthant's
+    and EG over the intersection is plain projected EG."""
+    g, mu, I, y, _ = _small_problem(ora, N=16, V=20, B=24)
+    lam, _ = ora.power(g, 2000, 1e-10)
+    gamma = ora.step_size(lam, mu, I)
+    xa, ta, _ = ora.eg(g, mu, I, y, np.zeros(g.d), gamma, 15)
+    xb, tb, _ = ora.eg_tv(g, mu, I, y, np.zeros(g.d), gamma, 15, tau=1e30)
+    assert ta == tb == 15
+    np.testing.assert_array_equal(xa, xb)
+
+
+def test_eg_tv_noiseless_recovery(ora):
+    """Noiseless data and a TV bound the truth meets: x* is the VI solution
+    on the intersection and EG over it recovers x*."""
+    g, mu, I, y, x_star = _noiseless(ora)
+    tau = 1.05 * ora.tv_norm(x_star)
+    A = dense_A(g.n_pix, g.n_views, g.n_bins, g.pixel_cm, g.bin_cm)
+    lam = np.linalg.eigvalsh(A.T @ A / g.n)[-1]
+    gamma = ora.step_size(lam, mu, I)
+    x, t, _ = ora.eg_tv(g, mu, I, y, np.zeros(g.d), gamma, 3000, tau=tau, tol=1e-10)
+    assert np.linalg.norm(x - x_star) <= 1e-6 * np.linalg.norm(x_star), t
+
+
 # ------------------------------------------------- the oracle's own rounding
 
 def test_long_double_agreement(ora):
