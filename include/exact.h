@@ -201,6 +201,70 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
                 exact_solve_info *info, void *stream);
 
 /*
+ * Constraint set of the paper's experiments (Sec. 5): X = {TV(x) <= tau}
+ * intersected with the orthant, TV the isotropic total variation of the
+ * N x N image with forward differences (nothing across the last row or
+ * column).  The TV-ball projection is approximated as the paper does: the
+ * TV-regularized point argmin ||x - v||^2 + lam TV(x) (eq.
+ * TV-regularization) with lam found by binary search until |TV(xbar) -
+ * tau| <= tv_tol; the regularized point is computed by prox_iters steps of
+ * fast gradient projection on the dual of TV denoising (Beck and Teboulle
+ * 2009) started from zero.  The binary search: if TV(v) <= tau the result
+ * is v; else hi starts at 1 and doubles (at most 60 times) until
+ * TV(xbar(hi)) <= tau, lo being its previous value (0 first); then up to
+ * max_bisect midpoints: the first within tv_tol is the result, TV > tau
+ * moves lo up, TV <= tau moves hi down; without a hit the result is
+ * xbar(hi).  The intersection with the orthant is Dykstra's algorithm (eq.
+ * projection-intersection), stopped once ||z_{k+1} - z_k||_2 <= dyk_tol or
+ * after max_outer rounds.  Defaults: the paper's tolerances (0.01, 1e-4),
+ * prox_iters 100, max_bisect 40, max_outer 200.
+ */
+typedef struct {
+    double tv_tol;
+    int32_t prox_iters;
+    int32_t max_bisect;
+    double dyk_tol;
+    int32_t max_outer;
+} exact_tv_opts;
+
+typedef struct {
+    int32_t rounds;      /* Dykstra rounds of the (last) projection          */
+    int32_t solves;      /* TV-regularized points computed (all projections) */
+    double tv;           /* TV of the result                                 */
+    double ms;           /* wall time of the call                            */
+} exact_tv_info;
+
+void exact_tv_opts_default(exact_tv_opts *opts);
+
+/* TV(x) of an n_pix x n_pix image x_dev (device), in double; blocking. */
+int exact_tv_norm(int32_t n_pix, const float *x_dev, double *tv_out, void *stream);
+
+/* The TV-regularized point x = argmin ||x - b||^2 + lam TV(x) by `iters`
+ * FGP steps from zero (lam <= 0: x = b).  Blocking. */
+int exact_tv_prox(int32_t n_pix, const float *b_dev, double lam, int32_t iters, float *x_dev,
+                  void *stream);
+
+/* Projection of z_dev onto {TV <= tau} intersected with the orthant, into
+ * out_dev (may equal z_dev).  tau > 0 and finite; opts nullable (defaults);
+ * info nullable.  Blocking. */
+int exact_project_tv(int32_t n_pix, const float *z_dev, double tau, const exact_tv_opts *opts,
+                     float *out_dev, exact_tv_info *info, void *stream);
+
+/*
+ * exact_solve over X = {TV <= tau} intersected with the orthant: both
+ * half-steps x_t - gamma F(.) are projected with exact_project_tv's
+ * algorithm (the paper's experimental set-up, Sec. 5).  opts as for
+ * exact_solve (stop_mode must be the natural residual); tv nullable;
+ * tv_info (nullable) receives the projection counts summed over the run.
+ * The known background of sp is honoured.  Blocking; far slower per step
+ * than exact_solve, since every projection solves tens to thousands of
+ * TV-regularized problems.
+ */
+int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_dev, float *x_dev,
+                   const exact_solve_opts *opts, double tau, const exact_tv_opts *tv,
+                   exact_solve_info *info, exact_tv_info *tv_info, void *stream);
+
+/*
  * Resident solver: the same iteration as exact_solve, split so that a caller
  * can keep the run's state on the device and advance it in pieces.
  *

@@ -1196,3 +1196,326 @@ int exact_batch_destroy(exact_batch bh)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// TV ball and orthant (the constraint set of the paper's experiments)
+
+namespace {
+
+void validate_tv_opts(const exact_tv_opts &o)
+{
+    if (!(std::isfinite(o.tv_tol) && o.tv_tol >= 0.0))
+        fail(-EINVAL, "tv_tol must be finite and >= 0");
+    if (o.prox_iters < 1 || o.prox_iters > 100000)
+        fail(-EINVAL, "prox_iters must be in [1, 100000]");
+    if (o.max_bisect < 0 || o.max_bisect > 200)
+        fail(-EINVAL, "max_bisect must be in [0, 200]");
+    if (!(std::isfinite(o.dyk_tol) && o.dyk_tol >= 0.0))
+        fail(-EINVAL, "dyk_tol must be finite and >= 0");
+    if (o.max_outer < 1)
+        fail(-EINVAL, "max_outer must be >= 1");
+}
+
+// Device work of the TV projection for one image size: the FGP fields, the
+// TV-ball and Dykstra buffers, the TV weight and reduction results, and the
+// captured graph of one TV-regularized solve (input w, output x, weight
+// read from `lam`).
+struct TvWork {
+    int N = 0;
+    long d = 0;
+    exact_tv_opts o;
+    std::unique_ptr<DevBuf> p, q, r, s, r2, s2, x, y, w, z, dp, dq, lam, parts, out;
+    double *h = nullptr;       // pinned: [0] lam to upload, [1..2] read back
+    Graph prox;
+    int solves = 0;
+
+    TvWork(int n, const exact_tv_opts &opts, hipStream_t st) : N(n), d((long)n * n), o(opts)
+    {
+        for (auto *b : {&p, &q, &r, &s, &r2, &s2, &x, &y, &w, &z, &dp, &dq})
+            b->reset(new DevBuf((size_t)d * 4));
+        lam.reset(new DevBuf(8));
+        const int np = std::max(exact::num_tv_parts(n), 2 * exact::num_flat_parts(d));
+        parts.reset(new DevBuf((size_t)np * 8));
+        out.reset(new DevBuf(16));
+        hip_check(hipHostMalloc((void **)&h, 32, hipHostMallocDefault), "hipHostMalloc");
+        prox.capture(st, [&]() {
+            return exact::launch_prox_graph_body(w->as<float>(), p->as<float>(), q->as<float>(),
+                                                 r->as<float>(), s->as<float>(), r2->as<float>(),
+                                                 s2->as<float>(), lam->as<double>(),
+                                                 o.prox_iters, x->as<float>(), N, st);
+        });
+    }
+    ~TvWork()
+    {
+        prox.reset();
+        if (h)
+            (void)hipHostFree(h);
+    }
+
+    double read1(hipStream_t st)
+    {
+        hip_check(hipMemcpyAsync(h + 1, out->p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        return h[1];
+    }
+    double tv_of(const float *img, hipStream_t st)
+    {
+        hip_check(exact::launch_tv_norm(img, N, parts->as<double>(), out->as<double>(), st),
+                  "tv_norm");
+        return read1(st);
+    }
+    // x = TV-regularized point of w for weight l; returns TV(x).
+    double solve(double l, hipStream_t st)
+    {
+        h[0] = l;
+        hip_check(hipMemcpyAsync(lam->p, h, 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        hip_check(hipGraphLaunch(prox.exec, st), "graph launch");
+        ++solves;
+        return tv_of(x->as<float>(), st);
+    }
+    void copy(float *dst, const float *src, hipStream_t st)
+    {
+        hip_check(hipMemcpyAsync(dst, src, (size_t)d * 4, hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync");
+    }
+
+    // y = approximate projection of w onto {TV <= tau} (binary search on
+    // the TV weight, the decisions of the definition in the header).
+    void tv_ball(double tau, hipStream_t st)
+    {
+        float *wp = w->as<float>(), *xp = x->as<float>(), *yp = y->as<float>();
+        if (tv_of(wp, st) <= tau) {
+            copy(yp, wp, st);
+            return;
+        }
+        double lo = 0.0, hi = 1.0;
+        double t = solve(hi, st);
+        for (int grow = 0; t > tau && grow < 60; ++grow) {
+            lo = hi;
+            hi = 2.0 * hi;
+            t = solve(hi, st);
+        }
+        copy(yp, xp, st);
+        for (int it = 0; it < o.max_bisect; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            t = solve(mid, st);
+            if (std::fabs(t - tau) <= o.tv_tol) {
+                copy(yp, xp, st);
+                break;
+            }
+            if (t > tau) {
+                lo = mid;
+            } else {
+                hi = mid;
+                copy(yp, xp, st);
+            }
+        }
+    }
+
+    // out = projection of in onto {TV <= tau} and the orthant (Dykstra).
+    // Returns the rounds taken.
+    int project(const float *in, float *outp, double tau, hipStream_t st)
+    {
+        float *zp = z->as<float>(), *pp = dp->as<float>(), *qp = dq->as<float>();
+        copy(zp, in, st);
+        hip_check(hipMemsetAsync(pp, 0, (size_t)d * 4, st), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(qp, 0, (size_t)d * 4, st), "hipMemsetAsync");
+        int k = 0;
+        while (k < o.max_outer) {
+            hip_check(exact::launch_dyk_pre(zp, pp, w->as<float>(), d, st), "dyk_pre");
+            tv_ball(tau, st);
+            hip_check(exact::launch_dyk_post(w->as<float>(), y->as<float>(), pp, qp, zp, d,
+                                             parts->as<double>(), out->as<double>(), st),
+                      "dyk_post");
+            ++k;
+            if (std::sqrt(read1(st)) <= o.dyk_tol)
+                break;
+        }
+        copy(outp, zp, st);
+        return k;
+    }
+};
+
+exact_tv_opts tv_opts_of(const exact_tv_opts *opts)
+{
+    exact_tv_opts o;
+    exact_tv_opts_default(&o);
+    if (opts)
+        o = *opts;
+    validate_tv_opts(o);
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+void exact_tv_opts_default(exact_tv_opts *o)
+{
+    if (!o)
+        return;
+    o->tv_tol = 0.01;
+    o->prox_iters = 100;
+    o->max_bisect = 40;
+    o->dyk_tol = 1e-4;
+    o->max_outer = 200;
+}
+
+int exact_tv_norm(int32_t n_pix, const float *x_dev, double *tv_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (n_pix < 1 || n_pix > 16384)
+            fail(-EINVAL, "n_pix must be in [1, 16384]");
+        if (!x_dev || !tv_out)
+            fail(-EINVAL, "NULL pointer");
+        OwnStream own((hipStream_t)stream);
+        DevBuf parts((size_t)exact::num_tv_parts(n_pix) * 8), out(8);
+        hip_check(exact::launch_tv_norm(x_dev, n_pix, parts.as<double>(), out.as<double>(), own.st),
+                  "tv_norm");
+        hip_check(hipMemcpyAsync(tv_out, out.p, 8, hipMemcpyDeviceToHost, own.st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
+        return 0;
+    });
+}
+
+int exact_tv_prox(int32_t n_pix, const float *b_dev, double lam, int32_t iters, float *x_dev,
+                  void *stream)
+{
+    return guarded([&]() -> int {
+        if (n_pix < 1 || n_pix > 16384)
+            fail(-EINVAL, "n_pix must be in [1, 16384]");
+        if (!b_dev || !x_dev)
+            fail(-EINVAL, "NULL pointer");
+        if (!std::isfinite(lam))
+            fail(-EINVAL, "lam must be finite");
+        exact_tv_opts o;
+        exact_tv_opts_default(&o);
+        o.prox_iters = iters;
+        validate_tv_opts(o);
+        OwnStream own((hipStream_t)stream);
+        const long d = (long)n_pix * n_pix;
+        if (!(lam > 0.0)) {
+            hip_check(hipMemcpyAsync(x_dev, b_dev, (size_t)d * 4, hipMemcpyDeviceToDevice, own.st),
+                      "hipMemcpyAsync");
+            hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
+            return 0;
+        }
+        TvWork W(n_pix, o, own.st);
+        W.copy(W.w->as<float>(), b_dev, own.st);
+        W.solve(lam, own.st);
+        W.copy(x_dev, W.x->as<float>(), own.st);
+        hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
+        return 0;
+    });
+}
+
+int exact_project_tv(int32_t n_pix, const float *z_dev, double tau, const exact_tv_opts *opts,
+                     float *out_dev, exact_tv_info *info, void *stream)
+{
+    return guarded([&]() -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (n_pix < 1 || n_pix > 16384)
+            fail(-EINVAL, "n_pix must be in [1, 16384]");
+        if (!z_dev || !out_dev)
+            fail(-EINVAL, "NULL pointer");
+        if (!(std::isfinite(tau) && tau > 0.0))
+            fail(-EINVAL, "tau must be finite and > 0");
+        const exact_tv_opts o = tv_opts_of(opts);
+        OwnStream own((hipStream_t)stream);
+        TvWork W(n_pix, o, own.st);
+        const int rounds = W.project(z_dev, out_dev, tau, own.st);
+        const double tv = W.tv_of(out_dev, own.st);
+        if (info) {
+            info->rounds = rounds;
+            info->solves = W.solves;
+            info->tv = tv;
+            info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return 0;
+    });
+}
+
+int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_dev, float *x_dev,
+                   const exact_solve_opts *opts, double tau, const exact_tv_opts *tv,
+                   exact_solve_info *info, exact_tv_info *tv_info, void *stream)
+{
+    return guarded([&]() -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!(std::isfinite(tau) && tau > 0.0))
+            fail(-EINVAL, "tau must be finite and > 0");
+        exact_solve_opts o;
+        exact_solve_opts_default(&o);
+        if (opts)
+            o = *opts;
+        if (o.stop_mode != EXACT_STOP_NATURAL_RESIDUAL)
+            fail(-EINVAL, "exact_solve_tv stops on the natural residual only");
+        const exact_tv_opts to = tv_opts_of(tv);
+        check_geometry(g);
+        OwnStream own((hipStream_t)stream);
+        hipStream_t st = own.st;
+        DevBuf state(sizeof(SolveState));
+        Problem p;
+        problem_init(p, g, sp, y_dev, x_dev, o, state.as<SolveState>(), st);
+        const Geo G = geo_of(g);
+        const long d = (long)g->N * g->N, n = (long)g->V * g->B;
+        const float gf = (float)p.gamma, inv_n = (float)(1.0 / (double)n);
+        DevBuf grad((size_t)d * 4), v((size_t)d * 4), xh((size_t)d * 4);
+        TvWork W(g->N, to, st);
+        int t = 0, rounds = 0;
+        double rho = -1.0;
+        bool converged = false;
+        // F(z) = (1/n) A^T r(z) from the padded pair of z, into grad
+        auto gradient = [&](const float *zp, const float *zTp) {
+            hip_check(exact::launch_forward_residual(G, zp, zTp, p.Y->as<float>(), p.spec,
+                                                     p.r->as<float>(), nullptr, st),
+                      "forward_residual");
+            hip_check(exact::launch_back(G, p.r->as<float>(), true, grad.as<float>(), inv_n,
+                                         nullptr, st),
+                      "back");
+        };
+        while (t < o.max_iters) {
+            gradient(p.xp->as<float>(), p.xTp->as<float>());
+            hip_check(exact::launch_axpy(x_dev, grad.as<float>(), gf, v.as<float>(), d, st), "axpy");
+            rounds = W.project(v.as<float>(), xh.as<float>(), tau, st);
+            hip_check(exact::launch_pad_pair(xh.as<float>(), p.xhp->as<float>(), p.xhTp->as<float>(),
+                                             g->N, st),
+                      "pad_pair");
+            hip_check(exact::launch_diff2(xh.as<float>(), x_dev, d, W.parts->as<double>(),
+                                          W.out->as<double>(), st),
+                      "diff2");
+            hip_check(hipMemcpyAsync(W.h + 1, W.out->p, 16, hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            rho = W.h[2] > 0.0 ? std::sqrt(W.h[1] / W.h[2]) : -1.0;
+            gradient(p.xhp->as<float>(), p.xhTp->as<float>());
+            hip_check(exact::launch_axpy(x_dev, grad.as<float>(), gf, v.as<float>(), d, st), "axpy");
+            rounds = W.project(v.as<float>(), x_dev, tau, st);
+            hip_check(exact::launch_pad_pair(x_dev, p.xp->as<float>(), p.xTp->as<float>(), g->N, st),
+                      "pad_pair");
+            ++t;
+            if (o.tol > 0.0 && rho >= 0.0 && rho <= o.tol) {
+                converged = true;
+                break;
+            }
+        }
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (info) {
+            info->iters = t;
+            info->resid = rho;
+            info->gamma = p.gamma;
+            info->lambda_hat = p.lam;
+            info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (tv_info) {
+            tv_info->rounds = rounds;
+            tv_info->solves = W.solves;
+            tv_info->tv = W.tv_of(x_dev, st);
+            tv_info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (o.tol > 0.0 && !converged)
+            return EXACT_ENOTCONV;
+        return 0;
+    });
+}
+
+}  // extern "C"

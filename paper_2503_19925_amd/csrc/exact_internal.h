@@ -204,4 +204,28 @@ hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *st
 hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int N,
                             const SolveState *state, hipStream_t st);
 
+// ---- TV-ball and orthant projection (exact_tv.hip)
+
+int num_tv_parts(int N);        // partial sums of k_tv_parts
+int num_flat_parts(long d);     // partial sums of the flat reductions
+// One TV-regularized point x = argmin ||x - b||^2 + lam TV(x) by `iters`
+// FGP steps from zero; lam is read on the device.  p, q, r, s, r2, s2 are
+// work fields of N*N floats.  Launch sequence only (capturable).
+hipError_t launch_prox_graph_body(const float *b, float *p, float *q, float *r, float *s,
+                                  float *r2, float *s2, const double *lam, int iters, float *x,
+                                  int N, hipStream_t st);
+// out[0] = TV(x) in double (parts: num_tv_parts(N) doubles).
+hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st);
+// Dykstra's round around the TV projection: w = z + p before it; after it
+// p = w - y, z = max(0, y + q), q = y + q - z and out[0] = ||z_new - z_old||^2.
+hipError_t launch_dyk_pre(const float *z, const float *p, float *w, long d, hipStream_t st);
+hipError_t launch_dyk_post(const float *w, const float *y, float *p, float *q, float *z, long d,
+                           double *parts, double *out, hipStream_t st);
+// z = x - gamma g.
+hipError_t launch_axpy(const float *x, const float *g, float gamma, float *z, long d,
+                       hipStream_t st);
+// out[0] = ||a - b||^2, out[1] = ||b||^2 in double (parts: 2 num_flat_parts(d)).
+hipError_t launch_diff2(const float *a, const float *b, long d, double *parts, double *out,
+                        hipStream_t st);
+
 }  // namespace exact

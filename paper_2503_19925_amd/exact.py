@@ -34,7 +34,8 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
            "exact_geometry_destroy", "exact_forward", "exact_backproject",
            "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
-           "exact_solver_profile",
+           "exact_solver_profile", "exact_tv_opts_default", "exact_tv_norm", "exact_tv_prox",
+           "exact_project_tv", "exact_solve_tv",
            "exact_count_nonzeros", "exact_run_footprint", "exact_batch_create",
            "exact_batch_add", "exact_batch_step", "exact_batch_sync", "exact_batch_poll",
            "exact_batch_remove", "exact_batch_destroy")
@@ -67,6 +68,16 @@ class SolveOpts(C.Structure):
     _fields_ = [("gamma", C.c_double), ("gamma_scale", C.c_double),
                 ("max_iters", C.c_int32), ("tol", C.c_double), ("stop_mode", C.c_int32),
                 ("check_every", C.c_int32), ("power_iters", C.c_int32)]
+
+
+class TvOpts(C.Structure):
+    _fields_ = [("tv_tol", C.c_double), ("prox_iters", C.c_int32), ("max_bisect", C.c_int32),
+                ("dyk_tol", C.c_double), ("max_outer", C.c_int32)]
+
+
+class TvInfo(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("solves", C.c_int32), ("tv", C.c_double),
+                ("ms", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -112,6 +123,14 @@ def load():
         "exact_batch_poll": ([vp, i32, C.POINTER(SolveInfo)], C.c_int),
         "exact_batch_remove": ([vp, i32], C.c_int),
         "exact_batch_destroy": ([vp], C.c_int),
+        "exact_tv_opts_default": ([C.POINTER(TvOpts)], None),
+        "exact_tv_norm": ([i32, vp, C.POINTER(dbl), vp], C.c_int),
+        "exact_tv_prox": ([i32, vp, dbl, i32, vp, vp], C.c_int),
+        "exact_project_tv": ([i32, vp, dbl, C.POINTER(TvOpts), vp, C.POINTER(TvInfo), vp],
+                             C.c_int),
+        "exact_solve_tv": ([vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts), dbl,
+                            C.POINTER(TvOpts), C.POINTER(SolveInfo), C.POINTER(TvInfo), vp],
+                           C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -393,3 +412,71 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- TV ball
+
+def _tv_opts(**kw):
+    o = TvOpts()
+    load().exact_tv_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown TV option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def _side(t):
+    n = int(round(t.numel() ** 0.5))
+    if n * n != t.numel():
+        raise ValueError("image must be square")
+    return n
+
+
+def exact_tv_norm(x, stream=None):
+    """Isotropic TV (forward differences) of a square device image."""
+    n = _side(x)
+    out = C.c_double()
+    _check("exact_tv_norm", load().exact_tv_norm(n, _dev(x, n * n, "x"), C.byref(out),
+                                                 _stream(stream)))
+    return out.value
+
+
+def exact_tv_prox(b, lam, x, iters=100, stream=None):
+    """x = argmin ||x - b||^2 + lam TV(x) by `iters` FGP steps."""
+    n = _side(b)
+    _check("exact_tv_prox", load().exact_tv_prox(n, _dev(b, n * n, "b"), float(lam), int(iters),
+                                                 _dev(x, n * n, "x"), _stream(stream)))
+    return x
+
+
+def _tv_info(i):
+    return dict(rounds=i.rounds, solves=i.solves, tv=i.tv, ms=i.ms)
+
+
+def exact_project_tv(z, tau, out, stream=None, **tvopts):
+    """out = projection of z onto {TV <= tau} and the orthant (Dykstra).
+    Returns a dict with rounds, solves, tv, ms."""
+    n = _side(z)
+    o = _tv_opts(**tvopts)
+    info = TvInfo()
+    _check("exact_project_tv", load().exact_project_tv(
+        n, _dev(z, n * n, "z"), float(tau), C.byref(o), _dev(out, n * n, "out"), C.byref(info),
+        _stream(stream)))
+    return _tv_info(info)
+
+
+def exact_solve_tv(g, mu, weight, y, x, tau, gamma=0.0, gamma_scale=0.25, max_iters=500,
+                   tol=0.0, power_iters=100, stream=None, background=None, **tvopts):
+    """EXACT over {TV <= tau} and the orthant, in place on x.  Returns
+    (solve info dict with converged, TV info dict)."""
+    sp = _Spec(mu, weight, background, g.n)
+    o = _opts(gamma, gamma_scale, max_iters, tol, 16, power_iters)
+    to = _tv_opts(**tvopts)
+    info, tinfo = SolveInfo(), TvInfo()
+    code = _check("exact_solve_tv", load().exact_solve_tv(
+        g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),
+        float(tau), C.byref(to), C.byref(info), C.byref(tinfo), _stream(stream)))
+    d = _info_dict(info)
+    d["converged"] = (code == 0) if tol > 0 else None
+    return d, _tv_info(tinfo)

@@ -120,3 +120,22 @@ def test_solver_profile_rejects_bad_arguments(lib):
     import ctypes
     out = (ctypes.c_double * 5)()
     assert lib.exact_solver_profile(None, 3, out, None) == -errno.EINVAL
+
+
+def test_tv_entry_points_reject_bad_arguments(lib):
+    from paper_2503_19925_amd.exact import TvOpts
+    o = TvOpts()
+    lib.exact_tv_opts_default(C.byref(o))
+    assert (o.tv_tol, o.prox_iters, o.max_bisect, o.dyk_tol, o.max_outer) == (0.01, 100, 40, 1e-4, 200)
+    out = C.c_double()
+    assert lib.exact_tv_norm(0, None, C.byref(out), None) == -errno.EINVAL
+    assert lib.exact_tv_norm(8, None, C.byref(out), None) == -errno.EINVAL
+    assert lib.exact_tv_prox(8, None, 1.0, 10, None, None) == -errno.EINVAL
+    assert lib.exact_project_tv(8, None, 1.0, None, None, None, None) == -errno.EINVAL
+    fake = C.c_void_p(16)
+    assert lib.exact_project_tv(8, fake, -1.0, None, fake, None, None) == -errno.EINVAL
+    assert "tau" in lib.exact_last_error().decode()
+    o.prox_iters = 0
+    assert lib.exact_project_tv(8, fake, 1.0, C.byref(o), fake, None, None) == -errno.EINVAL
+    assert lib.exact_solve_tv(None, None, None, None, None, 0.0, None, None, None, None) == -errno.EINVAL
+
