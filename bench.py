@@ -160,6 +160,46 @@ def batched_leg(count, torch, exact, synth):
             "serial_p50_s": pct(done_serial, 50), "serial_p99_s": pct(done_serial, 99)}
 
 
+def tv_leg(P, gamma, steps, torch, exact, synth):
+    """The constraint set of the paper's experiments (TV ball and orthant) at
+    the workload's size: one projection of a noisy copy of the phantom onto
+    {TV <= TV(phantom)} and the orthant, and `steps` EG steps over that set
+    from the same start.  The TV bound is the phantom's own (the paper's
+    oracle bound)."""
+    import numpy as np
+    N = P.n_pix
+    truth = synth.phantom_image(P.ell, N, P.pixel_cm)
+    tau = exact.exact_tv_norm(torch.as_tensor(truth.astype(np.float32), device="cuda"))
+    rng = np.random.default_rng(7)
+    z = np.maximum(0, truth + rng.normal(scale=0.2, size=truth.size)).astype(np.float32)
+    zt = torch.as_tensor(z, device="cuda")
+    out = torch.empty_like(zt)
+    info = exact.exact_project_tv(zt, tau, out)
+    fgp_steps = info["solves"] * 100
+    per_step_ms = info["ms"] / max(fgp_steps, 1)
+    bytes_step = 36.0 * N * N       # b, r, s, p, q read; p, q, r', s' written
+    res = {"tau": tau, "projection_ms": info["ms"], "rounds": info["rounds"],
+           "prox_solves": info["solves"], "ms_per_fgp_step": per_step_ms,
+           "fgp_step_roofline": {"bound": "hbm", "achieved": bytes_step / (per_step_ms * 1e-3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": bytes_step / (per_step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "note": "wall time per step including launch gaps and the "
+                                         "host-driven search; 36 B per pixel per step"}}
+    log("tv projection at %d^2: %.1f ms, %d rounds, %d solves" % (N, info["ms"], info["rounds"],
+                                                                  info["solves"]))
+    if steps > 0:
+        g = exact.Geometry(P.n_pix, P.n_views, P.n_bins)
+        y = torch.as_tensor(P.y, device="cuda")
+        x = torch.as_tensor(z, device="cuda")
+        sinfo, tinfo = exact.exact_solve_tv(g, P.mu, P.I, y, x, tau, gamma=gamma, max_iters=steps)
+        g.close()
+        res.update({"eg_steps": sinfo["iters"], "ms_per_eg_step": sinfo["ms"] / max(sinfo["iters"], 1),
+                    "eg_prox_solves": tinfo["solves"], "tv_after": tinfo["tv"]})
+        log("tv EG: %d steps, %.1f ms/step, %d solves" % (sinfo["iters"], res["ms_per_eg_step"],
+                                                          tinfo["solves"]))
+    return res
+
+
 def served_leg(count, torch, exact, synth):
     from paper_2503_19925_amd.serve import GpuBackend, Request, Server, summarize
     stream = synth.served_stream(300, 20.0, 501)[:count]
@@ -192,6 +232,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
+    ap.add_argument("--tv-steps", type=int, default=2,
+                    help="EG steps over the TV ball and orthant after one projection "
+                         "(-1 skips the TV leg)")
     ap.add_argument("--background-steps", type=int, default=100,
                     help="timed steps of the workload with known materials (0 to skip)")
     ap.add_argument("--served", type=int, default=40,
@@ -313,6 +356,11 @@ def main():
                       "relative_to_plain": ms_bg / ms_step}
         log("known background: %.4f ms/step" % ms_bg)
 
+    tv = None
+    if args.tv_steps >= 0:
+        Pt = synth.config_problem(args.workload, with_truth=False)
+        tv = tv_leg(Pt, info["gamma"], args.tv_steps, torch, exact, synth)
+
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
     served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
     if served:
@@ -357,6 +405,7 @@ def main():
                              "frac": fwd_achieved / HBM_PEAK_GBS},
         "to_tol": to_tol,
         "background": background,
+        "tv_ball": tv,
         "cpu_baseline": base,
         "batched": batched,
         "served": served,
