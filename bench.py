@@ -271,9 +271,18 @@ def main():
     y = torch.as_tensor(P.y, device=dev)
     x = torch.zeros(g.d, device=dev)
 
-    # set-up (untimed): step size by power iteration, resident state, graph
+    # set-up (outside the timed region, reported): step size by power
+    # iteration (100 products with A^T A), resident state, graph capture
+    torch.cuda.synchronize()
+    t_set = time.perf_counter()
     solver = exact.Solver(g, P.mu, P.I, y, x,
                           max_iters=args.warmup + args.steps + args.profile_steps, tol=0.0)
+    setup_ms = 1e3 * (time.perf_counter() - t_set)
+    torch.cuda.synchronize()
+    t_set = time.perf_counter()
+    lam_only, _ = exact.exact_step_size(g, None, None, 100)
+    power_ms = 1e3 * (time.perf_counter() - t_set)
+    log("set-up %.1f ms (power iteration alone %.1f ms)" % (setup_ms, power_ms))
     solver.step(args.warmup)
     torch.cuda.synchronize()
     _, info_w = solver.poll()
@@ -394,6 +403,8 @@ def main():
         "back_ms": t_back,
         "nnz": nnz,
         "step_phase_ms": dict(zip(exact.PHASE_NAMES, phase_ms)),
+        "setup_ms": setup_ms,
+        "power_iteration_ms": power_ms,
         "step_forward_grays": 2 * g.n / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9,
         "step_back_grays": 2 * g.n / (sum(t_bu) * 1e-3) / 1e9,
         "roofline": {"kernel": "k_back_update", "bound": "hbm", "achieved": achieved,

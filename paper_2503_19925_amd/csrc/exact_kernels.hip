@@ -87,6 +87,34 @@ __device__ __forceinline__ float tent(double d)
     return __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
 }
 
+// Fixed-order sum over the kRedThreads threads of the block's x-y plane
+// with one barrier: a butterfly within each wave, then the four wave sums in
+// order.  Threads with active = false (other z planes) contribute nothing
+// and only take part in the barrier; every thread gets the sum.
+template <int NV>
+__device__ __forceinline__ void plane_sum(double (&v)[NV], double (*lds)[kRedThreads / 64],
+                                          bool active)
+{
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        for (int off = 32; off > 0; off >>= 1)
+            v[q] += __shfl_xor(v[q], off);
+    if (active && (t & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            lds[q][t >> 6] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w)
+            s += lds[q][w];
+        v[q] = s;
+    }
+}
+
 // ---------------------------------------------------------------- forward
 
 #ifndef EXACT_FWD_SEGS
@@ -481,7 +509,7 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
                                                 double *__restrict__ part2, int tx, int ty)
 {
     __shared__ float tile[kBackY][kBackX + 1];
-    __shared__ double red[2][kRedThreads];
+    __shared__ double red[2][kRedThreads / 64];
     const bool plane0 = threadIdx.z == 0;
     const int Np = padded_cols(N);
     const int ix = tx * kBackX + threadIdx.x;
@@ -507,7 +535,7 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
         zTp[(size_t)ixT * Np + kPadX + iyT] = tile[threadIdx.x][threadIdx.y];
     if (kPartials) {
         double v2[2] = {num, den};
-        block_sum<2>(v2, red, plane0);
+        plane_sum<2>(v2, red, plane0);
         if (plane0 && threadIdx.x == 0 && threadIdx.y == 0) {
             part2[0] = v2[0];
             part2[1] = v2[1];

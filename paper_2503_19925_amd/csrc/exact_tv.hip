@@ -41,27 +41,57 @@ __device__ __forceinline__ float primal_at(const float *__restrict__ b,
 //   (r2, s2) = (p', q') + w ((p', q') - (p, q)).
 // L^T(x) = (x_ij - x_{i+1,j}, x_ij - x_{i,j+1}); the last row of p and the
 // last column of q stay zero.  lam (device) is the TV weight; l = lam / 2.
+//
+// A 32 x 8 block stages r (one row above), s (one column left) and b for its
+// tile plus one row below and one column right in LDS (zeros outside the
+// image), forms x on that extended tile, then updates its own pixels.
 __global__ __launch_bounds__(kTvX *kTvY) void k_fgp_step(
     const float *__restrict__ b, const float *__restrict__ r, const float *__restrict__ s,
     float *__restrict__ p, float *__restrict__ q, float *__restrict__ r2,
     float *__restrict__ s2, const double *__restrict__ lam, float w, int N)
 {
-    const int j = blockIdx.x * kTvX + threadIdx.x;
-    const int i = blockIdx.y * kTvY + threadIdx.y;
-    if (i >= N || j >= N)
-        return;
+    constexpr int RY = kTvY + 2, RX = kTvX + 1;     // r: rows i0-1 .. i0+8
+    constexpr int SY = kTvY + 1, SX = kTvX + 2;     // s: cols j0-1 .. j0+32
+    constexpr int XY = kTvY + 1, XX = kTvX + 1;     // b, x: tile + 1 row + 1 column
+    __shared__ float Rl[RY][RX], Sl[SY][SX], Bl[XY][XX], Xl[XY][XX];
+    const int tid = threadIdx.x + threadIdx.y * kTvX;
+    const int i0 = blockIdx.y * kTvY, j0 = blockIdx.x * kTvX;
     const float l = (float)(*lam * 0.5);
     const float inv8l = (float)(1.0 / (8.0 * (*lam * 0.5)));
-    const size_t c = (size_t)i * N + j;
-    const float xc = primal_at(b, r, s, l, N, i, j);
-    float a = 0.f, bq = 0.f;
+    for (int k = tid; k < RY * RX; k += kTvX * kTvY) {
+        const int gi = i0 - 1 + k / RX, gj = j0 + k % RX;
+        Rl[k / RX][k % RX] = (gi >= 0 && gi < N && gj < N) ? r[(size_t)gi * N + gj] : 0.f;
+    }
+    for (int k = tid; k < SY * SX; k += kTvX * kTvY) {
+        const int gi = i0 + k / SX, gj = j0 - 1 + k % SX;
+        Sl[k / SX][k % SX] = (gi < N && gj >= 0 && gj < N) ? s[(size_t)gi * N + gj] : 0.f;
+    }
+    for (int k = tid; k < XY * XX; k += kTvX * kTvY) {
+        const int gi = i0 + k / XX, gj = j0 + k % XX;
+        Bl[k / XX][k % XX] = (gi < N && gj < N) ? b[(size_t)gi * N + gj] : 0.f;
+    }
+    __syncthreads();
+    // x = b - l (r + s - r_up - s_left) on the extended tile
+    for (int k = tid; k < XY * XX; k += kTvX * kTvY) {
+        const int a = k / XX, c = k % XX;
+        const float L = ((Rl[a + 1][c] + Sl[a][c + 1]) - Rl[a][c]) - Sl[a][c];
+        Xl[a][c] = fmaf(-l, L, Bl[a][c]);
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.y, j = j0 + threadIdx.x;
+    if (i >= N || j >= N)
+        return;
+    const int ty = threadIdx.y, tx = threadIdx.x;
+    const float xc = Xl[ty][tx];
+    float av = 0.f, bv = 0.f;
     if (i + 1 < N)
-        a = fmaf(xc - primal_at(b, r, s, l, N, i + 1, j), inv8l, r[c]);
+        av = fmaf(xc - Xl[ty + 1][tx], inv8l, Rl[ty + 1][tx]);
     if (j + 1 < N)
-        bq = fmaf(xc - primal_at(b, r, s, l, N, i, j + 1), inv8l, s[c]);
-    const float nrm = sqrtf(fmaf(a, a, bq * bq));
+        bv = fmaf(xc - Xl[ty][tx + 1], inv8l, Sl[ty][tx + 1]);
+    const float nrm = sqrtf(fmaf(av, av, bv * bv));
     const float den = fmaxf(nrm, 1.f);
-    const float pn = a / den, qn = bq / den;
+    const float pn = av / den, qn = bv / den;
+    const size_t c = (size_t)i * N + j;
     const float po = p[c], qo = q[c];
     p[c] = pn;
     q[c] = qn;
