@@ -60,6 +60,11 @@
  *  Teboulle 2009) with a fixed number of steps; the intersection by
  *  Dykstra's algorithm (eq. projection-intersection).
  *
+ *  Dense measurements (the Gaussian measurement model, Sec. 2.2, and its
+ *  experiment in Sec. 5): the same model and operator with an explicit
+ *  matrix A of n rows a_i; EG over a ball centred at the origin (the
+ *  bounded set of Assumption assump-X) or the whole space.
+ *
  *  Step size (Theorem 2, Sec. 2.1; Lipschitz bound in Sec. 4.2):
  *  L <= lambda_max(Sigma) * sum_k J_k mu_k with Sigma = A^T A / n and
  *  J_k = sum_j I[j][k]; gamma = c / L.  lambda_max comes from ora_power.

@@ -784,6 +784,114 @@ int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const doub
     return t;
 }
 
+/* ------------------------------------- dense measurements (Sec. 2.2, Sec. 5) */
+
+/*
+ * The operator with an explicit measurement matrix A (n rows a_i, d
+ * columns, row-major), as in the Gaussian measurement model: the same
+ * single-index model and F(x) = (1/n) sum_i r_i a_i with
+ * r_i = sum_j y[j][i] - sum_j sum_k I[j][k] exp(-mu_k max(<a_i, x>, 0)).
+ */
+static void FN(dense_F)(long n, long d, const REAL *A, const FN(spec) *sp, const REAL *x,
+                        REAL *F, REAL *s, REAL *r)
+{
+    for (long i = 0; i < n; ++i) {
+        REAL acc = 0;
+        for (long j = 0; j < d; ++j)
+            acc += A[i * d + j] * x[j];
+        s[i] = acc;
+    }
+    FN(residual)(n, sp->K, sp->Wn, sp->mu, sp->Iwk, sp->y, s, 0, r, 0);
+    for (long j = 0; j < d; ++j)
+        F[j] = 0;
+    for (long i = 0; i < n; ++i)
+        for (long j = 0; j < d; ++j)
+            F[j] += r[i] * A[i * d + j];
+    for (long j = 0; j < d; ++j)
+        F[j] = F[j] / (REAL)n;
+}
+
+/* Projection onto the ball {||x||_2 <= radius} (radius <= 0: no constraint). */
+static void FN(ball)(long d, REAL radius, REAL *x)
+{
+    if (!(radius > 0))
+        return;
+    REAL nrm = sqrt(FN(dot)(x, x, d));
+    if (nrm > radius)
+        for (long j = 0; j < d; ++j)
+            x[j] = x[j] * (radius / nrm);
+}
+
+static FN(spec) FN(load_dense_spec)(long n, int K, int Wn, const double *mu, const double *Iwk,
+                                    const double *y)
+{
+    FN(spec) sp;
+    sp.K = K;
+    sp.Wn = Wn;
+    sp.mu = FN(to_real)(mu, K);
+    sp.Iwk = FN(to_real)(Iwk, (long)Wn * K);
+    sp.y = FN(to_real)(y, (long)Wn * n);
+    sp.bg = 0;
+    return sp;
+}
+
+void FN(ora_dense_operator)(long n, long d, const double *A, int K, int Wn, const double *mu,
+                            const double *Iwk, const double *y, const double *x, double *F)
+{
+    FN(spec) sp = FN(load_dense_spec)(n, K, Wn, mu, Iwk, y);
+    REAL *Ar = FN(to_real)(A, n * d), *xr = FN(to_real)(x, d);
+    REAL *Fr = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n), *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    FN(dense_F)(n, d, Ar, &sp, xr, Fr, s, r);
+    FN(to_double)(Fr, d, F);
+    FN(free_spec)(&sp);
+    free(Ar); free(xr); free(Fr); free(s); free(r);
+}
+
+/*
+ * Projected extragradient with a dense A over X = {||x|| <= radius} (the
+ * bounded set of Assumption assump-X centred at the origin; radius <= 0 is
+ * the whole space): both half-steps from x_t as in eq. extragrad-method.
+ * rho_hist and tol as in ora_eg.  Returns the steps taken.
+ */
+int FN(ora_dense_eg)(long n, long d, const double *A, int K, int Wn, const double *mu,
+                     const double *Iwk, const double *y, double *x, double gamma, double radius,
+                     int max_iters, double tol, double *rho_hist)
+{
+    FN(spec) sp = FN(load_dense_spec)(n, K, Wn, mu, Iwk, y);
+    REAL *Ar = FN(to_real)(A, n * d), *xt = FN(to_real)(x, d);
+    REAL *xh = (REAL *)malloc(sizeof(REAL) * (size_t)d), *F = (REAL *)malloc(sizeof(REAL) * (size_t)d);
+    REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n), *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
+    REAL gm = (REAL)gamma, R = (REAL)radius;
+    int t;
+    for (t = 1; t <= max_iters; ++t) {
+        FN(dense_F)(n, d, Ar, &sp, xt, F, s, r);
+        for (long j = 0; j < d; ++j)
+            xh[j] = xt[j] - gm * F[j];
+        FN(ball)(d, R, xh);
+        REAL num = 0, den = 0;
+        for (long j = 0; j < d; ++j) {
+            num += (xh[j] - xt[j]) * (xh[j] - xt[j]);
+            den += xt[j] * xt[j];
+        }
+        double rho = den > 0 ? (double)sqrt(num / den) : -1.0;
+        if (rho_hist)
+            rho_hist[t - 1] = rho;
+        FN(dense_F)(n, d, Ar, &sp, xh, F, s, r);
+        for (long j = 0; j < d; ++j)
+            xt[j] = xt[j] - gm * F[j];
+        FN(ball)(d, R, xt);
+        if (tol > 0 && rho >= 0 && rho <= tol)
+            break;
+    }
+    if (t > max_iters)
+        t = max_iters;
+    FN(to_double)(xt, d, x);
+    FN(free_spec)(&sp);
+    free(Ar); free(xt); free(xh); free(F); free(s); free(r);
+    return t;
+}
+
 /*
  * Largest eigenvalue of Sigma = A^T A / n by power iteration from the
  * constant unit vector, with Rayleigh quotients; stops when the quotient

@@ -113,6 +113,13 @@ def _lib():
                           C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                           C.c_double, C.c_int, C.c_void_p]
             f.restype = C.c_int
+            f = getattr(_LIB, "ora_dense_operator_" + p)
+            f.argtypes = [C.c_long, C.c_long, _dp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+            f.restype = None
+            f = getattr(_LIB, "ora_dense_eg_" + p)
+            f.argtypes = [C.c_long, C.c_long, _dp, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
+                          C.c_double, C.c_double, C.c_int, C.c_double, C.c_void_p]
+            f.restype = C.c_int
             f = getattr(_LIB, "ora_power_" + p)
             f.argtypes = [_gp, C.c_int, C.c_double, C.POINTER(C.c_int)]
             f.restype = C.c_double
@@ -329,6 +336,35 @@ def eg_tv(g, mu, I, y, x1, gamma, max_iters, tau, tol=0.0, prec="f64", bg=None, 
                            int(max_iters), float(tol), float(tau), float(kw["tv_tol"]),
                            int(kw["prox_iters"]), int(kw["max_bisect"]), float(kw["dyk_tol"]),
                            int(kw["max_outer"]), _ptr(hist))
+    return x, int(t), hist[:t]
+
+
+def dense_operator(A, mu, I, y, x, prec="f64"):
+    """F(x) = (1/n) A^T r for an explicit n x d matrix A (row-major)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n, d = A.shape
+    mu = _f64(mu)
+    K = mu.size
+    I = _f64(I)
+    Wn = I.size // K
+    F = np.empty(d)
+    _fn("dense_operator", prec)(n, d, A.ravel(), K, Wn, mu, I, _f64(y, Wn * n), _f64(x, d), F)
+    return F
+
+
+def dense_eg(A, mu, I, y, x1, gamma, max_iters, radius=0.0, tol=0.0, prec="f64"):
+    """Projected extragradient with an explicit A over the ball of the given
+    radius around 0 (radius <= 0: unconstrained).  Returns (x, steps, rho)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n, d = A.shape
+    mu = _f64(mu)
+    K = mu.size
+    I = _f64(I)
+    Wn = I.size // K
+    x = _f64(x1, d).copy()
+    hist = np.full(max(int(max_iters), 1), np.nan)
+    t = _fn("dense_eg", prec)(n, d, A.ravel(), K, Wn, mu, I, _f64(y, Wn * n), x, float(gamma),
+                              float(radius), int(max_iters), float(tol), _ptr(hist))
     return x, int(t), hist[:t]
 
 

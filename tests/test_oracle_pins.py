@@ -657,6 +657,88 @@ def test_eg_tv_noiseless_recovery(ora):
     assert np.linalg.norm(x - x_star) <= 1e-6 * np.linalg.norm(x_star), t
 
 
+# ------------------------------- dense measurements (Gaussian model, Sec. 5)
+
+def _gaussian(d, mult, seed, norm=3.0):
+    rng = np.random.default_rng(seed)
+    n = mult * d
+    A = rng.normal(size=(n, d))
+    xs = rng.normal(size=d)
+    xs *= norm / np.linalg.norm(xs)
+    y = np.exp(-np.maximum(A @ xs, 0.0))          # noiseless, mu = 1, Ibar = 1
+    return A, xs, y
+
+
+def test_dense_operator_equals_matrix_free_ct(ora):
+    """With A the explicit Joseph matrix (built pixel by pixel) the dense
+    operator is the CT operator."""
+    N, V, B = 10, 9, 15
+    g = ora.Geom(N, V, B)
+    A = dense_A(N, V, B, g.pixel_cm, g.bin_cm)
+    mu, I = synth.spectrum(6, 2, 1e4)
+    rng = np.random.default_rng(44)
+    x = rng.uniform(0, 1.5, g.d)
+    y = rng.poisson(5000, 2 * g.n).astype(np.float64)
+    F = ora.dense_operator(A, mu, I, y, x)
+    Fct = ora.operator(g, mu, I, y, x)
+    assert np.abs(F - Fct).max() <= 1e-11 * np.abs(Fct).max()
+
+
+def test_dense_scalar_closed_form(ora):
+    """d = n = 1, a = 1, monochromatic: F(x) = y - exp(-max(x, 0)); one EG
+    step from 0 by hand."""
+    y = math.exp(-1.0)
+    gam = 0.7
+    xh = 0.0 - gam * (y - 1.0)
+    x2 = 0.0 - gam * (y - math.exp(-xh))
+    x, t, rho = ora.dense_eg(np.ones((1, 1)), [1.0], [1.0], [y], [0.0], gam, 1)
+    assert abs(x[0] - x2) <= 1e-15 and t == 1
+    assert rho[0] == -1.0
+
+
+def test_dense_gaussian_fixed_point_and_monotone(ora):
+    """Noiseless Gaussian data: F(x*) = 0; the monotonicity identity of
+    Sec. 1.2 holds with the clamp active (a_i have both signs)."""
+    A, xs, y = _gaussian(15, 10, 45)
+    assert np.abs(ora.dense_operator(A, [1.0], [1.0], y, xs)).max() <= 1e-15
+    rng = np.random.default_rng(46)
+    psi = lambda s: np.exp(-np.maximum(s, 0.0))  # noqa: E731
+    for _ in range(5):
+        x, z = rng.normal(size=15), rng.normal(size=15)
+        Fx = ora.dense_operator(A, [1.0], [1.0], y, x)
+        Fz = ora.dense_operator(A, [1.0], [1.0], y, z)
+        lhs = np.dot(Fx - Fz, x - z)
+        sx, sz = A @ x, A @ z
+        rhs = np.mean((psi(sz) - psi(sx)) * (sx - sz))
+        assert lhs >= 0 and abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+def test_dense_gaussian_linear_convergence(ora):
+    """The Gaussian experiment's set-up (noiseless, monochromatic, ||x*|| = 3,
+    gamma = 0.25): the error falls at every checkpoint and the iterates reach
+    x* to 1e-5 (Theorem 1's linear rate)."""
+    A, xs, y = _gaussian(12, 40, 47)
+    errs = []
+    for T in (500, 1000, 2000, 4000):
+        x, t, _ = ora.dense_eg(A, [1.0], [1.0], y, np.zeros(12), 0.25, T)
+        errs.append(np.linalg.norm(x - xs) / 3.0)
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    # linear: doubling the steps at least squares the contraction, roughly
+    assert errs[3] <= 2 * errs[2] ** 2 / errs[1], errs
+    assert errs[-1] <= 1e-7, errs
+
+
+def test_dense_ball_constraint(ora):
+    """Over a ball smaller than ||x*|| every iterate stays in the ball and
+    the limit sits on its boundary."""
+    A, xs, y = _gaussian(10, 20, 48)
+    R = 2.0
+    for T in (1, 5, 50, 400):
+        x, t, _ = ora.dense_eg(A, [1.0], [1.0], y, np.zeros(10), 0.25, T, radius=R)
+        assert np.linalg.norm(x) <= R * (1 + 1e-12)
+    assert abs(np.linalg.norm(x) - R) <= 1e-6
+
+
 # ------------------------------------------------- the oracle's own rounding
 
 def test_long_double_agreement(ora):
