@@ -200,6 +200,40 @@ def tv_leg(P, gamma, steps, torch, exact, synth):
     return res
 
 
+def dense_leg(d, mult, steps, torch, exact):
+    """The Gaussian measurement model at scale: A is (mult d) x d standard
+    normal float32, drawn on the device with a seeded generator, x* of norm 3,
+    noiseless monochromatic counts y = exp(-max(A x*, 0)) (the set-up of the
+    paper's Gaussian experiment, larger).  Times `steps` EG steps with
+    gamma = 0.25; each step evaluates F twice, each evaluation reads A once."""
+    n = mult * d
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(601)
+    A = torch.randn(n, d, device="cuda", generator=gen)
+    xs = torch.randn(d, device="cuda", generator=gen)
+    xs *= 3.0 / torch.linalg.vector_norm(xs)
+    y = torch.exp(-torch.clamp(A @ xs, min=0.0))
+    x = torch.zeros(d, device="cuda")
+    exact.exact_dense_solve(A, [1.0], [1.0], y, x, gamma=0.25, max_iters=2)   # warm-up
+    x.zero_()
+    torch.cuda.synchronize()
+    info = exact.exact_dense_solve(A, [1.0], [1.0], y, x, gamma=0.25, max_iters=steps,
+                                   check_every=steps)
+    ms_step = info["ms"] / steps
+    bytes_f = 4.0 * n * d
+    achieved = 2 * bytes_f / (ms_step * 1e-3) / 1e9
+    err = float(torch.linalg.vector_norm(x - xs) / 3.0)
+    log("dense %d x %d: %.3f ms per EG step (%.1f GB/s over two reads of A)" % (
+        n, d, ms_step, achieved))
+    del A
+    return {"n": n, "d": d, "steps": steps, "ms_per_step": ms_step,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "note": "4 n d bytes per F evaluation, two per step; wall time of "
+                                 "the call, set-up included"},
+            "rel_error_after": err}
+
+
 def served_leg(count, torch, exact, synth):
     from paper_2503_19925_amd.serve import GpuBackend, Request, Server, summarize
     stream = synth.served_stream(300, 20.0, 501)[:count]
@@ -232,6 +266,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
+    ap.add_argument("--dense-steps", type=int, default=50,
+                    help="EG steps of the dense Gaussian-model leg (0 skips it)")
     ap.add_argument("--tv-steps", type=int, default=2,
                     help="EG steps over the TV ball and orthant after one projection "
                          "(-1 skips the TV leg)")
@@ -370,6 +406,8 @@ def main():
         Pt = synth.config_problem(args.workload, with_truth=False)
         tv = tv_leg(Pt, info["gamma"], args.tv_steps, torch, exact, synth)
 
+    dense = dense_leg(4096, 20, args.dense_steps, torch, exact) if args.dense_steps > 0 else None
+
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
     served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
     if served:
@@ -417,6 +455,7 @@ def main():
         "to_tol": to_tol,
         "background": background,
         "tv_ball": tv,
+        "dense_gaussian": dense,
         "cpu_baseline": base,
         "batched": batched,
         "served": served,

@@ -265,6 +265,29 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
                    exact_solve_info *info, exact_tv_info *tv_info, void *stream);
 
 /*
+ * EXACT with an explicit measurement matrix (the Gaussian measurement model
+ * of paper Sec. 2.2, Assumption Gaussian-assump, and its experiment in
+ * Sec. 5): A is n x d, row-major float32 on the device (a_i its rows; any
+ * real entries), the model and operator are those above,
+ *     F(x) = (1/n) sum_i r_i a_i,  r_i = sum_j y[j][i] - sum_k J_k exp(-mu_k max(<a_i, x>, 0)),
+ * with y [Wn][n] and the spectrum as in exact_spectrum (background must be
+ * NULL).  1 <= d <= 4096.  Each evaluation of F reads A once.
+ *
+ * exact_dense_operator writes F(x) to F_dev [d].
+ * exact_dense_solve runs eq. extragrad-method over X = {||x||_2 <= radius}
+ * (the bounded set of Assumption assump-X, centred at the origin; radius
+ * <= 0 means the whole space), x_dev [d] in/out, x_1 finite.  opts as for
+ * exact_solve (natural-residual stop only); gamma <= 0 selects
+ * gamma_scale / (lambda_max(A^T A / n) sum_k J_k mu_k) with lambda_max by
+ * power iteration.  Blocking; info nullable.
+ */
+int exact_dense_operator(int32_t n, int32_t d, const float *A_dev, const exact_spectrum *sp,
+                         const float *y_dev, const float *x_dev, float *F_dev, void *stream);
+int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spectrum *sp,
+                      const float *y_dev, float *x_dev, const exact_solve_opts *opts,
+                      double radius, exact_solve_info *info, void *stream);
+
+/*
  * Resident solver: the same iteration as exact_solve, split so that a caller
  * can keep the run's state on the device and advance it in pieces.
  *

@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libexact.so")
-SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_tv.hip", "csrc/exact_capi.hip"]
+SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_tv.hip", "csrc/exact_dense.hip",
+           "csrc/exact_capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

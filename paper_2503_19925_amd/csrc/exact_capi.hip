@@ -1519,3 +1519,168 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Explicit measurement matrix (the Gaussian measurement model)
+
+namespace {
+
+// Device state of one dense problem: window sums of y, the collapsed
+// spectrum, the partial gradients and the half-step iterate.
+struct DenseWork {
+    long n = 0;
+    int d = 0, K = 0;
+    std::unique_ptr<DevBuf> Y, J, mu, parts, parts2, xh;
+
+    DenseWork(long n_, int d_, const exact_spectrum *sp, const float *y_dev, SpecArg &a,
+              double *sjm, hipStream_t st)
+        : n(n_), d(d_)
+    {
+        if (n < 1 || d < 1 || d > exact::kDenseMaxCols)
+            fail(-EINVAL, "need n >= 1 and 1 <= d <= " + std::to_string(exact::kDenseMaxCols));
+        if (!y_dev)
+            fail(-EINVAL, "y is NULL");
+        a = make_spec(sp, sjm);
+        if (sp->background)
+            fail(-EINVAL, "a known background applies to CT scans only");
+        K = a.K;
+        Y.reset(new DevBuf((size_t)n * 4));
+        J.reset(new DevBuf((size_t)K * 4));
+        mu.reset(new DevBuf((size_t)K * 4));
+        parts.reset(new DevBuf((size_t)exact::dense_blocks(n) * d * 4));
+        parts2.reset(new DevBuf((size_t)exact::dense_sum_groups(n) * d * 4));
+        xh.reset(new DevBuf((size_t)d * 4));
+        hip_check(hipMemcpyAsync(J->p, a.J, (size_t)K * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(mu->p, a.mu, (size_t)K * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        DevBuf bad(4);
+        hip_check(hipMemsetAsync(bad.p, 0, 4, st), "hipMemsetAsync");
+        hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, Y->as<float>(), bad.as<int32_t>(), st),
+                  "window_sum");
+        int32_t hbad = 0;
+        hip_check(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (hbad)
+            fail(-EINVAL, "y contains negative or non-finite counts");
+    }
+
+    hipError_t F(const float *A, const float *x, bool linear, const int32_t *skip, hipStream_t st)
+    {
+        return exact::launch_dense_F(A, n, d, x, Y->as<float>(), J->as<float>(), mu->as<float>(), K,
+                                     linear, parts->as<float>(), parts2->as<float>(), skip, st);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int exact_dense_operator(int32_t n, int32_t d, const float *A_dev, const exact_spectrum *sp,
+                         const float *y_dev, const float *x_dev, float *F_dev, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!A_dev || !x_dev || !F_dev)
+            fail(-EINVAL, "NULL buffer");
+        OwnStream own((hipStream_t)stream);
+        SpecArg a;
+        DenseWork W(n, d, sp, y_dev, a, nullptr, own.st);
+        hip_check(W.F(A_dev, x_dev, false, nullptr, own.st), "dense_F");
+        hip_check(exact::launch_dense_finish(W.parts2->as<float>(), n, d, 0, x_dev, 0.f, 0.0, F_dev,
+                                             nullptr, own.st),
+                  "dense_finish");
+        hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
+        return 0;
+    });
+}
+
+int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spectrum *sp,
+                      const float *y_dev, float *x_dev, const exact_solve_opts *opts,
+                      double radius, exact_solve_info *info, void *stream)
+{
+    return guarded([&]() -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!A_dev || !x_dev)
+            fail(-EINVAL, "NULL buffer");
+        if (!std::isfinite(radius))
+            fail(-EINVAL, "radius must be finite (<= 0 for no constraint)");
+        exact_solve_opts o;
+        exact_solve_opts_default(&o);
+        if (opts)
+            o = *opts;
+        validate_opts(o);
+        if (o.stop_mode != EXACT_STOP_NATURAL_RESIDUAL)
+            fail(-EINVAL, "exact_dense_solve stops on the natural residual only");
+        OwnStream own((hipStream_t)stream);
+        hipStream_t st = own.st;
+        SpecArg a;
+        double sjm = 0.0;
+        DenseWork W(n, d, sp, y_dev, a, &sjm, st);
+        DevBuf state(sizeof(SolveState));
+        PinnedState hs;
+        SolveState *S = state.as<SolveState>();
+        double gamma = o.gamma, lam = 0.0;
+        if (gamma <= 0.0) {
+            // lambda_max(A^T A / n) by power iteration from the constant unit vector
+            DevBuf v0((size_t)d * 4), v1((size_t)d * 4);
+            hip_check(exact::launch_fill(v0.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st),
+                      "fill");
+            hip_check(exact::launch_state_init(S, 0.0, 0, 0, st), "state_init");
+            float *vin = v0.as<float>(), *vout = v1.as<float>();
+            for (int it = 1; it <= o.power_iters; ++it) {
+                hip_check(W.F(A_dev, vin, true, nullptr, st), "dense_F");
+                hip_check(exact::launch_dense_finish(W.parts2->as<float>(), n, d, 3, vin, 0.f, 0.0,
+                                                     vout, S, st),
+                          "dense_finish");
+                std::swap(vin, vout);
+                read_state(S, hs, st);
+                const double lam_new = hs.h->lam;
+                if (!(std::isfinite(lam_new) && lam_new > 0.0))
+                    fail(-EIO, "power iteration produced a non-positive eigenvalue estimate");
+                const bool done = it > 1 && std::fabs(lam_new - lam) <= 1e-7 * std::fabs(lam_new);
+                lam = lam_new;
+                if (done)
+                    break;
+            }
+            gamma = o.gamma_scale / (lam * sjm);
+        }
+        hip_check(exact::launch_state_init(S, o.tol, o.max_iters, 0, st), "state_init");
+        const float gf = (float)gamma;
+        float *xh = W.xh->as<float>();
+        Graph step;
+        step.capture(st, [&]() {
+            hipError_t e = W.F(A_dev, x_dev, false, &S->done, st);
+            if (e == hipSuccess)
+                e = exact::launch_dense_finish(W.parts2->as<float>(), n, d, 1, x_dev, gf, radius, xh,
+                                               S, st);
+            if (e == hipSuccess)
+                e = W.F(A_dev, xh, false, &S->done, st);
+            if (e == hipSuccess)
+                e = exact::launch_dense_finish(W.parts2->as<float>(), n, d, 2, x_dev, gf, radius,
+                                               x_dev, S, st);
+            return e;
+        });
+        int launched = 0;
+        while (launched < o.max_iters) {
+            const int chunk = std::min(o.check_every, o.max_iters - launched);
+            for (int c = 0; c < chunk; ++c)
+                hip_check(hipGraphLaunch(step.exec, st), "graph launch");
+            launched += chunk;
+            read_state(S, hs, st);
+            if (hs.h->done)
+                break;
+        }
+        read_state(S, hs, st);
+        step.reset();
+        if (info) {
+            info->iters = o.max_iters == 0 ? 0 : hs.h->t;
+            info->resid = o.max_iters == 0 ? -1.0 : hs.h->rho;
+            info->gamma = gamma;
+            info->lambda_hat = lam;
+            info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (o.tol > 0.0 && !hs.h->converged)
+            return EXACT_ENOTCONV;
+        return 0;
+    });
+}
+
+}  // extern "C"

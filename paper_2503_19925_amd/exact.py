@@ -35,7 +35,7 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
            "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
            "exact_solver_profile", "exact_tv_opts_default", "exact_tv_norm", "exact_tv_prox",
-           "exact_project_tv", "exact_solve_tv",
+           "exact_project_tv", "exact_solve_tv", "exact_dense_operator", "exact_dense_solve",
            "exact_count_nonzeros", "exact_run_footprint", "exact_batch_create",
            "exact_batch_add", "exact_batch_step", "exact_batch_sync", "exact_batch_poll",
            "exact_batch_remove", "exact_batch_destroy")
@@ -123,6 +123,9 @@ def load():
         "exact_batch_poll": ([vp, i32, C.POINTER(SolveInfo)], C.c_int),
         "exact_batch_remove": ([vp, i32], C.c_int),
         "exact_batch_destroy": ([vp], C.c_int),
+        "exact_dense_operator": ([i32, i32, vp, C.POINTER(Spectrum), vp, vp, vp, vp], C.c_int),
+        "exact_dense_solve": ([i32, i32, vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts), dbl,
+                               C.POINTER(SolveInfo), vp], C.c_int),
         "exact_tv_opts_default": ([C.POINTER(TvOpts)], None),
         "exact_tv_norm": ([i32, vp, C.POINTER(dbl), vp], C.c_int),
         "exact_tv_prox": ([i32, vp, dbl, i32, vp, vp], C.c_int),
@@ -480,3 +483,37 @@ def exact_solve_tv(g, mu, weight, y, x, tau, gamma=0.0, gamma_scale=0.25, max_it
     d = _info_dict(info)
     d["converged"] = (code == 0) if tol > 0 else None
     return d, _tv_info(tinfo)
+
+
+# ------------------------------------------------------- dense measurements
+
+def _dense_shape(A):
+    if A.dim() != 2:
+        raise ValueError("A must be a 2-D device tensor (n x d)")
+    return int(A.shape[0]), int(A.shape[1])
+
+
+def exact_dense_operator(A, mu, weight, y, x, F, stream=None):
+    """F = (1/n) A^T r for an explicit n x d matrix A (device, float32)."""
+    n, d = _dense_shape(A)
+    sp = _Spec(mu, weight)
+    _check("exact_dense_operator", load().exact_dense_operator(
+        n, d, _dev(A, n * d, "A"), C.byref(sp.s), _dev(y, sp.Wn * n, "y"), _dev(x, d, "x"),
+        _dev(F, d, "F"), _stream(stream)))
+    return F
+
+
+def exact_dense_solve(A, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
+                      radius=0.0, check_every=16, power_iters=100, stream=None):
+    """EXACT with an explicit matrix over the ball of the given radius
+    (radius <= 0: unconstrained), in place on x.  Returns the info dict."""
+    n, d = _dense_shape(A)
+    sp = _Spec(mu, weight)
+    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
+    info = SolveInfo()
+    code = _check("exact_dense_solve", load().exact_dense_solve(
+        n, d, _dev(A, n * d, "A"), C.byref(sp.s), _dev(y, sp.Wn * n, "y"), _dev(x, d, "x"),
+        C.byref(o), float(radius), C.byref(info), _stream(stream)))
+    out = _info_dict(info)
+    out["converged"] = (code == 0) if tol > 0 else None
+    return out

@@ -139,3 +139,17 @@ def test_tv_entry_points_reject_bad_arguments(lib):
     assert lib.exact_project_tv(8, fake, 1.0, C.byref(o), fake, None, None) == -errno.EINVAL
     assert lib.exact_solve_tv(None, None, None, None, None, 0.0, None, None, None, None) == -errno.EINVAL
 
+
+
+def test_dense_entry_points_reject_bad_arguments(lib):
+    from paper_2503_19925_amd.exact import Spectrum
+    import numpy as np
+    mu = np.array([1.0])
+    w = np.array([1.0])
+    sp = Spectrum(1, 1, mu.ctypes.data_as(C.POINTER(C.c_double)),
+                  w.ctypes.data_as(C.POINTER(C.c_double)), None)
+    fake = C.c_void_p(16)
+    assert lib.exact_dense_operator(10, 5, None, C.byref(sp), fake, fake, fake, None) == -errno.EINVAL
+    assert lib.exact_dense_solve(10, 5, fake, C.byref(sp), fake, None, None, 0.0, None, None) == -errno.EINVAL
+    assert lib.exact_dense_solve(10, 5, fake, C.byref(sp), fake, fake, None, float("inf"), None,
+                                 None) == -errno.EINVAL
