@@ -1530,7 +1530,7 @@ namespace {
 struct DenseWork {
     long n = 0;
     int d = 0, K = 0;
-    std::unique_ptr<DevBuf> Y, J, mu, parts, parts2, xh;
+    std::unique_ptr<DevBuf> Y, J, mu, parts, parts2, g, xh;
 
     DenseWork(long n_, int d_, const exact_spectrum *sp, const float *y_dev, SpecArg &a,
               double *sjm, hipStream_t st)
@@ -1547,8 +1547,9 @@ struct DenseWork {
         Y.reset(new DevBuf((size_t)n * 4));
         J.reset(new DevBuf((size_t)K * 4));
         mu.reset(new DevBuf((size_t)K * 4));
-        parts.reset(new DevBuf((size_t)exact::dense_blocks(n) * d * 4));
-        parts2.reset(new DevBuf((size_t)exact::dense_sum_groups(n) * d * 4));
+        parts.reset(new DevBuf((size_t)exact::dense_blocks(n, d) * d * 4));
+        parts2.reset(new DevBuf((size_t)exact::dense_sum_groups(n, d) * d * 4));
+        g.reset(new DevBuf((size_t)d * 4));
         xh.reset(new DevBuf((size_t)d * 4));
         hip_check(hipMemcpyAsync(J->p, a.J, (size_t)K * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
         hip_check(hipMemcpyAsync(mu->p, a.mu, (size_t)K * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
@@ -1566,7 +1567,8 @@ struct DenseWork {
     hipError_t F(const float *A, const float *x, bool linear, const int32_t *skip, hipStream_t st)
     {
         return exact::launch_dense_F(A, n, d, x, Y->as<float>(), J->as<float>(), mu->as<float>(), K,
-                                     linear, parts->as<float>(), parts2->as<float>(), skip, st);
+                                     linear, parts->as<float>(), parts2->as<float>(),
+                                     g->as<float>(), skip, st);
     }
 };
 
@@ -1584,7 +1586,7 @@ int exact_dense_operator(int32_t n, int32_t d, const float *A_dev, const exact_s
         SpecArg a;
         DenseWork W(n, d, sp, y_dev, a, nullptr, own.st);
         hip_check(W.F(A_dev, x_dev, false, nullptr, own.st), "dense_F");
-        hip_check(exact::launch_dense_finish(W.parts2->as<float>(), n, d, 0, x_dev, 0.f, 0.0, F_dev,
+        hip_check(exact::launch_dense_finish(W.g->as<float>(), d, 0, x_dev, 0.f, 0.0, F_dev,
                                              nullptr, own.st),
                   "dense_finish");
         hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
@@ -1627,8 +1629,8 @@ int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spec
             float *vin = v0.as<float>(), *vout = v1.as<float>();
             for (int it = 1; it <= o.power_iters; ++it) {
                 hip_check(W.F(A_dev, vin, true, nullptr, st), "dense_F");
-                hip_check(exact::launch_dense_finish(W.parts2->as<float>(), n, d, 3, vin, 0.f, 0.0,
-                                                     vout, S, st),
+                hip_check(exact::launch_dense_finish(W.g->as<float>(), d, 3, vin, 0.f, 0.0, vout,
+                                                     S, st),
                           "dense_finish");
                 std::swap(vin, vout);
                 read_state(S, hs, st);
@@ -1649,13 +1651,13 @@ int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spec
         step.capture(st, [&]() {
             hipError_t e = W.F(A_dev, x_dev, false, &S->done, st);
             if (e == hipSuccess)
-                e = exact::launch_dense_finish(W.parts2->as<float>(), n, d, 1, x_dev, gf, radius, xh,
-                                               S, st);
+                e = exact::launch_dense_finish(W.g->as<float>(), d, 1, x_dev, gf, radius, xh, S,
+                                               st);
             if (e == hipSuccess)
                 e = W.F(A_dev, xh, false, &S->done, st);
             if (e == hipSuccess)
-                e = exact::launch_dense_finish(W.parts2->as<float>(), n, d, 2, x_dev, gf, radius,
-                                               x_dev, S, st);
+                e = exact::launch_dense_finish(W.g->as<float>(), d, 2, x_dev, gf, radius, x_dev,
+                                               S, st);
             return e;
         });
         int launched = 0;

@@ -16,7 +16,6 @@ namespace exact {
 namespace {
 
 constexpr int kDT = 256;          // threads of the streaming and reduction blocks
-constexpr int kRB = 4;            // rows in flight per block
 constexpr int kSumRows = 32;      // partial gradients summed per reduction block
 constexpr int kFinT = 1024;       // threads of the single-block finish
 
@@ -27,7 +26,24 @@ __device__ __forceinline__ bool dskip(const int32_t *skip)
 
 // Rows [blockIdx.x * rpb, min(n, (blockIdx.x + 1) * rpb)) of A (n x d,
 // row-major); thread t owns columns t + 256 c, c < C.  linear: r_i = s_i
-// (the power iteration's A^T A x), else the spectral residual.
+// (the power iteration's A^T A x), else the spectral residual.  Rows go in
+// batches of RB; the next batch's loads are issued before the current
+// batch's block reduction, so they stay in flight across its barrier.
+template <int C, int RB>
+__device__ __forceinline__ void dense_load(const float *__restrict__ A, long row0, long i1, int d,
+                                           int t, float (&a)[RB][C])
+{
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const long row = row0 + q;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j = c * kDT + t;
+            a[q][c] = (row < i1 && j < d) ? A[(size_t)row * d + j] : 0.f;
+        }
+    }
+}
+
 template <int C>
 __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, long n, int d,
                                                  const float *__restrict__ x,
@@ -37,9 +53,10 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
                                                  long rpb, float *__restrict__ parts,
                                                  const int32_t *__restrict__ skip)
 {
+    constexpr int RB = C >= 16 ? 2 : 4;
     if (dskip(skip))
         return;
-    __shared__ float red[kRB][kDT / 64];
+    __shared__ float red[2][RB][kDT / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     float xr[C], g[C];
 #pragma unroll
@@ -50,19 +67,15 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
     }
     const long i0 = (long)blockIdx.x * rpb;
     const long i1 = min(n, i0 + rpb);
-    for (long i = i0; i < i1; i += kRB) {
-        float a[kRB][C], dot[kRB];
+    float a[RB][C];
+    dense_load<C, RB>(A, i0, i1, d, t, a);
+    int buf = 0;
+    for (long i = i0; i < i1; i += RB) {
+        float an[RB][C];
+        dense_load<C, RB>(A, i + RB, i1, d, t, an);
+        float dot[RB];
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) {
-            const long row = i + q;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int j = c * kDT + t;
-                a[q][c] = (row < i1 && j < d) ? A[(size_t)row * d + j] : 0.f;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kRB; ++q) {
+        for (int q = 0; q < RB; ++q) {
             float s = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c)
@@ -73,14 +86,14 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
         }
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < kRB; ++q)
-                red[q][wave] = dot[q];
+            for (int q = 0; q < RB; ++q)
+                red[buf][q][wave] = dot[q];
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) {
+        for (int q = 0; q < RB; ++q) {
             const long row = i + q;
-            const float s = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+            const float s = ((red[buf][q][0] + red[buf][q][1]) + red[buf][q][2]) + red[buf][q][3];
             float r = 0.f;
             if (row < i1) {
                 if (linear) {
@@ -97,7 +110,13 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
             for (int c = 0; c < C; ++c)
                 g[c] = fmaf(a[q][c], r, g[c]);
         }
-        __syncthreads();
+        // the other LDS buffer takes the next batch: no second barrier
+        buf ^= 1;
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                a[q][c] = an[q][c];
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -125,6 +144,22 @@ __global__ __launch_bounds__(kDT) void k_dense_sum(const float *__restrict__ par
     parts2[(size_t)blockIdx.y * d + j] = s;
 }
 
+// g[j] = inv_n * sum over groups of parts2[by][j], in order.
+__global__ __launch_bounds__(kDT) void k_dense_sum2(const float *__restrict__ parts2, int ng, int d,
+                                                    float inv_n, float *__restrict__ g,
+                                                    const int32_t *__restrict__ skip)
+{
+    if (dskip(skip))
+        return;
+    const int j = blockIdx.x * kDT + threadIdx.x;
+    if (j >= d)
+        return;
+    float s = 0.f;
+    for (int by = 0; by < ng; ++by)
+        s += parts2[(size_t)by * d + j];
+    g[j] = s * inv_n;
+}
+
 __device__ __forceinline__ double fin_sum(double v, double *lds)
 {
     const int t = threadIdx.x;
@@ -140,16 +175,15 @@ __device__ __forceinline__ double fin_sum(double v, double *lds)
     return s;
 }
 
-// One block: g_j = inv_n sum_by parts2[by][j] (in order).  mode 0: F = g.
+// One block, on g = F (the summed gradient).  mode 0: z = g.
 // mode 1 (half step) / 2 (full step): z = P(x - gamma g) with P the ball of
 // the given radius (radius <= 0: none); mode 1 also sets rho_t from
 // ||z - x||, ||x|| in the state; mode 2 advances t and applies the stop
 // test, as the CT finish does.  mode 3 (power iteration): u = g, then
 // lam = <v,u>/<v,v>, v = u / ||u||.  Columns j = t + kFinT c.
-__global__ __launch_bounds__(kFinT) void k_dense_finish(const float *__restrict__ parts2, int ng,
-                                                        int d, float inv_n, int mode,
-                                                        const float *x, float gamma, double radius,
-                                                        float *z, SolveState *st)
+__global__ __launch_bounds__(kFinT) void k_dense_finish(const float *__restrict__ g, int d,
+                                                        int mode, const float *x, float gamma,
+                                                        double radius, float *z, SolveState *st)
 {
     if (mode != 0 && mode != 3 && st->done)
         return;
@@ -157,10 +191,7 @@ __global__ __launch_bounds__(kFinT) void k_dense_finish(const float *__restrict_
     const int t = threadIdx.x;
     double zz = 0.0, vu = 0.0, vv = 0.0;
     for (int j = t; j < d; j += kFinT) {
-        float s = 0.f;
-        for (int by = 0; by < ng; ++by)
-            s += parts2[(size_t)by * d + j];
-        const float gj = s * inv_n;
+        const float gj = g[j];
         if (mode == 0) {
             z[j] = gj;
         } else if (mode == 3) {
@@ -236,19 +267,24 @@ int dense_cols(int d)
     return C;
 }
 
-int dense_blocks(long n)
+// Row blocks: one resident round of the streaming kernel (its register use
+// allows 3 blocks per CU at 16 column chunks, 4 at 8, 8 below), at least
+// 64 rows each.
+int dense_blocks(long n, int d)
 {
+    const int C = dense_cols(d);
+    const long cap = 256L * (C >= 16 ? 3 : (C == 8 ? 4 : 8));
     const long want = (n + 63) / 64;
-    return (int)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
+    return (int)(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
-int dense_sum_groups(long n) { return (dense_blocks(n) + kSumRows - 1) / kSumRows; }
+int dense_sum_groups(long n, int d) { return (dense_blocks(n, d) + kSumRows - 1) / kSumRows; }
 
 hipError_t launch_dense_F(const float *A, long n, int d, const float *x, const float *Y,
                           const float *J, const float *mu, int K, bool linear, float *parts,
-                          float *parts2, const int32_t *skip, hipStream_t st)
+                          float *parts2, float *g, const int32_t *skip, hipStream_t st)
 {
-    const int nb = dense_blocks(n);
+    const int nb = dense_blocks(n, d);
     const long rpb = (n + nb - 1) / nb;
     const int C = dense_cols(d);
     const dim3 grid(nb), blk(kDT);
@@ -261,17 +297,19 @@ hipError_t launch_dense_F(const float *A, long n, int d, const float *x, const f
     case 16: hipLaunchKernelGGL(k_dense_F<16>, grid, blk, 0, st, A, n, d, x, Y, J, mu, K, lin, rpb, parts, skip); break;
     default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_dense_sum, dim3((d + kDT - 1) / kDT, dense_sum_groups(n)), dim3(kDT), 0,
-                       st, parts, nb, d, parts2, skip);
+    const int ng = dense_sum_groups(n, d);
+    hipLaunchKernelGGL(k_dense_sum, dim3((d + kDT - 1) / kDT, ng), dim3(kDT), 0, st, parts, nb, d,
+                       parts2, skip);
+    hipLaunchKernelGGL(k_dense_sum2, dim3((d + kDT - 1) / kDT), dim3(kDT), 0, st, parts2, ng, d,
+                       (float)(1.0 / (double)n), g, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_dense_finish(const float *parts2, long n, int d, int mode, const float *x,
-                               float gamma, double radius, float *z, SolveState *state,
-                               hipStream_t st)
+hipError_t launch_dense_finish(const float *g, int d, int mode, const float *x, float gamma,
+                               double radius, float *z, SolveState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dense_finish, dim3(1), dim3(kFinT), 0, st, parts2, dense_sum_groups(n), d,
-                       (float)(1.0 / (double)n), mode, x, gamma, radius, z, state);
+    hipLaunchKernelGGL(k_dense_finish, dim3(1), dim3(kFinT), 0, st, g, d, mode, x, gamma, radius,
+                       z, state);
     return hipGetLastError();
 }
 

@@ -232,19 +232,18 @@ hipError_t launch_diff2(const float *a, const float *b, long d, double *parts, d
 
 constexpr int kDenseMaxCols = 4096;   // columns of A the streaming kernel holds
 int dense_cols(int d);                // column chunks per thread (power of two)
-int dense_blocks(long n);             // row blocks (partial gradients)
-int dense_sum_groups(long n);         // groups of partial gradients after the first sum
-// parts2 = partial gradients of (A^T r) over row blocks, summed in groups:
-// r_i = <a_i, x> (linear) or Y_i - sum_k J_k exp(-mu_k max(<a_i, x>, 0)).
-// parts: dense_blocks(n) * d floats; parts2: dense_sum_groups(n) * d.
+int dense_blocks(long n, int d);      // row blocks (partial gradients)
+int dense_sum_groups(long n, int d);  // groups of partial gradients after the first sum
+// g = (1/n) A^T r, r_i = <a_i, x> (linear) or Y_i - sum_k J_k exp(-mu_k
+// max(<a_i, x>, 0)), by one streaming pass over A and two fixed-order sums.
+// parts: dense_blocks * d floats; parts2: dense_sum_groups * d; g: d.
 hipError_t launch_dense_F(const float *A, long n, int d, const float *x, const float *Y,
                           const float *J, const float *mu, int K, bool linear, float *parts,
-                          float *parts2, const int32_t *skip, hipStream_t st);
-// Single-block finish: mode 0 z = g (= F); 1 half step z = P(x - gamma g) and
-// rho into the state; 2 full step (z may alias x), t and the stop test;
+                          float *parts2, float *g, const int32_t *skip, hipStream_t st);
+// Single-block finish on g: mode 0 z = g; 1 half step z = P(x - gamma g)
+// and rho into the state; 2 full step (z may alias x), t and the stop test;
 // 3 power iteration (x = v in, z = v out, lam and ||u|| into the state).
-hipError_t launch_dense_finish(const float *parts2, long n, int d, int mode, const float *x,
-                               float gamma, double radius, float *z, SolveState *state,
-                               hipStream_t st);
+hipError_t launch_dense_finish(const float *g, int d, int mode, const float *x, float gamma,
+                               double radius, float *z, SolveState *state, hipStream_t st);
 
 }  // namespace exact
