@@ -150,9 +150,10 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         const long double P = fixed32(ratio / cs);
         const long double Q = fixed32(-sn / cs);
         const long double A = fixed32(c + c * sn / cs - half * ratio / cs);
-        // largest crossing the kernels form: b up to B + 64 (candidate bins
-        // beyond the detector are formed, then discarded), k up to N
-        const long double span = fabsl(A) + (B + 64) * fabsl(P) + N * fabsl(Q) + 4.0L;
+        // largest crossing (or crossing minus pixel index) the kernels form:
+        // b up to B + 64 (candidate bins beyond the detector are formed, then
+        // discarded), k and j up to N
+        const long double span = fabsl(A) + (B + 64) * fabsl(P) + N * fabsl(Q) + N + 4.0L;
         if (!(span < 1048576.0L))
             fail(-EINVAL, "geometry too large for exact crossing arithmetic (|crossing| >= 2^20)");
         ViewGeom G;
@@ -162,7 +163,7 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         G.P = (double)P;
         G.Q = (double)Q;
         G.invP = (double)(1.0L / P);
-        G.sPhi = P < 0 ? -1 : 0;
+        G.omP = (double)(1.0L - fabsl(P));                        // exact
         G.wstep = (float)((long double)pixel_cm / fabsl(cs));
         G.vidx = v;
         (row ? rows : cols).push_back(G);
@@ -273,9 +274,10 @@ double power_iteration(const exact_geometry_s *g, int max_iters, hipStream_t st,
     int it = 0;
     for (it = 1; it <= max_iters; ++it) {
         hip_check(exact::launch_forward(G, vp.as<float>(), vTp.as<float>(), s.as<float>(),
-                                        exact::padded_bins(g->B), exact::kPadB, nullptr, st),
+                                        exact::padded_bins(g->B), exact::kPadB, true, nullptr,
+                                        st),
                   "forward");
-        hip_check(exact::launch_back(G, s.as<float>(), true, u.as<float>(), (float)(1.0 / (double)n),
+        hip_check(exact::launch_back(G, s.as<float>(), u.as<float>(), (float)(1.0 / (double)n),
                                      nullptr, st),
                   "back");
         hip_check(exact::launch_dot3(v.as<float>(), u.as<float>(), g->N, parts.as<double>(), st), "dot3");
@@ -385,7 +387,7 @@ int exact_forward(exact_geometry g, const float *x_dev, float *s_dev, void *stre
         hip_check(exact::launch_pad_pair(x_dev, xp.as<float>(), xTp.as<float>(), g->N, st),
                   "pad_pair");
         hip_check(exact::launch_forward(geo_of(g), xp.as<float>(), xTp.as<float>(), s_dev, g->B, 0,
-                                        nullptr, st),
+                                        false, nullptr, st),
                   "forward");
         return 0;
     });
@@ -397,8 +399,12 @@ int exact_backproject(exact_geometry g, const float *r_dev, float *img_dev, void
         check_geometry(g);
         if (!r_dev || !img_dev)
             fail(-EINVAL, "NULL buffer");
-        hip_check(exact::launch_back(geo_of(g), r_dev, false, img_dev, 1.0f, nullptr,
-                                     (hipStream_t)stream),
+        hipStream_t st = (hipStream_t)stream;
+        const size_t np = (size_t)g->V * exact::padded_bins(g->B);
+        AsyncBuf rw(np * sizeof(float), st);
+        hip_check(hipMemsetAsync(rw.p, 0, np * sizeof(float), st), "hipMemsetAsync");
+        hip_check(exact::launch_weigh_rows(geo_of(g), r_dev, rw.as<float>(), st), "weigh_rows");
+        hip_check(exact::launch_back(geo_of(g), rw.as<float>(), img_dev, 1.0f, nullptr, st),
                   "back");
         return 0;
     });
@@ -426,18 +432,12 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp, const float *y_de
         hip_check(exact::launch_pad_pair(x_dev, xp.as<float>(), xTp.as<float>(), g->N, st),
                   "pad_pair");
         hip_check(exact::launch_forward_residual(geo_of(g), xp.as<float>(), xTp.as<float>(),
-                                                 Y.as<float>(), a, rp.as<float>(), nullptr, st),
+                                                 Y.as<float>(), a, rp.as<float>(), r_dev, nullptr,
+                                                 st),
                   "forward_residual");
-        hip_check(exact::launch_back(geo_of(g), rp.as<float>(), true, F_dev, (float)(1.0 / (double)n),
+        hip_check(exact::launch_back(geo_of(g), rp.as<float>(), F_dev, (float)(1.0 / (double)n),
                                      nullptr, st),
                   "back");
-        if (r_dev)
-            hip_check(hipMemcpy2DAsync(r_dev, (size_t)g->B * sizeof(float),
-                                       rp.as<float>() + exact::kPadB,
-                                       (size_t)exact::padded_bins(g->B) * sizeof(float),
-                                       (size_t)g->B * sizeof(float), (size_t)g->V,
-                                       hipMemcpyDeviceToDevice, st),
-                      "hipMemcpy2DAsync");
         return 0;
     });
 }
@@ -739,11 +739,11 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st, hipEvent_t *marks = nu
         ++phase;
     };
     mark();
-    cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, skip, st));
+    cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, nullptr, skip, st));
     mark();
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, nullptr, xhp, xhTp, parts, skip, st));
     mark();
-    cap(exact::launch_forward_residual(G, xhp, xhTp, Y, p.spec, r, skip, st));
+    cap(exact::launch_forward_residual(G, xhp, xhTp, Y, p.spec, r, nullptr, skip, st));
     mark();
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, p.x, xp, xTp, nullptr, skip, st));
     mark();
@@ -1467,10 +1467,10 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
         // F(z) = (1/n) A^T r(z) from the padded pair of z, into grad
         auto gradient = [&](const float *zp, const float *zTp) {
             hip_check(exact::launch_forward_residual(G, zp, zTp, p.Y->as<float>(), p.spec,
-                                                     p.r->as<float>(), nullptr, st),
+                                                     p.r->as<float>(), nullptr, nullptr, st),
                       "forward_residual");
-            hip_check(exact::launch_back(G, p.r->as<float>(), true, grad.as<float>(), inv_n,
-                                         nullptr, st),
+            hip_check(exact::launch_back(G, p.r->as<float>(), grad.as<float>(), inv_n, nullptr,
+                                         st),
                       "back");
         };
         while (t < o.max_iters) {

@@ -23,23 +23,24 @@ constexpr int kMaxEnergies = 128;
 // order (incremental stepping in the forward, direct evaluation in the
 // back-projector).  Both kernels therefore apply bit-identical weights.
 //
-// The back-projector starts from the bin nearest to a pixel (the solution of
-// f(b, k) = j rounded to an integer) and examines only the bins that can lie
-// within one pixel of it.  Ab = A - kPadB P is A in padded-bin coordinates
-// (bin b of a padded sinogram row sits at index b + kPadB); sPhi is -1 when
-// P < 0 and 0 otherwise (a sign mask).
+// The back-projector takes, for a pixel, the bins floor(t) and floor(t) + 1
+// around the solution t of f(t, k) = j; invP = 1/P (rounded), Ab = A -
+// kPadB P is A in padded-bin coordinates (bin b of a padded sinogram row
+// sits at index b + kPadB) and omP = 1 - |P| (exact).  The fields the
+// back-projector reads come first.
 //
 // The geometry's table lists the row-stepping views first and the
 // column-stepping views after them (Geo::nrow of each); vidx is the view's
 // index v in the sinogram.
 struct alignas(8) ViewGeom {
-    double A, Ab, P, Q, invP;
-    float wstep;
+    double Ab, P, Q, invP, omP;
     int32_t vidx;
-    int32_t sPhi;
-    int32_t pad_;
+    int32_t pad0_;
+    double A;
+    float wstep;
+    int32_t pad1_;
 };
-static_assert(sizeof(ViewGeom) == 56, "ViewGeom layout");
+static_assert(sizeof(ViewGeom) == 64, "ViewGeom layout");
 
 // Padded layouts read by the projectors.  An image row (or a row of the
 // transposed image) holds kPadX zeros, the N pixels, kPadX zeros; a
@@ -47,6 +48,10 @@ static_assert(sizeof(ViewGeom) == 56, "ViewGeom layout");
 // that fall outside the image or the detector then read zeros at in-bounds
 // addresses, so the inner loops need no range tests.  The padding is zeroed
 // when a buffer is created and never written afterwards.
+//
+// A padded sinogram that the back-projector reads is **weighted**: row v
+// holds wstep_v r[v][b], the path-length factor of the view applied once
+// per ray by its producer instead of once per pixel and view.
 constexpr int kPadX = 2;
 constexpr int kPadB = 2;
 __host__ __device__ inline int padded_cols(int N) { return N + 2 * kPadX; }
@@ -142,15 +147,22 @@ int back_tiles_per_side(int N);
 // xp, xTp (padded, padding already zero) <- x and its transpose.
 hipError_t launch_pad_pair(const float *x, float *xp, float *xTp, int N, hipStream_t st);
 hipError_t launch_fill(float *x, float value, long count, hipStream_t st);
-// s = A x from the padded pair; s[vidx * s_stride + s_off + b].
+// s = A x from the padded pair; s[vidx * s_stride + s_off + b] (times the
+// view's wstep when weighted: the weighted padded sinogram the
+// back-projector reads).
 hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float *s,
-                          int s_stride, int s_off, const int32_t *skip, hipStream_t st);
-// r = Y - sum_k J_k exp(-mu_k (A x)_+) into a padded residual.
+                          int s_stride, int s_off, bool weighted, const int32_t *skip,
+                          hipStream_t st);
+// r = Y - sum_k J_k exp(-mu_k (A x)_+) into a weighted padded residual and,
+// when r_plain is not null, unweighted into the plain [V][B] layout.
 hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
-                                   const float *Y, const SpecArg &sp, float *r,
+                                   const float *Y, const SpecArg &sp, float *r, float *r_plain,
                                    const int32_t *skip, hipStream_t st);
-// img = scale A^T r; r padded (r_padded) or the plain [V][B] layout.
-hipError_t launch_back(const Geo &g, const float *r, bool r_padded, float *img, float scale,
+// rw (padded, padding already zero) <- the plain [V][B] sinogram r,
+// weighted row by row.
+hipError_t launch_weigh_rows(const Geo &g, const float *r, float *rw, hipStream_t st);
+// img = scale A^T r from a weighted padded sinogram.
+hipError_t launch_back(const Geo &g, const float *rw, float *img, float scale,
                        const int32_t *skip, hipStream_t st);
 hipError_t launch_window_sum(const float *y, int Wn, long n, float *Y,
                              int32_t *bad, hipStream_t st);
@@ -158,9 +170,9 @@ hipError_t launch_count_bad(const float *x, long count, int32_t *bad,
                             hipStream_t st);
 hipError_t launch_state_init(SolveState *state, double tol, int max_iters, int stop_mode,
                              hipStream_t st);
-// Back-projection fused with the update: g = scale A^T r (r padded) and
-// z = max(0, x - gamma g) for every pixel, written to zp and (transposed)
-// zTp in the padded layout and, when z is not null, to z.  With
+// Back-projection fused with the update: g = scale A^T r (r weighted and
+// padded) and z = max(0, x - gamma g) for every pixel, written to zp and
+// (transposed) zTp in the padded layout and, when z is not null, to z.  With
 // partials != nullptr also writes per-tile double partial sums of
 // ||z - x||^2 and ||x||^2 (2 per 16x16 tile, num_tiles of them).  z may
 // alias x.

@@ -81,12 +81,6 @@ __device__ __forceinline__ int clamp_int(int v, int hi)
     return r;
 }
 
-// (float)(1 - |d|) clamped below at 0 (it never exceeds 1).
-__device__ __forceinline__ float tent(double d)
-{
-    return __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
-}
-
 // Fixed-order sum over the kRedThreads threads of the block's x-y plane
 // with one barrier: a butterfly within each wave, then the four wave sums in
 // order.  Threads with active = false (other z planes) contribute nothing
@@ -166,19 +160,21 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 
 // The two taps of a ray on one padded image line: crossing f in padded
 // column coordinates (advanced by Q, exactly), weights (float)(1 - e0) and
-// (float)e0 of columns floor(f) and floor(f) + 1, and their values.  A tap
-// outside the image reads a padding zero; the column is clamped to the
-// padded row so that lines the ray does not reach read zeros too.
+// (float)e0 of columns floor(f) and floor(f) + 1 with e0 = f - floor(f),
+// and their values.  A tap outside the image reads a padding zero; the
+// column is clamped to the padded row so that lines the ray does not reach
+// read zeros too.  Every crossing with a tap inside the image has f >= 1
+// (padded), where truncation is floor; a crossing below 1 has both taps in
+// the padding, and truncating it (then clamping at 0) still reads padding.
 __device__ __forceinline__ void tap_pair(double &f, int N, double Q,
                                          const float *__restrict__ row, float &w0, float &w1,
                                          float &v0, float &v1)
 {
-    const double fl = floor(f);
-    const double e0 = f - fl;                 // exact, in [0, 1)
-    f += Q;                                   // exact
-    const int c = clamp_int<0>((int)fl, N + 2 * kPadX - 2);
-    w0 = (float)(1.0 - e0);                   // pixel floor(f)
-    w1 = (float)e0;                           // pixel floor(f) + 1: 1 - |f - (j0+1)| = e0
+    const double e0 = __builtin_amdgcn_fract(f);    // f - floor(f), exact, in [0, 1)
+    const int c = clamp_int<0>((int)f, N + 2 * kPadX - 2);
+    f += Q;                                         // exact
+    w0 = (float)(1.0 - e0);                         // pixel floor(f)
+    w1 = (float)e0;                                 // pixel floor(f) + 1: 1 - |f - (j0+1)| = e0
     v0 = at(row, (unsigned)c);
     v1 = at(row + 1, (unsigned)c);
 }
@@ -217,13 +213,16 @@ struct SpecPtr {
 // Forward projection of rays [64 bblock, 64 bblock + 64) of table view
 // `slot` by one workgroup of kFwdThreads * kSegs threads, reading the padded
 // image pair; with kResid the spectral residual replaces the line integral.
-// Ray i = vidx B + b goes to out[vidx * ostride + ooff + b].
+// Ray i = vidx B + b goes to out[vidx * ostride + ooff + b], times the
+// view's wstep when weighted, and unweighted to plain[i] when plain is not
+// null.
 template <bool kResid, class Spec>
 __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views, int N, int B,
                                               int nrow, const float *__restrict__ xp,
                                               const float *__restrict__ xTp,
                                               const float *__restrict__ Y, const Spec &sp,
                                               float *__restrict__ out, int ostride, int ooff,
+                                              bool weighted, float *__restrict__ plain,
                                               int slot, int bblock)
 {
     __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
@@ -283,17 +282,19 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     }
     const float s = tot.value() * G.wstep;
     const size_t o = (size_t)G.vidx * ostride + ooff + b;
+    const size_t i = (size_t)G.vidx * B + b;
+    float val = s;
     if (kResid) {
         // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0)))
-        const size_t i = (size_t)G.vidx * B + b;
         const float sp0 = fmaxf(s, 0.f) + (sp.bg ? sp.bg[i] : 0.f);
         float m = 0.f;
         for (int q = 0; q < sp.K; ++q)
             m = fmaf(sp.J[q], expf(-sp.mu[q] * sp0), m);
-        out[o] = Y[i] - m;
-    } else {
-        out[o] = s;
+        val = Y[i] - m;
     }
+    out[o] = weighted ? val * G.wstep : val;
+    if (plain)
+        plain[i] = val;
 }
 
 // Workgroup i takes view i % V and the (i / V)-th bin block centre-out, so
@@ -302,13 +303,14 @@ template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow,
     const float *__restrict__ xp, const float *__restrict__ xTp, const float *__restrict__ Y,
-    SpecArg sp, float *__restrict__ out, int ostride, int ooff, const int32_t *__restrict__ skip)
+    SpecArg sp, float *__restrict__ out, int ostride, int ooff, int weighted,
+    float *__restrict__ plain, const int32_t *__restrict__ skip)
 {
     if (skipped(skip))
         return;
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
-    forward_block<kResid>(views, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff, blockIdx.x % V,
-                          centre_out(blockIdx.x / V, nbb));
+    forward_block<kResid>(views, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff, weighted != 0,
+                          plain, blockIdx.x % V, centre_out(blockIdx.x / V, nbb));
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -348,58 +350,56 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 
 // ------------------------------------------------------------------- back
 
-// Taps of view G for pixel (line k, pixel j of that line), the path-length
-// factor left out: sum over bins b within one pixel of
-// (float)(1 - |f(b, k) - j|) * r[b].
+// Taps of view G for pixel (line k, pixel j of that line) from the weighted
+// padded row rv: acc + the sum over bins b within one pixel of
+// (float)(1 - |f(b, k) - j|) * rv[b], b in padded-bin numbers, the
+// path-length factor being in rv already.
 //
-// Two-candidate rule (every |P| >= 1): the nearest bin b0 has
-// |d0| <= (1/2 + tiny)|P| with d0 = f(b0, k) - j; moving away from the pixel
-// adds |P| >= 1 to |d|, and two bins towards it leave |d| >= (3/2 - tiny)|P|
-// >= 1, so only b0 and its neighbour on the pixel's side, b1 = b0 + delta,
-// can have positive weight (delta = -1 when d0 and P have the same sign,
-// +1 otherwise; either neighbour has weight 0 when d0 = 0).  b0 comes from
-// one rounding fma (kRoundMagic); d0 and d1 are exact.
+// Pair rule (every |P| >= 1).  Let t be the real solution of f(t, k) = j.
+// Bin b has positive weight iff |b - t| |P| < 1, so only b_f = floor(t)
+// and b_f + 1 can.  With d = f(b_f, k) - j = (b_f - t) P (exact), b_f's
+// weight is (float)(1 - |d|) and, as |d| <= |P|, b_f + 1 is at distance
+// |P| - |d| (exact), so its weight is (float)(|d| + (1 - |P|)): the same
+// floats the forward projector forms for these (bin, pixel) pairs.
 //
-// kPad: rv is a padded residual row (bin b at index b + kPadB); b0 is
-// clamped to [-1, B] so both taps index the row, and bins off the detector
-// read padding zeros.  Otherwise rv is a plain row and out-of-range taps get
-// weight 0 and an in-bounds address.
-template <bool kPad>
+// t is computed as -T (1/P) and truncated.  Its error is at most
+// |T| 2^-52 < 2^-32 (|T| < 2^20 by the geometry check), so when t lies
+// within that error of an integer n the truncation may give n where floor
+// gives n - 1 or the reverse.  For |P| = 1 there is no error (1/P = +-1);
+// otherwise |P| - 1 >= 2^-32 (P is a multiple of 2^-32), and the bin lost
+// (n - 1 or n + 1) is at distance >= 1 - error from t, hence weight <= 0,
+// while the pair still formed gets weights that round to the exact ones
+// (the far one to <= 0, the near one to the float of 1 - (error) |P|,
+// which is 1 as the exact one is).
+//
+// The pair is clamped to [0, B + 2 kPadB - 1]: a truncated t below 1
+// (negative t truncates upwards) or above the detector lands on two
+// padding bins, which read zero whatever their weights; a pair holding a
+// detector bin has t >= 1, where truncation is floor.
 __device__ __forceinline__ float taps_two(const ViewGeom &G, double kd, double jd, int B,
-                                          const float *__restrict__ rv)
+                                          const float *__restrict__ rv, float acc)
 {
-    const double T = fma(kd, G.Q, (kPad ? G.Ab : G.A) - jd);        // f(0, k) - j, exact
-    const double m = fma(-T, G.invP, kRoundMagic);                  // rint((j - f(0,k)) / P)
-    const int b0 = clamp_int<kPad ? 1 : -1>(low_int(m), kPad ? B + 2 : B);
-    const double d0 = fma((double)b0, G.P, T);                      // exact
-    // sign bit of `agree` set iff d0 and P have the same sign
-    const int agree = ~(__double2hiint(d0) ^ G.sPhi);
-    const int delta = ((agree >> 31) * 2) | 1;                      // -1 or +1
-    const int b1 = b0 + delta;
-    const double d1 = fma((double)delta, G.P, d0);                  // exact
-    float u0 = tent(d0), u1 = tent(d1);
-    unsigned i0 = (unsigned)b0, i1 = (unsigned)b1;
-    if (!kPad) {
-        const bool ok0 = i0 < (unsigned)B, ok1 = i1 < (unsigned)B;
-        u0 = ok0 ? u0 : 0.f;
-        u1 = ok1 ? u1 : 0.f;
-        i0 = ok0 ? i0 : 0u;
-        i1 = ok1 ? i1 : 0u;
-    }
-    return fmaf(u1, at(rv, i1), u0 * at(rv, i0));
+    const double T = fma(kd, G.Q, G.Ab - jd);                  // f(0, k) - j, padded; exact
+    const double t = -T * G.invP;
+    const int bf = clamp_int<0>((int)t, B + 2 * kPadB - 2);
+    const double d = fma((double)bf, G.P, T);                  // exact
+    const float u0 = __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
+    const float u1 = __builtin_amdgcn_fmed3f((float)(fabs(d) + G.omP), 0.f, 1.f);
+    const float *p = (const float *)((const char *)rv + ((unsigned)bf << 2));
+    return fmaf(u1, p[1], fmaf(u0, p[0], acc));
 }
 
 // General rule (bins narrower than pixels): every bin within `reach` of b0.
 // Works in true bin numbers with explicit range tests (the padding is too
-// narrow for the reach); rv points at bin 0 of the row.
+// narrow for the reach); rv points at bin 0 of a weighted row.
 __device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double jd, int B,
-                                            int reach, const float *__restrict__ rv)
+                                            int reach, const float *__restrict__ rv, float acc)
 {
     const double T = fma(kd, G.Q, G.A) - jd;                        // exact
     const double m = fma(-T, G.invP, kRoundMagic);
     const int b0 = min(max(low_int(m), -2 - reach), B + 1 + reach);
     const double d0 = fma((double)b0, G.P, T);                      // exact
-    float s = 0.f;
+    float s = acc;
     for (int q = -reach; q <= reach; ++q) {
         const int bb = b0 + q;
         const float u = (float)(1.0 - fabs(fma((double)q, G.P, d0)));   // exact distance
@@ -409,40 +409,33 @@ __device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double
     return s;
 }
 
-// Sum over views [v0, v1) of wstep * taps for pixel (kd, jd) of each view's
-// stepping line; r has rows of rstride floats (padded or plain).  Batches
-// of views: parameters and loads first, then a float sum of the batch
-// (wstep applied by fma), then one Kahan step.
-template <bool kTwo, bool kPad>
+// Sum over views [v0, v1) of the taps for pixel (kd, jd) of each view's
+// stepping line, from the weighted padded sinogram r.  Batches of views:
+// parameters and loads first, then a float sum of the batch, then one
+// Kahan step.
+template <bool kTwo>
 __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views, int v0, int v1,
                                              double kd, double jd, int B, int reach,
-                                             const float *__restrict__ r, int rstride,
-                                             Kahan &acc)
+                                             const float *__restrict__ r, Kahan &acc)
 {
-    const int roff = kPad ? kPadB : 0;
+    const int rstride = padded_bins(B);
     int v = v0;
     for (; v + kViewBatch <= v1; v += kViewBatch) {
-        float t[kViewBatch], w[kViewBatch];
+        float sb = 0.f;
 #pragma unroll
         for (int q = 0; q < kViewBatch; ++q) {
             const ViewGeom G = views[v + q];
             const float *rv = r + (size_t)G.vidx * rstride;
-            t[q] = kTwo ? taps_two<kPad>(G, kd, jd, B, rv)
-                        : taps_reach(G, kd, jd, B, reach, rv + roff);
-            w[q] = G.wstep;
+            sb = kTwo ? taps_two(G, kd, jd, B, rv, sb)
+                      : taps_reach(G, kd, jd, B, reach, rv + kPadB, sb);
         }
-        float sb = 0.f;
-#pragma unroll
-        for (int q = 0; q < kViewBatch; ++q)
-            sb = fmaf(w[q], t[q], sb);
         acc.add(sb);
     }
     for (; v < v1; ++v) {
         const ViewGeom G = views[v];
         const float *rv = r + (size_t)G.vidx * rstride;
-        acc.add((kTwo ? taps_two<kPad>(G, kd, jd, B, rv)
-                      : taps_reach(G, kd, jd, B, reach, rv + roff)) *
-                G.wstep);
+        acc.add(kTwo ? taps_two(G, kd, jd, B, rv, 0.f)
+                     : taps_reach(G, kd, jd, B, reach, rv + kPadB, 0.f));
     }
 }
 
@@ -452,23 +445,20 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
 // as 8 waves.  Plane 1 hands its sum to plane 0 through LDS; the result
 // (row part + column part, a fixed order) is meaningful in plane 0.  Every
 // thread of the block calls this (it holds a barrier).
-template <bool kTwo, bool kPad>
+template <bool kTwo>
 __device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ views, int V,
                                                   int B, int nrow, int reach,
                                                   const float *__restrict__ r, int ix, int iy,
                                                   bool inside)
 {
     __shared__ float part[kBackY][kBackX];
-    const int rstride = kPad ? padded_bins(B) : B;
     float v = 0.f;
     if (inside) {
         Kahan acc;
         if (threadIdx.z == 0)
-            gather_views<kTwo, kPad>(views, 0, nrow, (double)iy, (double)ix, B, reach, r,
-                                     rstride, acc);
+            gather_views<kTwo>(views, 0, nrow, (double)iy, (double)ix, B, reach, r, acc);
         else
-            gather_views<kTwo, kPad>(views, nrow, V, (double)ix, (double)iy, B, reach, r,
-                                     rstride, acc);
+            gather_views<kTwo>(views, nrow, V, (double)ix, (double)iy, B, reach, r, acc);
         v = acc.value();
     }
     if (threadIdx.z == 1)
@@ -477,7 +467,7 @@ __device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ v
     return threadIdx.z == 0 ? v + part[threadIdx.y][threadIdx.x] : 0.f;
 }
 
-template <bool kTwo, bool kPad>
+template <bool kTwo>
 __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float *__restrict__ img, float scale,
@@ -488,9 +478,21 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     const bool inside = ix < N && iy < N;
-    const float g = back_pixel_split<kTwo, kPad>(views, V, B, nrow, reach, r, ix, iy, inside);
+    const float g = back_pixel_split<kTwo>(views, V, B, nrow, reach, r, ix, iy, inside);
     if (inside && threadIdx.z == 0)
         img[(size_t)iy * N + ix] = g * scale;
+}
+
+// rw[vidx][kPadB + b] = wstep * r[vidx][b] for the view in table slot
+// blockIdx.y (the padding of rw is zero already).
+__global__ __launch_bounds__(256) void k_weigh_rows(const ViewGeom *__restrict__ views, int B,
+                                                    const float *__restrict__ r,
+                                                    float *__restrict__ rw)
+{
+    const ViewGeom G = views[blockIdx.y];
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < B)
+        rw[(size_t)G.vidx * padded_bins(B) + kPadB + b] = r[(size_t)G.vidx * B + b] * G.wstep;
 }
 
 // The projected update on one 16 x 16 tile once g = scale (A^T r) is known
@@ -558,8 +560,7 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back_update(
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     const bool inside = ix < N && iy < N;
-    const float g =
-        back_pixel_split<kTwo, true>(views, V, B, nrow, reach, r, ix, iy, inside) * scale;
+    const float g = back_pixel_split<kTwo>(views, V, B, nrow, reach, r, ix, iy, inside) * scale;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     update_epilogue<kPartials>(inside, g, N, x, gamma, z, zp, zTp,
                                kPartials ? partials + 2 * blk : nullptr, blockIdx.x, blockIdx.y);
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
     const SpecPtr sp{P.K, glob(P.J), glob(P.mu), P.bg ? glob(P.bg) : nullptr};
     forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xhp : P.xp),
                         glob(kAtHalf ? P.xhTp : P.xTp), glob(P.Y), sp, glob(P.r),
-                        padded_bins(P.B), kPadB, it.a, it.b);
+                        padded_bins(P.B), kPadB, true, nullptr, it.a, it.b);
 }
 
 template <bool kHalf>
@@ -796,11 +797,11 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void kb_back_update(
     // stores, so its view-table loads stay scalar
     float g;
     if (P.reach == 0)
-        g = back_pixel_split<true, true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
-                                         inside);
+        g = back_pixel_split<true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
+                                   inside);
     else
-        g = back_pixel_split<false, true>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
-                                          iy, inside);
+        g = back_pixel_split<false>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
+                                    iy, inside);
     g *= P.inv_n;
     const int ntx = (P.N + kBackX - 1) / kBackX;
     double *part2 = kHalf ? glob(P.parts) + 2 * (it.b * ntx + it.a) : nullptr;
@@ -930,47 +931,48 @@ hipError_t launch_fill(float *x, float value, long count, hipStream_t st)
 }
 
 hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float *s,
-                          int s_stride, int s_off, const int32_t *skip, hipStream_t st)
+                          int s_stride, int s_off, bool weighted, const int32_t *skip,
+                          hipStream_t st)
 {
     SpecArg none;
     none.K = 0;
     none.bg = nullptr;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off, skip);
+                       g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
+                       weighted ? 1 : 0, nullptr, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
-                                   const float *Y, const SpecArg &sp, float *r,
+                                   const float *Y, const SpecArg &sp, float *r, float *r_plain,
                                    const int32_t *skip, hipStream_t st)
 {
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, skip);
+                       g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1, r_plain,
+                       skip);
     return hipGetLastError();
 }
 
-hipError_t launch_back(const Geo &g, const float *r, bool r_padded, float *img, float scale,
+hipError_t launch_weigh_rows(const Geo &g, const float *r, float *rw, hipStream_t st)
+{
+    dim3 grid((g.B + 255) / 256, g.V);
+    hipLaunchKernelGGL(k_weigh_rows, grid, dim3(256), 0, st, g.views, g.B, r, rw);
+    return hipGetLastError();
+}
+
+hipError_t launch_back(const Geo &g, const float *rw, float *img, float scale,
                        const int32_t *skip, hipStream_t st)
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
     dim3 blk(kBackX, kBackY, 2);
-    if (g.reach == 0) {
-        if (r_padded)
-            hipLaunchKernelGGL((k_back<true, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
-                               g.nrow, 0, r, img, scale, skip);
-        else
-            hipLaunchKernelGGL((k_back<true, false>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
-                               g.nrow, 0, r, img, scale, skip);
-    } else {
-        if (r_padded)
-            hipLaunchKernelGGL((k_back<false, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
-                               g.nrow, g.reach, r, img, scale, skip);
-        else
-            hipLaunchKernelGGL((k_back<false, false>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
-                               g.nrow, g.reach, r, img, scale, skip);
-    }
+    if (g.reach == 0)
+        hipLaunchKernelGGL((k_back<true>), grid, blk, 0, st, g.views, g.N, g.V, g.B, g.nrow, 0,
+                           rw, img, scale, skip);
+    else
+        hipLaunchKernelGGL((k_back<false>), grid, blk, 0, st, g.views, g.N, g.V, g.B, g.nrow,
+                           g.reach, rw, img, scale, skip);
     return hipGetLastError();
 }
 
