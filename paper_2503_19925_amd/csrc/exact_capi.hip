@@ -166,6 +166,7 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
         G.omP = (double)(1.0L - fabsl(P));                        // exact
         G.wstep = (float)((long double)pixel_cm / fabsl(cs));
         G.vidx = v;
+        G.roff = v * exact::padded_bins(B);
         (row ? rows : cols).push_back(G);
         pmin = std::min(pmin, fabsl(P));
     }

@@ -26,16 +26,17 @@ constexpr int kMaxEnergies = 128;
 // The back-projector takes, for a pixel, the bins floor(t) and floor(t) + 1
 // around the solution t of f(t, k) = j; invP = 1/P (rounded), Ab = A -
 // kPadB P is A in padded-bin coordinates (bin b of a padded sinogram row
-// sits at index b + kPadB) and omP = 1 - |P| (exact).  The fields the
-// back-projector reads come first.
+// sits at index b + kPadB), omP = 1 - |P| (exact) and roff = vidx (B + 2
+// kPadB) is the first element of the view's padded sinogram row.  The
+// fields the back-projector reads come first.
 //
 // The geometry's table lists the row-stepping views first and the
 // column-stepping views after them (Geo::nrow of each); vidx is the view's
 // index v in the sinogram.
 struct alignas(8) ViewGeom {
     double Ab, P, Q, invP, omP;
+    int32_t roff;
     int32_t vidx;
-    int32_t pad0_;
     double A;
     float wstep;
     int32_t pad1_;
@@ -99,6 +100,14 @@ struct Geo {
 #define EXACT_GLOBAL __attribute__((address_space(1)))
 #else
 #define EXACT_GLOBAL
+#endif
+
+// Device code reads wave-uniform read-only tables through constant-address-
+// space pointers, which the compiler loads with scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define EXACT_CONSTANT __attribute__((address_space(4)))
+#else
+#define EXACT_CONSTANT
 #endif
 
 // One problem of a batch, as the batched kernels see it.

@@ -166,17 +166,22 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 // read zeros too.  Every crossing with a tap inside the image has f >= 1
 // (padded), where truncation is floor; a crossing below 1 has both taps in
 // the padding, and truncating it (then clamping at 0) still reads padding.
+//
+// The line is row `rowoff / Np` of img: the row's offset goes into the
+// per-lane element index (one add-and-shift) so that the base stays the
+// same scalar pointer for every line.
 __device__ __forceinline__ void tap_pair(double &f, int N, double Q,
-                                         const float *__restrict__ row, float &w0, float &w1,
-                                         float &v0, float &v1)
+                                         const float *__restrict__ img, int rowoff, float &w0,
+                                         float &w1, float &v0, float &v1)
 {
     const double e0 = __builtin_amdgcn_fract(f);    // f - floor(f), exact, in [0, 1)
     const int c = clamp_int<0>((int)f, N + 2 * kPadX - 2);
     f += Q;                                         // exact
     w0 = (float)(1.0 - e0);                         // pixel floor(f)
     w1 = (float)e0;                                 // pixel floor(f) + 1: 1 - |f - (j0+1)| = e0
-    v0 = at(row, (unsigned)c);
-    v1 = at(row + 1, (unsigned)c);
+    const unsigned i = (unsigned)(rowoff + c);
+    v0 = at(img, i);
+    v1 = at(img + 1, i);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -253,20 +258,71 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     Kahan acc;
     double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
     int k = kw0;
-    for (; k + kLineBatch - 1 <= kw1; k += kLineBatch) {
-        float w0[kLineBatch], w1[kLineBatch], v0[kLineBatch], v1[kLineBatch];
+    // Software-pipelined over batches of lines: the next batch's loads are
+    // issued before the current batch is summed, with two register sets used
+    // alternately (loop-carried copies between them would make the compiler
+    // wait for the loads) and scheduling barriers that keep that order.
+    float aw0[kLineBatch], aw1[kLineBatch], av0[kLineBatch], av1[kLineBatch];
+    float bw0[kLineBatch], bw1[kLineBatch], bv0[kLineBatch], bv1[kLineBatch];
+    const int nb = kw1 >= kw0 ? (kw1 - kw0 + 1) / kLineBatch : 0;
+    if (nb > 0) {
 #pragma unroll
         for (int q = 0; q < kLineBatch; ++q)
-            tap_pair(f, N, G.Q, img + (size_t)(k + q) * Np, w0[q], w1[q], v0[q], v1[q]);
-        float t = 0.f;
+            tap_pair(f, N, G.Q, img, (k + q) * Np, aw0[q], aw1[q], av0[q], av1[q]);
+        k += kLineBatch;
+        int i = 1;
+        for (; i + 1 < nb; i += 2) {
 #pragma unroll
-        for (int q = 0; q < kLineBatch; ++q)
-            t = fmaf(w1[q], v1[q], fmaf(w0[q], v0[q], t));
-        acc.add(t);
+            for (int q = 0; q < kLineBatch; ++q)
+                tap_pair(f, N, G.Q, img, (k + q) * Np, bw0[q], bw1[q], bv0[q], bv1[q]);
+            k += kLineBatch;
+            {
+                float s = 0.f;
+#pragma unroll
+                for (int q = 0; q < kLineBatch; ++q)
+                    s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
+                acc.add(s);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q)
+                tap_pair(f, N, G.Q, img, (k + q) * Np, aw0[q], aw1[q], av0[q], av1[q]);
+            k += kLineBatch;
+            {
+                float s = 0.f;
+#pragma unroll
+                for (int q = 0; q < kLineBatch; ++q)
+                    s = fmaf(bw1[q], bv1[q], fmaf(bw0[q], bv0[q], s));
+                acc.add(s);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (i < nb) {
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q)
+                tap_pair(f, N, G.Q, img, (k + q) * Np, bw0[q], bw1[q], bv0[q], bv1[q]);
+            k += kLineBatch;
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q)
+                s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
+            acc.add(s);
+            s = 0.f;
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q)
+                s = fmaf(bw1[q], bv1[q], fmaf(bw0[q], bv0[q], s));
+            acc.add(s);
+        } else {
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q)
+                s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
+            acc.add(s);
+        }
     }
     for (; k <= kw1; ++k) {
         float w0, w1, v0, v1;
-        tap_pair(f, N, G.Q, img + (size_t)k * Np, w0, w1, v0, v1);
+        tap_pair(f, N, G.Q, img, k * Np, w0, w1, v0, v1);
         acc.add(fmaf(w1, v1, w0 * v0));
     }
     part_s[seg][lane] = acc.s;
@@ -376,17 +432,33 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 // (negative t truncates upwards) or above the detector lands on two
 // padding bins, which read zero whatever their weights; a pair holding a
 // detector bin has t >= 1, where truncation is floor.
-__device__ __forceinline__ float taps_two(const ViewGeom &G, double kd, double jd, int B,
-                                          const float *__restrict__ rv, float acc)
+struct PairTap {
+    float u0, u1, r0, r1;
+};
+
+// The pair's weights and residual values (the loads are issued here and
+// waited for where the values are used).  r is the weighted padded
+// sinogram; the view's row offset goes into the per-lane element index, so
+// the base stays the same scalar pointer for every view.
+__device__ __forceinline__ PairTap tap_fetch(const ViewGeom &G, double kd, double jd, int B,
+                                             const float *__restrict__ r)
 {
     const double T = fma(kd, G.Q, G.Ab - jd);                  // f(0, k) - j, padded; exact
     const double t = -T * G.invP;
     const int bf = clamp_int<0>((int)t, B + 2 * kPadB - 2);
     const double d = fma((double)bf, G.P, T);                  // exact
-    const float u0 = __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
-    const float u1 = __builtin_amdgcn_fmed3f((float)(fabs(d) + G.omP), 0.f, 1.f);
-    const float *p = (const float *)((const char *)rv + ((unsigned)bf << 2));
-    return fmaf(u1, p[1], fmaf(u0, p[0], acc));
+    PairTap p;
+    p.u0 = __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
+    p.u1 = __builtin_amdgcn_fmed3f((float)(fabs(d) + G.omP), 0.f, 1.f);
+    const unsigned i = (unsigned)(G.roff + bf);
+    p.r0 = at(r, i);
+    p.r1 = at(r + 1, i);
+    return p;
+}
+
+__device__ __forceinline__ float tap_apply(const PairTap &p, float acc)
+{
+    return fmaf(p.u1, p.r1, fmaf(p.u0, p.r0, acc));
 }
 
 // General rule (bins narrower than pixels): every bin within `reach` of b0.
@@ -410,9 +482,11 @@ __device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double
 }
 
 // Sum over views [v0, v1) of the taps for pixel (kd, jd) of each view's
-// stepping line, from the weighted padded sinogram r.  Batches of views:
-// parameters and loads first, then a float sum of the batch, then one
-// Kahan step.
+// stepping line, from the weighted padded sinogram r.  Batches of views,
+// each summed in float (in view order) before one Kahan step.  With the
+// pair rule the loop is software-pipelined: the next batch's weights are
+// formed and its loads issued before the current batch is summed, so a
+// wave keeps two batches of loads in flight.
 template <bool kTwo>
 __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views, int v0, int v1,
                                              double kd, double jd, int B, int reach,
@@ -420,22 +494,71 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
 {
     const int rstride = padded_bins(B);
     int v = v0;
+    if (kTwo) {
+        // two register sets used alternately: a copy between them would
+        // make the compiler wait for the loads at the copy
+        PairTap ta[kViewBatch], tb[kViewBatch];
+        auto fetch = [&](PairTap(&t)[kViewBatch], int vb) {
+            // the batch's table pointer (constant address space: scalar
+            // loads), opaque to the loop optimiser so that the views' fields
+            // are read at small positive immediate offsets
+            using CView = const ViewGeom EXACT_CONSTANT;
+            CView *gp = (CView *)(views + vb);
+            asm("" : "+s"(gp));
+#pragma unroll
+            for (int q = 0; q < kViewBatch; ++q) {
+                const ViewGeom G = gp[q];
+                t[q] = tap_fetch(G, kd, jd, B, r);
+            }
+        };
+        auto apply = [&](const PairTap(&t)[kViewBatch]) {
+            float sb = 0.f;
+#pragma unroll
+            for (int q = 0; q < kViewBatch; ++q)
+                sb = tap_apply(t[q], sb);
+            acc.add(sb);
+        };
+        const int nb = (v1 - v0) / kViewBatch;
+        if (nb > 0) {
+            fetch(ta, v);
+            int i = 1;
+            // the scheduling barriers keep each batch's loads ahead of the
+            // previous batch's sum and the next batch's loads behind it
+            for (; i + 1 < nb; i += 2) {
+                fetch(tb, v + i * kViewBatch);
+                apply(ta);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(ta, v + (i + 1) * kViewBatch);
+                apply(tb);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (i < nb) {
+                fetch(tb, v + i * kViewBatch);
+                apply(ta);
+                apply(tb);
+            } else {
+                apply(ta);
+            }
+            v += nb * kViewBatch;
+        }
+        for (; v < v1; ++v) {
+            const ViewGeom G = views[v];
+            acc.add(tap_apply(tap_fetch(G, kd, jd, B, r), 0.f));
+        }
+        return;
+    }
     for (; v + kViewBatch <= v1; v += kViewBatch) {
         float sb = 0.f;
 #pragma unroll
         for (int q = 0; q < kViewBatch; ++q) {
             const ViewGeom G = views[v + q];
-            const float *rv = r + (size_t)G.vidx * rstride;
-            sb = kTwo ? taps_two(G, kd, jd, B, rv, sb)
-                      : taps_reach(G, kd, jd, B, reach, rv + kPadB, sb);
+            sb = taps_reach(G, kd, jd, B, reach, r + (size_t)G.vidx * rstride + kPadB, sb);
         }
         acc.add(sb);
     }
     for (; v < v1; ++v) {
         const ViewGeom G = views[v];
-        const float *rv = r + (size_t)G.vidx * rstride;
-        acc.add(kTwo ? taps_two(G, kd, jd, B, rv, 0.f)
-                     : taps_reach(G, kd, jd, B, reach, rv + kPadB, 0.f));
+        acc.add(taps_reach(G, kd, jd, B, reach, r + (size_t)G.vidx * rstride + kPadB, 0.f));
     }
 }
 
