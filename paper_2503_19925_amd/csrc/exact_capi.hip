@@ -27,6 +27,7 @@ struct exact_geometry_s {
     double pixel_cm, bin_cm;
     int device;
     ViewGeom *d_views;
+    int32_t *d_blk;
     std::vector<ViewGeom> h_views;
 };
 
@@ -68,7 +69,7 @@ int guarded(F &&body)
 
 Geo geo_of(const exact_geometry_s *g)
 {
-    return Geo{g->d_views, g->N, g->V, g->B, g->nrow, g->reach};
+    return Geo{g->d_views, g->d_blk, g->N, g->V, g->B, g->nrow, g->reach};
 }
 
 void check_geometry(const exact_geometry_s *g)
@@ -109,6 +110,7 @@ SpecArg make_spec(const exact_spectrum *sp, double *sum_J_mu)
         }
         a.J[k] = (float)J;
         a.mu[k] = (float)mu;
+        a.mu2[k] = (float)((long double)mu * 1.44269504088896340735992468100189214L);
         sjm += J * mu;
     }
     for (int j = 0; j < Wn; ++j) {
@@ -178,6 +180,49 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
     *reach = pmin >= 1.0L ? 0 : (int)floorl(1.0L / pmin + 0.5L + 0.01L);
     if (*reach > 32)
         fail(-EINVAL, "bins narrower than 1/32 of a pixel are not supported");
+    return out;
+}
+
+// First and last image line that any ray of each block of 64 bins reaches,
+// per table slot (the forward projector splits these lines among its
+// waves).  Ray b of a view crosses line k at f = A + b P + k Q and has a tap
+// inside the image iff floor(f) is in [-1, N - 1], i.e. f in [-1, N); the
+// line interval of one ray is taken one line wider on each side.  The
+// interval's ends are affine in b, so over a block they are extreme at its
+// first or last ray; the union of the rays' intervals lies within the hull
+// of those two.  A block no ray of which reaches a line gets first > last.
+std::vector<int32_t> block_lines(const std::vector<ViewGeom> &views, int N, int B)
+{
+    const int nbb = (B + 63) / 64;
+    std::vector<int32_t> out(2 * views.size() * (size_t)nbb);
+    for (size_t slot = 0; slot < views.size(); ++slot) {
+        const ViewGeom &G = views[slot];
+        for (int bb = 0; bb < nbb; ++bb) {
+            const long double ends[2] = {64.0L * bb, (long double)std::min(64 * bb + 63, B - 1)};
+            long double lo = 1e30L, hi = -1e30L;
+            if (G.Q != 0.0) {
+                for (long double b : ends) {
+                    const long double base = (long double)G.A + b * (long double)G.P;
+                    const long double ka = (-1.0L - base) / G.Q, kb = ((long double)N - base) / G.Q;
+                    lo = std::min(lo, floorl(std::min(ka, kb)) - 1.0L);
+                    hi = std::max(hi, ceill(std::max(ka, kb)) + 1.0L);
+                }
+            } else {
+                // every line or none: some ray's f in [-1, N) (one pixel wider)
+                const long double f0 = (long double)G.A + ends[0] * (long double)G.P;
+                const long double f1 = (long double)G.A + ends[1] * (long double)G.P;
+                if (std::max(f0, f1) >= -2.0L && std::min(f0, f1) < (long double)N + 1.0L) {
+                    lo = 0.0L;
+                    hi = N - 1;
+                }
+            }
+            lo = std::max(lo, 0.0L);
+            hi = std::min(hi, (long double)(N - 1));
+            const size_t i = 2 * (slot * nbb + bb);
+            out[i] = lo <= hi ? (int32_t)lo : N;
+            out[i + 1] = lo <= hi ? (int32_t)hi : -1;
+        }
+    }
     return out;
 }
 
@@ -342,6 +387,7 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         g->pixel_cm = pixel_cm;
         g->bin_cm = bin_cm;
         g->d_views = nullptr;
+        g->d_blk = nullptr;
         try {
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
             g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm,
@@ -350,9 +396,16 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
             hip_check(hipMalloc((void **)&g->d_views, bytes), "hipMalloc");
             hip_check(hipMemcpy(g->d_views, g->h_views.data(), bytes, hipMemcpyHostToDevice),
                       "hipMemcpy");
+            const std::vector<int32_t> blk = block_lines(g->h_views, n_pix, n_bins);
+            hip_check(hipMalloc((void **)&g->d_blk, blk.size() * sizeof(int32_t)), "hipMalloc");
+            hip_check(hipMemcpy(g->d_blk, blk.data(), blk.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice),
+                      "hipMemcpy");
         } catch (...) {
             if (g->d_views)
                 (void)hipFree(g->d_views);
+            if (g->d_blk)
+                (void)hipFree(g->d_blk);
             delete g;
             throw;
         }
@@ -369,6 +422,8 @@ int exact_geometry_destroy(exact_geometry g)
         (void)hipDeviceSynchronize();
         if (g->d_views)
             hip_check(hipFree(g->d_views), "hipFree");
+        if (g->d_blk)
+            hip_check(hipFree(g->d_blk), "hipFree");
         delete g;
         return 0;
     });
@@ -512,6 +567,7 @@ struct Problem {
         exact::BatchProb d;
         std::memset(&d, 0, sizeof(d));
         d.views = g->d_views;
+        d.blk = g->d_blk;
         d.N = g->N;
         d.V = g->V;
         d.B = g->B;
@@ -521,7 +577,7 @@ struct Problem {
         d.ntiles = exact::num_tiles(g->N);
         d.Y = Y->as<float>();
         d.J = specd->as<float>();
-        d.mu = specd->as<float>() + exact::kMaxEnergies;
+        d.mu2 = specd->as<float>() + exact::kMaxEnergies;
         d.bg = bg ? bg->as<float>() : nullptr;
         d.x = x;
         d.xp = xp->as<float>();
@@ -601,7 +657,7 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.specd.reset(new DevBuf(2 * exact::kMaxEnergies * 4));
     hip_check(hipMemcpyAsync(p.specd->p, p.spec.J, exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
               "hipMemcpyAsync");
-    hip_check(hipMemcpyAsync(p.specd->as<float>() + exact::kMaxEnergies, p.spec.mu,
+    hip_check(hipMemcpyAsync(p.specd->as<float>() + exact::kMaxEnergies, p.spec.mu2,
                              exact::kMaxEnergies * 4, hipMemcpyHostToDevice, st),
               "hipMemcpyAsync");
 

@@ -59,11 +59,14 @@ __host__ __device__ inline int padded_cols(int N) { return N + 2 * kPadX; }
 __host__ __device__ inline int padded_bins(int B) { return B + 2 * kPadB; }
 
 // Spectrum collapsed over windows, passed to kernels by value; bg (device,
-// [V][B], or null) holds known materials' line integrals per ray.
+// [V][B], or null) holds known materials' line integrals per ray.  The CT
+// residual evaluates exp(-mu_k t) as 2^(-mu2_k t) with mu2_k = mu_k log2(e)
+// (rounded once on the host).
 struct SpecArg {
     int32_t K;
     float J[kMaxEnergies];    // J_k = sum_j weight[j][k]
     float mu[kMaxEnergies];
+    float mu2[kMaxEnergies];
     const float *bg;
 };
 
@@ -84,6 +87,10 @@ struct SolveState {
 
 struct Geo {
     const ViewGeom *views;
+    // Per (table slot, block of 64 bins): first and last image line any of
+    // the block's rays reaches (first > last if none), conservative by one
+    // line; 2 ints each, slot-major.
+    const int32_t *blk;
     int N, V, B;
     int nrow;        // views[0, nrow) step along rows, views[nrow, V) along columns
     // Bins examined on each side of the nearest one in the back-projector;
@@ -115,8 +122,9 @@ struct BatchProb {
     const ViewGeom EXACT_GLOBAL *views;
     int32_t N, V, B, nrow, reach, K, ntiles, pad;
     const float EXACT_GLOBAL *Y;       // window sums of y
-    const float EXACT_GLOBAL *J;       // spectrum (device copies)
-    const float EXACT_GLOBAL *mu;
+    const int32_t EXACT_GLOBAL *blk;   // the geometry's block line table
+    const float EXACT_GLOBAL *J;       // spectrum (device copies; mu2 = mu log2(e))
+    const float EXACT_GLOBAL *mu2;
     const float EXACT_GLOBAL *bg;      // known materials' line integrals, or null
     float EXACT_GLOBAL *x;             // iterate (the caller's buffer)
     float EXACT_GLOBAL *xp;            // iterate and its transpose, padded rows

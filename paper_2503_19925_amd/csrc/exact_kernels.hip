@@ -125,23 +125,6 @@ __device__ __host__ __forceinline__ int centre_out(int r, int nbb)
     return (r % 2 == 0) ? c + r / 2 : c - (r + 1) / 2;
 }
 
-// Lines k (of the N) on which ray base + k Q can have a tap inside the image,
-// i.e. floor(f) in [-1, N-1]; conservative by one line at each end (the
-// per-line test stays authoritative).
-__device__ __forceinline__ void ray_lines(double base, double Q, int N, int &k0, int &k1)
-{
-    double lo = 0.0, hi = (double)(N - 1);
-    if (Q != 0.0) {
-        const double ka = (-1.0 - base) / Q, kb = ((double)N - base) / Q;
-        lo = fmax(lo, floor(fmin(ka, kb)) - 1.0);
-        hi = fmin(hi, ceil(fmax(ka, kb)) + 1.0);
-    } else if (!(base > -1.0 && base < (double)N)) {
-        hi = -1.0;
-    }
-    k0 = (int)lo;
-    k1 = (int)hi;
-}
-
 #ifndef EXACT_LINE_BATCH
 #define EXACT_LINE_BATCH 4
 #endif
@@ -184,34 +167,22 @@ __device__ __forceinline__ void tap_pair(double &f, int N, double Q,
     v1 = at(img + 1, i);
 }
 
-__device__ __forceinline__ int wave_min(int v)
-{
-    for (int off = 32; off > 0; off >>= 1)
-        v = min(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-    for (int off = 32; off > 0; off >>= 1)
-        v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
 // One lane per ray (v, b); the four waves of a workgroup take the same 64
-// rays and split the image lines those rays reach into four equal shares,
-// and their Kahan partial sums are combined in a fixed order.  A wave walks
+// rays and split the image lines those rays reach (from the geometry's
+// block table) into four equal shares, and their Kahan partial sums are
+// combined in a fixed order.  A wave walks
 // its lines in a wave-uniform loop, so the line's address is scalar; a ray
 // on a line it does not reach reads padding zeros.  The crossing advances
 // exactly by Q per line.  Column-stepping views read the transposed image so
 // that the lanes of a wave touch neighbouring addresses on every line.
 // Within a batch of lines the contributions are summed in float before the
 // Kahan step.
-// Spectrum read through device pointers (the batched kernels).
+// Spectrum read through device pointers (the batched kernels); mu2 holds
+// mu log2(e), as in SpecArg.
 struct SpecPtr {
     int32_t K;
     const float *__restrict__ J;
-    const float *__restrict__ mu;
+    const float *__restrict__ mu2;
     const float *__restrict__ bg;
 };
 
@@ -220,9 +191,11 @@ struct SpecPtr {
 // image pair; with kResid the spectral residual replaces the line integral.
 // Ray i = vidx B + b goes to out[vidx * ostride + ooff + b], times the
 // view's wstep when weighted, and unweighted to plain[i] when plain is not
-// null.
+// null.  blk[2 (slot nbb + bblock) + {0, 1}] bound the lines the block's
+// rays reach (conservatively; lines a ray misses read padding zeros).
 template <bool kResid, class Spec>
-__device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views, int N, int B,
+__device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views,
+                                              const int32_t *__restrict__ blk, int N, int B,
                                               int nrow, const float *__restrict__ xp,
                                               const float *__restrict__ xTp,
                                               const float *__restrict__ Y, const Spec &sp,
@@ -231,6 +204,7 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
                                               int slot, int bblock)
 {
     __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
+    __shared__ float part_m[kSegs][kFwdThreads];
     const int lane = threadIdx.x % kFwdThreads;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);  // wave-uniform
     const int b = bblock * kFwdThreads + lane;
@@ -239,15 +213,10 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     const int Np = padded_cols(N);
     const double base = fma((double)b, G.P, G.A);
 
-    int k0, k1;
-    ray_lines(base, G.Q, N, k0, k1);
-    if (b >= B) {
-        k0 = N;
-        k1 = -1;
-    }
-    // the four waves hold the same 64 rays: split the lines any of them
-    // reaches into equal shares
-    const int kmin = wave_min(k0), kmax = wave_max(k1);
+    // the waves hold the same 64 rays: split the lines any of them reaches
+    // into equal shares
+    const int bi = 2 * (slot * ((B + kFwdThreads - 1) / kFwdThreads) + bblock);
+    const int kmin = blk[bi], kmax = blk[bi + 1];
     int kw0 = 0, kw1 = -1;
     if (kmin <= kmax) {
         const int per = (kmax - kmin + kSegs) / kSegs;
@@ -328,8 +297,7 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     part_s[seg][lane] = acc.s;
     part_c[seg][lane] = acc.c;
     __syncthreads();
-    if (seg != 0 || b >= B)
-        return;
+    // every wave forms the rays' totals (the same fixed order)
     Kahan tot;
 #pragma unroll
     for (int q = 0; q < kSegs; ++q) {
@@ -337,17 +305,28 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         tot.add(-part_c[q][lane]);
     }
     const float s = tot.value() * G.wstep;
+    const bool ray = b < B;
     const size_t o = (size_t)G.vidx * ostride + ooff + b;
-    const size_t i = (size_t)G.vidx * B + b;
+    const size_t i = (size_t)G.vidx * B + (ray ? b : 0);
     float val = s;
     if (kResid) {
-        // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0)))
-        const float sp0 = fmaxf(s, 0.f) + (sp.bg ? sp.bg[i] : 0.f);
+        // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with
+        // exp(-mu t) = 2^(-mu log2(e) t); wave w sums the energies k = w,
+        // w + kSegs, ..., and the waves' sums are added in order
+        const float sp0 = fmaxf(s, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
         float m = 0.f;
-        for (int q = 0; q < sp.K; ++q)
-            m = fmaf(sp.J[q], expf(-sp.mu[q] * sp0), m);
-        val = Y[i] - m;
+        for (int q = seg; q < sp.K; q += kSegs)
+            m = fmaf(sp.J[q], exp2f(-sp.mu2[q] * sp0), m);
+        part_m[seg][lane] = m;
+        __syncthreads();
+        float mt = part_m[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSegs; ++q)
+            mt += part_m[q][lane];
+        val = Y[i] - mt;
     }
+    if (seg != 0 || !ray)
+        return;
     out[o] = weighted ? val * G.wstep : val;
     if (plain)
         plain[i] = val;
@@ -357,7 +336,8 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
 // the heaviest blocks of every view are dispatched first.
 template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
-    const ViewGeom *__restrict__ views, int N, int V, int B, int nrow,
+    const ViewGeom *__restrict__ views, const int32_t *__restrict__ blk, int N, int V, int B,
+    int nrow,
     const float *__restrict__ xp, const float *__restrict__ xTp, const float *__restrict__ Y,
     SpecArg sp, float *__restrict__ out, int ostride, int ooff, int weighted,
     float *__restrict__ plain, const int32_t *__restrict__ skip)
@@ -365,8 +345,8 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     if (skipped(skip))
         return;
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
-    forward_block<kResid>(views, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff, weighted != 0,
-                          plain, blockIdx.x % V, centre_out(blockIdx.x / V, nbb));
+    forward_block<kResid>(views, blk, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff,
+                          weighted != 0, plain, blockIdx.x % V, centre_out(blockIdx.x / V, nbb));
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -899,8 +879,8 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void kb_forward(const BatchProb
     const BatchProb &P = probs[it.p];
     if (glob(P.state)->done)
         return;
-    const SpecPtr sp{P.K, glob(P.J), glob(P.mu), P.bg ? glob(P.bg) : nullptr};
-    forward_block<true>(glob(P.views), P.N, P.B, P.nrow, glob(kAtHalf ? P.xhp : P.xp),
+    const SpecPtr sp{P.K, glob(P.J), glob(P.mu2), P.bg ? glob(P.bg) : nullptr};
+    forward_block<true>(glob(P.views), glob(P.blk), P.N, P.B, P.nrow, glob(kAtHalf ? P.xhp : P.xp),
                         glob(kAtHalf ? P.xhTp : P.xTp), glob(P.Y), sp, glob(P.r),
                         padded_bins(P.B), kPadB, true, nullptr, it.a, it.b);
 }
@@ -1061,8 +1041,8 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
     none.K = 0;
     none.bg = nullptr;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
-    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
+    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
+                       g.N, g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
                        weighted ? 1 : 0, nullptr, skip);
     return hipGetLastError();
 }
@@ -1072,8 +1052,8 @@ hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *x
                                    const int32_t *skip, hipStream_t st)
 {
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
-    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.N,
-                       g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1, r_plain,
+    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
+                       g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1, r_plain,
                        skip);
     return hipGetLastError();
 }
