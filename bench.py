@@ -45,6 +45,14 @@ WORKLOADS = {
                   "1448 bins, 64 energy bins, 4 windows, I0=1e3 Poisson",
 }
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 64 lanes (4 SIMDs of 16, one wave64 instruction
+# per 4 cycles each, packed FP32 not used) x 2.4 GHz, in T lane-instructions/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU instructions of the inner loops, counted in their gfx950 assembly
+# (Kahan steps included): per pixel and view in the gather, per ray and
+# line in the forward
+VALU_PER_PIXEL_VIEW = 15.0
+VALU_PER_RAY_LINE = 11.0
 
 
 def log(*a):
@@ -369,6 +377,13 @@ def main():
     achieved = sum(bytes_bu) / (sum(t_bu) * 1e-3) / 1e9
     bytes_fwd = 4.0 * nnz + 8.0 * g.d + 8.0 * g.n        # x operands, Y in, r out
     fwd_achieved = 2 * bytes_fwd / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9
+    # the same kernels against the VALU issue rate: lane-instructions of the
+    # inner loop per pixel-view (gather) and per ray-line crossing (forward,
+    # about nnz / 2 crossings: each has two taps except at the image edge)
+    valu_bu = VALU_PER_PIXEL_VIEW * g.d * P.n_views
+    valu_bu_tops = 2 * valu_bu / (sum(t_bu) * 1e-3) / 1e12
+    valu_fwd = VALU_PER_RAY_LINE * nnz / 2.0
+    valu_fwd_tops = 2 * valu_fwd / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e12
 
     to_tol = None
     if args.to_tol > 0:
@@ -448,10 +463,20 @@ def main():
         "roofline": {"kernel": "k_back_update", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, "k_back_update"),
-                     "bytes_per_launch": sum(bytes_bu) / 2, "ms_per_launch": sum(t_bu) / 2},
+                     "bytes_per_launch": sum(bytes_bu) / 2, "ms_per_launch": sum(t_bu) / 2,
+                     "alu_issue": {"bound": "alu", "achieved": valu_bu_tops,
+                                   "peak": VALU_PEAK_TOPS,
+                                   "unit": "T VALU lane-instructions/s",
+                                   "frac": valu_bu_tops / VALU_PEAK_TOPS,
+                                   "valu_per_pixel_view": VALU_PER_PIXEL_VIEW}},
         "roofline_forward": {"kernel": "k_forward<true>", "bound": "hbm",
                              "achieved": fwd_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": fwd_achieved / HBM_PEAK_GBS},
+                             "frac": fwd_achieved / HBM_PEAK_GBS,
+                             "alu_issue": {"bound": "alu", "achieved": valu_fwd_tops,
+                                           "peak": VALU_PEAK_TOPS,
+                                           "unit": "T VALU lane-instructions/s",
+                                           "frac": valu_fwd_tops / VALU_PEAK_TOPS,
+                                           "valu_per_ray_line": VALU_PER_RAY_LINE}},
         "to_tol": to_tol,
         "background": background,
         "tv_ball": tv,
