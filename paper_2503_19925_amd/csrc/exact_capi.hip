@@ -1281,14 +1281,14 @@ struct TvWork {
     int N = 0;
     long d = 0;
     exact_tv_opts o;
-    std::unique_ptr<DevBuf> p, q, r, s, r2, s2, x, y, w, z, dp, dq, lam, parts, out;
+    std::unique_ptr<DevBuf> p, q, r, s, p2, q2, r2, s2, x, y, w, z, dp, dq, lam, parts, out;
     double *h = nullptr;       // pinned: [0] lam to upload, [1..2] read back
     Graph prox;
     int solves = 0;
 
     TvWork(int n, const exact_tv_opts &opts, hipStream_t st) : N(n), d((long)n * n), o(opts)
     {
-        for (auto *b : {&p, &q, &r, &s, &r2, &s2, &x, &y, &w, &z, &dp, &dq})
+        for (auto *b : {&p, &q, &r, &s, &p2, &q2, &r2, &s2, &x, &y, &w, &z, &dp, &dq})
             b->reset(new DevBuf((size_t)d * 4));
         lam.reset(new DevBuf(8));
         const int np = std::max(exact::num_tv_parts(n), 2 * exact::num_flat_parts(d));
@@ -1296,10 +1296,10 @@ struct TvWork {
         out.reset(new DevBuf(16));
         hip_check(hipHostMalloc((void **)&h, 32, hipHostMallocDefault), "hipHostMalloc");
         prox.capture(st, [&]() {
-            return exact::launch_prox_graph_body(w->as<float>(), p->as<float>(), q->as<float>(),
-                                                 r->as<float>(), s->as<float>(), r2->as<float>(),
-                                                 s2->as<float>(), lam->as<double>(),
-                                                 o.prox_iters, x->as<float>(), N, st);
+            return exact::launch_prox_graph_body(
+                w->as<float>(), p->as<float>(), q->as<float>(), r->as<float>(), s->as<float>(),
+                p2->as<float>(), q2->as<float>(), r2->as<float>(), s2->as<float>(),
+                lam->as<double>(), o.prox_iters, x->as<float>(), N, st);
         });
     }
     ~TvWork()

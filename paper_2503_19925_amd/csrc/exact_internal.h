@@ -238,11 +238,12 @@ hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int
 int num_tv_parts(int N);        // partial sums of k_tv_parts
 int num_flat_parts(long d);     // partial sums of the flat reductions
 // One TV-regularized point x = argmin ||x - b||^2 + lam TV(x) by `iters`
-// FGP steps from zero; lam is read on the device.  p, q, r, s, r2, s2 are
-// work fields of N*N floats.  Launch sequence only (capturable).
+// FGP steps from zero; lam is read on the device.  p, q, r, s and p2, q2,
+// r2, s2 are work fields of N*N floats (the state alternates between the
+// two sets).  Launch sequence only (capturable).
 hipError_t launch_prox_graph_body(const float *b, float *p, float *q, float *r, float *s,
-                                  float *r2, float *s2, const double *lam, int iters, float *x,
-                                  int N, hipStream_t st);
+                                  float *p2, float *q2, float *r2, float *s2, const double *lam,
+                                  int iters, float *x, int N, hipStream_t st);
 // out[0] = TV(x) in double (parts: num_tv_parts(N) doubles).
 hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st);
 // Dykstra's round around the TV projection: w = z + p before it; after it

@@ -10,6 +10,7 @@
 // captured graph per proximal solve.  Reductions are fixed-order doubles.
 #include "exact_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace exact {
@@ -34,69 +35,106 @@ __device__ __forceinline__ float primal_at(const float *__restrict__ b,
     return fmaf(-l, L, b[c]);
 }
 
-// One FGP step: from the extrapolated dual point (r, s) to the new dual
-// point (p, q) (in place: each lane owns its pixel's p, q) and the next
-// extrapolated point (r2, s2) with momentum weight w:
+// FGP steps from the extrapolated dual point (r, s) to the new dual point
+// (p, q) and the next extrapolated point, each
 //   x = b - l L(r, s);  (p', q') = P_disc((r, s) + L^T(x) / (8 l));
-//   (r2, s2) = (p', q') + w ((p', q') - (p, q)).
-// L^T(x) = (x_ij - x_{i+1,j}, x_ij - x_{i,j+1}); the last row of p and the
-// last column of q stay zero.  lam (device) is the TV weight; l = lam / 2.
+//   (r, s) <- (p', q') + w_t ((p', q') - (p, q));  (p, q) <- (p', q'),
+// with momentum weight w_t for step t.  L^T(x) = (x_ij - x_{i+1,j},
+// x_ij - x_{i,j+1}); the last row of p and the last column of q stay zero.
+// lam (device) is the TV weight; l = lam / 2.
 //
-// A 32 x 8 block stages r (one row above), s (one column left) and b for its
-// tile plus one row below and one column right in LDS (zeros outside the
-// image), forms x on that extended tile, then updates its own pixels.
-__global__ __launch_bounds__(kTvX *kTvY) void k_fgp_step(
-    const float *__restrict__ b, const float *__restrict__ r, const float *__restrict__ s,
-    float *__restrict__ p, float *__restrict__ q, float *__restrict__ r2,
-    float *__restrict__ s2, const double *__restrict__ lam, float w, int N)
+// Temporal blocking: a step at a pixel reads the previous state within
+// Chebyshev distance 1, so a workgroup that holds its 32 x 32 tile and a
+// halo of kFgpHalo pixels in LDS (r, s, x) and registers (p, q, b) can take
+// up to kFgpHalo steps before its tile's values depend on anything outside:
+// after step t the cells within t of the region's edge are stale, the tile
+// is not.  Pixels outside the image hold zero state.  Each step's arithmetic
+// per pixel is the single-step formula's, so the result does not depend on
+// the blocking.  The state is read from one set of fields and written to
+// another (neighbouring workgroups read the halo).
+constexpr int kFgpTile = 32, kFgpHalo = 8, kFgpReg = kFgpTile + 2 * kFgpHalo;
+constexpr int kFgpThreads = 768;
+constexpr int kFgpCells = kFgpReg * kFgpReg / kFgpThreads;
+static_assert(kFgpReg * kFgpReg % kFgpThreads == 0, "region cells per thread");
+
+struct FgpSteps {
+    float w[kFgpHalo];   // momentum weight of each step of this launch
+    int32_t n;           // steps, 1..kFgpHalo
+};
+
+__global__ __launch_bounds__(kFgpThreads) void k_fgp_steps(
+    const float *__restrict__ b, const float *__restrict__ p, const float *__restrict__ q,
+    const float *__restrict__ r, const float *__restrict__ s, float *__restrict__ po,
+    float *__restrict__ qo, float *__restrict__ ro, float *__restrict__ so,
+    const double *__restrict__ lam, FgpSteps W, int N)
 {
-    constexpr int RY = kTvY + 2, RX = kTvX + 1;     // r: rows i0-1 .. i0+8
-    constexpr int SY = kTvY + 1, SX = kTvX + 2;     // s: cols j0-1 .. j0+32
-    constexpr int XY = kTvY + 1, XX = kTvX + 1;     // b, x: tile + 1 row + 1 column
-    __shared__ float Rl[RY][RX], Sl[SY][SX], Bl[XY][XX], Xl[XY][XX];
-    const int tid = threadIdx.x + threadIdx.y * kTvX;
-    const int i0 = blockIdx.y * kTvY, j0 = blockIdx.x * kTvX;
+    __shared__ float R[kFgpReg][kFgpReg + 1], S[kFgpReg][kFgpReg + 1], X[kFgpReg][kFgpReg + 1];
+    const int i0 = blockIdx.y * kFgpTile - kFgpHalo, j0 = blockIdx.x * kFgpTile - kFgpHalo;
     const float l = (float)(*lam * 0.5);
     const float inv8l = (float)(1.0 / (8.0 * (*lam * 0.5)));
-    for (int k = tid; k < RY * RX; k += kTvX * kTvY) {
-        const int gi = i0 - 1 + k / RX, gj = j0 + k % RX;
-        Rl[k / RX][k % RX] = (gi >= 0 && gi < N && gj < N) ? r[(size_t)gi * N + gj] : 0.f;
-    }
-    for (int k = tid; k < SY * SX; k += kTvX * kTvY) {
-        const int gi = i0 + k / SX, gj = j0 - 1 + k % SX;
-        Sl[k / SX][k % SX] = (gi < N && gj >= 0 && gj < N) ? s[(size_t)gi * N + gj] : 0.f;
-    }
-    for (int k = tid; k < XY * XX; k += kTvX * kTvY) {
-        const int gi = i0 + k / XX, gj = j0 + k % XX;
-        Bl[k / XX][k % XX] = (gi < N && gj < N) ? b[(size_t)gi * N + gj] : 0.f;
-    }
-    __syncthreads();
-    // x = b - l (r + s - r_up - s_left) on the extended tile
-    for (int k = tid; k < XY * XX; k += kTvX * kTvY) {
-        const int a = k / XX, c = k % XX;
-        const float L = ((Rl[a + 1][c] + Sl[a][c + 1]) - Rl[a][c]) - Sl[a][c];
-        Xl[a][c] = fmaf(-l, L, Bl[a][c]);
+    float pc[kFgpCells], qc[kFgpCells], bc[kFgpCells];
+#pragma unroll
+    for (int c = 0; c < kFgpCells; ++c) {
+        const int k = threadIdx.x + c * kFgpThreads;
+        const int a = k / kFgpReg, e = k % kFgpReg, gi = i0 + a, gj = j0 + e;
+        const bool in = gi >= 0 && gi < N && gj >= 0 && gj < N;
+        const size_t g = in ? (size_t)gi * N + gj : 0;
+        R[a][e] = in ? r[g] : 0.f;
+        S[a][e] = in ? s[g] : 0.f;
+        pc[c] = in ? p[g] : 0.f;
+        qc[c] = in ? q[g] : 0.f;
+        bc[c] = in ? b[g] : 0.f;
     }
     __syncthreads();
-    const int i = i0 + threadIdx.y, j = j0 + threadIdx.x;
-    if (i >= N || j >= N)
-        return;
-    const int ty = threadIdx.y, tx = threadIdx.x;
-    const float xc = Xl[ty][tx];
-    float av = 0.f, bv = 0.f;
-    if (i + 1 < N)
-        av = fmaf(xc - Xl[ty + 1][tx], inv8l, Rl[ty + 1][tx]);
-    if (j + 1 < N)
-        bv = fmaf(xc - Xl[ty][tx + 1], inv8l, Sl[ty][tx + 1]);
-    const float nrm = sqrtf(fmaf(av, av, bv * bv));
-    const float den = fmaxf(nrm, 1.f);
-    const float pn = av / den, qn = bv / den;
-    const size_t c = (size_t)i * N + j;
-    const float po = p[c], qo = q[c];
-    p[c] = pn;
-    q[c] = qn;
-    r2[c] = fmaf(w, pn - po, pn);
-    s2[c] = fmaf(w, qn - qo, qn);
+    for (int t = 0; t < W.n; ++t) {
+        // x = b - l (r + s - r_up - s_left) on the whole region (terms beyond
+        // the region's edge are taken as zero: those cells go stale)
+#pragma unroll
+        for (int c = 0; c < kFgpCells; ++c) {
+            const int k = threadIdx.x + c * kFgpThreads;
+            const int a = k / kFgpReg, e = k % kFgpReg;
+            const float up = a > 0 ? R[a - 1][e] : 0.f, left = e > 0 ? S[a][e - 1] : 0.f;
+            const float L = ((R[a][e] + S[a][e]) - up) - left;
+            X[a][e] = fmaf(-l, L, bc[c]);
+        }
+        __syncthreads();
+        const float w = W.w[t];
+#pragma unroll
+        for (int c = 0; c < kFgpCells; ++c) {
+            const int k = threadIdx.x + c * kFgpThreads;
+            const int a = k / kFgpReg, e = k % kFgpReg, gi = i0 + a, gj = j0 + e;
+            const bool in = gi >= 0 && gi < N && gj >= 0 && gj < N;
+            const float xc = X[a][e];
+            float av = 0.f, bv = 0.f;
+            if (gi + 1 < N && a + 1 < kFgpReg)
+                av = fmaf(xc - X[a + 1][e], inv8l, R[a][e]);
+            if (gj + 1 < N && e + 1 < kFgpReg)
+                bv = fmaf(xc - X[a][e + 1], inv8l, S[a][e]);
+            const float nrm = sqrtf(fmaf(av, av, bv * bv));
+            const float den = fmaxf(nrm, 1.f);
+            const float pn = in ? av / den : 0.f, qn = in ? bv / den : 0.f;
+            // only this cell's r, s are read in this phase: update in place
+            R[a][e] = fmaf(w, pn - pc[c], pn);
+            S[a][e] = fmaf(w, qn - qc[c], qn);
+            pc[c] = pn;
+            qc[c] = qn;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < kFgpCells; ++c) {
+        const int k = threadIdx.x + c * kFgpThreads;
+        const int a = k / kFgpReg, e = k % kFgpReg, gi = i0 + a, gj = j0 + e;
+        if (a < kFgpHalo || a >= kFgpHalo + kFgpTile || e < kFgpHalo || e >= kFgpHalo + kFgpTile)
+            continue;
+        if (gi >= N || gj >= N)
+            continue;
+        const size_t g = (size_t)gi * N + gj;
+        po[g] = pc[c];
+        qo[g] = qc[c];
+        ro[g] = R[a][e];
+        so[g] = S[a][e];
+    }
 }
 
 // x = b - l L(p, q), the primal point of the final dual iterate.
@@ -276,20 +314,30 @@ int num_tv_parts(int N)
 int num_flat_parts(long d) { return flat_blocks(d); }
 
 hipError_t launch_prox_graph_body(const float *b, float *p, float *q, float *r, float *s,
-                                  float *r2, float *s2, const double *lam, int iters, float *x,
-                                  int N, hipStream_t st)
+                                  float *p2, float *q2, float *r2, float *s2, const double *lam,
+                                  int iters, float *x, int N, hipStream_t st)
 {
     const long d = (long)N * N;
     hipLaunchKernelGGL(k_zero4, dim3(flat_blocks(d)), dim3(kTvRed), 0, st, p, q, r, s, d);
+    const dim3 grid((N + kFgpTile - 1) / kFgpTile, (N + kFgpTile - 1) / kFgpTile);
     double t = 1.0;
-    for (int k = 0; k < iters; ++k) {
-        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-        const float w = (float)((t - 1.0) / tn);
-        hipLaunchKernelGGL(k_fgp_step, tv_grid(N), dim3(kTvX, kTvY), 0, st, b, r, s, p, q, r2,
-                           s2, lam, w, N);
+    for (int k = 0; k < iters;) {
+        FgpSteps W;
+        W.n = std::min(kFgpHalo, iters - k);
+        for (int u = 0; u < kFgpHalo; ++u)
+            W.w[u] = 0.f;
+        for (int u = 0; u < W.n; ++u) {
+            const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+            W.w[u] = (float)((t - 1.0) / tn);
+            t = tn;
+        }
+        hipLaunchKernelGGL(k_fgp_steps, grid, dim3(kFgpThreads), 0, st, b, p, q, r, s, p2, q2,
+                           r2, s2, lam, W, N);
+        std::swap(p, p2);
+        std::swap(q, q2);
         std::swap(r, r2);
         std::swap(s, s2);
-        t = tn;
+        k += W.n;
     }
     hipLaunchKernelGGL(k_fgp_final, tv_grid(N), dim3(kTvX, kTvY), 0, st, b, p, q, lam, x, N);
     return hipGetLastError();
