@@ -763,7 +763,7 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
 {
     if (st->done)
         return;
-    __shared__ double red[3][kRedThreads];
+    __shared__ double red[3][kRedThreads / 64];
     double v3[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
         v3[0] += partials[2 * q];
@@ -771,7 +771,7 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
     }
     for (int q = threadIdx.x; q < n_avg; q += kRedThreads)
         v3[2] += avg_parts[q];
-    block_sum<3>(v3, red);
+    plane_sum<3>(v3, red, true);
     if (threadIdx.x == 0) {
         const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
         const int t = st->t + 1;
