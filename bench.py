@@ -49,9 +49,10 @@ HBM_PEAK_GBS = 8000.0
 # per 4 cycles each, packed FP32 not used) x 2.4 GHz, in T lane-instructions/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # VALU instructions of the inner loops, counted in their gfx950 assembly
-# (Kahan steps included): per pixel and view in the gather, per ray and
+# (Kahan steps included): per pixel and view in the gather (clamp-free
+# form, which the benchmark geometry uses), per ray and
 # line in the forward
-VALU_PER_PIXEL_VIEW = 15.0
+VALU_PER_PIXEL_VIEW = 14.0
 VALU_PER_RAY_LINE = 11.0
 
 

@@ -23,7 +23,7 @@ using exact::SpecArg;
 using exact::ViewGeom;
 
 struct exact_geometry_s {
-    int N, V, B, half_turns, reach, nrow;
+    int N, V, B, half_turns, reach, nrow, covers;
     double pixel_cm, bin_cm;
     int device;
     ViewGeom *d_views;
@@ -69,7 +69,7 @@ int guarded(F &&body)
 
 Geo geo_of(const exact_geometry_s *g)
 {
-    return Geo{g->d_views, g->d_blk, g->N, g->V, g->B, g->nrow, g->reach};
+    return Geo{g->d_views, g->d_blk, g->N, g->V, g->B, g->nrow, g->reach, g->covers};
 }
 
 void check_geometry(const exact_geometry_s *g)
@@ -224,6 +224,29 @@ std::vector<int32_t> block_lines(const std::vector<ViewGeom> &views, int N, int 
         }
     }
     return out;
+}
+
+// Whether the bin-pair rule needs no clamp: for every view and every pixel
+// (j, k) of the image, t = -(A_b - j + k Q) / P (padded bin coordinate) lies
+// in [-1/2, B + 2 kPadB - 3/2], so that trunc(t) is a bin of the padded row
+// whose neighbour is too.  t is affine in (j, k), so the image's corners
+// bound it; the half-bin margins dwarf the device's rounding of t.
+int pair_covers(const std::vector<ViewGeom> &views, int N, int B, int reach)
+{
+    if (reach != 0)
+        return 0;
+    const long double lo = -0.5L, hi = (long double)(B + 2 * exact::kPadB) - 1.5L;
+    for (const ViewGeom &G : views) {
+        for (int cj = 0; cj < 2; ++cj)
+            for (int ck = 0; ck < 2; ++ck) {
+                const long double j = cj ? N - 1 : 0, k = ck ? N - 1 : 0;
+                const long double t = -((long double)G.Ab - j + k * (long double)G.Q) /
+                                      (long double)G.P;
+                if (!(t >= lo && t <= hi))
+                    return 0;
+            }
+    }
+    return 1;
 }
 
 // Stream-ordered scratch buffer, released on the same stream.
@@ -392,6 +415,7 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
             g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm,
                                      &g->reach, &g->nrow);
+            g->covers = pair_covers(g->h_views, n_pix, n_bins, g->reach);
             const size_t bytes = sizeof(ViewGeom) * (size_t)n_views;
             hip_check(hipMalloc((void **)&g->d_views, bytes), "hipMalloc");
             hip_check(hipMemcpy(g->d_views, g->h_views.data(), bytes, hipMemcpyHostToDevice),
@@ -573,6 +597,7 @@ struct Problem {
         d.B = g->B;
         d.nrow = g->nrow;
         d.reach = g->reach;
+        d.covers = g->covers;
         d.K = spec.K;
         d.ntiles = exact::num_tiles(g->N);
         d.Y = Y->as<float>();

@@ -93,10 +93,14 @@ struct Geo {
     const int32_t *blk;
     int N, V, B;
     int nrow;        // views[0, nrow) step along rows, views[nrow, V) along columns
-    // Bins examined on each side of the nearest one in the back-projector;
-    // 1 (with the exact two-candidate rule) whenever every |P| >= 1, i.e.
-    // bins at least as wide as pixels.
+    // Bins examined on each side of the nearest one in the back-projector's
+    // general rule; 0 when every |P| >= 1 (bins at least as wide as
+    // pixels), where the bin-pair rule applies.
     int reach;
+    // Nonzero when, for every view and every pixel of the image, the pair
+    // rule's first bin trunc(t) lies in the padded row without clamping
+    // (the detector covers the image's projection with half a bin to spare).
+    int covers;
 };
 
 // Device code sees the descriptor's pointers as global-memory pointers
@@ -120,7 +124,7 @@ struct Geo {
 // One problem of a batch, as the batched kernels see it.
 struct BatchProb {
     const ViewGeom EXACT_GLOBAL *views;
-    int32_t N, V, B, nrow, reach, K, ntiles, pad;
+    int32_t N, V, B, nrow, reach, K, ntiles, covers;
     const float EXACT_GLOBAL *Y;       // window sums of y
     const int32_t EXACT_GLOBAL *blk;   // the geometry's block line table
     const float EXACT_GLOBAL *J;       // spectrum (device copies; mu2 = mu log2(e))

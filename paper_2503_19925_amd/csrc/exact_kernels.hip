@@ -419,13 +419,16 @@ struct PairTap {
 // The pair's weights and residual values (the loads are issued here and
 // waited for where the values are used).  r is the weighted padded
 // sinogram; the view's row offset goes into the per-lane element index, so
-// the base stays the same scalar pointer for every view.
+// the base stays the same scalar pointer for every view.  Without kClamp
+// the caller guarantees 0 <= trunc(t) <= B + 2 kPadB - 2 for every pixel of
+// the image (the geometry's coverage test), so the clamp is the identity.
+template <bool kClamp>
 __device__ __forceinline__ PairTap tap_fetch(const ViewGeom &G, double kd, double jd, int B,
                                              const float *__restrict__ r)
 {
     const double T = fma(kd, G.Q, G.Ab - jd);                  // f(0, k) - j, padded; exact
     const double t = -T * G.invP;
-    const int bf = clamp_int<0>((int)t, B + 2 * kPadB - 2);
+    const int bf = kClamp ? clamp_int<0>((int)t, B + 2 * kPadB - 2) : (int)t;
     const double d = fma((double)bf, G.P, T);                  // exact
     PairTap p;
     p.u0 = __builtin_amdgcn_fmed3f((float)(1.0 - fabs(d)), 0.f, 1.f);
@@ -474,7 +477,7 @@ __device__ __forceinline__ float taps_reach(const ViewGeom &G, double kd, double
 // pair rule the loop is software-pipelined: the next batch's weights are
 // formed and its loads issued before the current batch is summed, so a
 // wave keeps two batches of loads in flight.
-template <bool kTwo>
+template <bool kTwo, bool kClamp>
 __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views, int v0, int v1,
                                              double kd, double jd, int B, int reach,
                                              const float *__restrict__ r, Kahan &acc)
@@ -495,7 +498,7 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
 #pragma unroll
             for (int q = 0; q < kViewBatch; ++q) {
                 const ViewGeom G = gp[q];
-                t[q] = tap_fetch(G, kd, jd, B, r);
+                t[q] = tap_fetch<kClamp>(G, kd, jd, B, r);
             }
         };
         auto apply = [&](const PairTap(&t)[kViewBatch]) {
@@ -530,7 +533,7 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
         }
         for (; v < v1; ++v) {
             const ViewGeom G = views[v];
-            acc.add(tap_apply(tap_fetch(G, kd, jd, B, r), 0.f));
+            acc.add(tap_apply(tap_fetch<kClamp>(G, kd, jd, B, r), 0.f));
         }
         return;
     }
@@ -555,7 +558,7 @@ __device__ __forceinline__ void gather_views(const ViewGeom *__restrict__ views,
 // as 8 waves.  Plane 1 hands its sum to plane 0 through LDS; the result
 // (row part + column part, a fixed order) is meaningful in plane 0.  Every
 // thread of the block calls this (it holds a barrier).
-template <bool kTwo>
+template <bool kTwo, bool kClamp>
 __device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ views, int V,
                                                   int B, int nrow, int reach,
                                                   const float *__restrict__ r, int ix, int iy,
@@ -566,9 +569,9 @@ __device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ v
     if (inside) {
         Kahan acc;
         if (threadIdx.z == 0)
-            gather_views<kTwo>(views, 0, nrow, (double)iy, (double)ix, B, reach, r, acc);
+            gather_views<kTwo, kClamp>(views, 0, nrow, (double)iy, (double)ix, B, reach, r, acc);
         else
-            gather_views<kTwo>(views, nrow, V, (double)ix, (double)iy, B, reach, r, acc);
+            gather_views<kTwo, kClamp>(views, nrow, V, (double)ix, (double)iy, B, reach, r, acc);
         v = acc.value();
     }
     if (threadIdx.z == 1)
@@ -577,7 +580,7 @@ __device__ __forceinline__ float back_pixel_split(const ViewGeom *__restrict__ v
     return threadIdx.z == 0 ? v + part[threadIdx.y][threadIdx.x] : 0.f;
 }
 
-template <bool kTwo>
+template <bool kTwo, bool kClamp>
 __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float *__restrict__ img, float scale,
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     const bool inside = ix < N && iy < N;
-    const float g = back_pixel_split<kTwo>(views, V, B, nrow, reach, r, ix, iy, inside);
+    const float g = back_pixel_split<kTwo, kClamp>(views, V, B, nrow, reach, r, ix, iy, inside);
     if (inside && threadIdx.z == 0)
         img[(size_t)iy * N + ix] = g * scale;
 }
@@ -658,7 +661,7 @@ __device__ __forceinline__ void update_epilogue(bool inside, float g, int N, con
 // Back-projection fused with the update: the block's two z planes gather
 // the pixel's gradient from the padded residual, then plane 0 runs the
 // update epilogue.
-template <bool kTwo, bool kPartials>
+template <bool kTwo, bool kPartials, bool kClamp>
 __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back_update(
     const ViewGeom *__restrict__ views, int N, int V, int B, int nrow, int reach,
     const float *__restrict__ r, float scale, const float *x, float gamma, float *z,
@@ -670,7 +673,8 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back_update(
     const int ix = blockIdx.x * kBackX + threadIdx.x;
     const int iy = blockIdx.y * kBackY + threadIdx.y;
     const bool inside = ix < N && iy < N;
-    const float g = back_pixel_split<kTwo>(views, V, B, nrow, reach, r, ix, iy, inside) * scale;
+    const float g =
+        back_pixel_split<kTwo, kClamp>(views, V, B, nrow, reach, r, ix, iy, inside) * scale;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     update_epilogue<kPartials>(inside, g, N, x, gamma, z, zp, zTp,
                                kPartials ? partials + 2 * blk : nullptr, blockIdx.x, blockIdx.y);
@@ -906,12 +910,15 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void kb_back_update(
     // the gather of either projector variant comes before the epilogue's
     // stores, so its view-table loads stay scalar
     float g;
-    if (P.reach == 0)
-        g = back_pixel_split<true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
-                                   inside);
+    if (P.reach == 0 && P.covers)
+        g = back_pixel_split<true, false>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
+                                          inside);
+    else if (P.reach == 0)
+        g = back_pixel_split<true, true>(glob(P.views), P.V, P.B, P.nrow, 0, glob(P.r), ix, iy,
+                                         inside);
     else
-        g = back_pixel_split<false>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r), ix,
-                                    iy, inside);
+        g = back_pixel_split<false, true>(glob(P.views), P.V, P.B, P.nrow, P.reach, glob(P.r),
+                                          ix, iy, inside);
     g *= P.inv_n;
     const int ntx = (P.N + kBackX - 1) / kBackX;
     double *part2 = kHalf ? glob(P.parts) + 2 * (it.b * ntx + it.a) : nullptr;
@@ -1077,12 +1084,15 @@ hipError_t launch_back(const Geo &g, const float *rw, float *img, float scale,
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
     dim3 blk(kBackX, kBackY, 2);
-    if (g.reach == 0)
-        hipLaunchKernelGGL((k_back<true>), grid, blk, 0, st, g.views, g.N, g.V, g.B, g.nrow, 0,
-                           rw, img, scale, skip);
+    if (g.reach == 0 && g.covers)
+        hipLaunchKernelGGL((k_back<true, false>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                           g.nrow, 0, rw, img, scale, skip);
+    else if (g.reach == 0)
+        hipLaunchKernelGGL((k_back<true, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                           g.nrow, 0, rw, img, scale, skip);
     else
-        hipLaunchKernelGGL((k_back<false>), grid, blk, 0, st, g.views, g.N, g.V, g.B, g.nrow,
-                           g.reach, rw, img, scale, skip);
+        hipLaunchKernelGGL((k_back<false, true>), grid, blk, 0, st, g.views, g.N, g.V, g.B,
+                           g.nrow, g.reach, rw, img, scale, skip);
     return hipGetLastError();
 }
 
@@ -1152,23 +1162,27 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
 {
     dim3 grid((g.N + kBackX - 1) / kBackX, (g.N + kBackY - 1) / kBackY);
     dim3 blk(kBackX, kBackY, 2);
-    if (g.reach == 0) {
+#define EXACT_BU(TWO, PART, CLAMP)                                                              \
+    hipLaunchKernelGGL((k_back_update<TWO, PART, CLAMP>), grid, blk, 0, st, g.views, g.N, g.V, \
+                       g.B, g.nrow, TWO ? 0 : g.reach, r, scale, x, gamma, z, zp, zTp,         \
+                       partials, skip)
+    if (g.reach == 0 && g.covers) {
         if (partials)
-            hipLaunchKernelGGL((k_back_update<true, true>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, 0, r, scale, x, gamma, z, zp, zTp, partials, skip);
+            EXACT_BU(true, true, false);
         else
-            hipLaunchKernelGGL((k_back_update<true, false>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, 0, r, scale, x, gamma, z, zp, zTp, partials, skip);
+            EXACT_BU(true, false, false);
+    } else if (g.reach == 0) {
+        if (partials)
+            EXACT_BU(true, true, true);
+        else
+            EXACT_BU(true, false, true);
     } else {
         if (partials)
-            hipLaunchKernelGGL((k_back_update<false, true>), grid, blk, 0, st, g.views, g.N, g.V,
-                               g.B, g.nrow, g.reach, r, scale, x, gamma, z, zp, zTp, partials,
-                               skip);
+            EXACT_BU(false, true, true);
         else
-            hipLaunchKernelGGL((k_back_update<false, false>), grid, blk, 0, st, g.views, g.N,
-                               g.V, g.B, g.nrow, g.reach, r, scale, x, gamma, z, zp, zTp,
-                               partials, skip);
+            EXACT_BU(false, false, true);
     }
+#undef EXACT_BU
     return hipGetLastError();
 }
 

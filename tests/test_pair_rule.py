@@ -126,3 +126,39 @@ def test_round_to_nearest_in_place_of_truncation_fails():
     bad = sum(forward_weights(N, B, A, P, Q) != rint_rule(A, P, Q)
               for (A, P, Q) in views(N, V, B, 1, 1.0))
     assert bad > 0
+
+
+def covers(N, B, vs):
+    """The geometry's coverage test: t at the image's corners within
+    [-1/2, B + 2 PAD_B - 3/2] for every view."""
+    for (A, P, Q) in vs:
+        Ab = A - PAD_B * P
+        for j in (0, N - 1):
+            for k in (0, N - 1):
+                t = -((Ab - j) + k * Q) / P
+                if not (-0.5 <= t <= B + 2 * PAD_B - 1.5):
+                    return False
+    return True
+
+
+@pytest.mark.parametrize("N,V,B,half_turns,ratio,expect", [
+    (16, 12, 24, 1, 1.0, True),
+    (64, 45, 91, 1, 1.0, True),        # bins_for(64): the test workloads' detector
+    (512, 180, 725, 1, 1.0, True),     # the benchmark geometry
+    (24, 10, 20, 1, 1.0, False),       # detector narrower than the image
+    (31, 7, 11, 1, 2.0, False),
+])
+def test_clamp_free_pairs_stay_in_the_row(N, V, B, half_turns, ratio, expect):
+    """Where the coverage test passes, every pixel's first bin trunc(t) and
+    its neighbour lie in the padded row without clamping, so the gather may
+    skip the clamp."""
+    vs = views(N, V, B, half_turns, ratio)
+    assert covers(N, B, vs) == expect
+    if not expect:
+        return
+    k, j = np.meshgrid(np.arange(N, dtype=np.float64), np.arange(N, dtype=np.float64),
+                       indexing="ij")
+    for (A, P, Q) in vs:
+        T = ((A - PAD_B * P) - j) + k * Q
+        bf = np.trunc(-T * (1.0 / P))
+        assert bf.min() >= 0 and bf.max() + 1 <= B + 2 * PAD_B - 1
