@@ -311,12 +311,15 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     float val = s;
     if (kResid) {
         // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with
-        // exp(-mu t) = 2^(-mu log2(e) t); wave w sums the energies k = w,
+        // exp(-mu t) = 2^(-mu log2(e) t) by the hardware exp2 (whose result
+        // is exp2f's except below 2^-126, where it flushes a term that no
+        // count could register); wave w sums the energies k = w,
         // w + kSegs, ..., and the waves' sums are added in order
         const float sp0 = fmaxf(s, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
         float m = 0.f;
+#pragma unroll 4
         for (int q = seg; q < sp.K; q += kSegs)
-            m = fmaf(sp.J[q], exp2f(-sp.mu2[q] * sp0), m);
+            m = fmaf(sp.J[q], __builtin_amdgcn_exp2f(-sp.mu2[q] * sp0), m);
         part_m[seg][lane] = m;
         __syncthreads();
         float mt = part_m[0][lane];
