@@ -110,9 +110,12 @@ __global__ __launch_bounds__(kFgpThreads) void k_fgp_steps(
                 av = fmaf(xc - X[a + 1][e], inv8l, R[a][e]);
             if (gj + 1 < N && e + 1 < kFgpReg)
                 bv = fmaf(xc - X[a][e + 1], inv8l, S[a][e]);
-            const float nrm = sqrtf(fmaf(av, av, bv * bv));
-            const float den = fmaxf(nrm, 1.f);
-            const float pn = in ? av / den : 0.f, qn = in ? bv / den : 0.f;
+            // projection onto the unit disc: (a, b) / max(|(a, b)|, 1), with
+            // the hardware square root and reciprocal (1 ulp each; the
+            // reciprocal is 1 exactly when the point is inside the disc)
+            const float nrm = __builtin_amdgcn_sqrtf(fmaf(av, av, bv * bv));
+            const float inv = __builtin_amdgcn_rcpf(fmaxf(nrm, 1.f));
+            const float pn = in ? av * inv : 0.f, qn = in ? bv * inv : 0.f;
             // only this cell's r, s are read in this phase: update in place
             R[a][e] = fmaf(w, pn - pc[c], pn);
             S[a][e] = fmaf(w, qn - qc[c], qn);
