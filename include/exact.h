@@ -150,9 +150,11 @@ int exact_forward(exact_geometry g, const float *x_dev, float *s_dev,
 
 /*
  * Back-projection img = A^T r (the sum over rays of r_i a_i in the operator
- * of paper Sec. 1.2, eq. operator, without its 1/n).  Exact transpose of
- * exact_forward: the same weights, computed per pixel (gather), with no
- * atomics, so results are bitwise reproducible.  r_dev [V*B], img_dev [N*N].
+ * of paper Sec. 1.2, eq. operator, without its 1/n).  The transpose of
+ * exact_forward: the same float tent weights, formed per pixel (gather),
+ * with no atomics, so results are bitwise reproducible; the path-length
+ * factor multiplies r once per ray (into a stream-ordered scratch copy of
+ * V*(B+4) floats) before the gather.  r_dev [V*B], img_dev [N*N].
  */
 int exact_backproject(exact_geometry g, const float *r_dev, float *img_dev,
                       void *stream);

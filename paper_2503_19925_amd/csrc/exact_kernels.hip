@@ -389,10 +389,10 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 
 // ------------------------------------------------------------------- back
 
-// Taps of view G for pixel (line k, pixel j of that line) from the weighted
-// padded row rv: acc + the sum over bins b within one pixel of
-// (float)(1 - |f(b, k) - j|) * rv[b], b in padded-bin numbers, the
-// path-length factor being in rv already.
+// Taps of view G for pixel (line k, pixel j of that line): the sum over
+// bins b within one pixel of (float)(1 - |f(b, k) - j|) times the weighted
+// padded residual at bin b (padded-bin numbers; the path-length factor is in
+// the residual already), formed as u0 r0 + u1 r1 by tap_fetch and tap_apply.
 //
 // Pair rule (every |P| >= 1).  Let t be the real solution of f(t, k) = j.
 // Bin b has positive weight iff |b - t| |P| < 1, so only b_f = floor(t)
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_count_nnz(const ViewGeom *__res
 // (the far one to <= 0, the near one to the float of 1 - (error) |P|,
 // which is 1 as the exact one is).
 //
-// The pair is clamped to [0, B + 2 kPadB - 1]: a truncated t below 1
+// The pair (b_f, b_f + 1) is clamped into [0, B + 2 kPadB - 1]: a truncated t below 1
 // (negative t truncates upwards) or above the detector lands on two
 // padding bins, which read zero whatever their weights; a pair holding a
 // detector bin has t >= 1, where truncation is floor.
