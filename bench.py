@@ -21,8 +21,8 @@ report reconstructions/s and time-to-tolerance percentiles:
   bins, 2-4 windows; seed 401), each to natural residual 1e-4 (cap 5000
   steps), once one at a time with exact_solve and once in one batch;
   results are bitwise equal, so the accuracy is equal;
-* served: the first --served requests of a seeded Poisson stream at 20
-  requests/s (N in {256, 512, 1024}, 90/180/360 views, K = 30, Wn = 3,
+* served: the first --served requests (default 300) of a seeded Poisson
+  stream at 20 requests/s (N in {256, 512, 1024}, 90/180/360 views, K = 30, Wn = 3,
   I0 in {1e3, 1e4}, tolerance 1e-3 or 1e-4), admitted by HBM footprint and
   batched continuously; time-to-tolerance runs from arrival to the result on
   the host.
@@ -282,7 +282,7 @@ def main():
                          "(-1 skips the TV leg)")
     ap.add_argument("--background-steps", type=int, default=100,
                     help="timed steps of the workload with known materials (0 to skip)")
-    ap.add_argument("--served", type=int, default=40,
+    ap.add_argument("--served", type=int, default=300,
                     help="requests in the served leg (0 to skip)")
     ap.add_argument("--workload", default="solve_512", choices=sorted(WORKLOADS),
                     help="single-scan workload of the main line")
