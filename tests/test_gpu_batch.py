@@ -30,7 +30,8 @@ def ex():
 
 # uneven shapes: (N, V, B, K, Wn, seed)
 SHAPES = [(64, 40, 92, 10, 2, 11), (48, 33, 69, 23, 3, 12), (96, 25, 137, 40, 4, 13),
-          (32, 60, 46, 64, 2, 14), (80, 17, 114, 12, 3, 15), (56, 71, 80, 31, 4, 16)]
+          (32, 60, 46, 64, 2, 14), (80, 17, 114, 12, 3, 15), (56, 71, 80, 31, 4, 16),
+          (40, 21, 30, 9, 2, 17)]   # the last: detector narrower than the image
 
 
 def problems():

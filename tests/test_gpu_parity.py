@@ -70,6 +70,9 @@ SMALL_SHAPES = [
     ("one_pixel", 1, 3, 3, 1.0, 1),
     ("two_pixels", 2, 5, 4, 1.0, 1),
     ("one_view", 33, 1, 47, 1.0, 1),
+    # detectors narrower than the image: the gather's clamped pair rule
+    ("narrow_detector", 48, 30, 40, 1.0, 1),
+    ("narrow_detector_wide_bins", 31, 7, 11, 2.0, 1),
 ]
 
 
@@ -303,6 +306,13 @@ def test_solve_parity_small_64(ex, ora):
 def test_solve_parity_mid_128(ex, ora):
     rel = _solve_case(ex, ora, "small_64", 200, power=False, n_pix=128, n_views=90, n_bins=182,
                       K=30, Wn=3)
+    assert rel <= 1e-4
+
+
+def test_solve_parity_narrow_detector(ex, ora):
+    """A detector narrower than the image: the update kernels take the
+    clamped pair rule."""
+    rel = _solve_case(ex, ora, "small_64", 60, n_pix=48, n_views=30, n_bins=40)
     assert rel <= 1e-4
 
 
