@@ -204,10 +204,11 @@ class Problem:
 
 
 def make_problem(name, n_pix, n_views, n_bins, K, Wn, I0, n_ell, seed_phantom,
-                 seed_noise, half_turns=1, pixel_cm=None, with_truth=True):
-    """Draw the phantom, its analytic sinogram and Poisson counts."""
+                 seed_noise, half_turns=1, pixel_cm=None, with_truth=True, bin_cm=None):
+    """Draw the phantom, its analytic sinogram and Poisson counts.  Bins are
+    as wide as pixels unless bin_cm says otherwise."""
     pixel_cm = FOV_CM / n_pix if pixel_cm is None else float(pixel_cm)
-    bin_cm = pixel_cm
+    bin_cm = pixel_cm if bin_cm is None else float(bin_cm)
     mu, I = spectrum(K, Wn, I0)
     ell = ellipses(n_ell, seed_phantom)
     li = analytic_sinogram(ell, n_views, n_bins, bin_cm, half_turns)

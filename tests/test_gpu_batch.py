@@ -28,22 +28,28 @@ def ex():
     return exact
 
 
-# uneven shapes: (N, V, B, K, Wn, seed)
-SHAPES = [(64, 40, 92, 10, 2, 11), (48, 33, 69, 23, 3, 12), (96, 25, 137, 40, 4, 13),
-          (32, 60, 46, 64, 2, 14), (80, 17, 114, 12, 3, 15), (56, 71, 80, 31, 4, 16),
-          (40, 21, 30, 9, 2, 17)]   # the last: detector narrower than the image
+# uneven shapes: (N, V, B, K, Wn, seed, bin width in pixels)
+SHAPES = [(64, 40, 92, 10, 2, 11, 1.0), (48, 33, 69, 23, 3, 12, 1.0), (96, 25, 137, 40, 4, 13, 1.0),
+          (32, 60, 46, 64, 2, 14, 1.0), (80, 17, 114, 12, 3, 15, 1.0), (56, 71, 80, 31, 4, 16, 1.0),
+          (40, 21, 30, 9, 2, 17, 1.0),    # detector narrower than the image
+          (40, 19, 81, 8, 2, 18, 0.7)]    # bins narrower than pixels
 
 
 def problems():
     out = []
-    for N, V, B, K, Wn, seed in SHAPES:
-        P = synth.make_problem("batch", N, V, B, K, Wn, 1e4, 6, seed, seed + 100, with_truth=False)
+    for N, V, B, K, Wn, seed, ratio in SHAPES:
+        P = synth.make_problem("batch", N, V, B, K, Wn, 1e4, 6, seed, seed + 100, with_truth=False,
+                               bin_cm=ratio * synth.FOV_CM / N)
         out.append(P)
     return out
 
 
+def geometry(ex, P):
+    return ex.Geometry(P.n_pix, P.n_views, P.n_bins, pixel_cm=P.pixel_cm, bin_cm=P.bin_cm)
+
+
 def solo(ex, P, **opts):
-    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    g = geometry(ex, P)
     x = torch.zeros(g.d, device=DEV)
     info = ex.exact_solve(g, P.mu, P.I, torch.as_tensor(P.y, device=DEV), x, **opts)
     torch.cuda.synchronize()
@@ -55,7 +61,7 @@ def run_batch(ex, Ps, join_late=(), chunk=7, **opts):
     b = ex.Batch(1 << 34, capacity=len(Ps))
     geos, xs, ys, slots = [], [], [], {}
     for i, P in enumerate(Ps):
-        geos.append(ex.Geometry(P.n_pix, P.n_views, P.n_bins))
+        geos.append(geometry(ex, P))
         xs.append(torch.zeros(P.d, device=DEV))
         ys.append(torch.as_tensor(P.y, device=DEV))
     for i, P in enumerate(Ps):
@@ -111,7 +117,7 @@ def test_batch_budget_and_slots(ex):
     P = problems()[0]
     say("batch budget")
     need = ex.exact_run_footprint(P.n_pix, P.n_views, P.n_bins)
-    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    g = geometry(ex, P)
     y = torch.as_tensor(P.y, device=DEV)
     x1, x2 = torch.zeros(g.d, device=DEV), torch.zeros(g.d, device=DEV)
     b = ex.Batch(need + need // 2, capacity=4)
@@ -143,7 +149,7 @@ def test_batch_with_background_equals_solo(ex):
     say("batch with background")
     opts = dict(max_iters=30)
     b = ex.Batch(1 << 34, capacity=3)
-    geos = [ex.Geometry(P.n_pix, P.n_views, P.n_bins) for P in Ps]
+    geos = [geometry(ex, P) for P in Ps]
     xs = [torch.zeros(P.d, device=DEV) for P in Ps]
     bgs = [None if P.bg is None else torch.as_tensor(P.bg.astype(np.float32), device=DEV)
            for P in Ps]

@@ -53,7 +53,7 @@ def gaussian(d, n, seed, norm=3.0):
 
 
 @pytest.mark.parametrize("n,d,K,Wn", [(400, 20, 1, 1), (3000, 300, 7, 2), (2000, 1500, 12, 3),
-                                      (777, 4096, 3, 1), (5, 1, 1, 1)])
+                                      (1200, 900, 5, 2), (777, 4096, 3, 1), (5, 1, 1, 1)])
 def test_dense_operator_parity(ex, ora, n, d, K, Wn):
     say("dense operator", n, d, K, Wn)
     rng = np.random.default_rng(n + d)

@@ -133,6 +133,41 @@ def test_projectors_sampled_full_size(ex, ora, name):
     g.close()
 
 
+@pytest.mark.parametrize("case", [("tiny", 16, 12, 24, 1.0, 1), ("ragged", 21, 7, 31, 1.0, 1),
+                                  ("wide_bins", 12, 9, 14, 1.3, 1),
+                                  ("narrow_bins", 12, 9, 25, 0.7, 1)], ids=lambda c: c[0])
+def test_count_nonzeros(ex, ora, case):
+    """exact_count_nonzeros is the number of positive entries of the device's
+    A, whose columns are the forward projections of unit images (each entry
+    one weight times the view's step, exact); the oracle's A, from
+    unquantized crossings, may differ only in entries that are zero up to
+    rounding on one side."""
+    name, N, V, B, ratio, turns = case
+    say("count nonzeros", name, N, V, B, ratio)
+    g, go = geoms(ex, ora, N, V, B, ratio, turns)
+    cnt = ex.exact_count_nonzeros(g)
+    e = torch.zeros(g.d, device=DEV)
+    s = torch.empty(g.n, device=DEV)
+    A = np.empty((g.n, g.d))
+    A_ora = np.empty((g.n, g.d))
+    for p in range(g.d):
+        e.zero_()
+        e[p] = 1.0
+        ex.exact_forward(g, e, s)
+        A[:, p] = np64(s)
+        u = np.zeros(g.d)
+        u[p] = 1.0
+        A_ora[:, p] = ora.forward(go, u)
+    assert cnt == int((A > 0).sum())
+    n_ora = int((A_ora > 0).sum())
+    tiny = int(((A > 0) & (A < 1e-6 * A.max())).sum() +
+               ((A_ora > 0) & (A_ora < 1e-9 * A_ora.max())).sum())
+    print("  nnz device %d, oracle %d (its counter %d), rounding-level entries %d"
+          % (cnt, n_ora, ora.nnz(go), tiny), flush=True)
+    assert abs(cnt - n_ora) <= tiny
+    g.close()
+
+
 def test_adjoint_identity_on_gpu(ex):
     """<A x, y> = <x, A^T y> with the GPU's own projector pair: the weights are
     identical, so only float32 summation order separates the two."""
@@ -172,8 +207,8 @@ def test_determinism(ex):
 
 def _problem(ex, ora, name, **over):
     P = synth.config_problem(name, **over)
-    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
-    go = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins, pixel_cm=P.pixel_cm, bin_cm=P.bin_cm)
+    go = ora.Geom(P.n_pix, P.n_views, P.n_bins, pixel_cm=P.pixel_cm, bin_cm=P.bin_cm)
     return P, g, go
 
 
@@ -313,6 +348,14 @@ def test_solve_parity_narrow_detector(ex, ora):
     """A detector narrower than the image: the update kernels take the
     clamped pair rule."""
     rel = _solve_case(ex, ora, "small_64", 60, n_pix=48, n_views=30, n_bins=40)
+    assert rel <= 1e-4
+
+
+def test_solve_parity_narrow_bins(ex, ora):
+    """Bins 0.7 pixels wide: the update kernels take the general rule (every
+    bin within reach of the nearest)."""
+    rel = _solve_case(ex, ora, "small_64", 60, n_pix=40, n_views=36, n_bins=81,
+                      bin_cm=0.7 * 10.0 / 40)
     assert rel <= 1e-4
 
 
