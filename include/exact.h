@@ -131,8 +131,10 @@ void exact_solve_opts_default(exact_solve_opts *opts);
 /*
  * Builds the per-view tables of the geometry above and uploads them to the
  * current HIP device.  n_pix, n_views, n_bins >= 1; n_pix <= 16384 and
- * n_views * n_bins < 2^31; half_turns 1 (180 degrees) or 2 (360 degrees);
- * pixel_cm, bin_cm > 0 and finite.  *out receives the handle.
+ * n_views * (n_bins + 4) < 2^30 (the padded residual sinogram, n_views rows
+ * of n_bins + 4 floats, is addressed with 32-bit byte offsets); half_turns
+ * 1 (180 degrees) or 2 (360 degrees); pixel_cm, bin_cm > 0 and finite.
+ * *out receives the handle.
  */
 int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins,
                           int32_t half_turns, double pixel_cm, double bin_cm,

@@ -396,8 +396,11 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         *out = nullptr;
         if (n_pix < 1 || n_pix > 16384)
             fail(-EINVAL, "n_pix must be in [1, 16384]");
-        if (n_views < 1 || n_bins < 1 || (long long)n_views * n_bins >= (1LL << 31))
-            fail(-EINVAL, "n_views, n_bins must be >= 1 with n_views*n_bins < 2^31");
+        // every element of the padded residual (n_views rows of n_bins + 4)
+        // must have a 32-bit byte offset: the gather forms them that way
+        if (n_views < 1 || n_bins < 1 ||
+            (long long)n_views * ((long long)n_bins + 2 * exact::kPadB) >= (1LL << 30))
+            fail(-EINVAL, "n_views, n_bins must be >= 1 with n_views*(n_bins+4) < 2^30");
         if (half_turns != 1 && half_turns != 2)
             fail(-EINVAL, "half_turns must be 1 (180 degrees) or 2 (360 degrees)");
         if (!(std::isfinite(pixel_cm) && pixel_cm > 0.0 && std::isfinite(bin_cm) && bin_cm > 0.0))
@@ -443,12 +446,12 @@ int exact_geometry_destroy(exact_geometry g)
     return guarded([&]() -> int {
         if (!g)
             return 0;
+        // the handle and both tables are released whatever a free reports
+        std::unique_ptr<exact_geometry_s> own(g);
         (void)hipDeviceSynchronize();
-        if (g->d_views)
-            hip_check(hipFree(g->d_views), "hipFree");
-        if (g->d_blk)
-            hip_check(hipFree(g->d_blk), "hipFree");
-        delete g;
+        const hipError_t e1 = g->d_views ? hipFree(g->d_views) : hipSuccess;
+        const hipError_t e2 = g->d_blk ? hipFree(g->d_blk) : hipSuccess;
+        hip_check(e1 != hipSuccess ? e1 : e2, "hipFree");
         return 0;
     });
 }

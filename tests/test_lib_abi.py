@@ -57,6 +57,7 @@ def test_opts_defaults(lib):
     (16, 10, 10, 1, 0.1, float("nan")),
     (20000, 10, 10, 1, 0.1, 0.1),      # image too large
     (16, 65536, 65536, 1, 0.1, 0.1),   # too many rays
+    (16, 32768, 32765, 1, 0.1, 0.1),   # padded sinogram past 32-bit byte offsets
 ])
 def test_geometry_create_rejects(lib, args):
     h = C.c_void_p()
