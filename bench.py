@@ -95,15 +95,13 @@ def cpu_baseline(P, gamma, steps):
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic.json: rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
-    plain copy's reading), or None when the kernel source has changed since
-    the counters were taken."""
-    import hashlib
+    plain copy's reading), or None when the kernel source or its tile knobs
+    have changed since the counters were taken."""
+    from paper_2503_19925_amd import build as libbuild
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2503_19925_amd", "csrc", "exact_kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
-        if rec.get("kernel_source_sha1") != sha:
+        if rec.get("kernel_build_id") != libbuild.build_id():
             return None
         return rec["workloads"][workload][kernel]["hbm_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
