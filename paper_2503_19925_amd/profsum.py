@@ -9,6 +9,9 @@
         --kernel-trace --stats runs and benchmark logs of one GPU call
         (<out dir>/prof/bench, bench.log, prof_large, large.err) ->
         profiles/kernels_solve_512.md and profiles/kernels_large_1024.md.
+    python -m paper_2503_19925_amd.profsum utilisation <pmc dir>
+        two counter passes (A: SQ/GRBM, B: TA/TD/TCP/TCC) per workload under
+        <pmc dir>/<workload>_<pass> -> profiles/counters_utilisation.md.
     python -m paper_2503_19925_amd.profsum tests <kernel_stats.csv> <pytest log>
         a kernel trace of the GPU test suite -> profiles/kernels_gpu_tests.md,
         checked against every kernel compiled into libexact.so.
@@ -220,6 +223,87 @@ def cmd_kernels(out_dir):
     print("wrote kernels_solve_512.md and kernels_large_1024.md")
 
 
+# ------------------------------------------------------------- utilisation
+
+UTIL_PASSES = {
+    "A": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU "
+         "SQ_WAIT_INST_ANY SQ_INST_LEVEL_VMEM SQ_INSTS_VMEM_RD GRBM_GUI_ACTIVE GRBM_COUNT",
+    "B": "TA_TA_BUSY_sum TA_ADDR_STALLED_BY_TC_CYCLES_sum TD_TD_BUSY_sum TD_TC_STALL_sum "
+         "TCP_TCP_TA_DATA_STALL_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum "
+         "TCP_TCC_READ_REQ_LATENCY_sum TCC_HIT_sum TCC_MISS_sum GRBM_GUI_ACTIVE"}
+UTIL_BENCH = ("python3 bench.py --workload <workload> --steps 5 --warmup 2 --proj-reps 2 "
+              "--profile-steps 2 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
+              "--dense-steps 0 --background-steps 0")
+CUS, SIMDS, CLOCK_GHZ = 256, 1024, 2.4
+UTIL_KERNELS = ("k_forward<true>", "k_back_update<true, true, false>",
+                "k_back_update<true, false, false>")
+
+
+def cmd_utilisation(pmc_dir):
+    md = ["# Unit utilisation of the step's kernels (hardware counters)", "",
+          "Two rocprofv3 counter passes per workload on a short benchmark run (from",
+          "the repository root, TMPDIR=/tmp; `<workload>` = `solve_512`, then",
+          "`large_1024`; `<pass>` = A, then B):", "", "```",
+          "timeout -s KILL 120 rocprofv3 --pmc <counters of the pass> --output-format csv "
+          "-d gpurun_out/pmc3/<workload>_<pass> -o run -- " + UTIL_BENCH, "```", "",
+          "Pass A: `%s`." % UTIL_PASSES["A"], "", "Pass B: `%s`." % UTIL_PASSES["B"], "",
+          "Summarised by `python -m paper_2503_19925_amd.profsum utilisation gpurun_out/pmc3`.",
+          "", "Figures per dispatch (mean over the run's dispatches of the kernel), against",
+          "MI355X's 256 CUs (1024 SIMDs) at the published 2.4 GHz peak engine clock; the",
+          "duration is the dispatch's own (the counter run's timestamps), so a clock",
+          "below 2.4 GHz makes every fraction below a lower bound:", "",
+          "* VALU issue: SQ_INSTS_VALU x 4 cycles (a wave64 instruction on a 16-lane",
+          "  SIMD) / (1024 SIMDs x duration x 2.4 GHz);",
+          "* waves resident per SIMD: SQ_WAVE_CYCLES x 4 (quad-cycles) / (1024 x cycles);",
+          "* TA / TD busy: TA_TA_BUSY_sum, TD_TD_BUSY_sum / (256 CUs x cycles);",
+          "* L2 hit rate: TCC_HIT / (TCC_HIT + TCC_MISS); L2 read latency:",
+          "  TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum (cycles);",
+          "* HBM: the kernel's bytes per launch from the FETCH_SIZE / WRITE_SIZE passes",
+          "  (profiles/traffic.json, solve_512 only) over the dispatch's duration.", ""]
+    traffic = {}
+    try:
+        traffic = json.load(open(os.path.join(PROFILES, "traffic.json")))["workloads"]
+    except (OSError, ValueError, KeyError):
+        pass
+    for wl in ("solve_512", "large_1024"):
+        vals = collections.defaultdict(lambda: collections.defaultdict(list))
+        dur = collections.defaultdict(list)
+        for p in ("A", "B"):
+            path = os.path.join(pmc_dir, "%s_%s" % (wl, p), "run_counter_collection.csv")
+            for r in csv.DictReader(open(path)):
+                n = short(r["Kernel_Name"])
+                vals[n][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                if p == "A" and r["Counter_Name"] == "SQ_INSTS_VALU":
+                    dur[n].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+        md += ["## %s" % wl, "",
+               "| kernel | dispatches | duration (us) | VALU issue | waves / SIMD | TA busy "
+               "| TD busy | L2 hit | L2 read latency (cycles) | HBM (GB/s, of 8000) |",
+               "|---|---|---|---|---|---|---|---|---|---|"]
+        for k in UTIL_KERNELS:
+            v = {c: sum(x) / len(x) for c, x in vals[k].items()}
+            d = sum(dur[k]) / len(dur[k])
+            cyc = d * CLOCK_GHZ * 1e9
+            hbm = traffic.get(wl, {}).get(k, {}).get("hbm_bytes_per_launch")
+            md.append("| %s | %d | %.1f | %.0f %% | %.1f | %.0f %% | %.0f %% | %.1f %% | %.0f | %s |" % (
+                k, len(dur[k]), d * 1e6, 100 * v["SQ_INSTS_VALU"] * 4 / SIMDS / cyc,
+                v["SQ_WAVE_CYCLES"] * 4 / SIMDS / cyc, 100 * v["TA_TA_BUSY_sum"] / CUS / cyc,
+                100 * v["TD_TD_BUSY_sum"] / CUS / cyc,
+                100 * v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"]),
+                v["TCP_TCC_READ_REQ_LATENCY_sum"] / v["TCP_TCC_READ_REQ_sum"],
+                "%.0f" % (hbm / d / 1e9) if hbm else "-"))
+        md.append("")
+    md += ["Reading.  At 1024² the back-projection + update kernels issue VALU",
+           "instructions at about 95 % of the peak rate, so they are bound by",
+           "instruction issue; at 512² the same loop reaches about 60 %, the rest going",
+           "to the start and end of a grid that runs as a single round of waves.  The",
+           "forward keeps its address and data-return units (TA, TD) the busiest, the",
+           "vector-memory path that bounds it.  L2 hit rates of 80-94 % and HBM rates",
+           "far below 8 TB/s show the operands served from the XCDs' L2."]
+    with open(os.path.join(PROFILES, "counters_utilisation.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote counters_utilisation.md")
+
+
 # ------------------------------------------------------------- test coverage
 
 def compiled_kernels():
@@ -274,6 +358,8 @@ if __name__ == "__main__":
         cmd_counters(a[1], a[2])
     elif a[:1] == ["kernels"] and len(a) == 2:
         cmd_kernels(a[1])
+    elif a[:1] == ["utilisation"] and len(a) == 2:
+        cmd_utilisation(a[1])
     elif a[:1] == ["tests"] and len(a) == 3:
         cmd_tests(a[1], a[2])
     else:
