@@ -241,7 +241,42 @@ def dense_leg(d, mult, steps, torch, exact):
             "rel_error_after": err}
 
 
-def served_leg(count, torch, exact, synth):
+def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
+    """The same requests served one at a time in arrival order (first come,
+    first served) on the same GPU: each is solved alone by exact_solve with
+    its own step size, tolerance and cap (so the reconstructions equal the
+    served ones bit for bit), its service time measured on the wall clock
+    (counts upload + solve; geometry and lambda_max cached per shape as the
+    server does), and the queue formed from the stream's arrival times."""
+    import numpy as np
+    from paper_2503_19925_amd.serve import theorem2_gamma
+    geoms, finish, lats, svc = {}, 0.0, [], []
+    for r in sorted(reqs, key=lambda r: (r.arrival, r.rid)):
+        P = r.problem
+        key = (P.n_pix, P.n_views, P.n_bins, P.pixel_cm, P.bin_cm, P.half_turns)
+        if key not in geoms:
+            g = exact.Geometry(P.n_pix, P.n_views, P.n_bins, P.pixel_cm, P.bin_cm, P.half_turns)
+            geoms[key] = (g, exact.exact_step_size(g, None, None, power_iters)[0])
+        g, lam = geoms[key]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = torch.as_tensor(np.ascontiguousarray(P.y, dtype=np.float32), device="cuda")
+        x = torch.zeros(P.d, device="cuda")
+        exact.exact_solve(g, P.mu, P.I, y, x, gamma=theorem2_gamma(P, lam),
+                          max_iters=r.max_iters, tol=r.tol)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+        finish = max(r.arrival, finish) + svc[-1]
+        lats.append(finish - r.arrival)
+    for g, _ in geoms.values():
+        g.close()
+    span = finish - min(r.arrival for r in reqs)
+    return {"p50_s": pct(lats, 50), "p99_s": pct(lats, 99),
+            "recon_per_s": len(reqs) / span, "service_s_total": float(sum(svc)),
+            "note": "queue simulated from the measured solo solve times and the arrivals"}
+
+
+def served_leg(count, torch, exact, synth, serial=True):
     from paper_2503_19925_amd.serve import GpuBackend, Request, Server, summarize
     stream = synth.served_stream(300, 20.0, 501)[:count]
     reqs = [Request(q, s["arrival"], synth.make_problem("req%d" % q, with_truth=False,
@@ -259,6 +294,11 @@ def served_leg(count, torch, exact, synth):
     s = summarize(res)
     s["offered_req_per_s"] = (count - 1) / (reqs[-1].arrival - reqs[0].arrival)
     s["peak_running"] = srv.peak_running
+    if serial:
+        f = fcfs_one_at_a_time(reqs, torch, exact)
+        log("served one at a time (FCFS): p50 %.2f s, p99 %.2f s, %.2f recon/s"
+            % (f["p50_s"], f["p99_s"], f["recon_per_s"]))
+        s["fcfs_one_at_a_time"] = f
     return s
 
 
@@ -282,6 +322,8 @@ def main():
                     help="timed steps of the workload with known materials (0 to skip)")
     ap.add_argument("--served", type=int, default=300,
                     help="requests in the served leg (0 to skip)")
+    ap.add_argument("--served-serial", type=int, default=1,
+                    help="also serve the stream one request at a time (0 to skip)")
     ap.add_argument("--workload", default="solve_512", choices=sorted(WORKLOADS),
                     help="single-scan workload of the main line")
     ap.add_argument("--to-tol", type=float, default=0.0,
@@ -423,7 +465,8 @@ def main():
     dense = dense_leg(4096, 20, args.dense_steps, torch, exact) if args.dense_steps > 0 else None
 
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
-    served = served_leg(args.served, torch, exact, synth) if args.served > 0 else None
+    served = (served_leg(args.served, torch, exact, synth, serial=args.served_serial > 0)
+              if args.served > 0 else None)
     if served:
         log("served: p50 %.2f s, p99 %.2f s, %.2f recon/s" % (served["p50_s"], served["p99_s"],
                                                              served["recon_per_s"]))

@@ -53,6 +53,13 @@ class Result:
         return self.admitted - self.arrival
 
 
+def theorem2_gamma(P, lam, c_gamma=0.25):
+    """Step size c / (lambda_max(A^T A / n) sum_k J_k mu_k) of a problem
+    (Theorem 2, paper Sec. 2.1), J_k the window-summed intensities."""
+    J = np.asarray(P.I, dtype=np.float64).reshape(-1, len(P.mu)).sum(axis=0)
+    return c_gamma / (lam * float(np.dot(J, P.mu)))
+
+
 class GpuBackend:
     """exact_batch on the current HIP device; owns the scans' x and y."""
 
@@ -78,8 +85,7 @@ class GpuBackend:
                 + 4 * P.d + 4 * P.Wn * P.n)
 
     def gamma(self, P, lam):
-        J = np.asarray(P.I, dtype=np.float64).reshape(-1, len(P.mu)).sum(axis=0)
-        return 0.25 / (lam * float(np.dot(J, P.mu)))
+        return theorem2_gamma(P, lam)
 
     def add(self, req):
         P = req.problem
