@@ -27,7 +27,7 @@ struct exact_geometry_s {
     double pixel_cm, bin_cm;
     int device;
     ViewGeom *d_views;
-    int32_t *d_blk;
+    int32_t *d_blk, *d_order;
     std::vector<ViewGeom> h_views;
 };
 
@@ -69,7 +69,7 @@ int guarded(F &&body)
 
 Geo geo_of(const exact_geometry_s *g)
 {
-    return Geo{g->d_views, g->d_blk, g->N, g->V, g->B, g->nrow, g->reach, g->covers};
+    return Geo{g->d_views, g->d_blk, g->d_order, g->N, g->V, g->B, g->nrow, g->reach, g->covers};
 }
 
 void check_geometry(const exact_geometry_s *g)
@@ -224,6 +224,46 @@ std::vector<int32_t> block_lines(const std::vector<ViewGeom> &views, int N, int 
         }
     }
     return out;
+}
+
+// Dispatch order of the forward projector's workgroups (one per block of
+// 64 rays, item i = slot nbb + block, its weight the lines it walks from
+// the block table).  The hardware hands workgroups to the XCDs in turn and
+// fills each CU with `per_cu` of them at once, so workgroups i and
+// i + cus * k share a CU in the first round.  Longest blocks first; the
+// first cus * per_cu go to the CUs' slots greedily (each to the CU with the
+// fewest lines so far among those with a free slot), so that every CU's
+// first round holds about the same number of lines; the rest follow,
+// longest first, into slots as they free.  The order changes which
+// workgroup projects which rays, never the arithmetic.
+std::vector<int32_t> dispatch_order(const std::vector<int32_t> &blk, int cus, int per_cu)
+{
+    const int n = (int)(blk.size() / 2);
+    std::vector<int32_t> idx((size_t)n), order((size_t)n);
+    std::vector<long> w((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        idx[(size_t)i] = i;
+        w[(size_t)i] = std::max(0, blk[2 * (size_t)i + 1] - blk[2 * (size_t)i] + 1);
+    }
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
+    const long first = (long)cus * per_cu;
+    if (cus < 1 || per_cu < 1 || n < first)
+        return idx;
+    std::vector<long> load((size_t)cus, 0);
+    std::vector<int> used((size_t)cus, 0);
+    for (long r = 0; r < first; ++r) {
+        int best = -1;
+        for (int c = 0; c < cus; ++c)
+            if (used[(size_t)c] < per_cu && (best < 0 || load[(size_t)c] < load[(size_t)best]))
+                best = c;
+        order[(size_t)best + (size_t)cus * used[(size_t)best]] = idx[(size_t)r];
+        load[(size_t)best] += w[(size_t)idx[(size_t)r]];
+        ++used[(size_t)best];
+    }
+    for (long r = first; r < n; ++r)
+        order[(size_t)r] = idx[(size_t)r];
+    return order;
 }
 
 // Whether the bin-pair rule needs no clamp: for every view and every pixel
@@ -414,6 +454,7 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         g->bin_cm = bin_cm;
         g->d_views = nullptr;
         g->d_blk = nullptr;
+        g->d_order = nullptr;
         try {
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
             g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm,
@@ -428,11 +469,22 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
             hip_check(hipMemcpy(g->d_blk, blk.data(), blk.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
                       "hipMemcpy");
+            int cus = 0;
+            hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device),
+                      "hipDeviceGetAttribute");
+            const std::vector<int32_t> order =
+                dispatch_order(blk, cus, exact::fwd_resident_blocks_per_cu());
+            hip_check(hipMalloc((void **)&g->d_order, order.size() * sizeof(int32_t)), "hipMalloc");
+            hip_check(hipMemcpy(g->d_order, order.data(), order.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice),
+                      "hipMemcpy");
         } catch (...) {
             if (g->d_views)
                 (void)hipFree(g->d_views);
             if (g->d_blk)
                 (void)hipFree(g->d_blk);
+            if (g->d_order)
+                (void)hipFree(g->d_order);
             delete g;
             throw;
         }
@@ -446,12 +498,13 @@ int exact_geometry_destroy(exact_geometry g)
     return guarded([&]() -> int {
         if (!g)
             return 0;
-        // the handle and both tables are released whatever a free reports
+        // the handle and its tables are released whatever a free reports
         std::unique_ptr<exact_geometry_s> own(g);
         (void)hipDeviceSynchronize();
         const hipError_t e1 = g->d_views ? hipFree(g->d_views) : hipSuccess;
         const hipError_t e2 = g->d_blk ? hipFree(g->d_blk) : hipSuccess;
-        hip_check(e1 != hipSuccess ? e1 : e2, "hipFree");
+        const hipError_t e3 = g->d_order ? hipFree(g->d_order) : hipSuccess;
+        hip_check(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "hipFree");
         return 0;
     });
 }

@@ -91,6 +91,10 @@ struct Geo {
     // the block's rays reaches (first > last if none), conservative by one
     // line; 2 ints each, slot-major.
     const int32_t *blk;
+    // Dispatch order of the forward projector's workgroups: workgroup i
+    // projects the rays of block order[i] = slot * nbb + block (a
+    // permutation of the V * nbb blocks, nbb = ceil(B / 64)).
+    const int32_t *order;
     int N, V, B;
     int nrow;        // views[0, nrow) step along rows, views[nrow, V) along columns
     // Bins examined on each side of the nearest one in the back-projector's
@@ -162,6 +166,9 @@ hipError_t launch_count_nonzeros(const Geo &g, long long *parts, hipStream_t st)
 hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem *fwd, int nfwd,
                              const BatchItem *back, int nback, hipStream_t st);
 int fwd_items_per_view(int B);
+// Forward-projector workgroups one CU holds at once (from the kernel's
+// occupancy on the current device).
+int fwd_resident_blocks_per_cu();
 int fwd_block_centre_out(int r, int nbb);
 int back_tiles_per_side(int N);
 

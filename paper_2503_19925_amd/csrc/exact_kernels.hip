@@ -335,12 +335,12 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         plain[i] = val;
 }
 
-// Workgroup i takes view i % V and the (i / V)-th bin block centre-out, so
-// the heaviest blocks of every view are dispatched first.
+// Workgroup i projects ray block order[i] (the geometry's dispatch order:
+// longest blocks first, with the ones a CU holds at once balanced in lines).
 template <bool kResid>
 __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
-    const ViewGeom *__restrict__ views, const int32_t *__restrict__ blk, int N, int V, int B,
-    int nrow,
+    const ViewGeom *__restrict__ views, const int32_t *__restrict__ blk,
+    const int32_t *__restrict__ order, int N, int V, int B, int nrow,
     const float *__restrict__ xp, const float *__restrict__ xTp, const float *__restrict__ Y,
     SpecArg sp, float *__restrict__ out, int ostride, int ooff, int weighted,
     float *__restrict__ plain, const int32_t *__restrict__ skip)
@@ -348,8 +348,9 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     if (skipped(skip))
         return;
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
+    const int it = order[blockIdx.x];
     forward_block<kResid>(views, blk, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff,
-                          weighted != 0, plain, blockIdx.x % V, centre_out(blockIdx.x / V, nbb));
+                          weighted != 0, plain, it / nbb, it % nbb);
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -1059,7 +1060,7 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
     none.bg = nullptr;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
-                       g.N, g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
+                       g.order, g.N, g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
                        weighted ? 1 : 0, nullptr, skip);
     return hipGetLastError();
 }
@@ -1070,7 +1071,8 @@ hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *x
 {
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
-                       g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1, r_plain,
+                       g.order, g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1,
+                       r_plain,
                        skip);
     return hipGetLastError();
 }
@@ -1212,6 +1214,15 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
 }
 
 int fwd_items_per_view(int B) { return (B + kFwdThreads - 1) / kFwdThreads; }
+int fwd_resident_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward<true>, kFwdThreads * kSegs, 0) !=
+            hipSuccess ||
+        n < 1)
+        return 1;
+    return n;
+}
 int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }
 
