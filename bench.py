@@ -249,9 +249,10 @@ def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
     (counts upload + solve; geometry and lambda_max cached per shape as the
     server does), and the queue formed from the stream's arrival times."""
     import numpy as np
-    from paper_2503_19925_amd.serve import theorem2_gamma
-    geoms, finish, lats, svc = {}, 0.0, [], []
-    for r in sorted(reqs, key=lambda r: (r.arrival, r.rid)):
+    from paper_2503_19925_amd.serve import fcfs_latencies, theorem2_gamma
+    order = sorted(reqs, key=lambda r: (r.arrival, r.rid))
+    geoms, svc = {}, []
+    for r in order:
         P = r.problem
         key = (P.n_pix, P.n_views, P.n_bins, P.pixel_cm, P.bin_cm, P.half_turns)
         if key not in geoms:
@@ -266,11 +267,10 @@ def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
                           max_iters=r.max_iters, tol=r.tol)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t0)
-        finish = max(r.arrival, finish) + svc[-1]
-        lats.append(finish - r.arrival)
     for g, _ in geoms.values():
         g.close()
-    span = finish - min(r.arrival for r in reqs)
+    lats, finish = fcfs_latencies([r.arrival for r in order], svc)
+    span = finish - order[0].arrival
     return {"p50_s": pct(lats, 50), "p99_s": pct(lats, 99),
             "recon_per_s": len(reqs) / span, "service_s_total": float(sum(svc)),
             "note": "queue simulated from the measured solo solve times and the arrivals"}

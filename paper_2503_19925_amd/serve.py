@@ -184,6 +184,18 @@ class Server:
         return sorted(results, key=lambda z: z.rid)
 
 
+def fcfs_latencies(arrivals, service):
+    """Arrival-to-finish times of requests served one at a time in arrival
+    order by a single server: request i starts when it has arrived and
+    request i - 1 has finished, and takes service[i].  Returns (latencies,
+    finish time of the last)."""
+    finish, lat = float("-inf"), []
+    for a, s in sorted(zip(arrivals, service), key=lambda z: z[0]):
+        finish = max(a, finish) + s
+        lat.append(finish - a)
+    return lat, finish
+
+
 def summarize(results, duration=None):
     """p50/p99 time-to-tolerance (arrival to result on the host), the
     queueing share, and reconstructions per second over the stream."""
