@@ -34,10 +34,13 @@
  *  and released before the call's work completes on the stream).  Host
  *  spectrum arrays are copied during the call.
  *
- *  Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every call
- *  except exact_solve and exact_step_size is stream-ordered and returns
- *  before the GPU work finishes.  A geometry handle may be used from several
- *  streams at once.
+ *  Streams.  `stream` is a hipStream_t (NULL = the null stream).  The
+ *  projector, operator and stepping calls (exact_forward, exact_backproject,
+ *  exact_operator, exact_solver_step, exact_batch_step) are
+ *  stream-ordered and return before the GPU work
+ *  finishes; every other call that takes a stream orders its work after
+ *  the stream's and blocks until done (its comment says so).  A geometry
+ *  handle may be used from several streams at once.
  *
  *  Errors.  0 on success; a negative errno value on failure (-EINVAL bad
  *  argument, -ENOMEM out of memory, -ENOSPC a batch's budget or slots
@@ -277,7 +280,7 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
  * with y [Wn][n] and the spectrum as in exact_spectrum (background must be
  * NULL).  1 <= d <= 4096.  Each evaluation of F reads A once.
  *
- * exact_dense_operator writes F(x) to F_dev [d].
+ * exact_dense_operator writes F(x) to F_dev [d] (blocking).
  * exact_dense_solve runs eq. extragrad-method over X = {||x||_2 <= radius}
  * (the bounded set of Assumption assump-X, centred at the origin; radius
  * <= 0 means the whole space), x_dev [d] in/out, x_1 finite.  opts as for
