@@ -226,25 +226,29 @@ std::vector<int32_t> block_lines(const std::vector<ViewGeom> &views, int N, int 
     return out;
 }
 
-// Dispatch order of the forward projector's workgroups (one per block of
-// 64 rays, item i = slot nbb + block, its weight the lines it walks from
-// the block table).  The hardware hands workgroups to the XCDs in turn and
-// fills each CU with `per_cu` of them at once, so workgroups i and
-// i + cus * k share a CU in the first round.  Longest blocks first; the
-// first cus * per_cu go to the CUs' slots greedily (each to the CU with the
-// fewest lines so far among those with a free slot), so that every CU's
-// first round holds about the same number of lines; the rest follow,
-// longest first, into slots as they free.  The order changes which
-// workgroup projects which rays, never the arithmetic.
-std::vector<int32_t> dispatch_order(const std::vector<int32_t> &blk, int cus, int per_cu)
+// Lines a forward workgroup walks for block i (slot nbb + block) of a
+// geometry's block table.
+long block_weight(const std::vector<int32_t> &blk, size_t i)
 {
-    const int n = (int)(blk.size() / 2);
+    return std::max(0, blk[2 * i + 1] - blk[2 * i] + 1);
+}
+
+// Dispatch order of the forward projector's workgroups, one per item of
+// weight w[i] (the lines it walks).  The hardware hands workgroups to the
+// XCDs in turn and fills each CU with `per_cu` of them at once, so
+// workgroups i and i + cus * k share a CU in the first round.  Longest
+// items first; the first cus * per_cu go to the CUs' slots greedily (each
+// to the CU with the fewest lines so far among those with a free slot), so
+// that every CU's first round holds about the same number of lines; the
+// rest follow, longest first, into slots as they free.  Returns the item of
+// each workgroup.  The order changes which workgroup projects which rays,
+// never the arithmetic.
+std::vector<int32_t> balanced_order(const std::vector<long> &w, int cus, int per_cu)
+{
+    const int n = (int)w.size();
     std::vector<int32_t> idx((size_t)n), order((size_t)n);
-    std::vector<long> w((size_t)n);
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         idx[(size_t)i] = i;
-        w[(size_t)i] = std::max(0, blk[2 * (size_t)i + 1] - blk[2 * (size_t)i] + 1);
-    }
     std::stable_sort(idx.begin(), idx.end(),
                      [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
     const long first = (long)cus * per_cu;
@@ -264,6 +268,14 @@ std::vector<int32_t> dispatch_order(const std::vector<int32_t> &blk, int cus, in
     for (long r = first; r < n; ++r)
         order[(size_t)r] = idx[(size_t)r];
     return order;
+}
+
+// CUs of the current device and forward workgroups each holds at once.
+void forward_residency(int device, int *cus, int *per_cu)
+{
+    hip_check(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, device),
+              "hipDeviceGetAttribute");
+    *per_cu = exact::fwd_resident_blocks_per_cu();
 }
 
 // Whether the bin-pair rule needs no clamp: for every view and every pixel
@@ -469,11 +481,12 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
             hip_check(hipMemcpy(g->d_blk, blk.data(), blk.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
                       "hipMemcpy");
-            int cus = 0;
-            hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device),
-                      "hipDeviceGetAttribute");
-            const std::vector<int32_t> order =
-                dispatch_order(blk, cus, exact::fwd_resident_blocks_per_cu());
+            int cus = 0, per_cu = 0;
+            forward_residency(g->device, &cus, &per_cu);
+            std::vector<long> w(blk.size() / 2);
+            for (size_t i = 0; i < w.size(); ++i)
+                w[i] = block_weight(blk, i);
+            const std::vector<int32_t> order = balanced_order(w, cus, per_cu);
             hip_check(hipMalloc((void **)&g->d_order, order.size() * sizeof(int32_t)), "hipMalloc");
             hip_check(hipMemcpy(g->d_order, order.data(), order.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
@@ -977,7 +990,9 @@ namespace {
 // Item lists of the runs still running (as of the last sync), heaviest
 // first so the long tiles start early: runs by decreasing N, and each run's
 // forward items centre-out (central bin blocks hold the longest chords).
-// A run that stopped is left out: its workgroups would only return at once.
+// Items of one run stay together, so that the XCDs' L2 holds few runs'
+// images at a time.  A run that stopped is left out: its workgroups would
+// only return at once.
 void batch_rebuild(exact_batch_s *b)
 {
     std::vector<int> order;
