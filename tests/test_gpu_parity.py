@@ -168,6 +168,35 @@ def test_count_nonzeros(ex, ora, case):
     g.close()
 
 
+def test_projectors_sampled_max_image(ex, ora):
+    """The largest image the ABI accepts (16384^2, 1 GiB as float32) with
+    three views and a detector covering it: sampled rays (every one walks
+    16384 lines) and pixels against the oracle, one by one."""
+    N, V, B = 16384, 3, 23172
+    say("sampled projectors at the maximum image size", N, V, B)
+    g = ex.Geometry(N, V, B)
+    go = ora.Geom(N, V, B)
+    rng = np.random.default_rng(31)
+    x = rng.random(N * N, dtype=np.float32)
+    s = torch.empty(g.n, device=DEV)
+    ex.exact_forward(g, t32(x), s)
+    rays = np.unique(np.concatenate([rng.integers(0, g.n, 60), [0, B // 2, B - 1, g.n - 1,
+                                                                g.n - B // 2]]))
+    s_ora = ora.forward_rays(go, x, rays)
+    within(np64(s)[rays], s_ora, s_ora)
+    del s
+    r = rng.normal(size=g.n).astype(np.float32)
+    img = torch.empty(g.d, device=DEV)
+    ex.exact_backproject(g, t32(r), img)
+    pix = np.unique(np.concatenate([rng.integers(0, g.d, 40), [0, N - 1, g.d - N, g.d - 1,
+                                                               g.d // 2 + N // 2]]))
+    g_ora = ora.back_pixels(go, r, pix)
+    within(np64(img)[pix], g_ora, ora.back_pixels(go, np.abs(r), pix))
+    del img
+    g.close()
+    torch.cuda.empty_cache()
+
+
 def test_adjoint_identity_on_gpu(ex):
     """<A x, y> = <x, A^T y> with the GPU's own projector pair: the weights are
     identical, so only float32 summation order separates the two."""
