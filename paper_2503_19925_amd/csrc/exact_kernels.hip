@@ -773,12 +773,35 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
         return;
     __shared__ double red[3][kRedThreads / 64];
     double v3[3] = {0.0, 0.0, 0.0};
-    for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
-        v3[0] += partials[2 * q];
-        v3[1] += partials[2 * q + 1];
+    // a thread's partials q, q + 256, ... are loaded eight at a time, so that
+    // their loads are in flight together, and added in that order (an
+    // absent one adds +0.0: the sums are of squares, so this changes no bit)
+    constexpr int kU = 8;
+    for (int q0 = threadIdx.x; q0 < nparts; q0 += kU * kRedThreads) {
+        double a[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = q0 + u * kRedThreads;
+            a[u] = q < nparts ? partials[2 * q] : 0.0;
+            b[u] = q < nparts ? partials[2 * q + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            v3[0] += a[u];
+            v3[1] += b[u];
+        }
     }
-    for (int q = threadIdx.x; q < n_avg; q += kRedThreads)
-        v3[2] += avg_parts[q];
+    for (int q0 = threadIdx.x; q0 < n_avg; q0 += kU * kRedThreads) {
+        double a[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = q0 + u * kRedThreads;
+            a[u] = q < n_avg ? avg_parts[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            v3[2] += a[u];
+    }
     plane_sum<3>(v3, red, true);
     if (threadIdx.x == 0) {
         const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
