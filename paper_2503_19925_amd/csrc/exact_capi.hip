@@ -861,15 +861,29 @@ struct Graph {
     }
 };
 
+// The step finish's inputs: the update partials (and with the averaged
+// rule its partials) and the run's state.
+exact::FinishArgs finish_args(const Problem &p)
+{
+    const bool avg = p.stop_mode == EXACT_STOP_AVERAGED_ITERATE;
+    const long d = (long)p.g->N * p.g->N;
+    return exact::FinishArgs{p.parts->as<double>(), exact::num_tiles(p.g->N),
+                             avg ? p.avg_parts->as<double>() : nullptr,
+                             avg ? exact::num_avg_parts(d) : 0, p.state};
+}
+
 // Enqueue order of one extragradient step (paper Sec. 1.2, eq.
 // extragrad-method): F at x_t, half-step from x_t, F at x_{t+1/2}, full step
 // again from x_t, then the fixed-order residual reduction and stop test.
+// In the captured graph (marks == nullptr) that finish runs inside the next
+// step's first kernel, and the host settles the last one before it reads
+// the state (settle_finish); with marks, for per-phase timing, it runs as
+// its own kernel at the end of the step.
 hipError_t enqueue_step(const Problem &p, hipStream_t st, hipEvent_t *marks = nullptr)
 {
     const exact_geometry_s *g = p.g;
     const Geo G = geo_of(g);
     const long n = (long)g->V * g->B;
-    const int ntiles = exact::num_tiles(g->N);
     const float gf = (float)p.gamma;
     const float inv_n = (float)(1.0 / (double)n);
     SolveState *S = p.state;
@@ -889,8 +903,10 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st, hipEvent_t *marks = nu
             cap(hipEventRecord(marks[phase], st));
         ++phase;
     };
+    const exact::FinishArgs fin = finish_args(p);
     mark();
-    cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, nullptr, skip, st));
+    cap(exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, nullptr, skip, st,
+                                       marks ? nullptr : &fin));
     mark();
     cap(exact::launch_back_update(G, r, inv_n, p.x, gf, nullptr, xhp, xhTp, parts, skip, st));
     mark();
@@ -900,15 +916,19 @@ hipError_t enqueue_step(const Problem &p, hipStream_t st, hipEvent_t *marks = nu
     mark();
     if (p.stop_mode == EXACT_STOP_AVERAGED_ITERATE) {
         const long d = (long)g->N * g->N;
-        double *ap = p.avg_parts->as<double>();
         cap(exact::launch_avg_step(p.x, p.avg_ring->as<float>(), p.avg_R, p.avg_J,
-                                   p.avg_S->as<double>(), d, ap, S, st));
-        cap(exact::launch_eg_finish(parts, ntiles, ap, exact::num_avg_parts(d), S, st));
-    } else {
-        cap(exact::launch_eg_finish(parts, ntiles, nullptr, 0, S, st));
+                                   p.avg_S->as<double>(), d, p.avg_parts->as<double>(), S, st));
     }
+    if (marks)
+        cap(exact::launch_eg_finish(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg, S, st));
     mark();
     return e;
+}
+
+// Runs the last step's finish if the graph left it pending.
+void settle_finish(const Problem &p, hipStream_t st)
+{
+    hip_check(exact::launch_eg_finish_pending(finish_args(p), st), "finish");
 }
 
 }  // namespace
@@ -950,6 +970,7 @@ exact_solver_s *solver_build(exact_geometry_s *g, const exact_spectrum *sp, cons
 
 int solver_poll(exact_solver_s *s, exact_solve_info *info)
 {
+    settle_finish(s->prob, s->own->st);
     read_state(s->prob.state, *s->hs, s->own->st);
     fill_info(s->prob, *s->hs->h, info, s->t0);
     return s->hs->h->done ? 1 : 0;
@@ -1104,6 +1125,10 @@ int exact_solver_profile(exact_solver s, int32_t n_steps, double *phase_ms, void
         hipError_t e = hipEventRecord(order, user);
         if (e == hipSuccess)
             e = hipStreamWaitEvent(own, order, 0);
+        // a finish the graph left pending runs first: each profiled step
+        // then runs its own
+        if (e == hipSuccess)
+            e = exact::launch_eg_finish_pending(finish_args(s->prob), own);
         for (int t = 0; t < n_steps && e == hipSuccess; ++t)
             e = enqueue_step(s->prob, own, ev.data() + (size_t)t * kMarks);
         if (e == hipSuccess)

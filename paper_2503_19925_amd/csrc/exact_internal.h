@@ -81,7 +81,7 @@ struct SolveState {
     int32_t converged;
     int32_t max_iters;
     int32_t stop_mode;   // 0: natural residual rho; 1: averaged iterate
-    int32_t pad_;
+    int32_t pending;     // a completed step's finish (reduction, stop test) not yet run
     double crit;         // stop_mode 1: last ||xbar_s - xbar_{s-1}|| (-1 if none)
 };
 
@@ -183,9 +183,20 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
                           hipStream_t st);
 // r = Y - sum_k J_k exp(-mu_k (A x)_+) into a weighted padded residual and,
 // when r_plain is not null, unweighted into the plain [V][B] layout.
+// With fin (nullable), the kernel's last workgroup also runs the previous
+// step's finish when one is pending and marks this step's as pending (the
+// step's first kernel hides the finish; see k_forward).
+struct FinishArgs {
+    const double *partials;
+    int nparts;
+    const double *avg_parts;
+    int n_avg;
+    SolveState *state;
+};
 hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
                                    const float *Y, const SpecArg &sp, float *r, float *r_plain,
-                                   const int32_t *skip, hipStream_t st);
+                                   const int32_t *skip, hipStream_t st,
+                                   const FinishArgs *fin = nullptr);
 // rw (padded, padding already zero) <- the plain [V][B] sinogram r,
 // weighted row by row.
 hipError_t launch_weigh_rows(const Geo &g, const float *r, float *rw, hipStream_t st);
@@ -211,6 +222,9 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
 // raises done when t reaches max_iters or the run's stop rule holds: rho_t
 // <= tol (stop_mode 0), or, from the averaged-iterate partials (n_avg of
 // them), ||xbar_s - xbar_{s-1}|| <= tol (stop_mode 1).
+// The finish of a step whose finish is pending (no-op otherwise): settles
+// the state before the host reads it.
+hipError_t launch_eg_finish_pending(const FinishArgs &fin, hipStream_t st);
 hipError_t launch_eg_finish(const double *partials, int nparts, const double *avg_parts,
                             int n_avg, SolveState *state, hipStream_t st);
 

@@ -109,6 +109,74 @@ __device__ __forceinline__ void plane_sum(double (&v)[NV], double (*lds)[kRedThr
     }
 }
 
+// Fixed-order reduction of a run's update partials, rho_t, and the stop test
+// (with stop_mode 1 also the averaged-iterate partials and their criterion).
+// With kGated it runs only while a finish is pending (the single-scan path,
+// where the next step's first kernel or the host settles it) and clears the
+// flag; the batched path runs it unconditionally after every step.
+template <bool kGated>
+__device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
+                                             const double *__restrict__ avg_parts, int n_avg,
+                                             SolveState *st)
+{
+    if (st->done || (kGated && !st->pending))
+        return;
+    __shared__ double red[3][kRedThreads / 64];
+    double v3[3] = {0.0, 0.0, 0.0};
+    // a thread's partials q, q + 256, ... are loaded eight at a time, so that
+    // their loads are in flight together, and added in that order (an
+    // absent one adds +0.0: the sums are of squares, so this changes no bit)
+    constexpr int kU = 8;
+    for (int q0 = threadIdx.x; q0 < nparts; q0 += kU * kRedThreads) {
+        double a[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = q0 + u * kRedThreads;
+            a[u] = q < nparts ? partials[2 * q] : 0.0;
+            b[u] = q < nparts ? partials[2 * q + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            v3[0] += a[u];
+            v3[1] += b[u];
+        }
+    }
+    for (int q0 = threadIdx.x; q0 < n_avg; q0 += kU * kRedThreads) {
+        double a[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = q0 + u * kRedThreads;
+            a[u] = q < n_avg ? avg_parts[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            v3[2] += a[u];
+    }
+    plane_sum<3>(v3, red, true);
+    if (threadIdx.x == 0) {
+        const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
+        const int t = st->t + 1;
+        st->rho = rho;
+        st->t = t;
+        bool met;
+        if (st->stop_mode == 1) {
+            const double crit = sqrt(v3[2]);
+            st->crit = crit;
+            met = crit <= st->tol;
+        } else {
+            met = rho >= 0.0 && rho <= st->tol;
+        }
+        if (st->tol > 0.0 && met) {
+            st->converged = 1;
+            st->done = 1;
+        } else if (t >= st->max_iters) {
+            st->done = 1;
+        }
+        if (kGated)
+            st->pending = 0;
+    }
+}
+
 // ---------------------------------------------------------------- forward
 
 #ifndef EXACT_FWD_SEGS
@@ -343,10 +411,21 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     const int32_t *__restrict__ order, int N, int V, int B, int nrow,
     const float *__restrict__ xp, const float *__restrict__ xTp, const float *__restrict__ Y,
     SpecArg sp, float *__restrict__ out, int ostride, int ooff, int weighted,
-    float *__restrict__ plain, const int32_t *__restrict__ skip)
+    float *__restrict__ plain, const int32_t *__restrict__ skip, FinishArgs fin)
 {
     if (skipped(skip))
         return;
+    // The step's first kernel hides the previous step's finish in its last
+    // workgroup (the lightest block of the dispatch order): the finish runs
+    // if one is pending, and this step's is marked pending unless the run
+    // has just stopped.  Nothing that reads the stop flag runs before this
+    // kernel ends; its other workgroups may compute a residual that no
+    // later kernel uses.
+    if (kResid && fin.state && blockIdx.x == gridDim.x - 1) {
+        finish_block<true>(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg, fin.state);
+        if (threadIdx.x == 0 && !fin.state->done)
+            fin.state->pending = 1;
+    }
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
     const int it = order[blockIdx.x];
     forward_block<kResid>(views, blk, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff,
@@ -758,79 +837,18 @@ __global__ void k_state_init(SolveState *st, double tol, int max_iters, int stop
         st->converged = 0;
         st->max_iters = max_iters;
         st->stop_mode = stop_mode;
-        st->pad_ = 0;
+        st->pending = 0;
         st->crit = -1.0;
     }
 }
 
-// Fixed-order reduction of a run's update partials, rho_t, and the stop test
-// (with stop_mode 1 also the averaged-iterate partials and their criterion).
-__device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
-                                             const double *__restrict__ avg_parts, int n_avg,
-                                             SolveState *st)
-{
-    if (st->done)
-        return;
-    __shared__ double red[3][kRedThreads / 64];
-    double v3[3] = {0.0, 0.0, 0.0};
-    // a thread's partials q, q + 256, ... are loaded eight at a time, so that
-    // their loads are in flight together, and added in that order (an
-    // absent one adds +0.0: the sums are of squares, so this changes no bit)
-    constexpr int kU = 8;
-    for (int q0 = threadIdx.x; q0 < nparts; q0 += kU * kRedThreads) {
-        double a[kU], b[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int q = q0 + u * kRedThreads;
-            a[u] = q < nparts ? partials[2 * q] : 0.0;
-            b[u] = q < nparts ? partials[2 * q + 1] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            v3[0] += a[u];
-            v3[1] += b[u];
-        }
-    }
-    for (int q0 = threadIdx.x; q0 < n_avg; q0 += kU * kRedThreads) {
-        double a[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int q = q0 + u * kRedThreads;
-            a[u] = q < n_avg ? avg_parts[q] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            v3[2] += a[u];
-    }
-    plane_sum<3>(v3, red, true);
-    if (threadIdx.x == 0) {
-        const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
-        const int t = st->t + 1;
-        st->rho = rho;
-        st->t = t;
-        bool met;
-        if (st->stop_mode == 1) {
-            const double crit = sqrt(v3[2]);
-            st->crit = crit;
-            met = crit <= st->tol;
-        } else {
-            met = rho >= 0.0 && rho <= st->tol;
-        }
-        if (st->tol > 0.0 && met) {
-            st->converged = 1;
-            st->done = 1;
-        } else if (t >= st->max_iters) {
-            st->done = 1;
-        }
-    }
-}
-
+template <bool kGated>
 __global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restrict__ partials,
                                                            int nparts,
                                                            const double *__restrict__ avg_parts,
                                                            int n_avg, SolveState *st)
 {
-    finish_block(partials, nparts, avg_parts, n_avg, st);
+    finish_block<kGated>(partials, nparts, avg_parts, n_avg, st);
 }
 
 // ------------------------------------------------------ averaged iterate
@@ -957,7 +975,7 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void kb_back_update(
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
 {
     const BatchProb &P = probs[blockIdx.x];
-    finish_block(glob(P.parts), P.ntiles, nullptr, 0, glob(P.state));
+    finish_block<false>(glob(P.parts), P.ntiles, nullptr, 0, glob(P.state));
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,
@@ -1082,21 +1100,22 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
     none.K = 0;
     none.bg = nullptr;
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
+    const FinishArgs nofin{nullptr, 0, nullptr, 0, nullptr};
     hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
                        g.order, g.N, g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
-                       weighted ? 1 : 0, nullptr, skip);
+                       weighted ? 1 : 0, nullptr, skip, nofin);
     return hipGetLastError();
 }
 
 hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
                                    const float *Y, const SpecArg &sp, float *r, float *r_plain,
-                                   const int32_t *skip, hipStream_t st)
+                                   const int32_t *skip, hipStream_t st, const FinishArgs *fin)
 {
     dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
+    const FinishArgs f = fin ? *fin : FinishArgs{nullptr, 0, nullptr, 0, nullptr};
     hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
                        g.order, g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1,
-                       r_plain,
-                       skip);
+                       r_plain, skip, f);
     return hipGetLastError();
 }
 
@@ -1217,8 +1236,15 @@ hipError_t launch_back_update(const Geo &g, const float *r, float scale, const f
 hipError_t launch_eg_finish(const double *partials, int nparts, const double *avg_parts,
                             int n_avg, SolveState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_eg_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts,
+    hipLaunchKernelGGL(k_eg_finish<false>, dim3(1), dim3(kRedThreads), 0, st, partials, nparts,
                        avg_parts, n_avg, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_eg_finish_pending(const FinishArgs &fin, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_eg_finish<true>, dim3(1), dim3(kRedThreads), 0, st, fin.partials,
+                       fin.nparts, fin.avg_parts, fin.n_avg, fin.state);
     return hipGetLastError();
 }
 
