@@ -318,9 +318,10 @@ int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spec
  *
  * exact_solver_profile (for measurement) runs n_steps (1..4096) further
  * steps launched one kernel at a time instead of through the captured
- * graph, with HIP events recorded on the solver's stream around each of the
- * step's EXACT_STEP_PHASES kernels, and writes the average milliseconds of
- * each phase to phase_ms[EXACT_STEP_PHASES]:
+ * graph, each of the step's EXACT_STEP_PHASES phases its own kernel (in the
+ * graph the reduction [4] runs inside the next step's first kernel), with
+ * HIP events recorded on the solver's stream around each, and writes the
+ * average milliseconds of each phase to phase_ms[EXACT_STEP_PHASES]:
  *   [0] forward projection + spectral residual at x_t,
  *   [1] back-projection + half-step update and residual partials,
  *   [2] forward projection + spectral residual at x_{t+1/2},
