@@ -354,7 +354,7 @@ int exact_count_nonzeros(exact_geometry g, int64_t *nnz_out, void *stream);
  * Batched and served extragradient (many independent reconstructions of
  * different shapes at once).  A batch holds runs in slots; every
  * exact_batch_step advances all running runs by whole extragradient steps
- * with one captured graph of seven phase kernels, whose workgroups take
+ * with one captured graph of five phase kernels, whose workgroups take
  * (run, tile) items from device lists, heaviest runs first.  The per-item
  * arithmetic is exact_solve's own, so each run's iterates are bitwise the
  * same alone and in any batch.  A run that has stopped costs nothing further

@@ -979,7 +979,7 @@ int solver_poll(exact_solver_s *s, exact_solve_info *info)
 }  // namespace
 
 // A batch: many runs of different shapes advanced together, one captured
-// graph of seven batched phase kernels per step.  Runs occupy slots; the
+// graph of five batched phase kernels per step.  Runs occupy slots; the
 // device descriptors and item lists are rebuilt (and the graph recaptured)
 // at the next step after a run joins or leaves.
 struct exact_batch_s {
