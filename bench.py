@@ -10,14 +10,21 @@ back-projection, update and projection, twice; plus the double-precision
 residual reduction and stop test), replayed from a captured HIP graph with
 all state resident in HBM.
 
-Prints one JSON line: EG iterations/s (value), projector rays/s, the
-roofline fraction of the step's dominant kernel (`roofline`: whichever of the
-forward with its residual epilogue and the back-projection fused with the
-update takes more of the step; the other in `roofline_other`) on algorithmic
-bytes, from HIP events around each kernel of a few further steps launched
-one kernel at a time, and the CPU oracle timed on a bounded sample of the
-same workload.  Two more legs
-report reconstructions/s and time-to-tolerance percentiles:
+Prints one JSON line: EG iterations/s (value), projector rays/s, and the
+roofline of the step's dominant kernel (`roofline`: whichever of the forward
+with its residual epilogue and the back-projection fused with the update
+takes more of the step; the other in `roofline_other`).  The kernels are
+bound by VALU instruction issue (no dense contraction, and on-chip reuse
+serves nearly all operand traffic), so the roofline is taken against the
+VALU issue rate: the kernel's VALU lane-instructions per launch (from the
+hardware counter SQ_INSTS_VALU of the committed profile when it was taken on
+this build, else the instruction count of its inner loop) over its average
+launch duration, measured live with HIP events around back-to-back launches
+on the solver's stream.  Beside it: measured HBM bytes and rate, and the
+algorithmic bytes (4 B per nonzero of A), labelled as not a bound.  The CPU
+oracle is timed on a bounded sample of the same workload.  More legs report
+the 1024^2 workload solved to tolerance, reconstructions/s and
+time-to-tolerance percentiles:
 
 * batched: 64 uneven scans (N in {128..768}, 30-360 views, 10-64 energy
   bins, 2-4 windows; seed 401), each to natural residual 1e-4 (cap 5000
@@ -25,9 +32,11 @@ report reconstructions/s and time-to-tolerance percentiles:
   results are bitwise equal, so the accuracy is equal;
 * served: the first --served requests (default 300) of a seeded Poisson
   stream at 20 requests/s (N in {256, 512, 1024}, 90/180/360 views, K = 30, Wn = 3,
-  I0 in {1e3, 1e4}, tolerance 1e-3 or 1e-4), admitted by HBM footprint and
-  batched continuously; time-to-tolerance runs from arrival to the result on
-  the host.
+  I0 in {1e3, 1e4}, tolerance 1e-3 or 1e-4), admitted by HBM footprint,
+  shortest expected work first under a cap on work in flight, and batched
+  continuously; time-to-tolerance runs from arrival to the result on the
+  host.  Beside it the same stream served one request at a time in arrival
+  order (FCFS).
 """
 import argparse
 import json
@@ -52,10 +61,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # VALU instructions of the inner loops, counted in their gfx950 assembly
 # (Kahan steps included): per pixel and view in the gather (clamp-free
-# form, which the benchmark geometry uses), per ray and
-# line in the forward
+# form, which the benchmark geometry uses), per ray and line in the forward.
+# Used only when no counter reading of the current build is committed.
 VALU_PER_PIXEL_VIEW = 14.0
 VALU_PER_RAY_LINE = 11.0
+KERNEL_FWD = "k_forward<true>"
+KERNEL_BU = "k_back_update"
 
 
 def log(*a):
@@ -77,9 +88,27 @@ def event_time_ms(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
 def cpu_baseline(P, gamma, steps):
     """The oracle, untuned, on a bounded sample: `steps` EG iterations of the
-    same workload from x = 0 with the same step size, one thread."""
+    same workload from x = 0 with the same step size.  The oracle is serial
+    C (one thread); the host's CPU count and model are reported beside it."""
     import numpy as np
     from oracle import build as oracle_build
     from oracle import oracle as ora
@@ -89,9 +118,11 @@ def cpu_baseline(P, gamma, steps):
     t0 = time.perf_counter()
     ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(P.d), gamma, steps)
     dt = time.perf_counter() - t0
+    ncpu, model = host_cpu()
     return {"value": steps / dt, "unit": "EG iters/s", "cores": 1, "kind": "oracle",
-            "sample": "%d EG steps of %s from x=0 (float64 C oracle, one thread, "
-                      "%.1f s)" % (steps, P.name, dt)}
+            "sample": "%d EG steps of %s from x=0 (float64 C oracle, serial: one thread, "
+                      "%.1f s)" % (steps, P.name, dt),
+            "host_cpus": ncpu, "cpu_model": model}
 
 
 def measured_traffic(workload, kernel):
@@ -108,6 +139,45 @@ def measured_traffic(workload, kernel):
         return rec["workloads"][workload][kernel]["hbm_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_valu(workload, kernel):
+    """VALU lane-instructions per launch of `kernel` (SQ_INSTS_VALU per
+    dispatch x 64 lanes) from the committed counter summary
+    (profiles/valu.json), or None when the kernel source or its tile knobs
+    have changed since the counters were taken."""
+    from paper_2503_19925_amd import build as libbuild
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    try:
+        rec = json.load(open(path))
+        if rec.get("kernel_build_id") != libbuild.build_id():
+            return None
+        return rec["workloads"][workload][kernel]["valu_lane_instr_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def kernel_roofline(name, workload, ms, static_valu, alg_bytes):
+    """The roofline record of one kernel: VALU issue (the binding unit),
+    then the measured HBM traffic and the algorithmic bytes beside it."""
+    valu = measured_valu(workload, name)
+    src = "counters: SQ_INSTS_VALU x 64 per dispatch (profiles/valu.json)"
+    if valu is None:
+        valu, src = static_valu, "static: inner-loop instructions x units"
+    achieved = valu / (ms * 1e-3) / 1e12
+    traffic = measured_traffic(workload, name)
+    rec = {"kernel": name, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+           "unit": "T VALU lane-instructions/s", "frac": achieved / VALU_PEAK_TOPS,
+           "traffic": traffic, "ms_per_launch": ms,
+           "valu_lane_instr_per_launch": valu, "valu_source": src,
+           "hbm": None if traffic is None else {
+               "achieved": traffic / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "algorithmic": {"bytes_per_launch": alg_bytes,
+                           "GB_per_s": alg_bytes / (ms * 1e-3) / 1e9,
+                           "note": "4 B per nonzero of A plus compulsory I/O; served from "
+                                   "L2/L1, not a bound"}}
+    return rec
 
 
 def pct(v, q):
@@ -251,7 +321,7 @@ def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
     (counts upload + solve; geometry and lambda_max cached per shape as the
     server does), and the queue formed from the stream's arrival times."""
     import numpy as np
-    from paper_2503_19925_amd.serve import fcfs_latencies, theorem2_gamma
+    from paper_2503_19925_amd.serve import fcfs_latencies
     order = sorted(reqs, key=lambda r: (r.arrival, r.rid))
     geoms, svc = {}, []
     for r in order:
@@ -265,8 +335,7 @@ def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
         t0 = time.perf_counter()
         y = torch.as_tensor(np.ascontiguousarray(P.y, dtype=np.float32), device="cuda")
         x = torch.zeros(P.d, device="cuda")
-        exact.exact_solve(g, P.mu, P.I, y, x, gamma=theorem2_gamma(P, lam),
-                          max_iters=r.max_iters, tol=r.tol)
+        exact.exact_solve(g, P.mu, P.I, y, x, lambda_hat=lam, max_iters=r.max_iters, tol=r.tol)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t0)
     for g, _ in geoms.values():
@@ -278,7 +347,54 @@ def fcfs_one_at_a_time(reqs, torch, exact, power_iters=100):
             "note": "queue simulated from the measured solo solve times and the arrivals"}
 
 
-def served_leg(count, torch, exact, synth, serial=True):
+def large_leg(tol, torch, exact, synth, reps):
+    """The large low-dose workload (1024^2 image, 720 views x 1448 bins,
+    K = 64, Wn = 4, I0 = 1e3): the step's kernel durations and projector
+    rays/s, and a solve from x = 0 to natural residual `tol` (cap 20000
+    steps), timed on the wall clock around exact_solve (set-up included)."""
+    import numpy as np
+    P = synth.config_problem("large_1024", with_truth=False)
+    log("large_1024: generated")
+    g = exact.Geometry(P.n_pix, P.n_views, P.n_bins)
+    y = torch.as_tensor(P.y, device="cuda")
+    x = torch.zeros(g.d, device="cuda")
+    sv = exact.Solver(g, P.mu, P.I, y, x, max_iters=4, tol=0.0)
+    sv.step(4)
+    kms = sv.time_kernels(max(2, reps // 4))
+    _, info = sv.poll()
+    sv.close()
+    st = torch.cuda.current_stream()
+    x.zero_()
+    sv = exact.Solver(g, P.mu, P.I, y, x, gamma=info["gamma"], max_iters=22, tol=0.0)
+    sv.step(2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    sv.step(20)
+    e1.record(st)
+    e1.synchronize()
+    sv.close()
+    ms_step = e0.elapsed_time(e1) / 20
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = exact.exact_solve(g, P.mu, P.I, y, x, max_iters=20000, tol=tol, check_every=32)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    fwd_ms, bu_ms = (kms[0] + kms[2]) / 2, (kms[1] + kms[3]) / 2
+    log("large_1024: %.4f ms/step; to %.0e in %d steps, %.2f s" % (ms_step, tol, it["iters"], wall))
+    return {"workload": WORKLOADS["large_1024"], "ms_per_step": ms_step,
+            "EG_iters_per_s": 1e3 / ms_step, "kernel_ms": dict(zip(exact.PHASE_NAMES, kms)),
+            "forward_grays": g.n / (fwd_ms * 1e-3) / 1e9, "back_grays": g.n / (bu_ms * 1e-3) / 1e9,
+            "to_tol": {"tol": tol, "iters": it["iters"], "resid": it["resid"],
+                       "converged": it["converged"], "seconds": wall,
+                       "seconds_in_call": it["ms"] / 1e3, "gamma": it["gamma"]}}
+
+
+def served_leg(count, torch, exact, synth, serial=True, policy="sjf", work_cap=150.0,
+               max_wait=10.0, admit_all=False):
     from paper_2503_19925_amd.serve import GpuBackend, Request, Server, summarize
     stream = synth.served_stream(300, 20.0, 501)[:count]
     reqs = [Request(q, s["arrival"], synth.make_problem("req%d" % q, with_truth=False,
@@ -286,16 +402,29 @@ def served_leg(count, torch, exact, synth, serial=True):
             for q, s in enumerate(stream)]
     log("served leg: %d requests generated" % count)
     budget = 64 << 30
-    be = GpuBackend(budget, capacity=max(8, count), keep_x=False)
+
     def progress(r):
         log("served: request %d done (%d steps, %.2f s after arrival)" % (r.rid, r.iters, r.latency))
 
-    srv = Server(be, budget, chunk_steps=16, on_done=progress)
-    res = srv.run(reqs)
-    be.close()
-    s = summarize(res)
+    def play(pol, cap):
+        be = GpuBackend(budget, capacity=max(8, count), keep_x=False)
+        srv = Server(be, budget, chunk_steps=16, on_done=progress, policy=pol, work_cap=cap,
+                     max_wait=max_wait)
+        res = srv.run(reqs)
+        be.close()
+        out = summarize(res)
+        out.update({"policy": pol, "work_cap": cap, "peak_running": srv.peak_running})
+        if pol == "sjf":
+            out["max_wait_s"] = max_wait
+        return out
+
+    s = play(policy, work_cap)
     s["offered_req_per_s"] = (count - 1) / (reqs[-1].arrival - reqs[0].arrival)
-    s["peak_running"] = srv.peak_running
+    if admit_all:
+        a = play("fcfs", None)
+        log("served admit-all (FCFS, no cap): p50 %.2f s, p99 %.2f s, %.2f recon/s"
+            % (a["p50_s"], a["p99_s"], a["recon_per_s"]))
+        s["admit_all_fcfs"] = a
     if serial:
         f = fcfs_one_at_a_time(reqs, torch, exact)
         log("served one at a time (FCFS): p50 %.2f s, p99 %.2f s, %.2f recon/s"
@@ -310,8 +439,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--proj-reps", type=int, default=50)
-    ap.add_argument("--profile-steps", type=int, default=50,
-                    help="extra steps launched kernel by kernel for per-phase times")
+    ap.add_argument("--kernel-reps", type=int, default=20,
+                    help="back-to-back launches per step kernel for its average duration")
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="EG steps of the CPU oracle baseline (0 to skip)")
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
@@ -326,6 +455,17 @@ def main():
                     help="requests in the served leg (0 to skip)")
     ap.add_argument("--served-serial", type=int, default=1,
                     help="also serve the stream one request at a time (0 to skip)")
+    ap.add_argument("--served-policy", default="sjf", choices=("sjf", "fcfs"),
+                    help="admission order of the served leg")
+    ap.add_argument("--served-cap", type=float, default=150.0,
+                    help="work in flight of the served leg (step-cost units; <= 0: no cap)")
+    ap.add_argument("--served-max-wait", type=float, default=10.0,
+                    help="seconds after which a waiting request goes first")
+    ap.add_argument("--served-admit-all", type=int, default=0,
+                    help="also serve the stream admitting every request at once (FCFS)")
+    ap.add_argument("--large-to-tol", type=float, default=1e-4,
+                    help="solve the 1024^2 workload from x=0 to this natural residual "
+                         "(0 to skip)")
     ap.add_argument("--workload", default="solve_512", choices=sorted(WORKLOADS),
                     help="single-scan workload of the main line")
     ap.add_argument("--to-tol", type=float, default=0.0,
@@ -362,8 +502,7 @@ def main():
     # iteration (100 products with A^T A), resident state, graph capture
     torch.cuda.synchronize()
     t_set = time.perf_counter()
-    solver = exact.Solver(g, P.mu, P.I, y, x,
-                          max_iters=args.warmup + args.steps + args.profile_steps, tol=0.0)
+    solver = exact.Solver(g, P.mu, P.I, y, x, max_iters=args.warmup + args.steps, tol=0.0)
     setup_ms = 1e3 * (time.perf_counter() - t_set)
     torch.cuda.synchronize()
     t_set = time.perf_counter()
@@ -393,16 +532,13 @@ def main():
         raise RuntimeError("solver ran %d steps, expected %d" % (info["iters"], args.warmup + args.steps))
     log("timed %d steps: %.4f ms/step (events), %.4f ms/step (wall)" % (
         args.steps, ms_step, 1e3 * wall / args.steps))
-    # the same step kernel by kernel, HIP events around each phase on the
-    # solver's stream: per-kernel durations for the roofline
-    phase_ms = solver.profile(args.profile_steps)
-    _, info_p = solver.poll()
+    # each kernel of the step launched kernel_reps times back to back between
+    # two HIP events on the solver's stream: average duration per launch
+    kms = solver.time_kernels(args.kernel_reps)
     solver.close()
-    if info_p["iters"] != args.warmup + args.steps + args.profile_steps:
-        raise RuntimeError("profiled steps did not run")
-    log("per-phase ms: " + ", ".join("%s %.4f" % (n, t) for n, t in zip(exact.PHASE_NAMES, phase_ms)))
+    log("kernel ms: " + ", ".join("%s %.4f" % (n, t) for n, t in zip(exact.PHASE_NAMES, kms)))
 
-    # projector throughput and the back-projector's roofline
+    # standalone projector calls (each pads or weighs its input first)
     nnz = exact.exact_count_nonzeros(g)
     r = torch.randn(g.n, device=dev)
     img = torch.empty(g.d, device=dev)
@@ -410,45 +546,28 @@ def main():
     xb = torch.rand(g.d, device=dev)
     t_back = event_time_ms(lambda: exact.exact_backproject(g, r, img), args.proj_reps, torch)
     t_fwd = event_time_ms(lambda: exact.exact_forward(g, xb, s), args.proj_reps, torch)
-    log("nnz %d; exact_backproject %.4f ms, exact_forward (with padding copy) %.4f ms" % (
-        nnz, t_back, t_fwd))
-    # algorithmic bytes (4 B per nonzero of A plus compulsory I/O) of the
-    # step's back-projection + update kernel: r gathered per nonzero, r read
-    # once, x read, z written to the padded pair (and to x in the full step)
-    bytes_bu = [4.0 * nnz + 4.0 * g.n + 12.0 * g.d, 4.0 * nnz + 4.0 * g.n + 16.0 * g.d]
-    t_bu = [phase_ms[1], phase_ms[3]]
-    achieved = sum(bytes_bu) / (sum(t_bu) * 1e-3) / 1e9
-    bytes_fwd = 4.0 * nnz + 8.0 * g.d + 8.0 * g.n        # x operands, Y in, r out
-    fwd_achieved = 2 * bytes_fwd / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9
-    # the same kernels against the VALU issue rate: lane-instructions of the
-    # inner loop per pixel-view (gather) and per ray-line crossing (forward,
-    # about nnz / 2 crossings: each has two taps except at the image edge)
-    valu_bu = VALU_PER_PIXEL_VIEW * g.d * P.n_views
-    valu_bu_tops = 2 * valu_bu / (sum(t_bu) * 1e-3) / 1e12
-    valu_fwd = VALU_PER_RAY_LINE * nnz / 2.0
-    valu_fwd_tops = 2 * valu_fwd / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e12
-
-    roof_back = {"kernel": "k_back_update", "bound": "hbm", "achieved": achieved,
-                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                 "traffic": measured_traffic(args.workload, "k_back_update"),
-                 "bytes_per_launch": sum(bytes_bu) / 2, "ms_per_launch": sum(t_bu) / 2,
-                 "ms_per_step": sum(t_bu),
-                 "alu_issue": {"bound": "alu", "achieved": valu_bu_tops, "peak": VALU_PEAK_TOPS,
-                               "unit": "T VALU lane-instructions/s",
-                               "frac": valu_bu_tops / VALU_PEAK_TOPS,
-                               "valu_per_pixel_view": VALU_PER_PIXEL_VIEW}}
-    roof_fwd = {"kernel": "k_forward<true>", "bound": "hbm", "achieved": fwd_achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fwd_achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.workload, "k_forward<true>"),
-                "bytes_per_launch": bytes_fwd, "ms_per_launch": (phase_ms[0] + phase_ms[2]) / 2,
-                "ms_per_step": phase_ms[0] + phase_ms[2],
-                "alu_issue": {"bound": "alu", "achieved": valu_fwd_tops, "peak": VALU_PEAK_TOPS,
-                              "unit": "T VALU lane-instructions/s",
-                              "frac": valu_fwd_tops / VALU_PEAK_TOPS,
-                              "valu_per_ray_line": VALU_PER_RAY_LINE}}
+    log("nnz %d; exact_backproject %.4f ms, exact_forward %.4f ms (calls)" % (nnz, t_back, t_fwd))
+    fwd_ms = (kms[0] + kms[2]) / 2
+    bu_ms = (kms[1] + kms[3]) / 2
+    # algorithmic bytes (4 B per nonzero of A plus compulsory I/O): the
+    # forward reads x per nonzero, Y per ray and writes r; the
+    # back-projection + update gathers r per nonzero, reads r once and x,
+    # writes z to the padded pair (and to x in the full step)
+    bytes_fwd = 4.0 * nnz + 8.0 * g.d + 8.0 * g.n
+    bytes_bu = 4.0 * nnz + 4.0 * g.n + 14.0 * g.d
+    roof_fwd = kernel_roofline(KERNEL_FWD, args.workload, fwd_ms,
+                               VALU_PER_RAY_LINE * nnz / 2.0, bytes_fwd)
+    roof_back = kernel_roofline(KERNEL_BU, args.workload, bu_ms,
+                                VALU_PER_PIXEL_VIEW * g.d * P.n_views, bytes_bu)
     # the dominant kernel: the one that takes more of the step (two launches each)
-    roof_dominant, roof_other = ((roof_fwd, roof_back) if roof_fwd["ms_per_step"] >= roof_back["ms_per_step"]
+    roof_dominant, roof_other = ((roof_fwd, roof_back) if fwd_ms >= bu_ms
                                  else (roof_back, roof_fwd))
+    log("roofline %s: %.3f of VALU issue (%s)" % (roof_dominant["kernel"], roof_dominant["frac"],
+                                                 roof_dominant["valu_source"].split(":")[0]))
+
+    large = None
+    if args.large_to_tol > 0 and args.workload != "large_1024":
+        large = large_leg(args.large_to_tol, torch, exact, synth, args.kernel_reps)
 
     to_tol = None
     if args.to_tol > 0:
@@ -489,7 +608,10 @@ def main():
     dense = dense_leg(4096, 20, args.dense_steps, torch, exact) if args.dense_steps > 0 else None
 
     batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
-    served = (served_leg(args.served, torch, exact, synth, serial=args.served_serial > 0)
+    served = (served_leg(args.served, torch, exact, synth, serial=args.served_serial > 0,
+                         policy=args.served_policy,
+                         work_cap=args.served_cap if args.served_cap > 0 else None,
+                         max_wait=args.served_max_wait, admit_all=args.served_admit_all > 0)
               if args.served > 0 else None)
     if served:
         log("served: p50 %.2f s, p99 %.2f s, %.2f recon/s" % (served["p50_s"], served["p99_s"],
@@ -516,18 +638,21 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "n_pix": P.n_pix, "n_views": P.n_views, "n_bins": P.n_bins,
                    "n_energies": P.K, "n_windows": P.Wn, "parallelism": "single GPU"},
-        "forward_grays": g.n / (t_fwd * 1e-3) / 1e9,
-        "back_grays": g.n / (t_back * 1e-3) / 1e9,
-        "forward_ms": t_fwd,
-        "back_ms": t_back,
+        "forward_grays": g.n / (fwd_ms * 1e-3) / 1e9,
+        "back_grays": g.n / (bu_ms * 1e-3) / 1e9,
+        "grays_note": "rays per second of the step's kernels (forward + residual; "
+                      "back-projection + update), average launch durations",
+        "call_forward_grays": g.n / (t_fwd * 1e-3) / 1e9,
+        "call_back_grays": g.n / (t_back * 1e-3) / 1e9,
+        "call_forward_ms": t_fwd,
+        "call_back_ms": t_back,
         "nnz": nnz,
-        "step_phase_ms": dict(zip(exact.PHASE_NAMES, phase_ms)),
+        "kernel_ms": dict(zip(exact.PHASE_NAMES, kms)),
         "setup_ms": setup_ms,
         "power_iteration_ms": power_ms,
-        "step_forward_grays": 2 * g.n / ((phase_ms[0] + phase_ms[2]) * 1e-3) / 1e9,
-        "step_back_grays": 2 * g.n / (sum(t_bu) * 1e-3) / 1e9,
         "roofline": roof_dominant,
         "roofline_other": roof_other,
+        "large_1024": large,
         "to_tol": to_tol,
         "background": background,
         "tv_ball": tv,

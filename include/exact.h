@@ -114,6 +114,11 @@ typedef struct {
     int32_t stop_mode;   /* EXACT_STOP_NATURAL_RESIDUAL or _AVERAGED_ITERATE */
     int32_t check_every; /* steps between host reads of the device stop flag */
     int32_t power_iters; /* cap on power-iteration steps for lambda_max     */
+    double lambda_hat;   /* lambda_max(A^T A / n) of the geometry when already
+                            known (exact_step_size, or an earlier run's
+                            info): > 0 makes the automatic step size use it
+                            instead of running the power iteration; 0
+                            (default) runs it.  Ignored when gamma > 0.      */
 } exact_solve_opts;
 
 typedef struct {
@@ -122,13 +127,13 @@ typedef struct {
                             undefined, i.e. x_t = 0); with the averaged rule
                             the last ||xbar_{t+1} - xbar_t||                 */
     double gamma;        /* step size used                                   */
-    double lambda_hat;   /* lambda_max estimate (0 if gamma was given)       */
+    double lambda_hat;   /* lambda_max estimate used (0 if gamma was given) */
     double ms;           /* wall time of the call                            */
 } exact_solve_info;
 
 /* Fills opts with the defaults: gamma 0 (automatic), gamma_scale 0.25,
  * max_iters 500, tol 0, natural-residual stop, check_every 16,
- * power_iters 100. */
+ * power_iters 100, lambda_hat 0 (computed). */
 void exact_solve_opts_default(exact_solve_opts *opts);
 
 /*
@@ -342,6 +347,20 @@ int exact_solver_step(exact_solver s, int32_t n_steps, void *stream);
 int exact_solver_poll(exact_solver s, exact_solve_info *info);
 int exact_solver_destroy(exact_solver s);
 int exact_solver_profile(exact_solver s, int32_t n_steps, double *phase_ms, void *stream);
+
+/*
+ * exact_solver_time_kernels (for measurement) times each kernel of the
+ * step's EXACT_STEP_PHASES phases (numbered as for exact_solver_profile) as
+ * `reps` (1..4096) back-to-back launches between two HIP events on the
+ * solver's stream, after an untimed pass of the same launches, and writes
+ * the average milliseconds per launch to kernel_ms[EXACT_STEP_PHASES].  The run's state and iterate are left as
+ * they were: the kernels read the run's current buffers, the full-step
+ * update writes a scratch image instead of x, the reduction updates a
+ * scratch copy of the state, and the other kernels rewrite buffers that the
+ * next step writes again from the same inputs.  Works after the run has
+ * stopped too.  Ordered on `stream`; blocks until done.
+ */
+int exact_solver_time_kernels(exact_solver s, int32_t reps, double *kernel_ms, void *stream);
 
 /*
  * Exact number of positive entries of A (the tent weights that round to a

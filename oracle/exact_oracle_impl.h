@@ -736,13 +736,16 @@ int FN(ora_project_tv)(int N, const double *z, double tau, double tv_tol, int it
  * Projected extragradient over X = {TV(x) <= tau} intersected with the
  * orthant, the constraint set of the paper's experiments (Sec. 5): as
  * ora_eg, with both half-steps projected by tv_dykstra.  rho_hist as in
- * ora_eg; tol > 0 stops on the natural residual.  Returns the steps taken.
+ * ora_eg; tol > 0 stops on the natural residual.  *solves_out (if not
+ * NULL) receives the TV-regularized points computed over the run (the
+ * search's decision path).  Returns the steps taken.
  */
 int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const double *Iwk,
                   const double *y, const double *bg, double *x, double gamma, int max_iters,
                   double tol, double tau, double tv_tol, int prox_iters, int max_bisect,
-                  double dyk_tol, int max_outer, double *rho_hist)
+                  double dyk_tol, int max_outer, double *rho_hist, int *solves_out)
 {
+    int ns_total = 0, ns = 0;
     long n = (long)g->n_views * g->n_bins, d = (long)g->n_pix * g->n_pix;
     int N = g->n_pix;
     FN(spec) sp = FN(load_spec)(g, K, Wn, mu, Iwk, y, bg);
@@ -759,7 +762,8 @@ int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const doub
         for (long p = 0; p < d; ++p)
             v[p] = xt[p] - gm * F[p];
         FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
-                       max_outer, xh, 0, 0);
+                       max_outer, xh, 0, &ns);
+        ns_total += ns;
         REAL num = 0, den = 0;
         for (long p = 0; p < d; ++p) {
             num += (xh[p] - xt[p]) * (xh[p] - xt[p]);
@@ -772,12 +776,15 @@ int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const doub
         for (long p = 0; p < d; ++p)
             v[p] = xt[p] - gm * F[p];
         FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
-                       max_outer, xt, 0, 0);
+                       max_outer, xt, 0, &ns);
+        ns_total += ns;
         if (tol > 0 && rho >= 0 && rho <= tol)
             break;
     }
     if (t > max_iters)
         t = max_iters;
+    if (solves_out)
+        *solves_out = ns_total;
     FN(to_double)(xt, d, x);
     FN(free_spec)(&sp);
     free(xt); free(xh); free(v); free(F); free(s); free(r);

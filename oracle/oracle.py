@@ -111,7 +111,7 @@ def _lib():
             f = getattr(_LIB, "ora_eg_tv_" + p)
             f.argtypes = [_gp, C.c_int, C.c_int, _dp, _dp, _dp, C.c_void_p, _dp, C.c_double,
                           C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
-                          C.c_double, C.c_int, C.c_void_p]
+                          C.c_double, C.c_int, C.c_void_p, C.POINTER(C.c_int)]
             f.restype = C.c_int
             f = getattr(_LIB, "ora_dense_operator_" + p)
             f.argtypes = [C.c_long, C.c_long, _dp, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
@@ -319,9 +319,11 @@ def project_tv(z, tau, tv_tol=TV_DEFAULTS["tv_tol"], prox_iters=TV_DEFAULTS["pro
     return out, int(k), ns.value
 
 
-def eg_tv(g, mu, I, y, x1, gamma, max_iters, tau, tol=0.0, prec="f64", bg=None, **tvkw):
+def eg_tv(g, mu, I, y, x1, gamma, max_iters, tau, tol=0.0, prec="f64", bg=None,
+          want_solves=False, **tvkw):
     """Projected extragradient over TV ball intersected with the orthant.
-    Returns (x_last, steps, rho_hist)."""
+    Returns (x_last, steps, rho_hist); with want_solves=True also the
+    number of TV-regularized points the run computed."""
     kw = dict(TV_DEFAULTS)
     kw.update(tvkw)
     mu = _f64(mu)
@@ -332,10 +334,13 @@ def eg_tv(g, mu, I, y, x1, gamma, max_iters, tau, tol=0.0, prec="f64", bg=None, 
     x = _f64(x1, g.d).copy()
     hist = np.full(max(int(max_iters), 1), np.nan)
     b = _bg(bg, g.n)
+    ns = C.c_int(0)
     t = _fn("eg_tv", prec)(C.byref(g), K, Wn, mu, I, y, _ptr(b), x, float(gamma),
                            int(max_iters), float(tol), float(tau), float(kw["tv_tol"]),
                            int(kw["prox_iters"]), int(kw["max_bisect"]), float(kw["dyk_tol"]),
-                           int(kw["max_outer"]), _ptr(hist))
+                           int(kw["max_outer"]), _ptr(hist), C.byref(ns))
+    if want_solves:
+        return x, int(t), hist[:t], ns.value
     return x, int(t), hist[:t]
 
 

@@ -435,6 +435,7 @@ void exact_solve_opts_default(exact_solve_opts *o)
     o->stop_mode = EXACT_STOP_NATURAL_RESIDUAL;
     o->check_every = 16;
     o->power_iters = 100;
+    o->lambda_hat = 0.0;
 }
 
 const char *exact_last_error(void) { return g_last_error.c_str(); }
@@ -710,6 +711,8 @@ void validate_opts(exact_solve_opts &o)
         fail(-EINVAL, "gamma must be finite");
     if (o.gamma <= 0.0 && !(std::isfinite(o.gamma_scale) && o.gamma_scale > 0.0))
         fail(-EINVAL, "gamma_scale must be > 0 when gamma is automatic");
+    if (!(std::isfinite(o.lambda_hat) && o.lambda_hat >= 0.0))
+        fail(-EINVAL, "lambda_hat must be finite and >= 0");
     if (o.check_every < 1)
         o.check_every = 1;
     if (o.power_iters < 1)
@@ -783,7 +786,8 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
 
     p.gamma = o.gamma;
     if (p.gamma <= 0.0) {
-        p.lam = power_iteration(g, o.power_iters, st, nullptr);
+        // Theorem 2: gamma = c / (lambda_max(A^T A / n) sum_k J_k mu_k)
+        p.lam = o.lambda_hat > 0.0 ? o.lambda_hat : power_iteration(g, o.power_iters, st, nullptr);
         p.gamma = o.gamma_scale / (p.lam * sjm);
     }
     hip_check(exact::launch_pad_pair(x_dev, p.xp->as<float>(), p.xTp->as<float>(), g->N, st),
@@ -1149,6 +1153,99 @@ int exact_solver_profile(exact_solver s, int32_t n_steps, double *phase_ms, void
                 sum += ms;
             }
             phase_ms[q] = sum / n_steps;
+        }
+        return 0;
+    });
+}
+
+int exact_solver_time_kernels(exact_solver s, int32_t reps, double *kernel_ms, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!s)
+            fail(-EINVAL, "solver is NULL");
+        if (!kernel_ms)
+            fail(-EINVAL, "kernel_ms is NULL");
+        if (reps < 1 || reps > 4096)
+            fail(-EINVAL, "reps must be in [1, 4096]");
+        const Problem &p = s->prob;
+        const exact_geometry_s *g = p.g;
+        const Geo G = geo_of(g);
+        const long d = (long)g->N * g->N, n = (long)g->V * g->B;
+        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const float gf = (float)p.gamma;
+        const float inv_n = (float)(1.0 / (double)n);
+        hipStream_t own = s->own->st, user = (hipStream_t)stream;
+        // scratch: the full step's image and padded pair, and a state copy
+        // that the reduction may advance (never done, so no kernel skips)
+        DevBuf z((size_t)d * 4), zp(dp * 4), zTp(dp * 4), state(sizeof(SolveState));
+        SolveState *S = state.as<SolveState>();
+        const int32_t *skip = &S->done;
+        hipEvent_t order;
+        hip_check(hipEventCreateWithFlags(&order, hipEventDisableTiming), "hipEventCreate");
+        hipEvent_t ev[EXACT_STEP_PHASES + 1] = {};
+        struct Events {
+            hipEvent_t *v;
+            hipEvent_t o;
+            ~Events()
+            {
+                for (int i = 0; i <= EXACT_STEP_PHASES; ++i)
+                    if (v[i])
+                        (void)hipEventDestroy(v[i]);
+                (void)hipEventDestroy(o);
+            }
+        } guard{ev, order};
+        for (hipEvent_t &e : ev)
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+        hip_check(hipEventRecord(order, user), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(own, order, 0), "hipStreamWaitEvent");
+        // the graph's pending finish first, so the run's state is settled
+        hip_check(exact::launch_eg_finish_pending(finish_args(p), own), "finish");
+        hip_check(exact::launch_fill(zp.as<float>(), 0.f, (long)dp, own), "fill");
+        hip_check(exact::launch_fill(zTp.as<float>(), 0.f, (long)dp, own), "fill");
+        hip_check(exact::launch_state_init(S, 0.0, 0x7fffffff, 0, own), "state_init");
+        const exact::FinishArgs fin = finish_args(p);
+        float *Y = p.Y->as<float>(), *r = p.r->as<float>();
+        float *xp = p.xp->as<float>(), *xTp = p.xTp->as<float>();
+        float *xhp = p.xhp->as<float>(), *xhTp = p.xhTp->as<float>();
+        double *parts = p.parts->as<double>();
+        // one launch of the phase's kernel
+        auto launch = [&](int q) -> hipError_t {
+            switch (q) {
+            case 0:
+                return exact::launch_forward_residual(G, xp, xTp, Y, p.spec, r, nullptr, skip, own);
+            case 1:
+                return exact::launch_back_update(G, r, inv_n, p.x, gf, nullptr, xhp, xhTp, parts,
+                                                 skip, own);
+            case 2:
+                return exact::launch_forward_residual(G, xhp, xhTp, Y, p.spec, r, nullptr, skip,
+                                                      own);
+            case 3:
+                return exact::launch_back_update(G, r, inv_n, p.x, gf, z.as<float>(),
+                                                 zp.as<float>(), zTp.as<float>(), nullptr, skip,
+                                                 own);
+            default:
+                return exact::launch_eg_finish(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg,
+                                               S, own);
+            }
+        };
+        // two passes over the phases, the first untimed (clocks and caches
+        // settle), the second between the events
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int q = 0; q < EXACT_STEP_PHASES; ++q) {
+                if (pass == 1)
+                    hip_check(hipEventRecord(ev[q], own), "hipEventRecord");
+                for (int k = 0; k < reps; ++k)
+                    hip_check(launch(q), "timed kernel");
+            }
+        }
+        hip_check(hipEventRecord(ev[EXACT_STEP_PHASES], own), "hipEventRecord");
+        hip_check(hipEventRecord(order, own), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(user, order, 0), "hipStreamWaitEvent");
+        hip_check(hipStreamSynchronize(own), "hipStreamSynchronize");
+        for (int q = 0; q < EXACT_STEP_PHASES; ++q) {
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, ev[q], ev[q + 1]), "hipEventElapsedTime");
+            kernel_ms[q] = (double)ms / reps;
         }
         return 0;
     });
@@ -1798,7 +1895,10 @@ int exact_dense_solve(int32_t n, int32_t d, const float *A_dev, const exact_spec
         PinnedState hs;
         SolveState *S = state.as<SolveState>();
         double gamma = o.gamma, lam = 0.0;
-        if (gamma <= 0.0) {
+        if (gamma <= 0.0 && o.lambda_hat > 0.0) {
+            lam = o.lambda_hat;
+            gamma = o.gamma_scale / (lam * sjm);
+        } else if (gamma <= 0.0) {
             // lambda_max(A^T A / n) by power iteration from the constant unit vector
             DevBuf v0((size_t)d * 4), v1((size_t)d * 4);
             hip_check(exact::launch_fill(v0.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st),

@@ -114,50 +114,91 @@ __device__ __forceinline__ void plane_sum(double (&v)[NV], double (*lds)[kRedThr
 // With kGated it runs only while a finish is pending (the single-scan path,
 // where the next step's first kernel or the host settles it) and clears the
 // flag; the batched path runs it unconditionally after every step.
-template <bool kGated>
+//
+// The summation order is that of kRedThreads virtual lanes and does not
+// depend on the launching block's size kThreads (a 1-D block, a multiple
+// of 64 threads): virtual lane l adds partials l, l + kRedThreads, ... in
+// that order (eight loads in flight at a time), a butterfly sums each 64
+// consecutive virtual lanes, and the four group sums are added in order.
+// A block of kThreads < kRedThreads threads runs kRedThreads / kThreads
+// virtual lanes per thread; in a larger block the threads past
+// kRedThreads only take part in the barrier.  So the result is bitwise the
+// same wherever the finish runs (the forward's last workgroup, the host's
+// settle kernel, the batched finish) and whatever the forward's tile knobs.
+template <bool kGated, int kThreads>
 __device__ __forceinline__ void finish_block(const double *__restrict__ partials, int nparts,
                                              const double *__restrict__ avg_parts, int n_avg,
                                              SolveState *st)
 {
+    static_assert(kThreads % 64 == 0 &&
+                      (kThreads >= kRedThreads || kRedThreads % kThreads == 0),
+                  "finish_block: block size");
+    constexpr int kSets = kThreads >= kRedThreads ? 1 : kRedThreads / kThreads;
     if (st->done || (kGated && !st->pending))
         return;
     __shared__ double red[3][kRedThreads / 64];
-    double v3[3] = {0.0, 0.0, 0.0};
-    // a thread's partials q, q + 256, ... are loaded eight at a time, so that
-    // their loads are in flight together, and added in that order (an
-    // absent one adds +0.0: the sums are of squares, so this changes no bit)
-    constexpr int kU = 8;
-    for (int q0 = threadIdx.x; q0 < nparts; q0 += kU * kRedThreads) {
-        double a[kU], b[kU];
+    const int t = threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int q = q0 + u * kRedThreads;
-            a[u] = q < nparts ? partials[2 * q] : 0.0;
-            b[u] = q < nparts ? partials[2 * q + 1] : 0.0;
+    for (int set = 0; set < kSets; ++set) {
+        const int l = t + set * kThreads;           // virtual lane
+        const bool active = l < kRedThreads;
+        double v3[3] = {0.0, 0.0, 0.0};
+        // an absent partial adds +0.0: the sums are of squares, so this
+        // changes no bit
+        constexpr int kU = 8;
+        if (active) {
+            for (int q0 = l; q0 < nparts; q0 += kU * kRedThreads) {
+                double a[kU], b[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int q = q0 + u * kRedThreads;
+                    a[u] = q < nparts ? partials[2 * q] : 0.0;
+                    b[u] = q < nparts ? partials[2 * q + 1] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    v3[0] += a[u];
+                    v3[1] += b[u];
+                }
+            }
+            for (int q0 = l; q0 < n_avg; q0 += kU * kRedThreads) {
+                double a[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int q = q0 + u * kRedThreads;
+                    a[u] = q < n_avg ? avg_parts[q] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    v3[2] += a[u];
+            }
         }
+        // every lane of the wave takes part in the butterfly; the group's
+        // first lane keeps the sum in the group's fixed order
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            v3[0] += a[u];
-            v3[1] += b[u];
+        for (int q = 0; q < 3; ++q)
+            for (int off = 32; off > 0; off >>= 1)
+                v3[q] += __shfl_xor(v3[q], off);
+        if (active && (l & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                red[q][l >> 6] = v3[q];
         }
     }
-    for (int q0 = threadIdx.x; q0 < n_avg; q0 += kU * kRedThreads) {
-        double a[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int q = q0 + u * kRedThreads;
-            a[u] = q < n_avg ? avg_parts[q] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            v3[2] += a[u];
-    }
-    plane_sum<3>(v3, red, true);
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double v3[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < kRedThreads / 64; ++w)
+                s += red[q][w];
+            v3[q] = s;
+        }
         const double rho = v3[1] > 0.0 ? sqrt(v3[0] / v3[1]) : -1.0;
-        const int t = st->t + 1;
+        const int tt = st->t + 1;
         st->rho = rho;
-        st->t = t;
+        st->t = tt;
         bool met;
         if (st->stop_mode == 1) {
             const double crit = sqrt(v3[2]);
@@ -169,7 +210,7 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
         if (st->tol > 0.0 && met) {
             st->converged = 1;
             st->done = 1;
-        } else if (t >= st->max_iters) {
+        } else if (tt >= st->max_iters) {
             st->done = 1;
         }
         if (kGated)
@@ -422,7 +463,8 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     // kernel ends; its other workgroups may compute a residual that no
     // later kernel uses.
     if (kResid && fin.state && blockIdx.x == gridDim.x - 1) {
-        finish_block<true>(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg, fin.state);
+        finish_block<true, kFwdThreads * kSegs>(fin.partials, fin.nparts, fin.avg_parts,
+                                                 fin.n_avg, fin.state);
         if (threadIdx.x == 0 && !fin.state->done)
             fin.state->pending = 1;
     }
@@ -848,7 +890,7 @@ __global__ __launch_bounds__(kRedThreads) void k_eg_finish(const double *__restr
                                                            const double *__restrict__ avg_parts,
                                                            int n_avg, SolveState *st)
 {
-    finish_block<kGated>(partials, nparts, avg_parts, n_avg, st);
+    finish_block<kGated, kRedThreads>(partials, nparts, avg_parts, n_avg, st);
 }
 
 // ------------------------------------------------------ averaged iterate
@@ -975,7 +1017,7 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void kb_back_update(
 __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__restrict__ probs)
 {
     const BatchProb &P = probs[blockIdx.x];
-    finish_block<false>(glob(P.parts), P.ntiles, nullptr, 0, glob(P.state));
+    finish_block<false, kRedThreads>(glob(P.parts), P.ntiles, nullptr, 0, glob(P.state));
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,

@@ -34,7 +34,7 @@ EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_creat
            "exact_geometry_destroy", "exact_forward", "exact_backproject",
            "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
-           "exact_solver_profile", "exact_tv_opts_default", "exact_tv_norm", "exact_tv_prox",
+           "exact_solver_profile", "exact_solver_time_kernels", "exact_tv_opts_default", "exact_tv_norm", "exact_tv_prox",
            "exact_project_tv", "exact_solve_tv", "exact_dense_operator", "exact_dense_solve",
            "exact_count_nonzeros", "exact_run_footprint", "exact_batch_create",
            "exact_batch_add", "exact_batch_step", "exact_batch_sync", "exact_batch_poll",
@@ -67,7 +67,8 @@ class Spectrum(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("gamma", C.c_double), ("gamma_scale", C.c_double),
                 ("max_iters", C.c_int32), ("tol", C.c_double), ("stop_mode", C.c_int32),
-                ("check_every", C.c_int32), ("power_iters", C.c_int32)]
+                ("check_every", C.c_int32), ("power_iters", C.c_int32),
+                ("lambda_hat", C.c_double)]
 
 
 class TvOpts(C.Structure):
@@ -113,6 +114,7 @@ def load():
         "exact_solver_poll": ([vp, C.POINTER(SolveInfo)], C.c_int),
         "exact_solver_destroy": ([vp], C.c_int),
         "exact_solver_profile": ([vp, C.c_int32, C.POINTER(C.c_double), vp], C.c_int),
+        "exact_solver_time_kernels": ([vp, C.c_int32, C.POINTER(C.c_double), vp], C.c_int),
         "exact_count_nonzeros": ([vp, C.POINTER(C.c_int64), vp], C.c_int),
         "exact_run_footprint": ([i32, i32, i32], C.c_size_t),
         "exact_batch_create": ([C.c_size_t, i32, C.POINTER(vp)], C.c_int),
@@ -264,12 +266,13 @@ def exact_step_size(g, mu=None, weight=None, max_iters=100, gamma_scale=0.25, st
 
 
 def _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters,
-          stop_mode=STOP_NATURAL_RESIDUAL):
+          stop_mode=STOP_NATURAL_RESIDUAL, lambda_hat=0.0):
     o = SolveOpts()
     load().exact_solve_opts_default(C.byref(o))
     o.gamma, o.gamma_scale, o.max_iters, o.tol = float(gamma), float(gamma_scale), int(max_iters), float(tol)
     o.check_every, o.power_iters = int(check_every), int(power_iters)
     o.stop_mode = int(stop_mode)
+    o.lambda_hat = float(lambda_hat)
     return o
 
 
@@ -289,10 +292,11 @@ class Solver:
     step(n) enqueues n full extragradient steps on the stream."""
 
     def __init__(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-                 check_every=16, power_iters=100, stream=None, background=None):
+                 check_every=16, power_iters=100, stream=None, background=None, lambda_hat=0.0):
         sp = _Spec(mu, weight, background, g.n)
         self.g, self.x = g, x
-        o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters)
+        o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters,
+                  lambda_hat=lambda_hat)
         h = C.c_void_p()
         _check("exact_solver_create", load().exact_solver_create(
             g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),
@@ -316,6 +320,15 @@ class Solver:
             self.handle, int(n_steps), out, _stream(stream)))
         return list(out)
 
+    def time_kernels(self, reps, stream=None):
+        """Average ms per launch of each of the STEP_PHASES phase kernels,
+        each launched reps times back to back between two HIP events; the
+        run's state is left as it was."""
+        out = (C.c_double * STEP_PHASES)()
+        _check("exact_solver_time_kernels", load().exact_solver_time_kernels(
+            self.handle, int(reps), out, _stream(stream)))
+        return list(out)
+
     def close(self):
         if self.handle is not None and self.handle.value:
             _check("exact_solver_destroy", load().exact_solver_destroy(self.handle))
@@ -336,14 +349,16 @@ class Solver:
 
 def exact_solve(g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
                 check_every=16, power_iters=100, stream=None, stop_mode=STOP_NATURAL_RESIDUAL,
-                background=None):
+                background=None, lambda_hat=0.0):
     """Runs EXACT in place on x.  Returns a dict with iters, resid, gamma,
     lambda_hat, ms and converged (True/False, or None when tol == 0).  With
     stop_mode=STOP_AVERAGED_ITERATE x receives the averaged iterate and tol
     bounds ||xbar_{t+1} - xbar_t|| (absolute).  background: known materials'
-    line integrals per ray (device float32 [V*B]) or None."""
+    line integrals per ray (device float32 [V*B]) or None.  lambda_hat > 0:
+    the geometry's lambda_max, known already, for the automatic step size."""
     sp = _Spec(mu, weight, background, g.n)
-    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters, stop_mode)
+    o = _opts(gamma, gamma_scale, max_iters, tol, check_every, power_iters, stop_mode,
+              lambda_hat=lambda_hat)
     info = SolveInfo()
     code = _check("exact_solve", load().exact_solve(
         g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"), C.byref(o),
@@ -373,9 +388,9 @@ class Batch:
         self._keep = {}
 
     def add(self, g, mu, weight, y, x, gamma=0.0, gamma_scale=0.25, max_iters=500, tol=0.0,
-            power_iters=100, stream=None, background=None):
+            power_iters=100, stream=None, background=None, lambda_hat=0.0):
         sp = _Spec(mu, weight, background, g.n)
-        o = _opts(gamma, gamma_scale, max_iters, tol, 1, power_iters)
+        o = _opts(gamma, gamma_scale, max_iters, tol, 1, power_iters, lambda_hat=lambda_hat)
         slot = C.c_int32(-1)
         _check("exact_batch_add", load().exact_batch_add(
             self.handle, g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),

@@ -1,17 +1,33 @@
 """Continuous-batching request loop for EXACT reconstructions.
 
 Requests (scans with their own geometry, spectrum, counts and tolerance)
-arrive over time.  The loop admits them in arrival order while the sum of
-their device footprints (library state + the iterate and the counts) stays
-within an HBM budget, keeps every admitted scan's counts and iterate
-resident on the device, and advances all admitted scans together, a few
+arrive over time.  The loop keeps every admitted scan's counts and iterate
+resident on the device and advances all admitted scans together, a few
 extragradient steps at a time, in one exact_batch.  Between those chunks it
 retires scans that have stopped (copying the reconstruction to the host and
-freeing their memory) and admits new arrivals, so work of requests that
+freeing their memory) and admits waiting ones, so work of requests that
 arrive while others run overlaps on the device.
 
-Each scan's step size is Theorem 2's rule (paper Sec. 2.1) with
-lambda_max(A^T A / n) computed once per geometry and cached; its iterates are
+Admission has two limits and an order:
+
+* memory: the sum of the admitted scans' device footprints (library state +
+  the iterate and the counts) stays within an HBM budget;
+* work in flight (policy "sjf"): the admitted scans' summed cost of one
+  extragradient step (about the nonzeros of their projectors) stays within
+  `work_cap`, a few times what fills the GPU, so the GPU stays busy while
+  a scan's steps do not slow down by sharing it with every other scan;
+* order (policy "sjf"): the waiting scan with the least expected work goes
+  first (shortest job first): expected steps to its tolerance (the mean of
+  finished scans of the same class, a prior before any) times its step cost.
+  A scan that has waited `max_wait` seconds goes ahead of every younger one,
+  so a large scan is not starved by a stream of small ones.
+
+Policy "fcfs" admits in arrival order with no overtaking and no work cap
+(every scan that fits in memory runs at once).
+
+The step size is Theorem 2's rule (paper Sec. 2.1), computed in the library:
+lambda_max(A^T A / n) is computed once per geometry (exact_step_size) and
+handed to exact_batch_add, which forms gamma; each scan's iterates are
 bitwise those of a solo exact_solve with the same step size.
 
 The scheduler is host logic over a small backend interface (GpuBackend
@@ -53,11 +69,17 @@ class Result:
         return self.admitted - self.arrival
 
 
-def theorem2_gamma(P, lam, c_gamma=0.25):
-    """Step size c / (lambda_max(A^T A / n) sum_k J_k mu_k) of a problem
-    (Theorem 2, paper Sec. 2.1), J_k the window-summed intensities."""
-    J = np.asarray(P.I, dtype=np.float64).reshape(-1, len(P.mu)).sum(axis=0)
-    return c_gamma / (lam * float(np.dot(J, P.mu)))
+def step_cost(P):
+    """Relative cost of one extragradient step of a scan: its projectors'
+    work, about views x bins x image side (the Joseph matrix has about 1.3 N
+    nonzeros per ray), in units of 1e6."""
+    return P.n_views * P.n_bins * P.n_pix * 1e-6
+
+
+def scan_class(req):
+    """Scans whose iteration counts are pooled for the step estimate."""
+    P = req.problem
+    return (P.n_pix, P.n_views, P.n_bins, getattr(P, "I0", None), req.tol)
 
 
 class GpuBackend:
@@ -84,19 +106,16 @@ class GpuBackend:
         return (self.exact.exact_run_footprint(P.n_pix, P.n_views, P.n_bins)
                 + 4 * P.d + 4 * P.Wn * P.n)
 
-    def gamma(self, P, lam):
-        return theorem2_gamma(P, lam)
-
     def add(self, req):
         P = req.problem
         g, lam = self._geometry(P)
         dev = self.torch.device("cuda")
         y = self.torch.as_tensor(np.ascontiguousarray(P.y, dtype=np.float32), device=dev)
         x = self.torch.zeros(P.d, device=dev)
-        gamma = self.gamma(P, lam)
-        slot = self.batch.add(g, P.mu, P.I, y, x, gamma=gamma, max_iters=req.max_iters, tol=req.tol)
+        slot = self.batch.add(g, P.mu, P.I, y, x, lambda_hat=lam, max_iters=req.max_iters,
+                              tol=req.tol)
         self.live[slot] = (x, y)
-        return slot, gamma
+        return slot, self.batch.poll(slot)[1]["gamma"]
 
     def step(self, n):
         self.batch.step(n)
@@ -118,21 +137,62 @@ class GpuBackend:
         self.geoms.clear()
 
 
+class StepEstimate:
+    """Expected steps to tolerance per scan class: the mean over finished
+    scans of the class, else `prior` (per tolerance, else `default`)."""
+
+    def __init__(self, prior=None, default=1000.0):
+        self.prior = dict(prior or {})
+        self.default = float(default)
+        self.sum, self.cnt = {}, {}
+
+    def expect(self, req):
+        c = scan_class(req)
+        if self.cnt.get(c):
+            return self.sum[c] / self.cnt[c]
+        return float(self.prior.get(req.tol, self.default))
+
+    def record(self, req, iters):
+        c = scan_class(req)
+        self.sum[c] = self.sum.get(c, 0.0) + iters
+        self.cnt[c] = self.cnt.get(c, 0) + 1
+
+
 class Server:
-    """Admission by footprint, continuous batching, retirement.
+    """Admission by footprint and policy, continuous batching, retirement.
 
     run(requests) plays the arrival times against `clock` (seconds); with
     realtime=False the clock jumps to the next arrival when the device is
-    idle instead of sleeping."""
+    idle instead of sleeping.  policy "sjf" (default) or "fcfs" as in the
+    module docstring; work_cap in step_cost units (None: no cap); max_wait
+    in seconds."""
 
     def __init__(self, backend, hbm_budget_bytes, chunk_steps=8, realtime=True,
-                 clock=time.perf_counter, on_done=None):
+                 clock=time.perf_counter, on_done=None, policy="sjf", work_cap=None,
+                 max_wait=10.0, estimate=None, cost=step_cost):
+        if policy not in ("sjf", "fcfs"):
+            raise ValueError("policy must be 'sjf' or 'fcfs'")
         self.on_done = on_done      # called with each Result as it completes
         self.backend = backend
         self.budget = int(hbm_budget_bytes)
         self.chunk = int(chunk_steps)
         self.realtime = realtime
         self.clock = clock
+        self.policy = policy
+        self.work_cap = None if policy == "fcfs" else work_cap
+        self.max_wait = float(max_wait)
+        self.estimate = estimate if estimate is not None else StepEstimate()
+        self.cost = cost
+
+    def _next(self, pending, t):
+        """Index in `pending` of the scan to admit next (pending is in
+        arrival order)."""
+        if self.policy == "fcfs":
+            return 0
+        if t - pending[0].arrival >= self.max_wait:
+            return 0                                  # oldest, waited too long
+        work = [self.estimate.expect(r) * self.cost(r.problem) for r in pending]
+        return int(np.argmin(work))                   # ties: earliest arrival
 
     def run(self, requests):
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -140,26 +200,33 @@ class Server:
             if self.backend.footprint(r.problem) > self.budget:
                 raise ValueError("request %d alone exceeds the HBM budget" % r.rid)
         pending, running, results = [], {}, []
-        used, nxt = 0, 0
+        used, load, nxt = 0, 0.0, 0
         t0 = self.clock()
         skew = 0.0                                    # simulated-time advance
         now = lambda: self.clock() - t0 + skew        # noqa: E731
         self.peak_running = 0
+        self.peak_load = 0.0
         while nxt < len(reqs) or pending or running:
             t = now()
             while nxt < len(reqs) and reqs[nxt].arrival <= t:
                 pending.append(reqs[nxt])
                 nxt += 1
-            # admit in arrival order while memory allows (no overtaking)
             while pending:
-                fp = self.backend.footprint(pending[0].problem)
+                i = self._next(pending, t)
+                r = pending[i]
+                fp = self.backend.footprint(r.problem)
+                c = self.cost(r.problem)
                 if used + fp > self.budget:
                     break
-                r = pending.pop(0)
+                if (self.work_cap is not None and running and load + c > self.work_cap):
+                    break
+                pending.pop(i)
                 slot, gamma = self.backend.add(r)
-                running[slot] = (r, now(), fp, gamma)
+                running[slot] = (r, now(), fp, gamma, c)
                 used += fp
+                load += c
             self.peak_running = max(self.peak_running, len(running))
+            self.peak_load = max(self.peak_load, load)
             if not running:
                 if nxt < len(reqs):
                     wait = reqs[nxt].arrival - now()
@@ -174,13 +241,17 @@ class Server:
                 status, info = self.backend.poll(slot)
                 if status == 0:
                     continue
-                r, admitted, fp, gamma = running.pop(slot)
+                r, admitted, fp, gamma, c = running.pop(slot)
                 x = self.backend.retire(slot)
                 used -= fp
+                load -= c
+                self.estimate.record(r, info["iters"])
                 results.append(Result(r.rid, r.arrival, admitted, now(), info["iters"],
                                        info["resid"], status, gamma, x))
                 if self.on_done:
                     self.on_done(results[-1])
+            if not running:
+                load = 0.0                            # no drift from float sums
         return sorted(results, key=lambda z: z.rid)
 
 
@@ -208,6 +279,7 @@ def summarize(results, duration=None):
     return {"requests": len(results),
             "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()),
             "mean_queue_s": float(q.mean()),
             "p99_queue_share": float(q[i99] / lat[i99]) if lat[i99] > 0 else 0.0,
             "recon_per_s": len(results) / span if span > 0 else float("inf"),

@@ -21,6 +21,13 @@ shape classes (256^2 x 180 views x 363 bins, 512^2 x 180 x 725, 1024^2 x
 replays, best of three repeats per pass and of two passes over all
 variants.  A variant replaces the sources' defaults only if it beats them
 by more than 1 % (about the run-to-run spread).
+
+Correctness gate: every variant also runs a short solve (40 steps of the
+256^2 class from x = 0 with Theorem 2's step size); a variant whose iterate
+differs from the default build's by more than 1e-5 relative L2, or whose
+last residual rho differs by more than 1e-4 relative, is rejected (its sums
+run in another order, so bitwise equality is not expected, but a wrong
+reduction or a broken kernel shows far above these bounds).
 """
 import itertools
 import json
@@ -44,6 +51,7 @@ DEFAULT = dict(libbuild.DEFAULT_KNOBS)
 CLASSES = [("256", 256, 180, 363, 30, 3, 1e4, 400), ("512", 512, 180, 725, 30, 3, 1e4, 300),
            ("1024", 1024, 720, 1448, 64, 4, 1e3, 60)]
 MARGIN = 1.01
+GATE_STEPS, GATE_GAMMA = 40, 0.0    # gamma 0: Theorem 2's rule by power iteration
 
 
 def variants():
@@ -104,9 +112,19 @@ def time_one(path):
         sv.close()
         g.close()
         out[name] = best
+    # the correctness gate's short solve
+    name, N, V, B, K, Wn, I0, _ = CLASSES[0]
+    P = synth.make_problem("tune" + name, N, V, B, K, Wn, I0, 20, 7000 + N, 8000 + N,
+                           with_truth=False)
+    g = exact.Geometry(N, V, B)
+    x = torch.zeros(g.d, device="cuda")
+    info = exact.exact_solve(g, P.mu, P.I, torch.as_tensor(P.y, device="cuda"), x,
+                             gamma=GATE_GAMMA, max_iters=GATE_STEPS)
+    gate = {"x": x.cpu().numpy().astype("float64").tolist(), "rho": info["resid"]}
+    g.close()
     prop = torch.cuda.get_device_properties(0)
     dev = "%s (%s)" % (prop.name, getattr(prop, "gcnArchName", "?"))
-    print(json.dumps({"ms": out, "device": dev}), flush=True)
+    print(json.dumps({"ms": out, "device": dev, "gate": gate}), flush=True)
 
 
 def cmd_time(report=None, passes=2, per_run_timeout=300):
@@ -126,14 +144,25 @@ def cmd_time(report=None, passes=2, per_run_timeout=300):
                 raise SystemExit("timing run of %s failed (exit %d)" % (t, res.returncode))
             rec = json.loads(res.stdout.strip().splitlines()[-1])
             device = rec["device"]
+            r["gate"] = rec["gate"]
             for c, ms in rec["ms"].items():
                 r["ms"][c] = min(r["ms"].get(c, math.inf), ms)
             print("[tune]   %s" % " ".join("%s:%.4f" % kv for kv in sorted(rec["ms"].items())),
                   flush=True)
-    for r in rows.values():
-        r["score"] = math.exp(sum(math.log(1e3 / ms) for ms in r["ms"].values()) / len(r["ms"]))
-    best = max(rows.values(), key=lambda r: r["score"])
     base = rows[tag(DEFAULT)]
+    xb = base["gate"]["x"]
+    nb = math.sqrt(sum(v * v for v in xb))
+    for t, r in rows.items():
+        r["score"] = math.exp(sum(math.log(1e3 / ms) for ms in r["ms"].values()) / len(r["ms"]))
+        dx = math.sqrt(sum((a - b) ** 2 for a, b in zip(r["gate"]["x"], xb))) / nb
+        drho = abs(r["gate"]["rho"] - base["gate"]["rho"]) / abs(base["gate"]["rho"])
+        r["gate_ok"] = dx <= 1e-5 and drho <= 1e-4
+        if not r["gate_ok"]:
+            print("[tune] %s rejected: iterate differs by %.2e, rho by %.2e" % (t, dx, drho),
+                  flush=True)
+            r["score"] = 0.0
+        del r["gate"]
+    best = max(rows.values(), key=lambda r: r["score"])
     chosen = best if best["score"] > MARGIN * base["score"] else base
     rec = {"knobs": chosen["knobs"], "score_steps_per_s": chosen["score"],
            "default_score_steps_per_s": base["score"], "best": tag(best["knobs"]),

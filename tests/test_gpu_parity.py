@@ -126,11 +126,46 @@ def test_projectors_sampled_full_size(ex, ora, name):
     img = torch.empty(g.d, device=DEV)
     ex.exact_backproject(g, t32(r), img)
     pix = np.unique(np.concatenate([rng.integers(0, g.d, 48), [0, P.n_pix - 1, g.d - 1,
-                                                               g.d // 2 + P.n_pix // 2]]))
+                                                               g.d // 2 + P.n_pix // 2],
+                                    whole_tiles(P.n_pix), near_integer_bins(P, 300, rng)]))
+    say("  back-projection: %d pixels (5 whole 16x16 tiles, pixels on bin boundaries)"
+        % pix.size)
     g_ora = ora.back_pixels(go, r, pix)
     scale = ora.back_pixels(go, np.abs(r), pix)
     within(np64(img)[pix], g_ora, scale)
     g.close()
+
+
+def whole_tiles(N, T=16):
+    """Every pixel of the back-projector's 16 x 16 tiles at the four corners
+    and the centre of the image (the corner tiles hold the image's last row
+    and column)."""
+    c = (N // 2) // T * T
+    out = []
+    for ty, tx in [(0, 0), (0, N - T), (N - T, 0), (N - T, N - T), (c, c)]:
+        iy, ix = np.meshgrid(np.arange(ty, ty + T), np.arange(tx, tx + T), indexing="ij")
+        out.append((iy * N + ix).ravel())
+    return np.concatenate(out)
+
+
+def near_integer_bins(P, count, rng):
+    """Pixels whose centre projects to within 1e-3 bin of a bin centre for
+    some view (the bin pair's boundary: the tent weights there are 1 and 0,
+    and the gather picks the pair by truncating t), `count` of them drawn
+    with rng.  Geometry as in the header: pixel centres ((ix - c) d,
+    (iy - c) d), c = (N - 1)/2; view v at pi v / V; bin coordinate
+    t = <centre, (cos, sin)> / bin + (B - 1)/2."""
+    N, V, B = P.n_pix, P.n_views, P.n_bins
+    c = (N - 1) / 2.0
+    xi = (np.arange(N) - c) * P.pixel_cm
+    hits = []
+    for v in range(0, V, max(1, V // 120)):
+        th = np.pi * v / V
+        t = (xi[None, :] * np.cos(th) + xi[:, None] * np.sin(th)) / P.bin_cm + (B - 1) / 2.0
+        near = np.abs(t - np.round(t)) <= 1e-3
+        hits.append(np.flatnonzero(near.ravel()))
+    hits = np.unique(np.concatenate(hits))
+    return rng.choice(hits, size=min(count, hits.size), replace=False)
 
 
 @pytest.mark.parametrize("case", [("tiny", 16, 12, 24, 1.0, 1), ("ragged", 21, 7, 31, 1.0, 1),
@@ -241,9 +276,17 @@ def _problem(ex, ora, name, **over):
     return P, g, go
 
 
-@pytest.mark.parametrize("name", ["small_64", "solve_512"])
+# (config, overrides): the large workload's spectrum and dose (K = 64, Wn = 4,
+# I0 = 1e3) at a reduced size, so every pixel can be checked
+OPERATOR_CASES = {"small_64": ("small_64", {}), "solve_512": ("solve_512", {}),
+                  "lowdose_256": ("large_1024", dict(n_pix=256, n_views=180, n_bins=363,
+                                                     n_ell=20))}
+
+
+@pytest.mark.parametrize("name", sorted(OPERATOR_CASES))
 def test_operator_parity(ex, ora, name):
-    P, g, go = _problem(ex, ora, name)
+    cfg, over = OPERATOR_CASES[name]
+    P, g, go = _problem(ex, ora, cfg, **over)
     say("operator", name, P.n_pix, P.n_views, P.n_bins, P.K, P.Wn)
     y64 = P.y.astype(np.float64)
     x = (0.9 * P.x_true).astype(np.float32)
@@ -373,6 +416,67 @@ def test_solve_parity_mid_128(ex, ora):
     assert rel <= 1e-4
 
 
+def test_solve_parity_lowdose_256(ex, ora):
+    """The large workload's spectrum and dose (K = 64 energy bins, 4 windows,
+    I0 = 1e3) at 256^2 x 180 views: 50 steps."""
+    rel = _solve_case(ex, ora, "large_1024", 50, power=False, n_pix=256, n_views=180,
+                      n_bins=363, n_ell=20)
+    assert rel <= 1e-4
+
+
+def _golden(name):
+    """Header values and [section] rows of a stored oracle run."""
+    head, sec, cur = {}, {}, None
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        if line.startswith("["):
+            cur = line.strip("[]")
+            sec[cur] = []
+        elif "=" in line and cur is None:
+            k, v = line.split("=")
+            head[k.strip()] = float(v)
+        else:
+            sec[cur].append([float(t) for t in line.split()])
+    return head, {k: np.array(v) for k, v in sec.items()}
+
+
+def test_large_1024_against_stored_oracle_run(ex):
+    """The large low-dose workload at full size (1024^2, 720 views, 1448
+    bins, K = 64, Wn = 4, I0 = 1e3) against the oracle's values stored in
+    tests/golden/large_1024.txt (written by make_large_1024.py from the
+    oracle alone): the operator and the residual at x = float32(0.9 x_true)
+    per element at the parity bar on 4096 sampled pixels and rays, and three
+    EG steps from x = 0 (the step size stored with them) at 1e-4 relative
+    L2 over the sampled pixels."""
+    head, sec = _golden("large_1024.txt")
+    P = synth.config_problem("large_1024", with_truth=True)
+    assert float(P.y.astype(np.float64).sum()) == head["y_sum"]
+    say("large_1024 vs stored oracle run", P.n_pix, P.n_views, P.n_bins)
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    F = torch.empty(g.d, device=DEV)
+    r = torch.empty(g.n, device=DEV)
+    ex.exact_operator(g, P.mu, P.I, t32(P.y), t32((0.9 * P.x_true).astype(np.float32)), F, r)
+    fp = sec["F"]
+    within(np64(F)[fp[:, 0].astype(np.int64)], fp[:, 1], fp[:, 2])
+    rr = sec["r"]
+    within(np64(r)[rr[:, 0].astype(np.int64)], rr[:, 1], rr[:, 2])
+    x = torch.zeros(g.d, device=DEV)
+    steps = int(head["steps"])
+    info = ex.exact_solve(g, P.mu, P.I, t32(P.y), x, gamma=head["gamma"], max_iters=steps)
+    assert info["iters"] == steps
+    xs = np64(x)
+    xp = sec["x"]
+    pix, val = xp[:, 0].astype(np.int64), xp[:, 1]
+    rel = np.linalg.norm(xs[pix] - val) / np.linalg.norm(val)
+    nrm = abs(np.linalg.norm(xs) - head["x_norm"]) / head["x_norm"]
+    print("  %d steps: sampled rel L2 %.3e, norm rel %.3e (oracle float build drift %.3e)"
+          % (steps, rel, nrm, head["f32_rel_l2"]), flush=True)
+    assert rel <= 1e-4 and nrm <= 1e-4
+    g.close()
+
+
 def test_solve_parity_narrow_detector(ex, ora):
     """A detector narrower than the image: the update kernels take the
     clamped pair rule."""
@@ -407,8 +511,11 @@ def test_solve_stop_rule(ex, ora):
     assert info["converged"]
     assert info["resid"] <= tol
     assert abs(info["iters"] - t_ora) <= 1, (info["iters"], t_ora)
-    if info["iters"] == t_ora:
-        assert np.linalg.norm(np64(x) - x_ora) <= 1e-4 * np.linalg.norm(x_ora)
+    # the iterate against the oracle's run of exactly the GPU's step count
+    # (the same as x_ora when the stop steps coincide)
+    x_at, _, _ = ora.eg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d), gamma,
+                        info["iters"])
+    assert np.linalg.norm(np64(x) - x_at) <= 1e-4 * np.linalg.norm(x_at)
     # a cap below the stopping step reports non-convergence
     x2 = torch.zeros(g.d, device=DEV)
     info2 = ex.exact_solve(g, P.mu, P.I, t32(P.y), x2, gamma=gamma, max_iters=5, tol=tol)
@@ -466,8 +573,11 @@ def test_solve_averaged_stop_rule(ex, ora, small_gamma):
                           stop_mode=ex.STOP_AVERAGED_ITERATE, check_every=5)
     assert info["converged"] and info["resid"] <= tol
     assert abs(info["iters"] - t_ora) <= 2, (info["iters"], t_ora)
-    if info["iters"] == t_ora:
-        assert np.linalg.norm(np64(x) - xb_ora) <= 1e-4 * np.linalg.norm(xb_ora)
+    # the averaged iterate against the oracle's of exactly the GPU's step count
+    xb_at, t_at, _, _ = ora.eg_avg(go, P.mu, P.I, P.y.astype(np.float64), np.zeros(g.d),
+                                   small_gamma, info["iters"])
+    assert t_at == info["iters"]
+    assert np.linalg.norm(np64(x) - xb_at) <= 1e-4 * np.linalg.norm(xb_at)
     g.close()
 
 

@@ -46,6 +46,20 @@ def test_opts_defaults(lib):
     lib.exact_solve_opts_default(C.byref(o))
     assert o.gamma == 0.0 and o.gamma_scale == 0.25 and o.max_iters == 500
     assert o.tol == 0.0 and o.stop_mode == 0 and o.check_every == 16 and o.power_iters == 100
+    assert o.lambda_hat == 0.0
+
+
+def test_negative_lambda_hat_rejected(lib):
+    """A given lambda_max must be finite and >= 0 (checked before any device
+    work: the geometry handle is not even looked at first)."""
+    from paper_2503_19925_amd.exact import SolveOpts
+    o = SolveOpts()
+    lib.exact_solve_opts_default(C.byref(o))
+    for bad in (-1.0, float("nan"), float("inf")):
+        o.lambda_hat = bad
+        assert lib.exact_dense_solve(4, 2, C.c_void_p(16), None, None, C.c_void_p(16),
+                                     C.byref(o), 0.0, None, None) == -errno.EINVAL
+        assert "lambda_hat" in lib.exact_last_error().decode()
 
 
 @pytest.mark.parametrize("args", [
@@ -121,6 +135,7 @@ def test_solver_profile_rejects_bad_arguments(lib):
     import ctypes
     out = (ctypes.c_double * 5)()
     assert lib.exact_solver_profile(None, 3, out, None) == -errno.EINVAL
+    assert lib.exact_solver_time_kernels(None, 3, out, None) == -errno.EINVAL
 
 
 def test_tv_entry_points_reject_bad_arguments(lib):

@@ -612,6 +612,62 @@ def test_tv_ball_search(ora):
     np.testing.assert_array_equal(x, v)
 
 
+def _tv_case(N=24):
+    P = synth.make_problem("tv", N, 10, synth.bins_for(N), 5, 1, 1e4, 5, 51, 52)
+    rng = np.random.default_rng(42)
+    return P.x_true + rng.normal(scale=0.2, size=N * N)
+
+
+@pytest.mark.parametrize("frac", [0.2, 0.5, 0.8])
+def test_tv_ball_hit_is_within_tol_on_both_sides(ora, frac):
+    """Sec. 5: the search stops at the first weight whose regularized point
+    has |TV - tau| <= tv_tol.  With the default 40 midpoints these cases end
+    on a hit, so the result's TV is within tv_tol of tau on both sides, and
+    the result is the regularized point at the returned weight (recomputed
+    with tv_prox, which is pinned on its own above)."""
+    v = _tv_case()
+    tau = frac * ora.tv_norm(v)
+    x, lam, ns = ora.tv_ball(v, tau)
+    t = ora.tv_norm(x)
+    assert tau - 0.01 <= t <= tau + 0.01, (t, tau)
+    np.testing.assert_array_equal(x, ora.tv_prox(v, lam))
+    # a tighter tolerance needs at least as many solves and still hits
+    x2, lam2, ns2 = ora.tv_ball(v, tau, tv_tol=1e-4)
+    assert abs(ora.tv_norm(x2) - tau) <= 1e-4 and ns2 >= ns
+
+
+def test_tv_ball_doubling_and_no_hit_branch(ora):
+    """Without midpoints (max_bisect 0) the result is xbar(hi) for the first
+    hi = 2^k, k >= 0, whose regularized point lies in the ball: hi is a power
+    of two, TV(xbar(hi)) <= tau and, unless hi = 1, TV(xbar(hi / 2)) > tau.
+    With one midpoint the rule is: a hit or TV <= tau at mid returns
+    xbar(mid), TV > tau returns xbar(hi)."""
+    v = _tv_case()
+    tv_v = ora.tv_norm(v)
+    for frac in (0.05, 0.3, 0.7, 0.95):
+        tau = frac * tv_v
+        x, hi, ns = ora.tv_ball(v, tau, max_bisect=0)
+        k = int(round(np.log2(hi)))
+        assert hi == 2.0 ** k and k >= 0 and ns == k + 1
+        np.testing.assert_array_equal(x, ora.tv_prox(v, hi))
+        assert ora.tv_norm(x) <= tau
+        if k > 0:
+            assert ora.tv_norm(ora.tv_prox(v, hi / 2)) > tau
+        # one midpoint
+        x1, lam1, ns1 = ora.tv_ball(v, tau, max_bisect=1)
+        lo = hi / 2 if k > 0 else 0.0
+        mid = (lo + hi) / 2
+        xm = ora.tv_prox(v, mid)
+        tm = ora.tv_norm(xm)
+        assert ns1 == ns + 1
+        if abs(tm - tau) <= 0.01 or tm <= tau:
+            assert lam1 == mid
+            np.testing.assert_array_equal(x1, xm)
+        else:
+            assert lam1 == hi
+            np.testing.assert_array_equal(x1, x)
+
+
 def test_tv_orthant_projection_properties(ora):
     """Dykstra's projection onto {TV <= tau} and the orthant: the result is
     feasible (x >= 0, TV <= tau + tv_tol) and satisfies the projection
@@ -740,6 +796,25 @@ def test_dense_ball_constraint(ora):
 
 
 # ------------------------------------------------- the oracle's own rounding
+
+def test_long_double_operator_at_512(ora):
+    """The oracle's own error for one F at the 512^2 workload (512^2 image,
+    180 views, 725 bins, K = 30, Wn = 3): the double build against the same
+    text in x87 long double, per pixel, relative to the per-pixel scale
+    (1/n) A^T (Y + m) of the GPU parity bar.  Measured below 1e-15; the bar
+    here is 1e-12."""
+    P = synth.config_problem("solve_512", with_truth=True)
+    g = ora.Geom(P.n_pix, P.n_views, P.n_bins)
+    y = P.y.astype(np.float64)
+    x = (0.9 * P.x_true).astype(np.float32).astype(np.float64)
+    F64, s64, _ = ora.operator(g, P.mu, P.I, y, x, want_sr=True)
+    Fld = ora.operator(g, P.mu, P.I, y, x, prec="ld")
+    _, m = ora.residual(s64, P.mu, P.I, y)
+    scale = ora.back(g, y.reshape(P.Wn, -1).sum(0) + m) / g.n
+    err = np.abs(F64 - Fld) / scale
+    print("  long double vs double, F at 512^2: max %.2e of the per-pixel scale" % err.max())
+    assert err.max() <= 1e-12
+
 
 def test_long_double_agreement(ora):
     """The same oracle text in x87 long double: the double version's error is

@@ -1,11 +1,12 @@
 """Host logic of the request loop (paper_2503_19925_amd.serve) on the CPU,
-with a fake backend: admission in arrival order under an HBM budget,
+with a fake backend: admission under an HBM budget (in arrival order, or
+shortest expected work first under a cap on work in flight, with aging),
 retirement, timing and the summary."""
 from types import SimpleNamespace
 
 import pytest
 
-from paper_2503_19925_amd.serve import Request, Server, summarize
+from paper_2503_19925_amd.serve import Request, Server, StepEstimate, summarize
 
 
 class FakeClock:
@@ -53,14 +54,16 @@ class FakeBackend:
         return None
 
 
-def req(rid, arrival, fp, need):
-    return Request(rid, arrival, SimpleNamespace(fp=fp, need=need), tol=1e-4)
+def req(rid, arrival, fp, need, cost=1.0, tol=1e-4):
+    P = SimpleNamespace(fp=fp, need=need, cost=cost, n_pix=need, n_views=1, n_bins=1, I0=1.0)
+    return Request(rid, arrival, P, tol=tol)
 
 
-def make(budget, chunk=4):
+def make(budget, chunk=4, policy="fcfs", **kw):
     clock = FakeClock()
     be = FakeBackend(clock)
-    return Server(be, budget, chunk_steps=chunk, realtime=False, clock=clock), be
+    return Server(be, budget, chunk_steps=chunk, realtime=False, clock=clock, policy=policy,
+                  cost=lambda P: P.cost, **kw), be
 
 
 def test_admission_respects_budget_and_order():
@@ -105,3 +108,61 @@ def test_summary_percentiles():
     s = summarize(res)
     assert abs(s["p50_s"] - 0.0505) < 2e-3 and s["p99_s"] <= 0.1 + 1e-9
     assert s["mean_iters"] == pytest.approx(50.5)
+
+
+def test_sjf_admits_least_expected_work_first():
+    """Expected work = expected steps (prior per tolerance) x step cost: the
+    cheapest waiting scan goes first, ties in arrival order."""
+    srv, be = make(budget=10 ** 6, policy="sjf", work_cap=1.0,
+                   estimate=StepEstimate(prior={1e-3: 100, 1e-4: 1000}))
+    reqs = [req(0, 0.0, 1, 40, cost=1.0, tol=1e-4),     # 1000
+            req(1, 0.0, 1, 40, cost=4.0, tol=1e-3),     # 400
+            req(2, 0.0, 1, 40, cost=1.0, tol=1e-3),     # 100
+            req(3, 0.0, 1, 40, cost=1.0, tol=1e-3)]     # 100
+    srv.run(reqs)
+    assert be.order == [2, 3, 1, 0]
+    assert be.max_live == 1                       # the cap holds one scan of cost >= 1
+
+
+def test_sjf_work_cap_and_first_admission():
+    """Scans are admitted while their summed step cost stays within the cap;
+    a scan costlier than the cap still runs when nothing else does."""
+    srv, be = make(budget=10 ** 6, policy="sjf", work_cap=3.0)
+    reqs = [req(i, 0.0, 1, 20, cost=1.0) for i in range(5)] + [req(5, 0.0, 1, 20, cost=7.0)]
+    res = srv.run(reqs)
+    assert be.max_live == 3 and srv.peak_load <= 7.0
+    assert all(r.status == 1 for r in res)
+    assert be.order[-1] == 5
+
+
+def test_sjf_learns_step_counts_per_class():
+    """After a scan of a class finishes, its measured steps replace the prior."""
+    est = StepEstimate(default=1000.0)
+    srv, be = make(budget=10 ** 6, policy="sjf", work_cap=1.0, estimate=est)
+    a = req(0, 0.0, 1, 8, cost=1.0)
+    srv.run([a])
+    assert est.expect(a) == 8
+    b = req(1, 0.0, 1, 500, cost=1.0)             # another class (n_pix differs)
+    assert est.expect(b) == 1000.0
+
+
+def test_sjf_aging_admits_a_starved_scan():
+    """A large scan overtaken by a stream of small ones goes first once it has
+    waited max_wait seconds."""
+    srv, be = make(budget=10 ** 6, policy="sjf", work_cap=1.0, max_wait=0.05, chunk=4,
+                   estimate=StepEstimate(prior={1e-4: 1000, 1e-3: 4}))
+    big = req(0, 0.0, 1, 40, cost=1.0, tol=1e-4)
+    small = [req(1 + i, 0.0, 1, 4, cost=0.5, tol=1e-3) for i in range(60)]
+    srv.run([big] + small)
+    pos = be.order.index(0)
+    # 4 ms per chunk, 2 small scans of 4 steps per chunk: 50 ms is ~25 chunks
+    assert 0 < pos < 60
+    srv2, be2 = make(budget=10 ** 6, policy="sjf", work_cap=1.0, max_wait=1e9, chunk=4,
+                     estimate=StepEstimate(prior={1e-4: 1000, 1e-3: 4}))
+    srv2.run([big] + small)
+    assert be2.order.index(0) == 60               # without aging it goes last
+
+
+def test_policy_is_checked():
+    with pytest.raises(ValueError):
+        Server(None, 1, policy="lifo")
