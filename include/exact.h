@@ -181,6 +181,26 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp,
                    float *r_dev, void *stream);
 
 /*
+ * exact_operator for callers that cannot allocate device memory during the
+ * call: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results (bitwise) and stream ordering
+ * as exact_operator, and no allocation of any kind on the device: the
+ * call's scratch (the window sums of y, the padded image and its transpose,
+ * the padded residual) lives in a static device array of
+ * EXACT_NOALLOC_SCRATCH_MIB MiB, one per GPU the library runs on, held
+ * until the process ends.  Needs 4 (V B + 2 N (N + 4) + V (B + 4)) bytes
+ * (each part rounded up to 256) of it, else -ENOSPC (1024^2 with 720 views
+ * x 1448 bins needs 17 MB).  The geometry must belong to the current
+ * device (-EINVAL).  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (the call clears what must start at zero):
+ * calls that overlap on one GPU (on different streams or threads) race, so
+ * the caller serialises them.
+ */
+#define EXACT_NOALLOC_SCRATCH_MIB 32
+int exact_operator_noalloc(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
+                           const float *x_dev, float *F_dev, float *r_dev, void *stream);
+
+/*
  * lambda_max(Sigma), Sigma = A^T A / n (paper Sec. 1.3), by power iteration
  * from the constant vector with double-precision Rayleigh quotients (at
  * most max_iters steps, stopping when the quotient changes by less than

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -587,6 +588,85 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp, const float *y_de
                   "forward_residual");
         hip_check(exact::launch_back(geo_of(g), rp.as<float>(), F_dev, (float)(1.0 / (double)n),
                                      nullptr, st),
+                  "back");
+        return 0;
+    });
+}
+
+}  // extern "C"
+
+// Scratch of exact_operator_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name
+// as an address (in host code it is a stand-in, not device memory): the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and is kept below.
+namespace {
+constexpr size_t kNoAllocBytes = (size_t)EXACT_NOALLOC_SCRATCH_MIB << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;      // per device ordinal, null until looked up
+
+// The calling thread's current device's copy of `scratch`.
+unsigned char *scratch_on(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)device >= g_scratch_ptr.size())
+        g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)device]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!ptr)
+            fail(-EIO, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[(size_t)device] = ptr;
+    }
+    return static_cast<unsigned char *>(g_scratch_ptr[(size_t)device]);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" {
+
+int exact_operator_noalloc(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
+                           const float *x_dev, float *F_dev, float *r_dev, void *stream)
+{
+    return guarded([&]() -> int {
+        check_geometry(g);
+        if (!y_dev || !x_dev || !F_dev)
+            fail(-EINVAL, "NULL buffer");
+        const SpecArg a = make_spec(sp, nullptr);
+        int device = -1;
+        hip_check(hipGetDevice(&device), "hipGetDevice");
+        if (device != g->device)
+            fail(-EINVAL, "the geometry was created on device " + std::to_string(g->device) +
+                              ", the current device is " + std::to_string(device));
+        const long n = (long)g->V * g->B;
+        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t np = (size_t)g->V * exact::padded_bins(g->B);
+        const size_t oY = 0, oxp = align256(4 * (size_t)n), oxTp = oxp + align256(4 * dp),
+                     orp = oxTp + align256(4 * dp), need = orp + align256(4 * np);
+        if (need > kNoAllocBytes)
+            fail(-ENOSPC, "exact_operator_noalloc needs " + std::to_string(need) +
+                              " bytes of scratch; the static array holds " +
+                              std::to_string(kNoAllocBytes));
+        unsigned char *base = scratch_on(device);
+        float *Y = reinterpret_cast<float *>(base + oY);
+        float *xp = reinterpret_cast<float *>(base + oxp);
+        float *xTp = reinterpret_cast<float *>(base + oxTp);
+        float *rp = reinterpret_cast<float *>(base + orp);
+        hipStream_t st = (hipStream_t)stream;
+        // the array keeps the previous call's contents: the padding the
+        // projectors read must be zero again (fill kernels, not memsets, so
+        // that the call can be captured into a graph)
+        hip_check(exact::launch_fill(xp, 0.f, (long)dp, st), "fill");
+        hip_check(exact::launch_fill(xTp, 0.f, (long)dp, st), "fill");
+        hip_check(exact::launch_fill(rp, 0.f, (long)np, st), "fill");
+        hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, Y, nullptr, st), "window_sum");
+        hip_check(exact::launch_pad_pair(x_dev, xp, xTp, g->N, st), "pad_pair");
+        hip_check(exact::launch_forward_residual(geo_of(g), xp, xTp, Y, a, rp, r_dev, nullptr, st),
+                  "forward_residual");
+        hip_check(exact::launch_back(geo_of(g), rp, F_dev, (float)(1.0 / (double)n), nullptr, st),
                   "back");
         return 0;
     });

@@ -32,7 +32,7 @@ EXACT_ENOTCONV = 1
 
 EXPORTS = ("exact_solve_opts_default", "exact_last_error", "exact_geometry_create",
            "exact_geometry_destroy", "exact_forward", "exact_backproject",
-           "exact_operator", "exact_step_size", "exact_solve", "exact_solver_create",
+           "exact_operator", "exact_operator_noalloc", "exact_step_size", "exact_solve", "exact_solver_create",
            "exact_solver_step", "exact_solver_poll", "exact_solver_destroy",
            "exact_solver_profile", "exact_solver_time_kernels", "exact_tv_opts_default", "exact_tv_norm", "exact_tv_prox",
            "exact_project_tv", "exact_solve_tv", "exact_dense_operator", "exact_dense_solve",
@@ -104,6 +104,7 @@ def load():
         "exact_forward": ([vp, vp, vp, vp], C.c_int),
         "exact_backproject": ([vp, vp, vp, vp], C.c_int),
         "exact_operator": ([vp, C.POINTER(Spectrum), vp, vp, vp, vp, vp], C.c_int),
+        "exact_operator_noalloc": ([vp, C.POINTER(Spectrum), vp, vp, vp, vp, vp], C.c_int),
         "exact_step_size": ([vp, C.POINTER(Spectrum), i32, dbl, C.POINTER(dbl),
                              C.POINTER(dbl), vp], C.c_int),
         "exact_solve": ([vp, C.POINTER(Spectrum), vp, vp, C.POINTER(SolveOpts),
@@ -251,6 +252,16 @@ def exact_backproject(g, r, img, stream=None):
 def exact_operator(g, mu, weight, y, x, F, r=None, stream=None, background=None):
     sp = _Spec(mu, weight, background, g.n)
     _check("exact_operator", load().exact_operator(
+        g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),
+        _dev(F, g.d, "F"), None if r is None else _dev(r, g.n, "r"), _stream(stream)))
+    return F
+
+
+def exact_operator_noalloc(g, mu, weight, y, x, F, r=None, stream=None, background=None):
+    """exact_operator with its scratch in the library's static device array
+    (no device allocation in the call); calls on one GPU must not overlap."""
+    sp = _Spec(mu, weight, background, g.n)
+    _check("exact_operator_noalloc", load().exact_operator_noalloc(
         g.handle, C.byref(sp.s), _dev(y, sp.Wn * g.n, "y"), _dev(x, g.d, "x"),
         _dev(F, g.d, "F"), None if r is None else _dev(r, g.n, "r"), _stream(stream)))
     return F

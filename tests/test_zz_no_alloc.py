@@ -1,0 +1,73 @@
+"""exact_operator_noalloc (the operator with its scratch in a static device
+array, for callers that cannot allocate) against exact_operator through the
+C ABI: bitwise equal results on two calls in a row, the second on a smaller
+geometry (the array keeps the first call's contents, so this checks that
+the call clears what must read zero), with and without a known background;
+an input beyond the array's size is refused."""
+import errno
+
+import numpy as np
+import pytest
+
+from paper_2503_19925_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ex():
+    from paper_2503_19925_amd import exact
+    exact.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return exact
+
+
+def _pair(ex, P, background=None):
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    y = torch.as_tensor(P.y, device=DEV)
+    x = torch.as_tensor((0.9 * P.x_true).astype(np.float32), device=DEV)
+    bg = None if background is None else torch.as_tensor(background, device=DEV)
+    F1, F2 = torch.empty(g.d, device=DEV), torch.full((g.d,), np.nan, device=DEV)
+    r1, r2 = torch.empty(g.n, device=DEV), torch.full((g.n,), np.nan, device=DEV)
+    ex.exact_operator(g, P.mu, P.I, y, x, F1, r1, background=bg)
+    ex.exact_operator_noalloc(g, P.mu, P.I, y, x, F2, r2, background=bg)
+    torch.cuda.synchronize()
+    g.close()
+    return F1, F2, r1, r2
+
+
+def test_noalloc_operator_equals_operator_twice(ex):
+    big = synth.config_problem("small_64", n_pix=160, n_views=90, n_bins=227)
+    small = synth.config_problem("small_64")
+    for P in (big, small):
+        say("noalloc operator", P.n_pix, P.n_views, P.n_bins)
+        F1, F2, r1, r2 = _pair(ex, P)
+        assert torch.equal(F1, F2) and torch.equal(r1, r2), P.n_pix
+    Pb = synth.with_background(small)
+    say("noalloc operator with background", Pb.n_pix)
+    F1, F2, r1, r2 = _pair(ex, Pb, Pb.bg.astype(np.float32))
+    assert torch.equal(F1, F2) and torch.equal(r1, r2)
+
+
+def test_noalloc_operator_refuses_oversized_input(ex):
+    mib = 32
+    # padded pair alone: 2 N (N + 4) floats > 32 MiB for N = 2048
+    N, V, B = 2048, 4, 2897
+    say("noalloc operator oversized", N, V, B)
+    g = ex.Geometry(N, V, B)
+    y = torch.ones(V * B, device=DEV)
+    x = torch.zeros(N * N, device=DEV)
+    F = torch.empty(N * N, device=DEV)
+    with pytest.raises(ex.ExactError) as e:
+        ex.exact_operator_noalloc(g, [0.2], [1.0], y, x, F)
+    assert e.value.code == -errno.ENOSPC
+    assert str(mib << 20) in str(e.value)
+    g.close()
