@@ -49,11 +49,19 @@ def defines(knobs):
     return ["-D%s=%d" % (k, knobs[k]) for k in sorted(knobs)]
 
 
+# sources whose text decides what the step's kernels do (the kernels, the
+# shared declarations, and the host code that builds the kernels' tables and
+# work lists)
+KERNEL_SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_internal.h", "csrc/exact_capi.hip"]
+
+
 def build_id(knobs=None):
-    """SHA-1 of the kernel source and the knob values it is compiled with:
+    """SHA-1 of the kernel sources and the knob values they are compiled with:
     what a stored hardware-counter reading is valid for."""
     knobs = tuned_knobs() if knobs is None else knobs
-    h = hashlib.sha1(open(os.path.join(HERE, SOURCES[0]), "rb").read())
+    h = hashlib.sha1()
+    for src in KERNEL_SOURCES:
+        h.update(open(os.path.join(HERE, src), "rb").read())
     h.update(" ".join(defines(knobs)).encode())
     return h.hexdigest()
 

@@ -81,6 +81,15 @@ __device__ __forceinline__ int clamp_int(int v, int hi)
     return r;
 }
 
+// min(max(v, lo), hi) for lo <= hi with lo wave-uniform (a scalar register)
+// in one instruction.
+[[maybe_unused]] __device__ __forceinline__ int clamp_int_s(int v, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "s"(lo), "v"(hi));
+    return r;
+}
+
 // Fixed-order sum over the kRedThreads threads of the block's x-y plane
 // with one barrier: a butterfly within each wave, then the four wave sums in
 // order.  Threads with active = false (other z planes) contribute nothing
@@ -220,10 +229,7 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
 
 // ---------------------------------------------------------------- forward
 
-#ifndef EXACT_FWD_SEGS
-#define EXACT_FWD_SEGS 4
-#endif
-constexpr int kSegs = EXACT_FWD_SEGS;   // waves per forward workgroup, each a share of the lines
+constexpr int kSegs = kFwdSegs;   // waves per forward workgroup, each a share of the lines
 
 // Bin block of rank r when the blocks of a view are taken centre-out (the
 // central blocks hold the longest chords): c, c-1, c+1, c-2, ... with
@@ -234,13 +240,10 @@ __device__ __host__ __forceinline__ int centre_out(int r, int nbb)
     return (r % 2 == 0) ? c + r / 2 : c - (r + 1) / 2;
 }
 
-#ifndef EXACT_LINE_BATCH
-#define EXACT_LINE_BATCH 4
-#endif
 #ifndef EXACT_VIEW_BATCH
 #define EXACT_VIEW_BATCH 4
 #endif
-constexpr int kLineBatch = EXACT_LINE_BATCH;   // lines whose loads are in flight together
+constexpr int kLineBatch = kFwdLineBatch;      // lines whose loads are in flight together
 constexpr int kViewBatch = EXACT_VIEW_BATCH;   // views likewise in the back-projector
 
 // Element i of a float array through a 32-bit byte offset: with a
@@ -294,6 +297,70 @@ struct SpecPtr {
     const float *__restrict__ mu2;
     const float *__restrict__ bg;
 };
+
+// End of a forward ray: the kSegs waves' Kahan partials of the ray (in
+// ps/pc[seg][lane], this view's) are combined in segment order, times the
+// view's path length; with kResid the spectral residual replaces the line
+// integral: r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with
+// exp(-mu t) = 2^(-mu log2(e) t) by the hardware exp2 (whose result is
+// exp2f's except below 2^-126, where it flushes a term that no count could
+// register); wave `seg` sums the energies k = seg, seg + kSegs, ..., and the
+// waves' sums are added in order.  Ray i = vidx B + b goes to
+// out[vidx ostride + ooff + b], times wstep when weighted, and unweighted
+// to plain[i] when plain is not null.  Every thread of the workgroup calls
+// this (it holds barriers); waves with active = false only take part in
+// them.
+template <bool kResid, class Spec>
+__device__ __forceinline__ void forward_ray_end(const Kahan &acc, bool active, int seg, int lane,
+                                                const ViewGeom &G, int b, int B,
+                                                float (*ps)[kFwdThreads], float (*pc)[kFwdThreads],
+                                                float (*pm)[kFwdThreads],
+                                                const float *__restrict__ Y, const Spec &sp,
+                                                float *__restrict__ out, int ostride, int ooff,
+                                                bool weighted, float *__restrict__ plain)
+{
+    if (active) {
+        ps[seg][lane] = acc.s;
+        pc[seg][lane] = acc.c;
+    }
+    __syncthreads();
+    const bool ray = b < B;
+    const size_t i = (size_t)G.vidx * B + (ray ? b : 0);
+    float val = 0.f;
+    if (active) {
+        Kahan tot;
+#pragma unroll
+        for (int q = 0; q < kSegs; ++q) {
+            tot.add(ps[q][lane]);
+            tot.add(-pc[q][lane]);
+        }
+        val = tot.value() * G.wstep;
+    }
+    if (kResid) {
+        if (active) {
+            const float sp0 = fmaxf(val, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
+            float m = 0.f;
+#pragma unroll 4
+            for (int q = seg; q < sp.K; q += kSegs)
+                m = fmaf(sp.J[q], __builtin_amdgcn_exp2f(-sp.mu2[q] * sp0), m);
+            pm[seg][lane] = m;
+        }
+        __syncthreads();
+        if (active) {
+            float mt = pm[0][lane];
+#pragma unroll
+            for (int q = 1; q < kSegs; ++q)
+                mt += pm[q][lane];
+            val = Y[i] - mt;
+        }
+    }
+    if (!active || seg != 0 || !ray)
+        return;
+    const size_t o = (size_t)G.vidx * ostride + ooff + b;
+    out[o] = weighted ? val * G.wstep : val;
+    if (plain)
+        plain[i] = val;
+}
 
 // Forward projection of rays [64 bblock, 64 bblock + 64) of table view
 // `slot` by one workgroup of kFwdThreads * kSegs threads, reading the padded
@@ -403,45 +470,8 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         tap_pair(f, N, G.Q, img, k * Np, w0, w1, v0, v1);
         acc.add(fmaf(w1, v1, w0 * v0));
     }
-    part_s[seg][lane] = acc.s;
-    part_c[seg][lane] = acc.c;
-    __syncthreads();
-    // every wave forms the rays' totals (the same fixed order)
-    Kahan tot;
-#pragma unroll
-    for (int q = 0; q < kSegs; ++q) {
-        tot.add(part_s[q][lane]);
-        tot.add(-part_c[q][lane]);
-    }
-    const float s = tot.value() * G.wstep;
-    const bool ray = b < B;
-    const size_t o = (size_t)G.vidx * ostride + ooff + b;
-    const size_t i = (size_t)G.vidx * B + (ray ? b : 0);
-    float val = s;
-    if (kResid) {
-        // r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with
-        // exp(-mu t) = 2^(-mu log2(e) t) by the hardware exp2 (whose result
-        // is exp2f's except below 2^-126, where it flushes a term that no
-        // count could register); wave w sums the energies k = w,
-        // w + kSegs, ..., and the waves' sums are added in order
-        const float sp0 = fmaxf(s, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
-        float m = 0.f;
-#pragma unroll 4
-        for (int q = seg; q < sp.K; q += kSegs)
-            m = fmaf(sp.J[q], __builtin_amdgcn_exp2f(-sp.mu2[q] * sp0), m);
-        part_m[seg][lane] = m;
-        __syncthreads();
-        float mt = part_m[0][lane];
-#pragma unroll
-        for (int q = 1; q < kSegs; ++q)
-            mt += part_m[q][lane];
-        val = Y[i] - mt;
-    }
-    if (seg != 0 || !ray)
-        return;
-    out[o] = weighted ? val * G.wstep : val;
-    if (plain)
-        plain[i] = val;
+    forward_ray_end<kResid>(acc, true, seg, lane, G, b, B, part_s, part_c, part_m, Y, sp, out,
+                            ostride, ooff, weighted, plain);
 }
 
 // Workgroup i projects ray block order[i] (the geometry's dispatch order:
@@ -472,6 +502,176 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
     const int it = order[blockIdx.x];
     forward_block<kResid>(views, blk, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff,
                           weighted != 0, plain, it / nbb, it % nbb);
+}
+
+// ------------------------------------------------ forward, LDS groups
+
+// The grouped forward (built when EXACT_FWD_GROUP >= 2; measured slower
+// than k_forward on MI355X, so the default build leaves it out): a
+// workgroup projects one group (FwdGroup) of up to kGV adjacent views and
+// one block of 64 bins, with one wave per (view, segment): wave (g, s)
+// takes view slot0 + g and share s of that view's
+// lines of the block, exactly the lines, batches and summation order
+// forward_block gives the same rays, so every ray's result is bitwise the
+// same as the ungrouped kernel's.  What changes is where the image values
+// come from: the segment's waves (one per view) walk their lines in
+// lockstep, a batch of kLineBatch lines per step, and the image lines of a
+// step are staged once in LDS for all of them (a window of kWinCols padded
+// columns around the views' crossings, filled by global-to-LDS loads of 64
+// floats per wave instruction, double-buffered so that the next step's
+// window loads while the current one is read).  A lane's two taps then read
+// LDS instead of issuing a vector-memory load per line.
+constexpr int kGV = kGroupViews;
+constexpr int kWinH = 2 * kLineBatch;
+constexpr int kGrpThreads = kFwdThreads * kSegs * kGV;
+static_assert(kGrpThreads <= 1024, "grouped forward: workgroup too large");
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// Stages the window of one step: image lines L0 .. L0 + rows - 1 (clamped
+// to the image; a line past it is never read) and padded columns colbase ..
+// colbase + kWinCols - 1 of img into win (kWinCols floats per line).  Each
+// wave instruction moves 64 consecutive floats; wave g of the segment's kGV
+// waves takes the halves g, g + kGV, ...
+[[maybe_unused]] __device__ __forceinline__ void stage_window(const float *__restrict__ img,
+                                                              int Np, int N, int L0, int rows,
+                                                              int colbase, float *win, int g,
+                                                              int lane)
+{
+    for (int i = g; i < 2 * rows; i += kGV) {
+        const int r = i >> 1, h = i & 1;
+        const int line = min(L0 + r, N - 1);
+        const float *src = img + ((size_t)line * Np + colbase + 64 * h + lane);
+        __builtin_amdgcn_global_load_lds((gvoid_t *)src, (lvoid_t *)(win + r * kWinCols + 64 * h),
+                                         4, 0, 0);
+    }
+}
+
+template <bool kResid>
+__global__ __launch_bounds__(kGrpThreads, 2) void k_forward_lds(
+    const ViewGeom *__restrict__ views, const int32_t *__restrict__ blk,
+    const FwdGroup *__restrict__ groups, int N, int B, int nrow, const float *__restrict__ xp,
+    const float *__restrict__ xTp, const float *__restrict__ Y, SpecArg sp,
+    float *__restrict__ out, int ostride, int ooff, int weighted, float *__restrict__ plain,
+    const int32_t *__restrict__ skip, FinishArgs fin)
+{
+    if (skipped(skip))
+        return;
+    // as k_forward: the step's first kernel runs the previous step's finish
+    // in its last workgroup
+    if (kResid && fin.state && blockIdx.x == gridDim.x - 1) {
+        finish_block<true, kGrpThreads>(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg,
+                                        fin.state);
+        if (threadIdx.x == 0 && !fin.state->done)
+            fin.state->pending = 1;
+    }
+    __shared__ float winA[kSegs][kWinH * kWinCols];
+    __shared__ float winB[kSegs][kWinH * kWinCols];
+    using CGroup = const FwdGroup EXACT_CONSTANT;
+    CGroup &Gr = *((CGroup *)groups + blockIdx.x);
+    const int lane = threadIdx.x % kFwdThreads;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);
+    const int g = wave % kGV, seg = wave / kGV;
+    const int nv = Gr.nv, bb = Gr.bb;
+    const bool active = g < nv;
+    const int slot = Gr.slot0 + (active ? g : 0);
+    const int b = bb * kFwdThreads + lane;
+    const ViewGeom G = views[slot];
+    const float *__restrict__ img = slot < nrow ? xp : xTp;
+    const int Np = padded_cols(N);
+    const double base = fma((double)b, G.P, G.A);
+
+    // this view's share of the block's lines, as forward_block takes it
+    const int bi = 2 * (slot * ((B + kFwdThreads - 1) / kFwdThreads) + bb);
+    const int kmin = blk[bi], kmax = blk[bi + 1];
+    int kw0 = 0, kw1 = -1;
+    if (kmin <= kmax) {
+        const int per = (kmax - kmin + kSegs) / kSegs;
+        kw0 = kmin + seg * per;
+        kw1 = min(kmax, kw0 + per - 1);
+    }
+    const int cnt = (active && kw1 >= kw0) ? kw1 - kw0 + 1 : 0;
+    const int nb = cnt / kLineBatch, rem = cnt % kLineBatch;
+    const int kbase = Gr.kbase[seg], J = Gr.nsteps[seg], rows = Gr.rows[seg];
+    const double c0 = Gr.c0[seg], c1 = Gr.c1[seg];
+    // this view's batch i runs at step i + off, on window lines dk ..
+    const int delta = cnt > 0 ? kw0 - kbase : 0;
+    const int off = delta / kLineBatch, dk = delta % kLineBatch;
+    int Jmax = 0;
+#pragma unroll
+    for (int q = 0; q < kSegs; ++q)
+        Jmax = max(Jmax, Gr.nsteps[q]);
+    // first padded column of step j's window, shifted into the padded row
+    auto colbase_of = [&](int j) {
+        const int c = (int)floor(fma(c1, (double)j, c0));
+        return __builtin_amdgcn_readfirstlane(min(max(c, 0), Np - kWinCols));
+    };
+
+    Kahan acc;
+    double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
+    // one step of this wave's lines from window w: a full batch (summed in
+    // float, then one Kahan step) or the remainder lines one by one, as
+    // forward_block sums them
+    auto step = [&](int j, const float *w) {
+        const int i = j - off;                         // this wave's batch
+        if (i < 0 || i > nb || (i == nb && rem == 0))
+            return;
+        // the tap column clamped into the window [cb, cb + kWinCols - 2]; wr
+        // addresses padded column c of the wave's first window line as wr[c]
+        const int cb = colbase_of(j), cbhi = cb + kWinCols - 2;
+        const float *wr = w + (dk * kWinCols - cb);
+        if (i < nb) {
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q) {
+                const double e0 = __builtin_amdgcn_fract(f);
+                const int c = clamp_int_s((int)f, cb, cbhi);
+                f += G.Q;
+                const float w0 = (float)(1.0 - e0), w1 = (float)e0;
+                const float v0 = wr[q * kWinCols + c], v1 = wr[q * kWinCols + c + 1];
+                s = fmaf(w1, v1, fmaf(w0, v0, s));
+            }
+            acc.add(s);
+        } else {
+            for (int q = 0; q < rem; ++q) {
+                const double e0 = __builtin_amdgcn_fract(f);
+                const int c = clamp_int_s((int)f, cb, cbhi);
+                f += G.Q;
+                const float w0 = (float)(1.0 - e0), w1 = (float)e0;
+                const float v0 = wr[q * kWinCols + c], v1 = wr[q * kWinCols + c + 1];
+                acc.add(fmaf(w1, v1, w0 * v0));
+            }
+        }
+    };
+    auto stage = [&](int j, float *w) {
+        if (j < J)
+            stage_window(img, Np, N, kbase + kLineBatch * j, rows, colbase_of(j), w, g, lane);
+    };
+
+    stage(0, winA[seg]);
+    __syncthreads();
+    for (int j = 0; j < Jmax; j += 2) {
+        stage(j + 1, winB[seg]);
+        step(j, winA[seg]);
+        __syncthreads();
+        if (j + 1 >= Jmax)
+            break;
+        stage(j + 2, winA[seg]);
+        step(j + 1, winB[seg]);
+        __syncthreads();
+    }
+    // the windows are free (every staged step has been read): the rays'
+    // partials go there
+    float *pbase = &winA[0][0];
+    static_assert(3 * kGV * kSegs * kFwdThreads <= kSegs * kWinH * kWinCols,
+                  "grouped forward: partials do not fit the window");
+    auto part = [&](int which) {
+        return reinterpret_cast<float(*)[kFwdThreads]>(pbase +
+                                                        (which * kGV + g) * kSegs * kFwdThreads);
+    };
+    forward_ray_end<kResid>(acc, active, seg, lane, G, b, B, part(0), part(1), part(2), Y, sp, out,
+                            ostride, ooff, weighted != 0, plain);
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -1134,6 +1334,31 @@ hipError_t launch_fill(float *x, float value, long count, hipStream_t st)
     return hipGetLastError();
 }
 
+// The forward launches: the grouped kernel over the geometry's groups, then
+// the ungrouped kernel over the blocks left (every block when there are no
+// groups).  The first launch carries the step finish (fin).
+template <bool kResid>
+hipError_t launch_forward_any(const Geo &g, const float *xp, const float *xTp, const float *Y,
+                              const SpecArg &sp, float *out, int ostride, int ooff, bool weighted,
+                              float *plain, const int32_t *skip, hipStream_t st,
+                              const FinishArgs &fin)
+{
+    const FinishArgs nofin{nullptr, 0, nullptr, 0, nullptr};
+    if constexpr (kGV >= 2) {
+        if (g.ngroups > 0)
+            hipLaunchKernelGGL(k_forward_lds<kResid>, dim3(g.ngroups), dim3(kGrpThreads), 0, st,
+                               g.views, g.blk, g.groups, g.N, g.B, g.nrow, xp, xTp, Y, sp, out,
+                               ostride, ooff, weighted ? 1 : 0, plain, skip, fin);
+    }
+    const int nblocks = g.ngroups > 0 ? g.nleft : ((g.B + kFwdThreads - 1) / kFwdThreads) * g.V;
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_forward<kResid>, dim3(nblocks), dim3(kFwdThreads * kSegs), 0, st,
+                           g.views, g.blk, g.ngroups > 0 ? g.left : g.order, g.N, g.V, g.B, g.nrow,
+                           xp, xTp, Y, sp, out, ostride, ooff, weighted ? 1 : 0, plain, skip,
+                           g.ngroups > 0 ? nofin : fin);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float *s,
                           int s_stride, int s_off, bool weighted, const int32_t *skip,
                           hipStream_t st)
@@ -1141,24 +1366,18 @@ hipError_t launch_forward(const Geo &g, const float *xp, const float *xTp, float
     SpecArg none;
     none.K = 0;
     none.bg = nullptr;
-    dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     const FinishArgs nofin{nullptr, 0, nullptr, 0, nullptr};
-    hipLaunchKernelGGL(k_forward<false>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
-                       g.order, g.N, g.V, g.B, g.nrow, xp, xTp, nullptr, none, s, s_stride, s_off,
-                       weighted ? 1 : 0, nullptr, skip, nofin);
-    return hipGetLastError();
+    return launch_forward_any<false>(g, xp, xTp, nullptr, none, s, s_stride, s_off, weighted,
+                                     nullptr, skip, st, nofin);
 }
 
 hipError_t launch_forward_residual(const Geo &g, const float *xp, const float *xTp,
                                    const float *Y, const SpecArg &sp, float *r, float *r_plain,
                                    const int32_t *skip, hipStream_t st, const FinishArgs *fin)
 {
-    dim3 grid(((g.B + kFwdThreads - 1) / kFwdThreads) * g.V);
     const FinishArgs f = fin ? *fin : FinishArgs{nullptr, 0, nullptr, 0, nullptr};
-    hipLaunchKernelGGL(k_forward<true>, grid, dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
-                       g.order, g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, 1,
-                       r_plain, skip, f);
-    return hipGetLastError();
+    return launch_forward_any<true>(g, xp, xTp, Y, sp, r, padded_bins(g.B), kPadB, true, r_plain,
+                                    skip, st, f);
 }
 
 hipError_t launch_weigh_rows(const Geo &g, const float *r, float *rw, hipStream_t st)
@@ -1313,6 +1532,16 @@ int fwd_resident_blocks_per_cu()
         n < 1)
         return 1;
     return n;
+}
+int fwd_grouped_resident_blocks_per_cu()
+{
+    int n = 0;
+    if constexpr (kGV >= 2) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward_lds<true>, kGrpThreads,
+                                                         0) != hipSuccess)
+            n = 0;
+    }
+    return n < 1 ? 1 : n;
 }
 int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }

@@ -102,6 +102,27 @@ def test_batch_equals_solo_bitwise(ex):
         assert torch.equal(xs[i], xs_solo), i
 
 
+# images of 124 pixels or more: with a build that has the grouped
+# (LDS-staged) forward, the single-scan path projects most blocks with it
+# while the batched kernels project every block ungrouped, so equality shows
+# that the two forward kernels give bitwise the same rays
+GROUPED_SHAPES = [(128, 30, 182, 64, 4, 31, 1.0), (256, 90, 363, 17, 2, 32, 1.0),
+                  (160, 47, 227, 30, 3, 33, 1.0), (200, 200, 200, 10, 2, 34, 1.0)]
+
+
+def test_batch_equals_solo_bitwise_grouped(ex):
+    Ps = [synth.make_problem("batch", N, V, B, K, Wn, 1e4, 6, seed, seed + 100,
+                             with_truth=False, bin_cm=ratio * synth.FOV_CM / N)
+          for N, V, B, K, Wn, seed, ratio in GROUPED_SHAPES]
+    say("batch vs solo (grouped forward)", [(P.n_pix, P.n_views, P.n_bins) for P in Ps])
+    opts = dict(max_iters=12)
+    xs, infos = run_batch(ex, Ps, chunk=5, **opts)
+    for i, P in enumerate(Ps):
+        xs_solo, info = solo(ex, P, **opts)
+        assert infos[i][1]["iters"] == info["iters"] == 12
+        assert torch.equal(xs[i], xs_solo), i
+
+
 def test_batch_join_late_and_fixed_steps(ex):
     """Runs that join after others have advanced, fixed step counts (tol 0)."""
     Ps = problems()[:4]

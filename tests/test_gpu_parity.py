@@ -73,6 +73,12 @@ SMALL_SHAPES = [
     # detectors narrower than the image: the gather's clamped pair rule
     ("narrow_detector", 48, 30, 40, 1.0, 1),
     ("narrow_detector_wide_bins", 31, 7, 11, 2.0, 1),
+    # images wide enough for the grouped (LDS-staged) forward of a build that
+    # has it, with the blocks it leaves to the ungrouped kernel
+    ("grouped_ragged", 130, 33, 184, 1.0, 1),
+    ("grouped_full_turn", 160, 50, 227, 1.0, 2),
+    ("grouped_wide_bins", 128, 29, 140, 1.3, 1),
+    ("grouped_narrow_bins", 128, 29, 260, 0.7, 1),
 ]
 
 
