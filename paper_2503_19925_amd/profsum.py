@@ -11,14 +11,15 @@
         profiles/kernels_solve_512.md and profiles/kernels_large_1024.md.
     python -m paper_2503_19925_amd.profsum utilisation <pmc dir>
         two counter passes (A: SQ/GRBM, B: TA/TD/TCP/TCC) per workload under
-        <pmc dir>/<workload>_<pass> -> profiles/counters_utilisation.md.
+        <pmc dir>/<workload>_<pass> -> profiles/counters_utilisation.md and
+        profiles/valu.json (VALU instructions per launch, read by bench.py).
     python -m paper_2503_19925_amd.profsum tests <kernel_stats.csv> <pytest log>
         a kernel trace of the GPU test suite -> profiles/kernels_gpu_tests.md,
         checked against every kernel compiled into libexact.so.
 
-traffic.json carries the build id (kernel source and tile knobs) the
-counters were taken on; bench.py reports its figures only while that id is
-the current one.
+traffic.json and valu.json carry the build id (kernel source and tile
+knobs) the counters were taken on; bench.py reports their figures only while
+that id is the current one.
 """
 import collections
 import csv
@@ -39,16 +40,18 @@ from paper_2503_19925_amd import build as libbuild  # noqa: E402
 COPY_MIB = 256
 PMC_COMMAND = ("timeout -s KILL 150 rocprofv3 --pmc <counter> --output-format csv -d "
                "gpurun_out/pmc/<counter> -o run -- python3 bench.py --steps 5 --warmup 2 "
-               "--proj-reps 5 --profile-steps 5 --batch 0 --served 0 --cpu-steps 0 "
-               "--calibrate-copy-mb 256")
+               "--proj-reps 5 --kernel-reps 5 --batch 0 --served 0 --cpu-steps 0 "
+               "--large-to-tol 0 --calibrate-copy-mb 256")
 BENCH_TRACE = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/bench --output-format csv "
                "-o bench -- python3 bench.py --steps 50 --warmup 5 --cpu-steps 0 --batch 0 "
-               "--served 0 --profile-steps 20")
+               "--served 0 --large-to-tol 0 --kernel-reps 20")
 LARGE_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_large "
                "-o large -- python3 bench.py --workload large_1024 --steps 10 --warmup 2 "
-               "--proj-reps 5 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 --dense-steps 0")
+               "--proj-reps 5 --kernel-reps 5 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
+               "--dense-steps 0")
 LARGE_BENCH = ("python3 bench.py --workload large_1024 --steps 20 --warmup 3 --proj-reps 10 "
-               "--batch 0 --served 0 --cpu-steps 0 --tv-steps -1 --dense-steps 0 --to-tol 1e-4")
+               "--kernel-reps 10 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
+               "--dense-steps 0 --to-tol 1e-4")
 TESTS_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_tests "
                "-o tests -- python3 -u -m pytest tests -m gpu -x -q --timeout 600 "
                "--timeout-method thread")
@@ -159,7 +162,7 @@ def table(rows):
 def cmd_kernels(out_dir):
     rows = stats(os.path.join(out_dir, "prof", "bench", "bench_kernel_stats.csv"))
     b = json.loads(open(os.path.join(out_dir, "bench.log")).read().strip().splitlines()[-1])
-    ph = b["step_phase_ms"]
+    ph = b["kernel_ms"]
 
     def get(rs, name):
         return [r for r in rs if r[0] == name][0][2]
@@ -181,27 +184,29 @@ def cmd_kernels(out_dir):
           "the benchmark's other calls: power iteration (k_forward<false>,",
           "k_back<true, false>, k_dot3, k_normalize), the standalone projector timings",
           "(exact_backproject = k_weigh_rows + k_back<true, false>; exact_forward =",
-          "fills + k_pad_pair + k_forward<false>), the profiled steps (the same four",
-          "kernels launched one by one, then k_eg_finish), the known-background leg (the same kernels),",
+          "fills + k_pad_pair + k_forward<false>), the kernel timings (each step kernel",
+          "launched back to back, an untimed and a timed pass, the full-step update into",
+          "a scratch image), the known-background leg (the same kernels),"
           "the TV-ball leg (k_fgp_steps, k_fgp_final, k_tv_parts, k_dyk_*, and the EG",
           "kernels of two steps) and the dense leg (k_dense_*).", "",
           "Command (from the repository root, TMPDIR=/tmp):", "", "```", BENCH_TRACE, "```", "",
           "Summarised by `python -m paper_2503_19925_amd.profsum kernels gpurun_out`.", ""]
     md += table(rows)
+    fwd_b = (ph["forward_residual_x"] + ph["forward_residual_xh"]) / 2 * 1e3
     md += ["", "**Agreement with the benchmark's event timing.** The default `python bench.py`",
-           "run (same build) timed the step at %.4f ms (graph replay, HIP events) and," % b["ms_per_step"],
-           "with HIP events around each kernel of 50 steps launched one by one, the",
-           "phases at: forward at x_t %.2f us, back + half update %.2f us, forward at"
+           "run (same build, not under the profiler) timed the step at %.4f ms (graph" % b["ms_per_step"],
+           "replay, HIP events) and each step kernel over back-to-back launches between",
+           "HIP events: forward at x_t %.2f us, back + half update %.2f us, forward at"
            % (ph["forward_residual_x"] * 1e3, ph["back_update_half"] * 1e3),
-           "x_{t+1/2} %.2f us, back + full update %.2f us, finish %.2f us (the events"
+           "x_{t+1/2} %.2f us, back + full update %.2f us, finish %.2f us.  The profiler's"
            % (ph["forward_residual_xh"] * 1e3, ph["back_update_full"] * 1e3, ph["finish"] * 1e3),
-           "between launches add about a microsecond of gap to each).  The profiler's",
-           "averages: k_forward<true> %.2f us, k_back_update<true, true, false> %.2f us," % (fwd, bh),
-           "k_back_update<true, false, false> %.2f us (and the standalone k_eg_finish<false> %.2f us);" % (bf, fin),
-           "the graph's four kernels sum to %.1f us per step, %.1f us short of the"
+           "averages: k_forward<true> %.2f us (the benchmark's forward mean %.2f us, %+.1f %%)," % (
+               fwd, fwd_b, 100 * (fwd_b - fwd) / fwd),
+           "k_back_update<true, true, false> %.2f us, k_back_update<true, false, false> %.2f us" % (bh, bf),
+           "(and the standalone k_eg_finish<false> %.2f us); the graph's four kernels sum to" % fin,
+           "%.1f us per step, %.1f us short of the replayed step: the gaps between the"
            % (tot, b["ms_per_step"] * 1e3 - tot),
-           "replayed step: the gaps between the graph's kernels and what the finish",
-           "adds to the first kernel's last workgroup."]
+           "graph's kernels and what the finish adds to the first kernel's last workgroup."]
     with open(os.path.join(PROFILES, "kernels_solve_512.md"), "w") as f:
         f.write("\n".join(md) + "\n")
 
@@ -209,7 +214,7 @@ def cmd_kernels(out_dir):
     err = open(os.path.join(out_dir, "large.err")).read()
     m = re.search(r"timed 20 steps: ([0-9.]+) ms/step", err)
     t = re.search(r"to tolerance 1e-04: (\d+) steps, ([0-9.]+) s", err)
-    phl = re.search(r"per-phase ms: (.*)", err).group(1)
+    phl = re.search(r"kernel ms: (.*)", err).group(1)
     md = ["# Kernel times, workload large_1024 (EXACT step)", "",
           "1024x1024 image, 720 views over 180 deg, 1448 bins, K=64 energy bins, 4 windows,",
           "I0=1e3.  nnz(A) = 1,357,334,016 (device count); algorithmic bytes per",
@@ -219,7 +224,7 @@ def cmd_kernels(out_dir):
     md += table(rl)
     md += ["", "Benchmark line of the same workload (HIP events, not under the profiler):",
            "`%s`:" % LARGE_BENCH,
-           "%s ms per EG step (%.0f EG iters/s); per-phase ms %s; solving from x = 0 to"
+           "%s ms per EG step (%.0f EG iters/s); kernel ms %s; solving from x = 0 to"
            % (m.group(1), 1e3 / float(m.group(1)), phl),
            "natural residual 1e-4 took %s steps and %s s." % (t.group(1), t.group(2))]
     with open(os.path.join(PROFILES, "kernels_large_1024.md"), "w") as f:
@@ -236,8 +241,8 @@ UTIL_PASSES = {
          "TCP_TCP_TA_DATA_STALL_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum "
          "TCP_TCC_READ_REQ_LATENCY_sum TCC_HIT_sum TCC_MISS_sum GRBM_GUI_ACTIVE"}
 UTIL_BENCH = ("python3 bench.py --workload <workload> --steps 5 --warmup 2 --proj-reps 2 "
-              "--profile-steps 2 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
-              "--dense-steps 0 --background-steps 0")
+              "--kernel-reps 2 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
+              "--dense-steps 0 --background-steps 0 --large-to-tol 0")
 CUS, SIMDS, CLOCK_GHZ = 256, 1024, 2.4
 UTIL_KERNELS = ("k_forward<true>", "k_back_update<true, true, false>",
                 "k_back_update<true, false, false>")
@@ -258,6 +263,10 @@ def cmd_utilisation(pmc_dir):
           "below 2.4 GHz makes every fraction below a lower bound:", "",
           "* VALU issue: SQ_INSTS_VALU x 4 cycles (a wave64 instruction on a 16-lane",
           "  SIMD) / (1024 SIMDs x duration x 2.4 GHz);",
+          "* VALU busy: SQ_ACTIVE_INST_VALU x 4 (quad-cycles the SIMDs spend in VALU",
+          "  instructions, multi-pass ones such as double-precision converts counted in",
+          "  full) / (1024 SIMDs x duration x 2.4 GHz): above the issue figure by what",
+          "  instructions taking more than one pass cost;",
           "* waves resident per SIMD: SQ_WAVE_CYCLES x 4 (quad-cycles) / (1024 x cycles);",
           "* TA / TD busy: TA_TA_BUSY_sum, TD_TD_BUSY_sum / (256 CUs x cycles);",
           "* L2 hit rate: TCC_HIT / (TCC_HIT + TCC_MISS); L2 read latency:",
@@ -269,6 +278,7 @@ def cmd_utilisation(pmc_dir):
         traffic = json.load(open(os.path.join(PROFILES, "traffic.json")))["workloads"]
     except (OSError, ValueError, KeyError):
         pass
+    valu_rec = {}
     for wl in ("solve_512", "large_1024"):
         vals = collections.defaultdict(lambda: collections.defaultdict(list))
         dur = collections.defaultdict(list)
@@ -280,21 +290,35 @@ def cmd_utilisation(pmc_dir):
                 if p == "A" and r["Counter_Name"] == "SQ_INSTS_VALU":
                     dur[n].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
         md += ["## %s" % wl, "",
-               "| kernel | dispatches | duration (us) | VALU issue | waves / SIMD | TA busy "
-               "| TD busy | L2 hit | L2 read latency (cycles) | HBM (GB/s, of 8000) |",
-               "|---|---|---|---|---|---|---|---|---|---|"]
+               "| kernel | dispatches | duration (us) | VALU issue | VALU busy | waves / SIMD "
+               "| TA busy | TD busy | L2 hit | L2 read latency (cycles) | HBM (GB/s, of 8000) |",
+               "|---|---|---|---|---|---|---|---|---|---|---|"]
+        wrec = valu_rec.setdefault(wl, {})
         for k in UTIL_KERNELS:
             v = {c: sum(x) / len(x) for c, x in vals[k].items()}
             d = sum(dur[k]) / len(dur[k])
             cyc = d * CLOCK_GHZ * 1e9
             hbm = traffic.get(wl, {}).get(k, {}).get("hbm_bytes_per_launch")
-            md.append("| %s | %d | %.1f | %.0f %% | %.1f | %.0f %% | %.0f %% | %.1f %% | %.0f | %s |" % (
-                k, len(dur[k]), d * 1e6, 100 * v["SQ_INSTS_VALU"] * 4 / SIMDS / cyc,
-                v["SQ_WAVE_CYCLES"] * 4 / SIMDS / cyc, 100 * v["TA_TA_BUSY_sum"] / CUS / cyc,
-                100 * v["TD_TD_BUSY_sum"] / CUS / cyc,
-                100 * v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"]),
-                v["TCP_TCC_READ_REQ_LATENCY_sum"] / v["TCP_TCC_READ_REQ_sum"],
-                "%.0f" % (hbm / d / 1e9) if hbm else "-"))
+            issue = v["SQ_INSTS_VALU"] * 4 / SIMDS / cyc
+            busy = v["SQ_ACTIVE_INST_VALU"] * 4 / SIMDS / cyc
+            ta = v["TA_TA_BUSY_sum"] / CUS / cyc
+            md.append("| %s | %d | %.1f | %.0f %% | %.0f %% | %.1f | %.0f %% | %.0f %% | %.1f %% "
+                      "| %.0f | %s |" % (
+                          k, len(dur[k]), d * 1e6, 100 * issue, 100 * busy,
+                          v["SQ_WAVE_CYCLES"] * 4 / SIMDS / cyc, 100 * ta,
+                          100 * v["TD_TD_BUSY_sum"] / CUS / cyc,
+                          100 * v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"]),
+                          v["TCP_TCC_READ_REQ_LATENCY_sum"] / v["TCP_TCC_READ_REQ_sum"],
+                          "%.0f" % (hbm / d / 1e9) if hbm else "-"))
+            wrec[k] = {"valu_lane_instr_per_launch": 64.0 * v["SQ_INSTS_VALU"],
+                       "valu_active_quad_cycles": v["SQ_ACTIVE_INST_VALU"],
+                       "duration_us": d * 1e6, "valu_issue_frac": issue, "valu_busy_frac": busy,
+                       "ta_busy_frac": ta, "dispatches": len(dur[k])}
+        bu = [wrec[k] for k in UTIL_KERNELS if k.startswith("k_back_update")]
+        wrec["k_back_update"] = {f: sum(b[f] for b in bu) / len(bu)
+                                 for f in ("valu_lane_instr_per_launch", "valu_active_quad_cycles",
+                                           "duration_us", "valu_issue_frac", "valu_busy_frac",
+                                           "ta_busy_frac")}
         md.append("")
     md += ["Reading.  At 1024² the back-projection + update kernels issue VALU",
            "instructions at about 95 % of the peak rate, so they are bound by",
@@ -305,7 +329,13 @@ def cmd_utilisation(pmc_dir):
            "far below 8 TB/s show the operands served from the XCDs' L2."]
     with open(os.path.join(PROFILES, "counters_utilisation.md"), "w") as f:
         f.write("\n".join(md) + "\n")
-    print("wrote counters_utilisation.md")
+    rec = {"kernel_build_id": libbuild.build_id(), "knobs": libbuild.tuned_knobs(),
+           "note": "SQ_INSTS_VALU per dispatch x 64 lanes; fractions against 1024 SIMDs at "
+                   "2.4 GHz over the dispatch's duration (counter run)",
+           "workloads": valu_rec}
+    with open(os.path.join(PROFILES, "valu.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print("wrote counters_utilisation.md and valu.json (%s)" % rec["kernel_build_id"])
 
 
 # ------------------------------------------------------------- test coverage

@@ -206,6 +206,10 @@ class Server:
         now = lambda: self.clock() - t0 + skew        # noqa: E731
         self.peak_running = 0
         self.peak_load = 0.0
+        # host-side time split: set-up of admitted scans, the chunks' steps
+        # (enqueue and wait), retirement; and the number of chunks
+        self.stats = {"add_s": 0.0, "step_s": 0.0, "retire_s": 0.0, "chunks": 0}
+        clk = self.clock
         while nxt < len(reqs) or pending or running:
             t = now()
             while nxt < len(reqs) and reqs[nxt].arrival <= t:
@@ -221,7 +225,9 @@ class Server:
                 if (self.work_cap is not None and running and load + c > self.work_cap):
                     break
                 pending.pop(i)
+                t1 = clk()
                 slot, gamma = self.backend.add(r)
+                self.stats["add_s"] += clk() - t1
                 running[slot] = (r, now(), fp, gamma, c)
                 used += fp
                 load += c
@@ -236,13 +242,18 @@ class Server:
                         else:
                             skew += wait
                 continue
+            t1 = clk()
             self.backend.step(self.chunk)
+            self.stats["step_s"] += clk() - t1
+            self.stats["chunks"] += 1
             for slot in list(running):
                 status, info = self.backend.poll(slot)
                 if status == 0:
                     continue
                 r, admitted, fp, gamma, c = running.pop(slot)
+                t1 = clk()
                 x = self.backend.retire(slot)
+                self.stats["retire_s"] += clk() - t1
                 used -= fp
                 load -= c
                 self.estimate.record(r, info["iters"])
