@@ -242,13 +242,21 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev,
  * tau| <= tv_tol; the regularized point is computed by prox_iters steps of
  * fast gradient projection on the dual of TV denoising (Beck and Teboulle
  * 2009) started from zero.  The binary search: if TV(v) <= tau the result
- * is v; else hi starts at 1 and doubles (at most 60 times) until
- * TV(xbar(hi)) <= tau, lo being its previous value (0 first); then up to
- * max_bisect midpoints: the first within tv_tol is the result, TV > tau
- * moves lo up, TV <= tau moves hi down; without a hit the result is
- * xbar(hi).  The intersection with the orthant is Dykstra's algorithm (eq.
- * projection-intersection), stopped once ||z_{k+1} - z_k||_2 <= dyk_tol or
- * after max_outer rounds.  Defaults: the paper's tolerances (0.01, 1e-4),
+ * is v; else it brackets the weight, then halves the bracket.  The first
+ * search of a projection call (or of a solve) starts cold: hi starts at 1
+ * and doubles (at most 60 times) until TV(xbar(hi)) <= tau, lo being its
+ * previous value (0 first).  Later searches of the same call start warm at
+ * the weight lam0 of the previous one: xbar(lam0) first; if its TV is above
+ * tau, lo = lam0 and hi grows by 5/4, then doubles, while TV(xbar(hi)) >
+ * tau; otherwise hi = lam0 and lo shrinks by 4/5, then halves, while
+ * TV(xbar(lo)) <= tau (at most 60 times each way); a point met on the way
+ * within tv_tol of tau is the result.  Then up to max_bisect midpoints: the
+ * first within tv_tol is the result, TV > tau moves lo up, TV <= tau moves
+ * hi down; without a hit the result is xbar(hi).  (The paper leaves the
+ * search's start open; the warm start is this library's reading, shared by
+ * its test oracle.)  The intersection with the orthant is Dykstra's
+ * algorithm (eq. projection-intersection), stopped once ||z_{k+1} - z_k||_2
+ * <= dyk_tol or after max_outer rounds.  Defaults: the paper's tolerances (0.01, 1e-4),
  * prox_iters 100, max_bisect 40, max_outer 200.
  */
 typedef struct {

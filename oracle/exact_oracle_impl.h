@@ -588,17 +588,30 @@ static void FN(tv_prox)(int N, const REAL *b, REAL lam, int iters, REAL *x)
 
 /*
  * Approximate projection onto the TV ball {TV(x) <= tau} as in Sec. 5: the
- * TV-regularized point for a lam found by binary search, until
- * |TV(xbar) - tau| <= tv_tol.  If TV(v) <= tau the result is v.  Otherwise
- * hi starts at 1 and doubles (at most 60 times) until TV(xbar(hi)) <= tau,
- * lo being the previous value (0 first); then up to max_bisect midpoints
- * mid = (lo + hi)/2: the first with |TV - tau| <= tv_tol is returned, else
- * TV > tau moves lo to mid and TV <= tau moves hi to mid.  Without a hit the
- * result is xbar(hi), the last point inside the ball.  Returns the number
- * of proximal solves; *lam_out receives the lam of the result.
+ * TV-regularized point xbar(lam) for a lam found by binary search, until
+ * |TV(xbar) - tau| <= tv_tol.  If TV(v) <= tau the result is v (lam 0).
+ *
+ * The search first brackets the weight, keeping hi the weight of the last
+ * point found inside the ball (TV <= tau) and lo one whose point lies
+ * outside (TV > tau), then halves [lo, hi].  The paper does not say where
+ * the search starts; here:
+ *   - cold (lam0 <= 0): hi starts at 1 and doubles (at most 60 times) while
+ *     TV(xbar(hi)) > tau, lo being its previous value (0 first);
+ *   - warm (lam0 > 0, the weight of a previous projection of the same run):
+ *     the first point is xbar(lam0).  If its TV is above tau, lo = lam0 and
+ *     hi grows by 5/4, then doubles (at most 60 times), while TV(xbar(hi))
+ *     > tau (lo following hi); if it is at or below tau, hi = lam0 and lo
+ *     shrinks by 4/5, then halves (at most 60 times), while TV(xbar(lo)) <=
+ *     tau (hi following lo), lo = 0 if it never rises above tau.  A point
+ *     met while bracketing with |TV - tau| <= tv_tol is the result.
+ * Then up to max_bisect midpoints mid = (lo + hi)/2: the first with |TV -
+ * tau| <= tv_tol is the result, TV > tau moves lo to mid and TV <= tau moves
+ * hi to mid.  Without a hit the result is xbar(hi), the last point inside
+ * the ball.  Returns the number of proximal solves; *lam_out receives the
+ * lam of the result.
  */
 static int FN(tv_ball)(int N, const REAL *v, REAL tau, REAL tv_tol, int iters, int max_bisect,
-                       REAL *out, REAL *lam_out)
+                       REAL lam0, REAL *out, REAL *lam_out)
 {
     long d = (long)N * N;
     if (FN(tv_norm)(N, v) <= tau) {
@@ -608,41 +621,97 @@ static int FN(tv_ball)(int N, const REAL *v, REAL tau, REAL tv_tol, int iters, i
         return 0;
     }
     REAL *x = (REAL *)malloc(sizeof(REAL) * (size_t)d);
-    REAL lo = 0, hi = 1;
     int solves = 0;
-    FN(tv_prox)(N, v, hi, iters, x);
-    ++solves;
-    REAL t = FN(tv_norm)(N, x);
-    for (int grow = 0; t > tau && grow < 60; ++grow) {
-        lo = hi;
-        hi = 2 * hi;
+    REAL lo, hi, t;
+    int hit = 0;
+#define ORA_KEEP(L)                          \
+    do {                                     \
+        for (long i = 0; i < d; ++i)         \
+            out[i] = x[i];                   \
+        *lam_out = (L);                      \
+    } while (0)
+    if (lam0 <= 0) {
+        lo = 0;
+        hi = 1;
         FN(tv_prox)(N, v, hi, iters, x);
         ++solves;
         t = FN(tv_norm)(N, x);
+        for (int grow = 0; t > tau && grow < 60; ++grow) {
+            lo = hi;
+            hi = 2 * hi;
+            FN(tv_prox)(N, v, hi, iters, x);
+            ++solves;
+            t = FN(tv_norm)(N, x);
+        }
+        ORA_KEEP(hi);
+    } else {
+        FN(tv_prox)(N, v, lam0, iters, x);
+        ++solves;
+        t = FN(tv_norm)(N, x);
+        if (fabs(t - tau) <= tv_tol) {
+            ORA_KEEP(lam0);
+            hit = 1;
+        } else if (t > tau) {
+            lo = lam0;
+            hi = lam0 * 5 / 4;
+            for (int grow = 0;; ++grow) {
+                FN(tv_prox)(N, v, hi, iters, x);
+                ++solves;
+                t = FN(tv_norm)(N, x);
+                if (fabs(t - tau) <= tv_tol) {
+                    ORA_KEEP(hi);
+                    hit = 1;
+                    break;
+                }
+                if (t <= tau || grow + 1 >= 60)
+                    break;
+                lo = hi;
+                hi = 2 * hi;
+            }
+            if (!hit)
+                ORA_KEEP(hi);
+        } else {
+            hi = lam0;
+            ORA_KEEP(hi);
+            lo = lam0 * 4 / 5;
+            for (int shrink = 0;; ++shrink) {
+                FN(tv_prox)(N, v, lo, iters, x);
+                ++solves;
+                t = FN(tv_norm)(N, x);
+                if (fabs(t - tau) <= tv_tol) {
+                    ORA_KEEP(lo);
+                    hit = 1;
+                    break;
+                }
+                if (t > tau)
+                    break;
+                hi = lo;
+                ORA_KEEP(hi);
+                if (shrink + 1 >= 60) {
+                    lo = 0;
+                    break;
+                }
+                lo = lo / 2;
+            }
+        }
     }
-    for (long i = 0; i < d; ++i)
-        out[i] = x[i];
-    *lam_out = hi;
-    for (int it = 0; it < max_bisect; ++it) {
+    for (int it = 0; !hit && it < max_bisect; ++it) {
         REAL mid = (lo + hi) / 2;
         FN(tv_prox)(N, v, mid, iters, x);
         ++solves;
         t = FN(tv_norm)(N, x);
         if (fabs(t - tau) <= tv_tol) {
-            for (long i = 0; i < d; ++i)
-                out[i] = x[i];
-            *lam_out = mid;
+            ORA_KEEP(mid);
             break;
         }
         if (t > tau) {
             lo = mid;
         } else {
             hi = mid;
-            for (long i = 0; i < d; ++i)
-                out[i] = x[i];
-            *lam_out = mid;
+            ORA_KEEP(mid);
         }
     }
+#undef ORA_KEEP
     free(x);
     return solves;
 }
@@ -652,11 +721,13 @@ static int FN(tv_ball)(int N, const REAL *v, REAL tau, REAL tv_tol, int iters, i
  * Dykstra's algorithm (Sec. 5, eq. projection-intersection): z_0 = z,
  * p_0 = q_0 = 0; y_k = P_TV(z_k + p_k), p_{k+1} = z_k + p_k - y_k,
  * z_{k+1} = max(0, y_k + q_k), q_{k+1} = y_k + q_k - z_{k+1}; stops once
- * ||z_{k+1} - z_k||_2 <= tol or after max_outer rounds.  P_TV is tv_ball.
+ * ||z_{k+1} - z_k||_2 <= tol or after max_outer rounds.  P_TV is tv_ball,
+ * warm-started from *lam_carry (the weight of the last TV-ball point the
+ * run found, 0 for none), which each round updates.
  */
 static void FN(tv_dykstra)(int N, const REAL *z, REAL tau, REAL tv_tol, int iters,
                            int max_bisect, REAL tol, int max_outer, REAL *out, int *rounds,
-                           int *solves)
+                           int *solves, REAL *lam_carry)
 {
     long d = (long)N * N;
     REAL *p = (REAL *)calloc((size_t)d, sizeof(REAL)), *q = (REAL *)calloc((size_t)d, sizeof(REAL));
@@ -668,7 +739,9 @@ static void FN(tv_dykstra)(int N, const REAL *z, REAL tau, REAL tv_tol, int iter
         REAL lam;
         for (long i = 0; i < d; ++i)
             w[i] = out[i] + p[i];
-        ns += FN(tv_ball)(N, w, tau, tv_tol, iters, max_bisect, y, &lam);
+        ns += FN(tv_ball)(N, w, tau, tv_tol, iters, max_bisect, *lam_carry, y, &lam);
+        if (lam > 0)
+            *lam_carry = lam;
         REAL sq = 0;
         for (long i = 0; i < d; ++i) {
             p[i] = w[i] - y[i];
@@ -707,11 +780,11 @@ void FN(ora_tv_prox)(int N, const double *b, double lam, int iters, double *x)
 }
 
 int FN(ora_tv_ball)(int N, const double *v, double tau, double tv_tol, int iters,
-                    int max_bisect, double *out, double *lam_out)
+                    int max_bisect, double lam0, double *out, double *lam_out)
 {
     long d = (long)N * N;
     REAL *vr = FN(to_real)(v, d), *o = (REAL *)malloc(sizeof(REAL) * (size_t)d), lam = 0;
-    int ns = FN(tv_ball)(N, vr, (REAL)tau, (REAL)tv_tol, iters, max_bisect, o, &lam);
+    int ns = FN(tv_ball)(N, vr, (REAL)tau, (REAL)tv_tol, iters, max_bisect, (REAL)lam0, o, &lam);
     FN(to_double)(o, d, out);
     if (lam_out)
         *lam_out = (double)lam;
@@ -725,8 +798,9 @@ int FN(ora_project_tv)(int N, const double *z, double tau, double tv_tol, int it
     long d = (long)N * N;
     REAL *zr = FN(to_real)(z, d), *o = (REAL *)malloc(sizeof(REAL) * (size_t)d);
     int rounds = 0;
+    REAL lam_carry = 0;
     FN(tv_dykstra)(N, zr, (REAL)tau, (REAL)tv_tol, iters, max_bisect, (REAL)tol, max_outer, o,
-                   &rounds, solves);
+                   &rounds, solves, &lam_carry);
     FN(to_double)(o, d, out);
     free(zr); free(o);
     return rounds;
@@ -735,7 +809,8 @@ int FN(ora_project_tv)(int N, const double *z, double tau, double tv_tol, int it
 /*
  * Projected extragradient over X = {TV(x) <= tau} intersected with the
  * orthant, the constraint set of the paper's experiments (Sec. 5): as
- * ora_eg, with both half-steps projected by tv_dykstra.  rho_hist as in
+ * ora_eg, with both half-steps projected by tv_dykstra, each TV-ball search
+ * warm-started from the weight of the run's previous one.  rho_hist as in
  * ora_eg; tol > 0 stops on the natural residual.  *solves_out (if not
  * NULL) receives the TV-regularized points computed over the run (the
  * search's decision path).  Returns the steps taken.
@@ -756,13 +831,14 @@ int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const doub
     REAL *s = (REAL *)malloc(sizeof(REAL) * (size_t)n);
     REAL *r = (REAL *)malloc(sizeof(REAL) * (size_t)n);
     REAL gm = (REAL)gamma;
+    REAL lam_carry = 0;
     int t;
     for (t = 1; t <= max_iters; ++t) {
         FN(apply_F)(g, &sp, xt, F, s, r);
         for (long p = 0; p < d; ++p)
             v[p] = xt[p] - gm * F[p];
         FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
-                       max_outer, xh, 0, &ns);
+                       max_outer, xh, 0, &ns, &lam_carry);
         ns_total += ns;
         REAL num = 0, den = 0;
         for (long p = 0; p < d; ++p) {
@@ -776,7 +852,7 @@ int FN(ora_eg_tv)(const ora_geom *g, int K, int Wn, const double *mu, const doub
         for (long p = 0; p < d; ++p)
             v[p] = xt[p] - gm * F[p];
         FN(tv_dykstra)(N, v, (REAL)tau, (REAL)tv_tol, prox_iters, max_bisect, (REAL)dyk_tol,
-                       max_outer, xt, 0, &ns);
+                       max_outer, xt, 0, &ns, &lam_carry);
         ns_total += ns;
         if (tol > 0 && rho >= 0 && rho <= tol)
             break;

@@ -101,8 +101,8 @@ def _lib():
             f.argtypes = [C.c_int, _dp, C.c_double, C.c_int, _dp]
             f.restype = None
             f = getattr(_LIB, "ora_tv_ball_" + p)
-            f.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _dp,
-                          C.POINTER(C.c_double)]
+            f.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                          _dp, C.POINTER(C.c_double)]
             f.restype = C.c_int
             f = getattr(_LIB, "ora_project_tv_" + p)
             f.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
@@ -294,14 +294,15 @@ def tv_prox(b, lam, iters=TV_DEFAULTS["prox_iters"], prec="f64"):
 
 
 def tv_ball(v, tau, tv_tol=TV_DEFAULTS["tv_tol"], prox_iters=TV_DEFAULTS["prox_iters"],
-            max_bisect=TV_DEFAULTS["max_bisect"], prec="f64"):
+            max_bisect=TV_DEFAULTS["max_bisect"], lam0=0.0, prec="f64"):
     """Approximate projection onto {TV <= tau} by binary search on the TV
-    weight.  Returns (x, lam, proximal solves)."""
+    weight, cold (lam0 <= 0) or warm-started at lam0.  Returns (x, lam,
+    proximal solves)."""
     v, N = _img(v)
     out = np.empty(N * N)
     lam = C.c_double(0.0)
     ns = _fn("tv_ball", prec)(N, v, float(tau), float(tv_tol), int(prox_iters),
-                              int(max_bisect), out, C.byref(lam))
+                              int(max_bisect), float(lam0), out, C.byref(lam))
     return out, lam.value, int(ns)
 
 

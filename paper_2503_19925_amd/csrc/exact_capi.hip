@@ -531,36 +531,41 @@ double power_iteration(const exact_geometry_s *g, int max_iters, hipStream_t st,
     hip_check(exact::launch_fill(v.as<float>(), (float)(1.0 / std::sqrt((double)d)), d, st), "fill");
     hip_check(exact::launch_pad_pair(v.as<float>(), vp.as<float>(), vTp.as<float>(), g->N, st),
               "pad_pair");
-    hip_check(exact::launch_state_init(state.as<SolveState>(), 0.0, 0, 0, st), "state_init");
-    double lam = 0.0;
-    int it = 0;
-    for (it = 1; it <= max_iters; ++it) {
-        hip_check(exact::launch_forward(G, vp.as<float>(), vTp.as<float>(), s.as<float>(),
-                                        exact::padded_bins(g->B), exact::kPadB, true, nullptr,
-                                        st),
-                  "forward");
-        hip_check(exact::launch_back(G, s.as<float>(), u.as<float>(), (float)(1.0 / (double)n),
-                                     nullptr, st),
-                  "back");
-        hip_check(exact::launch_dot3(v.as<float>(), u.as<float>(), g->N, parts.as<double>(), st), "dot3");
-        hip_check(exact::launch_dot3_finish(parts.as<double>(), nparts, state.as<SolveState>(), st), "dot3_finish");
-        hip_check(exact::launch_normalize(u.as<float>(), v.as<float>(), vp.as<float>(), vTp.as<float>(),
-                                          g->N, state.as<SolveState>(), st),
-                  "normalize");
-        read_state(state.as<SolveState>(), hs, st);
-        const double lam_new = hs.h->lam;
-        if (!(std::isfinite(lam_new) && lam_new > 0.0))
-            fail(-EIO, "power iteration produced a non-positive eigenvalue estimate");
-        const bool done = it > 1 && std::fabs(lam_new - lam) <= 1e-7 * std::fabs(lam_new);
-        lam = lam_new;
-        if (done)
+    SolveState *S = state.as<SolveState>();
+    hip_check(exact::launch_state_init(S, 0.0, max_iters, 0, st), "state_init");
+    // steps go to the device in chunks; the stop test runs there (every
+    // kernel of a step after the stop is a no-op), and the host reads the
+    // state once per chunk
+    constexpr int kChunk = 16;
+    const int32_t *skip = &S->done;
+    for (int it = 0; it < max_iters;) {
+        for (int c = 0; c < kChunk && it < max_iters; ++c, ++it) {
+            hip_check(exact::launch_forward(G, vp.as<float>(), vTp.as<float>(), s.as<float>(),
+                                            exact::padded_bins(g->B), exact::kPadB, true, skip,
+                                            st),
+                      "forward");
+            hip_check(exact::launch_back(G, s.as<float>(), u.as<float>(), (float)(1.0 / (double)n),
+                                         skip, st),
+                      "back");
+            hip_check(exact::launch_dot3(v.as<float>(), u.as<float>(), g->N, parts.as<double>(),
+                                         skip, st),
+                      "dot3");
+            hip_check(exact::launch_dot3_finish(parts.as<double>(), nparts, S, 1e-7, st),
+                      "dot3_finish");
+            hip_check(exact::launch_normalize(u.as<float>(), v.as<float>(), vp.as<float>(),
+                                              vTp.as<float>(), g->N, S, st),
+                      "normalize");
+        }
+        read_state(S, hs, st);
+        if (hs.h->done)
             break;
     }
+    if (hs.h->converged < 0)
+        fail(-EIO, "power iteration produced a non-positive eigenvalue estimate");
     if (iters_out)
-        *iters_out = it > max_iters ? max_iters : it;
-    return lam;
+        *iters_out = hs.h->t;
+    return hs.h->lam;
 }
-
 }  // namespace
 
 extern "C" {
@@ -1804,8 +1809,13 @@ struct TvWork {
                   "hipMemcpyAsync");
     }
 
+    // Weight of the last TV-ball point this work found (0: none yet); the
+    // next search starts there.
+    double lam_carry = 0.0;
+
     // y = approximate projection of w onto {TV <= tau} (binary search on
-    // the TV weight, the decisions of the definition in the header).
+    // the TV weight, cold or warm-started from lam_carry, the decisions of
+    // the definition in the header).
     void tv_ball(double tau, hipStream_t st)
     {
         float *wp = w->as<float>(), *xp = x->as<float>(), *yp = y->as<float>();
@@ -1813,28 +1823,81 @@ struct TvWork {
             copy(yp, wp, st);
             return;
         }
-        double lo = 0.0, hi = 1.0;
-        double t = solve(hi, st);
-        for (int grow = 0; t > tau && grow < 60; ++grow) {
-            lo = hi;
-            hi = 2.0 * hi;
+        double lo = 0.0, hi = 1.0, t = 0.0, lam = 0.0;
+        bool hit = false;
+        auto keep = [&](double l) {               // y = xbar(l), the result so far
+            copy(yp, xp, st);
+            lam = l;
+        };
+        const double lam0 = lam_carry;
+        if (lam0 <= 0.0) {
             t = solve(hi, st);
+            for (int grow = 0; t > tau && grow < 60; ++grow) {
+                lo = hi;
+                hi = 2.0 * hi;
+                t = solve(hi, st);
+            }
+            keep(hi);
+        } else {
+            t = solve(lam0, st);
+            if (std::fabs(t - tau) <= o.tv_tol) {
+                keep(lam0);
+                hit = true;
+            } else if (t > tau) {
+                lo = lam0;
+                hi = lam0 * 5.0 / 4.0;
+                for (int grow = 0;; ++grow) {
+                    t = solve(hi, st);
+                    if (std::fabs(t - tau) <= o.tv_tol) {
+                        keep(hi);
+                        hit = true;
+                        break;
+                    }
+                    if (t <= tau || grow + 1 >= 60)
+                        break;
+                    lo = hi;
+                    hi = 2.0 * hi;
+                }
+                if (!hit)
+                    keep(hi);
+            } else {
+                hi = lam0;
+                keep(hi);
+                lo = lam0 * 4.0 / 5.0;
+                for (int shrink = 0;; ++shrink) {
+                    t = solve(lo, st);
+                    if (std::fabs(t - tau) <= o.tv_tol) {
+                        keep(lo);
+                        hit = true;
+                        break;
+                    }
+                    if (t > tau)
+                        break;
+                    hi = lo;
+                    keep(hi);
+                    if (shrink + 1 >= 60) {
+                        lo = 0.0;
+                        break;
+                    }
+                    lo = lo / 2.0;
+                }
+            }
         }
-        copy(yp, xp, st);
-        for (int it = 0; it < o.max_bisect; ++it) {
+        for (int it = 0; !hit && it < o.max_bisect; ++it) {
             const double mid = 0.5 * (lo + hi);
             t = solve(mid, st);
             if (std::fabs(t - tau) <= o.tv_tol) {
-                copy(yp, xp, st);
+                keep(mid);
                 break;
             }
             if (t > tau) {
                 lo = mid;
             } else {
                 hi = mid;
-                copy(yp, xp, st);
+                keep(mid);
             }
         }
+        lam_carry = lam;
     }
 
     // out = projection of in onto {TV <= tau} and the orthant (Dykstra).

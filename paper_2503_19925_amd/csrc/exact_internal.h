@@ -298,12 +298,15 @@ hipError_t launch_avg_step(const float *x, float *ring, int R, int J, double *S,
 // x = xbar at the last index reached (s = t + 1).
 hipError_t launch_avg_output(const double *S, float *x, long d, const SolveState *state,
                              hipStream_t st);
-// Power iteration helpers: partials of <v,u>, <v,v>, <u,u>; reduction into
-// state->lam and state->unorm; v = u / unorm (and its transpose).
+// Power iteration helpers: partials of <v,u>, <v,v>, <u,u> (no-op while
+// *skip); reduction into state->lam and state->unorm with the stop test
+// (state->t counts the steps; done at relative change <= rel_tol, at
+// state->max_iters, or with converged = -1 for a non-positive estimate);
+// v = u / unorm (and its transpose), a no-op once done.
 hipError_t launch_dot3(const float *v, const float *u, int N, double *partials,
-                       hipStream_t st);
+                       const int32_t *skip, hipStream_t st);
 hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *state,
-                              hipStream_t st);
+                              double rel_tol, hipStream_t st);
 // v = u / ||u|| (the norm from the state), also into the padded pair.
 hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int N,
                             const SolveState *state, hipStream_t st);

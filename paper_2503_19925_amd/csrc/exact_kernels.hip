@@ -1222,8 +1222,11 @@ __global__ __launch_bounds__(kRedThreads) void kb_finish(const BatchProb *__rest
 
 __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ v,
                                                       const float *__restrict__ u, long d,
-                                                      double *__restrict__ partials)
+                                                      double *__restrict__ partials,
+                                                      const int32_t *__restrict__ skip)
 {
+    if (skipped(skip))
+        return;
     __shared__ double red[3][kRedThreads];
     double a[3] = {0.0, 0.0, 0.0};
     for (long i = blockIdx.x * (long)kRedThreads + threadIdx.x; i < d;
@@ -1241,9 +1244,18 @@ __global__ __launch_bounds__(kRedThreads) void k_dot3(const float *__restrict__ 
     }
 }
 
+// One power-iteration step's Rayleigh quotient lam = <v, u> / <v, v> and
+// ||u|| into the state, and the stop test on the device: done once lam
+// changes by at most rel_tol (relative) from the previous step's, once t
+// reaches max_iters, or at once with converged = -1 if lam is not finite and
+// positive.  No-op once done, so that steps enqueued past the stop change
+// nothing.
 __global__ __launch_bounds__(kRedThreads) void k_dot3_finish(const double *__restrict__ partials,
-                                                             int nparts, SolveState *st)
+                                                             int nparts, SolveState *st,
+                                                             double rel_tol)
 {
+    if (st->done)
+        return;
     __shared__ double red[3][kRedThreads];
     double a[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nparts; q += kRedThreads) {
@@ -1253,8 +1265,23 @@ __global__ __launch_bounds__(kRedThreads) void k_dot3_finish(const double *__res
     }
     block_sum<3>(a, red);
     if (threadIdx.x == 0) {
-        st->lam = a[1] > 0.0 ? a[0] / a[1] : 0.0;
+        const double lam = a[1] > 0.0 ? a[0] / a[1] : 0.0;
         st->unorm = sqrt(a[2]);
+        if (!(isfinite(lam) && lam > 0.0)) {
+            st->lam = lam;
+            st->converged = -1;
+            st->done = 1;
+            return;
+        }
+        const bool conv = st->t >= 1 && fabs(lam - st->lam) <= rel_tol * fabs(lam);
+        st->lam = lam;
+        st->t += 1;
+        if (conv) {
+            st->converged = 1;
+            st->done = 1;
+        } else if (st->t >= st->max_iters) {
+            st->done = 1;
+        }
     }
 }
 
@@ -1264,6 +1291,8 @@ __global__ __launch_bounds__(kTile * 8) void k_normalize(const float *__restrict
                                                          float *__restrict__ vTp, int N,
                                                          const SolveState *__restrict__ st)
 {
+    if (st->done)
+        return;
     __shared__ float tile[kTile][kTile + 1];
     const double nrm = st->unorm;
     const float inv = nrm > 0.0 ? (float)(1.0 / nrm) : 0.f;
@@ -1546,17 +1575,20 @@ int fwd_grouped_resident_blocks_per_cu()
 int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }
 
-hipError_t launch_dot3(const float *v, const float *u, int N, double *partials, hipStream_t st)
+hipError_t launch_dot3(const float *v, const float *u, int N, double *partials,
+                       const int32_t *skip, hipStream_t st)
 {
     const long d = (long)N * N;
-    hipLaunchKernelGGL(k_dot3, dim3(dot_blocks(d)), dim3(kRedThreads), 0, st, v, u, d, partials);
+    hipLaunchKernelGGL(k_dot3, dim3(dot_blocks(d)), dim3(kRedThreads), 0, st, v, u, d, partials,
+                       skip);
     return hipGetLastError();
 }
 
 hipError_t launch_dot3_finish(const double *partials, int nparts, SolveState *state,
-                              hipStream_t st)
+                              double rel_tol, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dot3_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state);
+    hipLaunchKernelGGL(k_dot3_finish, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, state,
+                       rel_tol);
     return hipGetLastError();
 }
 

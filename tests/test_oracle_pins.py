@@ -668,6 +668,51 @@ def test_tv_ball_doubling_and_no_hit_branch(ora):
             np.testing.assert_array_equal(x1, x)
 
 
+def test_tv_ball_warm_start(ora):
+    """The warm-started search (a reading: the paper leaves the search's
+    start open) with lam0 from a previous projection:
+    * at the weight of a hit, the first solve hits again: one solve;
+    * from below (lam0 too small, TV above tau) the bracket grows by 5/4,
+      then doubles; without midpoints the result is xbar(hi) for the first
+      such hi with TV <= tau (or a hit met on the way);
+    * from above (lam0 too large) it shrinks by 4/5, then halves, while TV
+      stays <= tau; without midpoints the result is xbar(hi), hi the
+      smallest weight tried inside the ball;
+    * with midpoints every warm search ends on a hit, |TV - tau| <= tv_tol,
+      and its point is the regularized point at the returned weight."""
+    v = _tv_case()
+    tau = 0.5 * ora.tv_norm(v)
+    x0, lam, ns0 = ora.tv_ball(v, tau)
+    x1, lam1, ns1 = ora.tv_ball(v, tau, lam0=lam)
+    assert ns1 == 1 and lam1 == lam
+    np.testing.assert_array_equal(x1, x0)
+    tv = lambda L: ora.tv_norm(ora.tv_prox(v, L))   # noqa: E731
+    # from below, no midpoints
+    lam0 = 0.3 * lam
+    xb, hb, nb = ora.tv_ball(v, tau, lam0=lam0, max_bisect=0)
+    k = int(round(np.log2(hb / (1.25 * lam0))))
+    assert hb == 1.25 * lam0 * 2.0 ** k and k >= 0 and nb == k + 2
+    np.testing.assert_array_equal(xb, ora.tv_prox(v, hb))
+    assert tv(hb) <= tau + 0.01
+    assert tv(hb / 2 if k > 0 else lam0) > tau
+    # from above, no midpoints
+    lam0 = 5.0 * lam
+    xa, ha, na = ora.tv_ball(v, tau, lam0=lam0, max_bisect=0)
+    tried = [lam0] + [0.8 * lam0 * 0.5 ** j for j in range(na - 1)]
+    assert na >= 2 and all(tv(L) <= tau for L in tried[:-1])
+    last = tv(tried[-1])
+    if abs(last - tau) <= 0.01:
+        assert ha == tried[-1]                    # a hit while shrinking
+    else:
+        assert last > tau and ha == tried[-2]     # the last left the ball
+    np.testing.assert_array_equal(xa, ora.tv_prox(v, ha))
+    # with midpoints: a hit, from either side
+    for lam0 in (0.3 * lam, 0.9 * lam, 1.1 * lam, 5.0 * lam):
+        xw, lw, nw = ora.tv_ball(v, tau, lam0=lam0)
+        assert abs(ora.tv_norm(xw) - tau) <= 0.01
+        np.testing.assert_array_equal(xw, ora.tv_prox(v, lw))
+
+
 def test_tv_orthant_projection_properties(ora):
     """Dykstra's projection onto {TV <= tau} and the orthant: the result is
     feasible (x >= 0, TV <= tau + tv_tol) and satisfies the projection
