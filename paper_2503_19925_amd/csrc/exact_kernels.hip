@@ -486,10 +486,10 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
 {
     if (skipped(skip))
         return;
-    // The step's first kernel hides the previous step's finish in its last
-    // workgroup (the lightest block of the dispatch order): the finish runs
-    // if one is pending, and this step's is marked pending unless the run
-    // has just stopped.  Nothing that reads the stop flag runs before this
+    // The step's first kernel hides the previous step's finish in one more
+    // workgroup after the projection's, dispatched last: the finish runs if
+    // one is pending, and this step's is marked pending unless the run has
+    // just stopped.  Nothing that reads the stop flag runs before this
     // kernel ends; its other workgroups may compute a residual that no
     // later kernel uses.
     if (kResid && fin.state && blockIdx.x == gridDim.x - 1) {
@@ -497,6 +497,7 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
                                                  fin.n_avg, fin.state);
         if (threadIdx.x == 0 && !fin.state->done)
             fin.state->pending = 1;
+        return;
     }
     const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
     const int it = order[blockIdx.x];
@@ -1380,11 +1381,13 @@ hipError_t launch_forward_any(const Geo &g, const float *xp, const float *xTp, c
                                ostride, ooff, weighted ? 1 : 0, plain, skip, fin);
     }
     const int nblocks = g.ngroups > 0 ? g.nleft : ((g.B + kFwdThreads - 1) / kFwdThreads) * g.V;
+    const FinishArgs &f = g.ngroups > 0 ? nofin : fin;
+    // with a finish, one more workgroup (the last) runs it
     if (nblocks > 0)
-        hipLaunchKernelGGL(k_forward<kResid>, dim3(nblocks), dim3(kFwdThreads * kSegs), 0, st,
-                           g.views, g.blk, g.ngroups > 0 ? g.left : g.order, g.N, g.V, g.B, g.nrow,
-                           xp, xTp, Y, sp, out, ostride, ooff, weighted ? 1 : 0, plain, skip,
-                           g.ngroups > 0 ? nofin : fin);
+        hipLaunchKernelGGL(k_forward<kResid>, dim3(nblocks + (f.state ? 1 : 0)),
+                           dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
+                           g.ngroups > 0 ? g.left : g.order, g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp,
+                           out, ostride, ooff, weighted ? 1 : 0, plain, skip, f);
     return hipGetLastError();
 }
 
