@@ -174,7 +174,7 @@ def cmd_kernels(out_dir):
           "512x512 image, 180 views over 180 deg, 725 bins, K=30 energy bins, 3 windows.",
           "One EG step is a captured graph of four kernels: k_forward<true> (forward",
           "projection + spectral residual at x_t, written weighted into the padded",
-          "residual; its last workgroup also runs the previous step's finish),",
+          "residual; one more workgroup, dispatched last, runs the previous step's finish),",
           "k_back_update<true, true, false> (back-projection + half-step update +",
           "residual partials; the bin-pair rule, clamp-free on this covered geometry),",
           "k_forward<true> at x_{t+1/2} and k_back_update<true, false, false>",
@@ -206,7 +206,7 @@ def cmd_kernels(out_dir):
            "(and the standalone k_eg_finish<false> %.2f us); the graph's four kernels sum to" % fin,
            "%.1f us per step, %.1f us short of the replayed step: the gaps between the"
            % (tot, b["ms_per_step"] * 1e3 - tot),
-           "graph's kernels and what the finish adds to the first kernel's last workgroup."]
+           "graph's kernels and the finish workgroup of the first kernel."]
     with open(os.path.join(PROFILES, "kernels_solve_512.md"), "w") as f:
         f.write("\n".join(md) + "\n")
 
@@ -321,7 +321,7 @@ def cmd_utilisation(pmc_dir):
                                            "ta_busy_frac")}
         md.append("")
     md += ["Reading.  At 1024² the back-projection + update kernels issue VALU",
-           "instructions at about 95 % of the peak rate, so they are bound by",
+           "instructions at about 91 % of the peak rate, so they are bound by",
            "instruction issue; at 512² the same loop reaches about 60 %, the rest going",
            "to the start and end of a grid that runs as a single round of waves.  The",
            "forward keeps its address and data-return units (TA, TD) the busiest, the",
