@@ -284,26 +284,38 @@ def tv_leg(P, gamma, steps, torch, exact, synth):
     info = exact.exact_project_tv(zt, tau, out)
     fgp_steps = info["solves"] * 100
     per_step_ms = info["ms"] / max(fgp_steps, 1)
-    bytes_step = 36.0 * N * N       # b, r, s, p, q read; p, q, r', s' written
     res = {"tau": tau, "projection_ms": info["ms"], "rounds": info["rounds"],
            "prox_solves": info["solves"], "ms_per_fgp_step": per_step_ms,
-           "fgp_step_roofline": {"bound": "hbm", "achieved": bytes_step / (per_step_ms * 1e-3) / 1e9,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": bytes_step / (per_step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                 "note": "wall time per step including launch gaps and the "
-                                         "host-driven search; 36 B per pixel per step"}}
+           "fgp_note": "wall time of the projection per FGP step (searches, Dykstra rounds and "
+                       "launch gaps included); a launch takes 8 steps with the state in LDS, so "
+                       "HBM moves 36 B per pixel per launch, not per step: the steps are bound "
+                       "by the workgroups' arithmetic and barriers, not by HBM"}
     log("tv projection at %d^2: %.1f ms, %d rounds, %d solves" % (N, info["ms"], info["rounds"],
                                                                   info["solves"]))
     if steps > 0:
+        # `steps` EG steps from the noisy start, and the same run cut at its
+        # first two steps (deterministic, so the difference is the cost of
+        # the later steps); the first steps carry the searches' cold start
         g = exact.Geometry(P.n_pix, P.n_views, P.n_bins)
         y = torch.as_tensor(P.y, device="cuda")
-        x = torch.as_tensor(z, device="cuda")
-        sinfo, tinfo = exact.exact_solve_tv(g, P.mu, P.I, y, x, tau, gamma=gamma, max_iters=steps)
+        runs = {}
+        for n in sorted({min(2, steps), steps}):
+            x = torch.as_tensor(z, device="cuda")
+            runs[n] = exact.exact_solve_tv(g, P.mu, P.I, y, x, tau, gamma=gamma, max_iters=n)
         g.close()
+        sinfo, tinfo = runs[steps]
         res.update({"eg_steps": sinfo["iters"], "ms_per_eg_step": sinfo["ms"] / max(sinfo["iters"], 1),
                     "eg_prox_solves": tinfo["solves"], "tv_after": tinfo["tv"]})
-        log("tv EG: %d steps, %.1f ms/step, %d solves" % (sinfo["iters"], res["ms_per_eg_step"],
-                                                          tinfo["solves"]))
+        s2, t2 = runs[min(2, steps)]
+        res["first_steps"] = {"steps": s2["iters"], "ms_per_eg_step": s2["ms"] / max(s2["iters"], 1),
+                              "prox_solves": t2["solves"]}
+        if steps > 2:
+            k = sinfo["iters"] - s2["iters"]
+            res["later_steps"] = {"steps": k, "ms_per_eg_step": (sinfo["ms"] - s2["ms"]) / max(k, 1),
+                                  "prox_solves_per_step": (tinfo["solves"] - t2["solves"]) / max(k, 1)}
+        log("tv EG: %d steps, %.1f ms/step, %d solves (first %d steps %.1f ms/step)" % (
+            sinfo["iters"], res["ms_per_eg_step"], tinfo["solves"], s2["iters"],
+            res["first_steps"]["ms_per_eg_step"]))
     return res
 
 
@@ -475,7 +487,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="scans in the batched leg (0 to skip)")
     ap.add_argument("--dense-steps", type=int, default=50,
                     help="EG steps of the dense Gaussian-model leg (0 skips it)")
-    ap.add_argument("--tv-steps", type=int, default=2,
+    ap.add_argument("--tv-steps", type=int, default=8,
                     help="EG steps over the TV ball and orthant after one projection "
                          "(-1 skips the TV leg)")
     ap.add_argument("--background-steps", type=int, default=100,

@@ -1747,61 +1747,59 @@ void validate_tv_opts(const exact_tv_opts &o)
 }
 
 // Device work of the TV projection for one image size: the FGP fields, the
-// TV-ball and Dykstra buffers, the TV weight and reduction results, and the
-// captured graph of one TV-regularized solve (input w, output x, weight
-// read from `lam`).
+// TV-ball and Dykstra buffers and the reduction results.  A proximal solve
+// is a short run of kernel launches (the weight a kernel argument) ending in
+// the point's TV, which the last kernel writes to pinned host memory; the
+// host waits for the stream and reads it.  A search keeps its current
+// result in one of two output buffers and solves into the other, so keeping
+// a point moves no data.
 struct TvWork {
     int N = 0;
     long d = 0;
     exact_tv_opts o;
-    std::unique_ptr<DevBuf> p, q, r, s, p2, q2, r2, s2, x, y, w, z, dp, dq, lam, parts, out;
-    double *h = nullptr;       // pinned: [0] lam to upload, [1..2] read back
-    Graph prox;
+    std::unique_ptr<DevBuf> p, q, r, s, p2, q2, r2, s2, xb[2], w, z, dp, dq, parts;
+    double *h = nullptr;       // pinned, coherent: [1..2] reduction results
+    double *hd = nullptr;      // its device address
     int solves = 0;
 
-    TvWork(int n, const exact_tv_opts &opts, hipStream_t st) : N(n), d((long)n * n), o(opts)
+    TvWork(int n, const exact_tv_opts &opts, hipStream_t) : N(n), d((long)n * n), o(opts)
     {
-        for (auto *b : {&p, &q, &r, &s, &p2, &q2, &r2, &s2, &x, &y, &w, &z, &dp, &dq})
+        for (auto *b : {&p, &q, &r, &s, &p2, &q2, &r2, &s2, &xb[0], &xb[1], &w, &z, &dp, &dq})
             b->reset(new DevBuf((size_t)d * 4));
-        lam.reset(new DevBuf(8));
         const int np = std::max(exact::num_tv_parts(n), 2 * exact::num_flat_parts(d));
         parts.reset(new DevBuf((size_t)np * 8));
-        out.reset(new DevBuf(16));
-        hip_check(hipHostMalloc((void **)&h, 32, hipHostMallocDefault), "hipHostMalloc");
-        prox.capture(st, [&]() {
-            return exact::launch_prox_graph_body(
-                w->as<float>(), p->as<float>(), q->as<float>(), r->as<float>(), s->as<float>(),
-                p2->as<float>(), q2->as<float>(), r2->as<float>(), s2->as<float>(),
-                lam->as<double>(), o.prox_iters, x->as<float>(), N, st);
-        });
+        hip_check(hipHostMalloc((void **)&h, 32, hipHostMallocMapped | hipHostMallocCoherent),
+                  "hipHostMalloc");
+        hip_check(hipHostGetDevicePointer((void **)&hd, h, 0), "hipHostGetDevicePointer");
     }
     ~TvWork()
     {
-        prox.reset();
         if (h)
             (void)hipHostFree(h);
     }
 
-    double read1(hipStream_t st)
+    // The reduction result(s) the stream's last kernels wrote to h[1..2].
+    double sync1(hipStream_t st)
     {
-        hip_check(hipMemcpyAsync(h + 1, out->p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         return h[1];
     }
     double tv_of(const float *img, hipStream_t st)
     {
-        hip_check(exact::launch_tv_norm(img, N, parts->as<double>(), out->as<double>(), st),
-                  "tv_norm");
-        return read1(st);
+        hip_check(exact::launch_tv_norm(img, N, parts->as<double>(), hd + 1, st), "tv_norm");
+        return sync1(st);
     }
-    // x = TV-regularized point of w for weight l; returns TV(x).
-    double solve(double l, hipStream_t st)
+    // xb[k] = TV-regularized point of w for weight l; returns TV(xb[k]).
+    double solve(int k, double l, hipStream_t st)
     {
-        h[0] = l;
-        hip_check(hipMemcpyAsync(lam->p, h, 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
-        hip_check(hipGraphLaunch(prox.exec, st), "graph launch");
+        hip_check(exact::launch_prox(w->as<float>(), p->as<float>(), q->as<float>(),
+                                     r->as<float>(), s->as<float>(), p2->as<float>(),
+                                     q2->as<float>(), r2->as<float>(), s2->as<float>(), l,
+                                     o.prox_iters, xb[k]->as<float>(), N, parts->as<double>(),
+                                     hd + 1, st),
+                  "prox");
         ++solves;
-        return tv_of(x->as<float>(), st);
+        return sync1(st);
     }
     void copy(float *dst, const float *src, hipStream_t st)
     {
@@ -1813,33 +1811,35 @@ struct TvWork {
     // next search starts there.
     double lam_carry = 0.0;
 
-    // y = approximate projection of w onto {TV <= tau} (binary search on
-    // the TV weight, cold or warm-started from lam_carry, the decisions of
-    // the definition in the header).
-    void tv_ball(double tau, hipStream_t st)
+    // Approximate projection of w onto {TV <= tau} (binary search on the TV
+    // weight, cold or warm-started from lam_carry, the decisions of the
+    // definition in the header), given tw = TV(w).  Returns the buffer that
+    // holds the result: w itself, or xb[0] or xb[1].
+    const float *tv_ball(double tau, double tw, hipStream_t st)
     {
-        float *wp = w->as<float>(), *xp = x->as<float>(), *yp = y->as<float>();
-        if (tv_of(wp, st) <= tau) {
-            copy(yp, wp, st);
-            return;
-        }
+        if (tw <= tau)
+            return w->as<float>();
+        int cur = 0;               // the buffer the next solve writes
+        const float *res = nullptr;
         double lo = 0.0, hi = 1.0, t = 0.0, lam = 0.0;
         bool hit = false;
-        auto keep = [&](double l) {               // y = xbar(l), the result so far
-            copy(yp, xp, st);
+        auto sol = [&](double l) { return solve(cur, l, st); };
+        auto keep = [&](double l) {   // the last solve's point is the result so far
+            res = xb[cur]->as<float>();
+            cur ^= 1;
             lam = l;
         };
         const double lam0 = lam_carry;
         if (lam0 <= 0.0) {
-            t = solve(hi, st);
+            t = sol(hi);
             for (int grow = 0; t > tau && grow < 60; ++grow) {
                 lo = hi;
                 hi = 2.0 * hi;
-                t = solve(hi, st);
+                t = sol(hi);
             }
             keep(hi);
         } else {
-            t = solve(lam0, st);
+            t = sol(lam0);
             if (std::fabs(t - tau) <= o.tv_tol) {
                 keep(lam0);
                 hit = true;
@@ -1847,7 +1847,7 @@ struct TvWork {
                 lo = lam0;
                 hi = lam0 * 5.0 / 4.0;
                 for (int grow = 0;; ++grow) {
-                    t = solve(hi, st);
+                    t = sol(hi);
                     if (std::fabs(t - tau) <= o.tv_tol) {
                         keep(hi);
                         hit = true;
@@ -1865,7 +1865,7 @@ struct TvWork {
                 keep(hi);
                 lo = lam0 * 4.0 / 5.0;
                 for (int shrink = 0;; ++shrink) {
-                    t = solve(lo, st);
+                    t = sol(lo);
                     if (std::fabs(t - tau) <= o.tv_tol) {
                         keep(lo);
                         hit = true;
@@ -1885,7 +1885,7 @@ struct TvWork {
         }
         for (int it = 0; !hit && it < o.max_bisect; ++it) {
             const double mid = 0.5 * (lo + hi);
-            t = solve(mid, st);
+            t = sol(mid);
             if (std::fabs(t - tau) <= o.tv_tol) {
                 keep(mid);
                 break;
@@ -1898,6 +1898,7 @@ struct TvWork {
             }
         }
         lam_carry = lam;
+        return res;
     }
 
     // out = projection of in onto {TV <= tau} and the orthant (Dykstra).
@@ -1910,13 +1911,15 @@ struct TvWork {
         hip_check(hipMemsetAsync(qp, 0, (size_t)d * 4, st), "hipMemsetAsync");
         int k = 0;
         while (k < o.max_outer) {
-            hip_check(exact::launch_dyk_pre(zp, pp, w->as<float>(), d, st), "dyk_pre");
-            tv_ball(tau, st);
-            hip_check(exact::launch_dyk_post(w->as<float>(), y->as<float>(), pp, qp, zp, d,
-                                             parts->as<double>(), out->as<double>(), st),
+            hip_check(exact::launch_dyk_pre(zp, pp, w->as<float>(), N, parts->as<double>(),
+                                            hd + 1, st),
+                      "dyk_pre");
+            const float *y = tv_ball(tau, sync1(st), st);
+            hip_check(exact::launch_dyk_post(w->as<float>(), y, pp, qp, zp, d,
+                                             parts->as<double>(), hd + 1, st),
                       "dyk_post");
             ++k;
-            if (std::sqrt(read1(st)) <= o.dyk_tol)
+            if (std::sqrt(sync1(st)) <= o.dyk_tol)
                 break;
         }
         copy(outp, zp, st);
@@ -1990,8 +1993,8 @@ int exact_tv_prox(int32_t n_pix, const float *b_dev, double lam, int32_t iters, 
         }
         TvWork W(n_pix, o, own.st);
         W.copy(W.w->as<float>(), b_dev, own.st);
-        W.solve(lam, own.st);
-        W.copy(x_dev, W.x->as<float>(), own.st);
+        W.solve(0, lam, own.st);
+        W.copy(x_dev, W.xb[0]->as<float>(), own.st);
         hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
         return 0;
     });
@@ -2069,10 +2072,8 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
                                              g->N, st),
                       "pad_pair");
             hip_check(exact::launch_diff2(xh.as<float>(), x_dev, d, W.parts->as<double>(),
-                                          W.out->as<double>(), st),
+                                          W.hd + 1, st),
                       "diff2");
-            hip_check(hipMemcpyAsync(W.h + 1, W.out->p, 16, hipMemcpyDeviceToHost, st),
-                      "hipMemcpyAsync");
             hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
             rho = W.h[2] > 0.0 ? std::sqrt(W.h[1] / W.h[2]) : -1.0;
             gradient(p.xhp->as<float>(), p.xhTp->as<float>());

@@ -316,17 +316,21 @@ hipError_t launch_normalize(const float *u, float *v, float *vp, float *vTp, int
 int num_tv_parts(int N);        // partial sums of k_tv_parts
 int num_flat_parts(long d);     // partial sums of the flat reductions
 // One TV-regularized point x = argmin ||x - b||^2 + lam TV(x) by `iters`
-// FGP steps from zero; lam is read on the device.  p, q, r, s and p2, q2,
-// r2, s2 are work fields of N*N floats (the state alternates between the
-// two sets).  Launch sequence only (capturable).
-hipError_t launch_prox_graph_body(const float *b, float *p, float *q, float *r, float *s,
-                                  float *p2, float *q2, float *r2, float *s2, const double *lam,
-                                  int iters, float *x, int N, hipStream_t st);
-// out[0] = TV(x) in double (parts: num_tv_parts(N) doubles).
+// (>= 1) FGP steps from zero, and out[0] = TV(x) in double (parts:
+// num_tv_parts(N)).  p, q, r, s and p2, q2, r2, s2 are work fields of N*N
+// floats (the state alternates between the two sets); out may be pinned
+// host memory's device address.  Launch sequence only.
+hipError_t launch_prox(const float *b, float *p, float *q, float *r, float *s, float *p2,
+                       float *q2, float *r2, float *s2, double lam, int iters, float *x, int N,
+                       double *parts, double *out, hipStream_t st);
+// out[0] = TV(x) in double (parts: num_tv_parts(N) doubles; out may be
+// pinned host memory's device address, as for the Dykstra sums below).
 hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st);
-// Dykstra's round around the TV projection: w = z + p before it; after it
-// p = w - y, z = max(0, y + q), q = y + q - z and out[0] = ||z_new - z_old||^2.
-hipError_t launch_dyk_pre(const float *z, const float *p, float *w, long d, hipStream_t st);
+// Dykstra's round around the TV projection: w = z + p and out[0] = TV(w)
+// before it (parts: num_tv_parts(N)); after it p = w - y, z = max(0, y + q),
+// q = y + q - z and out[0] = ||z_new - z_old||^2.
+hipError_t launch_dyk_pre(const float *z, const float *p, float *w, int N, double *parts,
+                          double *out, hipStream_t st);
 hipError_t launch_dyk_post(const float *w, const float *y, float *p, float *q, float *z, long d,
                            double *parts, double *out, hipStream_t st);
 // z = x - gamma g.
