@@ -56,15 +56,19 @@ WORKLOADS = {
                   "1448 bins, 64 energy bins, 4 windows, I0=1e3 Poisson",
 }
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak: 256 CUs x 64 lanes (4 SIMDs of 16, one wave64 instruction
-# per 4 cycles each, packed FP32 not used) x 2.4 GHz, in T lane-instructions/s
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU issue peak: the published FP32 vector rate, 157.3 TFLOP/s = 78.6 T
+# lane-operations/s (256 CUs x 4 SIMDs x one wave64 instruction per 2 cycles
+# x 2.4 GHz).  Measured on MI355X, two-operand 32-bit instructions issue at
+# that rate, while the three-operand FP32 FMA and the FP64 add and fract take
+# 4 cycles; so for a kernel's mix this peak is an upper bound, and its
+# fraction a lower bound.
+VALU_PEAK_TOPS = 256 * 4 * 64 * 2.4e9 / 2 / 1e12
 # VALU instructions of the inner loops, counted in their gfx950 assembly
 # (Kahan steps included): per pixel and view in the gather (clamp-free
 # form, which the benchmark geometry uses), per ray and line in the forward.
 # Used only when no counter reading of the current build is committed.
 VALU_PER_PIXEL_VIEW = 14.0
-VALU_PER_RAY_LINE = 11.0
+VALU_PER_RAY_LINE = 12.5
 KERNEL_FWD = "k_forward<true>"
 KERNEL_BU = "k_back_update"
 
@@ -196,6 +200,11 @@ def kernel_roofline(name, workload, ms, static_valu, alg_bytes):
     traffic = measured_traffic(workload, name)
     rec = {"kernel": name, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
            "unit": "T VALU lane-instructions/s", "frac": achieved / VALU_PEAK_TOPS,
+           "frac_at_4_cycles": 2.0 * achieved / VALU_PEAK_TOPS,
+           "peak_note": "published FP32 vector rate (one wave64 instruction per 2 cycles per "
+                        "SIMD); the FP64 crossing arithmetic and three-operand FMAs issue at "
+                        "one per 4 cycles, against which frac_at_4_cycles is taken: the "
+                        "kernel's mix bound lies between the two",
            "traffic": traffic, "ms_per_launch": ms,
            "valu_lane_instr_per_launch": valu, "valu_source": src,
            "hbm": None if traffic is None else {

@@ -188,7 +188,7 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp,
  * call's scratch (the window sums of y, the padded image and its transpose,
  * the padded residual) lives in a static device array of
  * EXACT_NOALLOC_SCRATCH_MIB MiB, one per GPU the library runs on, held
- * until the process ends.  Needs 4 (V B + 2 N (N + 4) + V (B + 4)) bytes
+ * until the process ends.  Needs 4 (V B + 2 (N (N + 8) + 64) + V (B + 4)) bytes
  * (each part rounded up to 256) of it, else -ENOSPC (1024^2 with 720 views
  * x 1448 bins needs 17 MB).  The geometry must belong to the current
  * device (-EINVAL).  Every call on a GPU shares that GPU's array, which

@@ -29,9 +29,6 @@ struct exact_geometry_s {
     int device;
     ViewGeom *d_views;
     int32_t *d_blk, *d_order;
-    exact::FwdGroup *d_groups;
-    int32_t *d_left;
-    int ngroups, nleft;
     std::vector<ViewGeom> h_views;
 };
 
@@ -73,8 +70,8 @@ int guarded(F &&body)
 
 Geo geo_of(const exact_geometry_s *g)
 {
-    return Geo{g->d_views, g->d_blk, g->d_order, g->N,      g->V,       g->B,     g->nrow,
-               g->reach,   g->covers, g->d_groups, g->ngroups, g->d_left, g->nleft};
+    return Geo{g->d_views, g->d_blk, g->d_order, g->N,     g->V,
+               g->B,       g->nrow,  g->reach,   g->covers};
 }
 
 void check_geometry(const exact_geometry_s *g)
@@ -188,22 +185,23 @@ std::vector<ViewGeom> build_views(int N, int V, int B, int half_turns, double pi
     return out;
 }
 
-// First and last image line that any ray of each block of 64 bins reaches,
-// per table slot (the forward projector splits these lines among its
-// waves).  Ray b of a view crosses line k at f = A + b P + k Q and has a tap
-// inside the image iff floor(f) is in [-1, N - 1], i.e. f in [-1, N); the
-// line interval of one ray is taken one line wider on each side.  The
+// First and last image line that any ray of each block of kFwdRays bins
+// reaches, per table slot (the forward projector splits these lines among
+// its waves).  Ray b of a view crosses line k at f = A + b P + k Q and has
+// a tap inside the image iff floor(f) is in [-1, N - 1], i.e. f in [-1, N);
+// the line interval of one ray is taken one line wider on each side.  The
 // interval's ends are affine in b, so over a block they are extreme at its
 // first or last ray; the union of the rays' intervals lies within the hull
 // of those two.  A block no ray of which reaches a line gets first > last.
 std::vector<int32_t> block_lines(const std::vector<ViewGeom> &views, int N, int B)
 {
-    const int nbb = (B + 63) / 64;
+    const int R = exact::kFwdRays, nbb = (B + R - 1) / R;
     std::vector<int32_t> out(2 * views.size() * (size_t)nbb);
     for (size_t slot = 0; slot < views.size(); ++slot) {
         const ViewGeom &G = views[slot];
         for (int bb = 0; bb < nbb; ++bb) {
-            const long double ends[2] = {64.0L * bb, (long double)std::min(64 * bb + 63, B - 1)};
+            const long double ends[2] = {(long double)R * bb,
+                                         (long double)std::min(R * bb + R - 1, B - 1)};
             long double lo = 1e30L, hi = -1e30L;
             if (G.Q != 0.0) {
                 for (long double b : ends) {
@@ -273,142 +271,6 @@ std::vector<int32_t> balanced_order(const std::vector<long> &w, int cus, int per
     for (long r = first; r < n; ++r)
         order[(size_t)r] = idx[(size_t)r];
     return order;
-}
-
-// One group of the grouped forward (exact::FwdGroup): views slot0 ..
-// slot0 + n - 1 and bin block bb.  For each segment s, every view with
-// lines there takes lines kw0 .. kw1 of it, as the kernels split the
-// block's line range, in batches of L lines; a view whose kw0 is kbase + d
-// runs its batch i at step i + d / L on window lines d mod L + q.  The
-// group is formed only if the step offsets add at most a quarter (at least
-// two steps) to the longest view's steps, and one window of kWinCols
-// columns, moving by c1 per step, holds every crossing of every ray of the
-// block (including the lanes past the detector's last bin) on the lines of
-// each step.  The crossing of ray b on line k is A + bP + kQ (+ kPadX,
-// padded), affine in b and in the step, so the extremes over a step are at
-// b in {64 bb, 64 bb + 63} and the batch's first and last line, and over a
-// view's steps at its first and last; the window's start c0 + c1 j keeps a
-// column (and 1e-6 for the device's rounding of it) below every crossing
-// and W - 3 columns above it.  Returns false if the group does not fit.
-bool make_group(const std::vector<ViewGeom> &views, const std::vector<int32_t> &blk, int B,
-                int slot0, int n, int bb, exact::FwdGroup *out)
-{
-    const int nbb = (B + 63) / 64, L = exact::kFwdLineBatch, S = exact::kFwdSegs;
-    exact::FwdGroup Gr;
-    std::memset(&Gr, 0, sizeof(Gr));
-    Gr.slot0 = slot0;
-    Gr.nv = n;
-    Gr.bb = bb;
-    for (int s = 0; s < S; ++s) {
-        int kw0[8], cnt[8], kbase = 1 << 30, smax = 0;
-        long double qsum = 0.0L;
-        int nonempty = 0;
-        for (int w = 0; w < n; ++w) {
-            cnt[w] = 0;
-            const size_t bi = 2 * ((size_t)(slot0 + w) * nbb + bb);
-            const int kmin = blk[bi], kmax = blk[bi + 1];
-            if (kmin > kmax)
-                continue;
-            const int per = (kmax - kmin + S) / S;
-            const int a = kmin + s * per, e = std::min(kmax, a + per - 1);
-            if (e < a)
-                continue;
-            kw0[w] = a;
-            cnt[w] = e - a + 1;
-            kbase = std::min(kbase, a);
-            smax = std::max(smax, (cnt[w] + L - 1) / L);
-            qsum += (long double)views[(size_t)(slot0 + w)].Q;
-            ++nonempty;
-        }
-        if (nonempty == 0)
-            continue;
-        int J = 0, dmax = 0;
-        for (int w = 0; w < n; ++w)
-            if (cnt[w] > 0) {
-                J = std::max(J, (kw0[w] - kbase) / L + (cnt[w] + L - 1) / L);
-                dmax = std::max(dmax, (kw0[w] - kbase) % L);
-            }
-        if (J > smax + std::max(2, smax / 4))
-            return false;
-        const long double qbar = qsum / nonempty;
-        long double lo = 1e30L, hi = -1e30L;
-        for (int w = 0; w < n; ++w) {
-            if (cnt[w] == 0)
-                continue;
-            const ViewGeom &G = views[(size_t)(slot0 + w)];
-            const int steps = (cnt[w] + L - 1) / L, off = (kw0[w] - kbase) / L;
-            for (int cb = 0; cb < 2; ++cb)
-                for (int cq = 0; cq < 2; ++cq)
-                    for (int cj = 0; cj < 2; ++cj) {
-                        // ray b on line kw0 + L i + q at step j = i + off
-                        const long double b = 64.0L * bb + (cb ? 63 : 0);
-                        const long double i = cj ? steps - 1 : 0;
-                        const long double k = (long double)kw0[w] + (cq ? L - 1 : 0) + L * i;
-                        const long double j = i + off;
-                        const long double x = (long double)G.A + b * (long double)G.P +
-                                              k * (long double)G.Q + exact::kPadX -
-                                              j * L * qbar;
-                        lo = std::min(lo, x);
-                        hi = std::max(hi, x);
-                    }
-        }
-        if (!(hi - lo + 4.0L + 2e-6L <= (long double)exact::kWinCols))
-            return false;
-        Gr.kbase[s] = kbase;
-        Gr.nsteps[s] = J;
-        Gr.rows[s] = L + dmax;
-        Gr.c0[s] = (double)(lo - 1.0L - 1e-6L);
-        Gr.c1[s] = (double)(L * qbar);
-        Gr.weight = std::max(Gr.weight, J);
-    }
-    *out = Gr;
-    return true;
-}
-
-// The grouped forward's work: for each stepping class and bin block, the
-// class's views are taken in table order, each time the largest group
-// (kGroupViews down to 2 views) that make_group accepts; a view no group
-// takes leaves its block (slot nbb + block) to the ungrouped kernel.  Groups
-// go longest first; the left blocks in the ungrouped kernel's balanced
-// order.  No groups when the padded image is narrower than the window.
-void forward_groups(const std::vector<ViewGeom> &views, const std::vector<int32_t> &blk, int N,
-                    int B, int nrow, int cus, int per_cu, std::vector<exact::FwdGroup> *groups,
-                    std::vector<int32_t> *left)
-{
-    const int nbb = (B + 63) / 64, V = (int)views.size();
-    const bool fits = exact::padded_cols(N) >= exact::kWinCols && exact::kGroupViews >= 2;
-    std::vector<int32_t> rest;
-    for (int cls = 0; cls < 2; ++cls) {
-        const int lo = cls == 0 ? 0 : nrow, hi = cls == 0 ? nrow : V;
-        for (int bb = 0; bb < nbb; ++bb) {
-            for (int i = lo; i < hi;) {
-                int took = 0;
-                for (int n = std::min(exact::kGroupViews, hi - i); fits && n >= 2 && !took; --n) {
-                    exact::FwdGroup Gr;
-                    if (make_group(views, blk, B, i, n, bb, &Gr)) {
-                        groups->push_back(Gr);
-                        took = n;
-                    }
-                }
-                if (!took) {
-                    rest.push_back(i * nbb + bb);
-                    took = 1;
-                }
-                i += took;
-            }
-        }
-    }
-    std::stable_sort(groups->begin(), groups->end(),
-                     [](const exact::FwdGroup &a, const exact::FwdGroup &b) {
-                         return a.weight > b.weight;
-                     });
-    std::vector<long> w(rest.size());
-    for (size_t i = 0; i < rest.size(); ++i)
-        w[i] = block_weight(blk, (size_t)rest[i]);
-    const std::vector<int32_t> ord = balanced_order(w, cus, per_cu);
-    left->resize(rest.size());
-    for (size_t i = 0; i < rest.size(); ++i)
-        (*left)[i] = rest[(size_t)ord[i]];
 }
 
 // CUs of the current device and forward workgroups each holds at once.
@@ -520,7 +382,7 @@ double power_iteration(const exact_geometry_s *g, int max_iters, hipStream_t st,
     const Geo G = geo_of(g);
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
     const int nparts = exact::num_dot_parts(d);
-    const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+    const size_t dp = (size_t)exact::padded_image_floats(g->N);
     const size_t np = (size_t)g->V * exact::padded_bins(g->B);
     DevBuf v(d * 4), vp(dp * 4), vTp(dp * 4), u(d * 4), s(np * 4), parts(nparts * 3 * 8),
         state(sizeof(SolveState));
@@ -614,10 +476,6 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
         g->d_views = nullptr;
         g->d_blk = nullptr;
         g->d_order = nullptr;
-        g->d_groups = nullptr;
-        g->d_left = nullptr;
-        g->ngroups = 0;
-        g->nleft = 0;
         try {
             hip_check(hipGetDevice(&g->device), "hipGetDevice");
             g->h_views = build_views(n_pix, n_views, n_bins, half_turns, pixel_cm, bin_cm,
@@ -642,25 +500,6 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
             hip_check(hipMemcpy(g->d_order, order.data(), order.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
                       "hipMemcpy");
-            std::vector<exact::FwdGroup> groups;
-            std::vector<int32_t> left;
-            forward_groups(g->h_views, blk, n_pix, n_bins, g->nrow, cus,
-                           exact::fwd_grouped_resident_blocks_per_cu(), &groups, &left);
-            g->ngroups = (int)groups.size();
-            g->nleft = (int)left.size();
-            if (g->ngroups > 0) {
-                hip_check(hipMalloc((void **)&g->d_groups, groups.size() * sizeof(exact::FwdGroup)),
-                          "hipMalloc");
-                hip_check(hipMemcpy(g->d_groups, groups.data(),
-                                    groups.size() * sizeof(exact::FwdGroup), hipMemcpyHostToDevice),
-                          "hipMemcpy");
-            }
-            if (g->nleft > 0) {
-                hip_check(hipMalloc((void **)&g->d_left, left.size() * sizeof(int32_t)), "hipMalloc");
-                hip_check(hipMemcpy(g->d_left, left.data(), left.size() * sizeof(int32_t),
-                                    hipMemcpyHostToDevice),
-                          "hipMemcpy");
-            }
         } catch (...) {
             if (g->d_views)
                 (void)hipFree(g->d_views);
@@ -668,10 +507,6 @@ int exact_geometry_create(int32_t n_pix, int32_t n_views, int32_t n_bins, int32_
                 (void)hipFree(g->d_blk);
             if (g->d_order)
                 (void)hipFree(g->d_order);
-            if (g->d_groups)
-                (void)hipFree(g->d_groups);
-            if (g->d_left)
-                (void)hipFree(g->d_left);
             delete g;
             throw;
         }
@@ -688,11 +523,9 @@ int exact_geometry_destroy(exact_geometry g)
         // the handle and its tables are released whatever a free reports
         std::unique_ptr<exact_geometry_s> own(g);
         (void)hipDeviceSynchronize();
-        const hipError_t e[5] = {g->d_views ? hipFree(g->d_views) : hipSuccess,
+        const hipError_t e[3] = {g->d_views ? hipFree(g->d_views) : hipSuccess,
                                  g->d_blk ? hipFree(g->d_blk) : hipSuccess,
-                                 g->d_order ? hipFree(g->d_order) : hipSuccess,
-                                 g->d_groups ? hipFree(g->d_groups) : hipSuccess,
-                                 g->d_left ? hipFree(g->d_left) : hipSuccess};
+                                 g->d_order ? hipFree(g->d_order) : hipSuccess};
         for (hipError_t x : e)
             hip_check(x, "hipFree");
         return 0;
@@ -706,7 +539,7 @@ int exact_forward(exact_geometry g, const float *x_dev, float *s_dev, void *stre
         if (!x_dev || !s_dev)
             fail(-EINVAL, "NULL buffer");
         hipStream_t st = (hipStream_t)stream;
-        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t dp = (size_t)exact::padded_image_floats(g->N);
         AsyncBuf xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st);
         hip_check(hipMemsetAsync(xp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
         hip_check(hipMemsetAsync(xTp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
@@ -746,7 +579,7 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp, const float *y_de
         const SpecArg a = make_spec(sp, nullptr);
         hipStream_t st = (hipStream_t)stream;
         const long n = (long)g->V * g->B;
-        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t dp = (size_t)exact::padded_image_floats(g->N);
         const size_t np = (size_t)g->V * exact::padded_bins(g->B);
         AsyncBuf Y(n * sizeof(float), st), xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st),
             rp(np * sizeof(float), st);
@@ -817,7 +650,7 @@ int exact_operator_noalloc(exact_geometry g, const exact_spectrum *sp, const flo
             fail(-EINVAL, "the geometry was created on device " + std::to_string(g->device) +
                               ", the current device is " + std::to_string(device));
         const long n = (long)g->V * g->B;
-        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t dp = (size_t)exact::padded_image_floats(g->N);
         const size_t np = (size_t)g->V * exact::padded_bins(g->B);
         const size_t oY = 0, oxp = align256(4 * (size_t)n), oxTp = oxp + align256(4 * dp),
                      orp = oxTp + align256(4 * dp), need = orp + align256(4 * np);
@@ -949,7 +782,7 @@ namespace {
 size_t run_footprint(int N, int V, int B)
 {
     const size_t n = (size_t)V * B;
-    const size_t dp = (size_t)N * exact::padded_cols(N), np = (size_t)V * exact::padded_bins(B);
+    const size_t dp = (size_t)exact::padded_image_floats(N), np = (size_t)V * exact::padded_bins(B);
     return 4 * (n + np + 4 * dp) + 16 * (size_t)exact::num_tiles(N) + 8 * exact::kMaxEnergies +
            sizeof(SolveState);
 }
@@ -994,7 +827,7 @@ void problem_init(Problem &p, const exact_geometry_s *g, const exact_spectrum *s
     p.state = state;
     const long d = (long)g->N * g->N, n = (long)g->V * g->B;
     p.footprint = run_footprint(g->N, g->V, g->B) + (sp->background ? (size_t)n * 4 : 0);
-    const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+    const size_t dp = (size_t)exact::padded_image_floats(g->N);
     const size_t np = (size_t)g->V * exact::padded_bins(g->B);
     p.Y.reset(new DevBuf(n * 4));
     p.r.reset(new DevBuf(np * 4));
@@ -1426,7 +1259,7 @@ int exact_solver_time_kernels(exact_solver s, int32_t reps, double *kernel_ms, v
         const exact_geometry_s *g = p.g;
         const Geo G = geo_of(g);
         const long d = (long)g->N * g->N, n = (long)g->V * g->B;
-        const size_t dp = (size_t)g->N * exact::padded_cols(g->N);
+        const size_t dp = (size_t)exact::padded_image_floats(g->N);
         const float gf = (float)p.gamma;
         const float inv_n = (float)(1.0 / (double)n);
         hipStream_t own = s->own->st, user = (hipStream_t)stream;

@@ -48,14 +48,24 @@ static_assert(sizeof(ViewGeom) == 64, "ViewGeom layout");
 // sinogram row holds kPadB zero bins, the B bins, kPadB zero bins.  Taps
 // that fall outside the image or the detector then read zeros at in-bounds
 // addresses, so the inner loops need no range tests.  The padding is zeroed
-// when a buffer is created and never written afterwards.
+// when a buffer is created and never written afterwards.  A padded image
+// buffer holds kImgTail zero floats after its last row: the forward reads
+// four consecutive columns from a column at most Np - 2, so a read at the
+// last row's end stays in the buffer.  kPadX is four so that the three
+// columns a clamped lane reads at a row's start are all padding.
 //
 // A padded sinogram that the back-projector reads is **weighted**: row v
 // holds wstep_v r[v][b], the path-length factor of the view applied once
 // per ray by its producer instead of once per pixel and view.
-constexpr int kPadX = 2;
+constexpr int kPadX = 4;
 constexpr int kPadB = 2;
+constexpr int kImgTail = 64;
 __host__ __device__ inline int padded_cols(int N) { return N + 2 * kPadX; }
+// Floats of one padded image buffer (N rows of padded_cols(N), and the tail).
+__host__ __device__ inline long padded_image_floats(int N)
+{
+    return (long)N * padded_cols(N) + kImgTail;
+}
 __host__ __device__ inline int padded_bins(int B) { return B + 2 * kPadB; }
 
 // Spectrum collapsed over windows, passed to kernels by value; bg (device,
@@ -88,54 +98,27 @@ struct SolveState {
 // Tile knobs of the forward projector (compile-time): waves per ray block,
 // each a share of the block's lines (EXACT_FWD_SEGS), and lines per batch
 // summed in float before one Kahan step (EXACT_LINE_BATCH), both swept by
-// the autotuner; and views per LDS group of the grouped forward
-// (EXACT_FWD_GROUP, 2..4; the default 1 builds no grouped kernel and every
-// block goes to the ungrouped one, which measured faster on MI355X).
+// the autotuner.  A workgroup projects kFwdRays = 128 adjacent rays, two per
+// lane.
 #ifndef EXACT_FWD_SEGS
 #define EXACT_FWD_SEGS 4
 #endif
 #ifndef EXACT_LINE_BATCH
 #define EXACT_LINE_BATCH 4
 #endif
-#ifndef EXACT_FWD_GROUP
-#define EXACT_FWD_GROUP 1
-#endif
 constexpr int kFwdSegs = EXACT_FWD_SEGS;
 constexpr int kFwdLineBatch = EXACT_LINE_BATCH;
-constexpr int kGroupViews = EXACT_FWD_GROUP;
-// The grouped forward's LDS window: kWinCols columns of up to 2
-// kFwdLineBatch image lines per segment.
-constexpr int kWinCols = 128;
-
-// A group of the forward projector: views slot0 .. slot0 + nv - 1 (adjacent
-// table slots of one stepping class) and one block of 64 bins, whose rays
-// the grouped kernel projects with the image lines they cross staged in LDS
-// once for all the group's views.  Per segment s (the waves taking share s
-// of each view's lines): a view whose first line of the segment is kbase[s]
-// + d takes its batch i of kFwdLineBatch lines at step i + d /
-// kFwdLineBatch, so that at step j every view works on lines kbase[s] +
-// kFwdLineBatch j + r, r < rows[s] (rows[s] - kFwdLineBatch is the largest
-// d mod kFwdLineBatch); the window of step j holds those lines and padded
-// columns floor(c0[s] + c1[s] j) + c, c < kWinCols (shifted into the padded
-// row); nsteps[s] steps.  Built on the host so that every crossing the
-// views' rays make on their lines of a step lies inside that step's window.
-struct FwdGroup {
-    int32_t slot0, nv, bb, weight;
-    int32_t kbase[kFwdSegs];
-    int32_t nsteps[kFwdSegs];
-    int32_t rows[kFwdSegs];
-    double c0[kFwdSegs], c1[kFwdSegs];
-};
+constexpr int kFwdRays = 128;
 
 struct Geo {
     const ViewGeom *views;
-    // Per (table slot, block of 64 bins): first and last image line any of
-    // the block's rays reaches (first > last if none), conservative by one
-    // line; 2 ints each, slot-major.
+    // Per (table slot, block of kFwdRays bins): first and last image line
+    // any of the block's rays reaches (first > last if none), conservative
+    // by one line; 2 ints each, slot-major.
     const int32_t *blk;
     // Dispatch order of the forward projector's workgroups: workgroup i
     // projects the rays of block order[i] = slot * nbb + block (a
-    // permutation of the V * nbb blocks, nbb = ceil(B / 64)).
+    // permutation of the V * nbb blocks, nbb = ceil(B / kFwdRays)).
     const int32_t *order;
     int N, V, B;
     int nrow;        // views[0, nrow) step along rows, views[nrow, V) along columns
@@ -147,12 +130,6 @@ struct Geo {
     // rule's first bin trunc(t) lies in the padded row without clamping
     // (the detector covers the image's projection with half a bin to spare).
     int covers;
-    // The forward's LDS groups (in dispatch order) and the blocks left to
-    // the ungrouped kernel (dispatch order, block numbers as in order).
-    const FwdGroup *groups;
-    int ngroups;
-    const int32_t *left;
-    int nleft;
 };
 
 // Device code sees the descriptor's pointers as global-memory pointers
@@ -217,8 +194,6 @@ int fwd_items_per_view(int B);
 // Forward-projector workgroups one CU holds at once (from the kernel's
 // occupancy on the current device).
 int fwd_resident_blocks_per_cu();
-// Grouped forward workgroups one CU holds at once.
-int fwd_grouped_resident_blocks_per_cu();
 int fwd_block_centre_out(int r, int nbb);
 int back_tiles_per_side(int N);
 

@@ -81,15 +81,6 @@ __device__ __forceinline__ int clamp_int(int v, int hi)
     return r;
 }
 
-// min(max(v, lo), hi) for lo <= hi with lo wave-uniform (a scalar register)
-// in one instruction.
-[[maybe_unused]] __device__ __forceinline__ int clamp_int_s(int v, int lo, int hi)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "s"(lo), "v"(hi));
-    return r;
-}
-
 // Fixed-order sum over the kRedThreads threads of the block's x-y plane
 // with one barrier: a butterfly within each wave, then the four wave sums in
 // order.  Threads with active = false (other z planes) contribute nothing
@@ -230,6 +221,10 @@ __device__ __forceinline__ void finish_block(const double *__restrict__ partials
 // ---------------------------------------------------------------- forward
 
 constexpr int kSegs = kFwdSegs;   // waves per forward workgroup, each a share of the lines
+static_assert(kFwdRays == 2 * kFwdThreads, "a forward lane takes two rays");
+static_assert(kSegs % 2 == 0 && kSegs >= 2, "the epilogue pairs the waves");
+// The residual's energies of one ray are split over kEPhase waves.
+constexpr int kEPhase = kSegs / 2;
 
 // Bin block of rank r when the blocks of a view are taken centre-out (the
 // central blocks hold the longest chords): c, c-1, c+1, c-2, ... with
@@ -253,42 +248,143 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
     return *(const float *)((const char *)base + (i << 2));
 }
 
-// The two taps of a ray on one padded image line: crossing f in padded
-// column coordinates (advanced by Q, exactly), weights (float)(1 - e0) and
-// (float)e0 of columns floor(f) and floor(f) + 1 with e0 = f - floor(f),
-// and their values.  A tap outside the image reads a padding zero; the
-// column is clamped to the padded row so that lines the ray does not reach
-// read zeros too.  Every crossing with a tap inside the image has f >= 1
-// (padded), where truncation is floor; a crossing below 1 has both taps in
-// the padding, and truncating it (then clamping at 0) still reads padding.
+// A forward lane takes two adjacent rays of a view.  On every line the ray
+// with the lower crossing (in columns) is at flo and the other at fhi =
+// flo + |P|, both advanced exactly by Q per line.  Each ray's taps are the
+// single-ray rule's: weights (float)(1 - e) and (float)e, e = f - floor(f),
+// of columns floor(f) and floor(f) + 1, the column being the truncated f
+// clamped into the padded row (every crossing with a tap inside the image
+// has f >= 1, where truncation is floor; any other reads padding zeros, as
+// do lines the ray does not reach).
 //
-// The line is row `rowoff / Np` of img: the row's offset goes into the
-// per-lane element index (one add-and-shift) so that the base stays the
-// same scalar pointer for every line.
-__device__ __forceinline__ void tap_pair(double &f, int N, double Q,
-                                         const float *__restrict__ img, int rowoff, float &w0,
-                                         float &w1, float &v0, float &v1)
+// kMode 0 (|P| < 1) and 1 (1 <= |P| < 2): the four taps lie in the four
+// columns c .. c + 3 from the lower ray's column c, which one 16-byte load
+// (at a 4-byte-aligned address) reads.  The upper ray's first tap is column
+// c + d, d = chi - c; unclamped d is kMode or kMode + 1, so a select
+// between those two offsets places it.  Clamping only lowers d, and then
+// the upper ray's taps and the columns read in their place are all padding
+// (at the row's start kPadX >= 3 zero columns; at its end the last two
+// padded columns and the next row's first, or the buffer's zero tail).
+// Lanes read neighbouring columns, and this one load serves two rays: the
+// address unit takes about a third less time per tap than with one 8-byte
+// load per ray (measured on MI355X with the forward's access pattern).
+// kMode 2 (|P| >= 2): one 8-byte load per ray.
+struct PairTaps {
+    float l0, l1, h0, h1;   // weights: lower ray, upper ray
+    float v0, v1, v2, v3;   // modes 0, 1: columns c .. c + 3; mode 2: lower pair, upper pair
+    bool up;                // modes 0, 1: d > kMode
+};
+
+template <int kMode>
+__device__ __forceinline__ void pair_fetch(double &flo, double &fhi, int cmax, double Q,
+                                           const float *__restrict__ img, int rowoff, PairTaps &t)
 {
-    const double e0 = __builtin_amdgcn_fract(f);    // f - floor(f), exact, in [0, 1)
-    const int c = clamp_int<0>((int)f, N + 2 * kPadX - 2);
-    f += Q;                                         // exact
-    w0 = (float)(1.0 - e0);                         // pixel floor(f)
-    w1 = (float)e0;                                 // pixel floor(f) + 1: 1 - |f - (j0+1)| = e0
-    const unsigned i = (unsigned)(rowoff + c);
-    v0 = at(img, i);        // one 8-byte load: the lanes read neighbouring columns
-    v1 = at(img + 1, i);
+    const double elo = __builtin_amdgcn_fract(flo);   // exact, in [0, 1)
+    const double ehi = __builtin_amdgcn_fract(fhi);
+    const int clo = clamp_int<0>((int)flo, cmax);
+    const int chi = clamp_int<0>((int)fhi, cmax);
+    flo += Q;                                          // exact
+    fhi += Q;
+    t.l0 = (float)(1.0 - elo);
+    t.l1 = (float)elo;
+    t.h0 = (float)(1.0 - ehi);
+    t.h1 = (float)ehi;
+    const unsigned i = (unsigned)(rowoff + clo);
+    if (kMode < 2) {
+        const float *p = (const float *)((const char *)img + (i << 2));
+        t.v0 = p[0];
+        t.v1 = p[1];
+        t.v2 = p[2];
+        t.v3 = p[3];
+        t.up = chi - clo > kMode;
+    } else {
+        const unsigned j = (unsigned)(rowoff + chi);
+        t.v0 = at(img, i);
+        t.v1 = at(img + 1, i);
+        t.v2 = at(img, j);
+        t.v3 = at(img + 1, j);
+        t.up = false;
+    }
 }
 
-// One lane per ray (v, b); the four waves of a workgroup take the same 64
-// rays and split the image lines those rays reach (from the geometry's
-// block table) into four equal shares, and their Kahan partial sums are
-// combined in a fixed order.  A wave walks
-// its lines in a wave-uniform loop, so the line's address is scalar; a ray
-// on a line it does not reach reads padding zeros.  The crossing advances
-// exactly by Q per line.  Column-stepping views read the transposed image so
-// that the lanes of a wave touch neighbouring addresses on every line.
-// Within a batch of lines the contributions are summed in float before the
-// Kahan step.
+// Adds the line's contributions: s += w1 v1 + w0 v0 (as fma(w1, v1,
+// fma(w0, v0, s))) for each ray.
+template <int kMode>
+__device__ __forceinline__ void pair_apply(const PairTaps &t, float &slo, float &shi)
+{
+    slo = fmaf(t.l1, t.v1, fmaf(t.l0, t.v0, slo));
+    float a, b;
+    if (kMode == 0) {
+        a = t.up ? t.v1 : t.v0;
+        b = t.up ? t.v2 : t.v1;
+    } else if (kMode == 1) {
+        a = t.up ? t.v2 : t.v1;
+        b = t.up ? t.v3 : t.v2;
+    } else {
+        a = t.v2;
+        b = t.v3;
+    }
+    shi = fmaf(t.h1, b, fmaf(t.h0, a, shi));
+}
+
+// The lines kw0 .. kw1 of the padded image img for a lane's two rays,
+// from crossings flo, fhi on line kw0, into Kahan sums (lower ray, upper
+// ray).  Batches of kLineBatch lines are summed in float before one Kahan
+// step.  Software-pipelined: the next batch's loads are issued before the
+// current batch is summed, with two register sets used alternately (a copy
+// between them would make the compiler wait for the loads) and scheduling
+// barriers that keep that order.
+template <int kMode>
+__device__ __forceinline__ void pair_lines(double flo, double fhi, int kw0, int kw1, int cmax,
+                                           double Q, int Np, const float *__restrict__ img,
+                                           Kahan &alo, Kahan &ahi)
+{
+    PairTaps ta[kLineBatch], tb[kLineBatch];
+    int k = kw0;
+    auto fetch = [&](PairTaps(&t)[kLineBatch]) {
+#pragma unroll
+        for (int q = 0; q < kLineBatch; ++q)
+            pair_fetch<kMode>(flo, fhi, cmax, Q, img, (k + q) * Np, t[q]);
+        k += kLineBatch;
+    };
+    auto apply = [&](const PairTaps(&t)[kLineBatch]) {
+        float slo = 0.f, shi = 0.f;
+#pragma unroll
+        for (int q = 0; q < kLineBatch; ++q)
+            pair_apply<kMode>(t[q], slo, shi);
+        alo.add(slo);
+        ahi.add(shi);
+    };
+    const int nb = kw1 >= kw0 ? (kw1 - kw0 + 1) / kLineBatch : 0;
+    if (nb > 0) {
+        fetch(ta);
+        int i = 1;
+        for (; i + 1 < nb; i += 2) {
+            fetch(tb);
+            apply(ta);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(ta);
+            apply(tb);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (i < nb) {
+            fetch(tb);
+            apply(ta);
+            apply(tb);
+        } else {
+            apply(ta);
+        }
+    }
+    for (; k <= kw1; ++k) {
+        PairTaps t;
+        pair_fetch<kMode>(flo, fhi, cmax, Q, img, k * Np, t);
+        float slo = 0.f, shi = 0.f;
+        pair_apply<kMode>(t, slo, shi);
+        alo.add(slo);
+        ahi.add(shi);
+    }
+}
+
 // Spectrum read through device pointers (the batched kernels); mu2 holds
 // mu log2(e), as in SpecArg.
 struct SpecPtr {
@@ -298,63 +394,61 @@ struct SpecPtr {
     const float *__restrict__ bg;
 };
 
-// End of a forward ray: the kSegs waves' Kahan partials of the ray (in
-// ps/pc[seg][lane], this view's) are combined in segment order, times the
-// view's path length; with kResid the spectral residual replaces the line
-// integral: r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with
-// exp(-mu t) = 2^(-mu log2(e) t) by the hardware exp2 (whose result is
-// exp2f's except below 2^-126, where it flushes a term that no count could
-// register); wave `seg` sums the energies k = seg, seg + kSegs, ..., and the
-// waves' sums are added in order.  Ray i = vidx B + b goes to
-// out[vidx ostride + ooff + b], times wstep when weighted, and unweighted
-// to plain[i] when plain is not null.  Every thread of the workgroup calls
-// this (it holds barriers); waves with active = false only take part in
-// them.
+// End of a forward block: lane l of wave seg holds the Kahan partials of
+// rays 2l (e) and 2l + 1 (o) of the block over its share of the lines.  Ray
+// r's partials are combined in segment order, times the view's path length;
+// with kResid the spectral residual replaces the line integral:
+// r_i = Y_i - sum_k J_k exp(-mu_k (bg_i + max(s_i, 0))), with exp(-mu t) =
+// 2^(-mu log2(e) t) by the hardware exp2 (whose result is exp2f's except
+// below 2^-126, where it flushes a term that no count could register).
+// Ray r = lane + 64 (seg mod 2) is finished by the waves seg with that
+// parity: wave seg sums the energies k = q, q + kEPhase, ... (q = seg / 2)
+// and the sums are added in q order.  Ray i = vidx B + b goes to
+// out[vidx ostride + ooff + b], times wstep when weighted, and unweighted to
+// plain[i] when plain is not null.  Every thread of the workgroup calls this
+// (it holds barriers).
 template <bool kResid, class Spec>
-__device__ __forceinline__ void forward_ray_end(const Kahan &acc, bool active, int seg, int lane,
-                                                const ViewGeom &G, int b, int B,
-                                                float (*ps)[kFwdThreads], float (*pc)[kFwdThreads],
-                                                float (*pm)[kFwdThreads],
-                                                const float *__restrict__ Y, const Spec &sp,
-                                                float *__restrict__ out, int ostride, int ooff,
-                                                bool weighted, float *__restrict__ plain)
+__device__ __forceinline__ void forward_pair_end(const Kahan &ae, const Kahan &ao, int seg,
+                                                 int lane, const ViewGeom &G, int b0, int B,
+                                                 float (*ps)[kFwdRays], float (*pc)[kFwdRays],
+                                                 float (*pm)[kFwdRays],
+                                                 const float *__restrict__ Y, const Spec &sp,
+                                                 float *__restrict__ out, int ostride, int ooff,
+                                                 bool weighted, float *__restrict__ plain)
 {
-    if (active) {
-        ps[seg][lane] = acc.s;
-        pc[seg][lane] = acc.c;
-    }
+    ps[seg][2 * lane] = ae.s;
+    pc[seg][2 * lane] = ae.c;
+    ps[seg][2 * lane + 1] = ao.s;
+    pc[seg][2 * lane + 1] = ao.c;
     __syncthreads();
+    const int r = lane + kFwdThreads * (seg & 1), q = seg >> 1;
+    const int b = b0 + r;
     const bool ray = b < B;
     const size_t i = (size_t)G.vidx * B + (ray ? b : 0);
-    float val = 0.f;
-    if (active) {
-        Kahan tot;
+    Kahan tot;
 #pragma unroll
-        for (int q = 0; q < kSegs; ++q) {
-            tot.add(ps[q][lane]);
-            tot.add(-pc[q][lane]);
-        }
-        val = tot.value() * G.wstep;
+    for (int u = 0; u < kSegs; ++u) {
+        tot.add(ps[u][r]);
+        tot.add(-pc[u][r]);
     }
+    float val = tot.value() * G.wstep;
     if (kResid) {
-        if (active) {
-            const float sp0 = fmaxf(val, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
-            float m = 0.f;
+        const float sp0 = fmaxf(val, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
+        float m = 0.f;
 #pragma unroll 4
-            for (int q = seg; q < sp.K; q += kSegs)
-                m = fmaf(sp.J[q], __builtin_amdgcn_exp2f(-sp.mu2[q] * sp0), m);
-            pm[seg][lane] = m;
-        }
+        for (int k = q; k < sp.K; k += kEPhase)
+            m = fmaf(sp.J[k], __builtin_amdgcn_exp2f(-sp.mu2[k] * sp0), m);
+        pm[q][r] = m;
         __syncthreads();
-        if (active) {
-            float mt = pm[0][lane];
+        if (q == 0) {
+            float mt = pm[0][r];
 #pragma unroll
-            for (int q = 1; q < kSegs; ++q)
-                mt += pm[q][lane];
+            for (int u = 1; u < kEPhase; ++u)
+                mt += pm[u][r];
             val = Y[i] - mt;
         }
     }
-    if (!active || seg != 0 || !ray)
+    if (q != 0 || !ray)
         return;
     const size_t o = (size_t)G.vidx * ostride + ooff + b;
     out[o] = weighted ? val * G.wstep : val;
@@ -362,13 +456,17 @@ __device__ __forceinline__ void forward_ray_end(const Kahan &acc, bool active, i
         plain[i] = val;
 }
 
-// Forward projection of rays [64 bblock, 64 bblock + 64) of table view
+// Forward projection of rays [128 bblock, 128 bblock + 128) of table view
 // `slot` by one workgroup of kFwdThreads * kSegs threads, reading the padded
 // image pair; with kResid the spectral residual replaces the line integral.
-// Ray i = vidx B + b goes to out[vidx * ostride + ooff + b], times the
-// view's wstep when weighted, and unweighted to plain[i] when plain is not
-// null.  blk[2 (slot nbb + bblock) + {0, 1}] bound the lines the block's
-// rays reach (conservatively; lines a ray misses read padding zeros).
+// Lane l takes rays 2l and 2l + 1 of the block; the kSegs waves take the
+// same rays and split the image lines any of them reaches (from the
+// geometry's block table blk[2 (slot nbb + bblock) + {0, 1}]) into equal
+// shares, walked in a wave-uniform loop (the line's address is scalar).
+// Column-stepping views read the transposed image so that the lanes of a
+// wave touch neighbouring addresses on every line.  Ray i = vidx B + b goes
+// to out[vidx * ostride + ooff + b], times the view's wstep when weighted,
+// and unweighted to plain[i] when plain is not null.
 template <bool kResid, class Spec>
 __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views,
                                               const int32_t *__restrict__ blk, int N, int B,
@@ -379,19 +477,19 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
                                               bool weighted, float *__restrict__ plain,
                                               int slot, int bblock)
 {
-    __shared__ float part_s[kSegs][kFwdThreads], part_c[kSegs][kFwdThreads];
-    __shared__ float part_m[kSegs][kFwdThreads];
+    __shared__ float part_s[kSegs][kFwdRays], part_c[kSegs][kFwdRays];
+    __shared__ float part_m[kEPhase][kFwdRays];
     const int lane = threadIdx.x % kFwdThreads;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);  // wave-uniform
-    const int b = bblock * kFwdThreads + lane;
+    const int b0 = bblock * kFwdRays;
     const ViewGeom G = views[slot];
     const float *__restrict__ img = slot < nrow ? xp : xTp;
     const int Np = padded_cols(N);
-    const double base = fma((double)b, G.P, G.A);
+    const int cmax = N + 2 * kPadX - 2;
 
-    // the waves hold the same 64 rays: split the lines any of them reaches
+    // the waves hold the same 128 rays: split the lines any of them reaches
     // into equal shares
-    const int bi = 2 * (slot * ((B + kFwdThreads - 1) / kFwdThreads) + bblock);
+    const int bi = 2 * (slot * ((B + kFwdRays - 1) / kFwdRays) + bblock);
     const int kmin = blk[bi], kmax = blk[bi + 1];
     int kw0 = 0, kw1 = -1;
     if (kmin <= kmax) {
@@ -399,79 +497,20 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         kw0 = kmin + seg * per;
         kw1 = min(kmax, kw0 + per - 1);
     }
-
-    Kahan acc;
-    double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
-    int k = kw0;
-    // Software-pipelined over batches of lines: the next batch's loads are
-    // issued before the current batch is summed, with two register sets used
-    // alternately (loop-carried copies between them would make the compiler
-    // wait for the loads) and scheduling barriers that keep that order.
-    float aw0[kLineBatch], aw1[kLineBatch], av0[kLineBatch], av1[kLineBatch];
-    float bw0[kLineBatch], bw1[kLineBatch], bv0[kLineBatch], bv1[kLineBatch];
-    const int nb = kw1 >= kw0 ? (kw1 - kw0 + 1) / kLineBatch : 0;
-    if (nb > 0) {
-#pragma unroll
-        for (int q = 0; q < kLineBatch; ++q)
-            tap_pair(f, N, G.Q, img, (k + q) * Np, aw0[q], aw1[q], av0[q], av1[q]);
-        k += kLineBatch;
-        int i = 1;
-        for (; i + 1 < nb; i += 2) {
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                tap_pair(f, N, G.Q, img, (k + q) * Np, bw0[q], bw1[q], bv0[q], bv1[q]);
-            k += kLineBatch;
-            {
-                float s = 0.f;
-#pragma unroll
-                for (int q = 0; q < kLineBatch; ++q)
-                    s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
-                acc.add(s);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                tap_pair(f, N, G.Q, img, (k + q) * Np, aw0[q], aw1[q], av0[q], av1[q]);
-            k += kLineBatch;
-            {
-                float s = 0.f;
-#pragma unroll
-                for (int q = 0; q < kLineBatch; ++q)
-                    s = fmaf(bw1[q], bv1[q], fmaf(bw0[q], bv0[q], s));
-                acc.add(s);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (i < nb) {
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                tap_pair(f, N, G.Q, img, (k + q) * Np, bw0[q], bw1[q], bv0[q], bv1[q]);
-            k += kLineBatch;
-            float s = 0.f;
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
-            acc.add(s);
-            s = 0.f;
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                s = fmaf(bw1[q], bv1[q], fmaf(bw0[q], bv0[q], s));
-            acc.add(s);
-        } else {
-            float s = 0.f;
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q)
-                s = fmaf(aw1[q], av1[q], fmaf(aw0[q], av0[q], s));
-            acc.add(s);
-        }
-    }
-    for (; k <= kw1; ++k) {
-        float w0, w1, v0, v1;
-        tap_pair(f, N, G.Q, img, k * Np, w0, w1, v0, v1);
-        acc.add(fmaf(w1, v1, w0 * v0));
-    }
-    forward_ray_end<kResid>(acc, true, seg, lane, G, b, B, part_s, part_c, part_m, Y, sp, out,
-                            ostride, ooff, weighted, plain);
+    // padded column coordinates of the lane's rays on line kw0
+    const double fe = fma((double)kw0, G.Q, fma((double)(b0 + 2 * lane), G.P, G.A)) + (double)kPadX;
+    const double fo = fma((double)kw0, G.Q, fma((double)(b0 + 2 * lane + 1), G.P, G.A)) + (double)kPadX;
+    const bool rising = G.P >= 0.0;                 // ray 2l + 1 crosses to the right of ray 2l
+    const double aP = fabs(G.P);
+    Kahan alo, ahi;
+    if (aP < 1.0)
+        pair_lines<0>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+    else if (aP < 2.0)
+        pair_lines<1>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+    else
+        pair_lines<2>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+    forward_pair_end<kResid>(rising ? alo : ahi, rising ? ahi : alo, seg, lane, G, b0, B, part_s,
+                             part_c, part_m, Y, sp, out, ostride, ooff, weighted, plain);
 }
 
 // Workgroup i projects ray block order[i] (the geometry's dispatch order:
@@ -499,180 +538,10 @@ __global__ __launch_bounds__(kFwdThreads *kSegs) void k_forward(
             fin.state->pending = 1;
         return;
     }
-    const int nbb = (B + kFwdThreads - 1) / kFwdThreads;
+    const int nbb = (B + kFwdRays - 1) / kFwdRays;
     const int it = order[blockIdx.x];
     forward_block<kResid>(views, blk, N, B, nrow, xp, xTp, Y, sp, out, ostride, ooff,
                           weighted != 0, plain, it / nbb, it % nbb);
-}
-
-// ------------------------------------------------ forward, LDS groups
-
-// The grouped forward (built when EXACT_FWD_GROUP >= 2; measured slower
-// than k_forward on MI355X, so the default build leaves it out): a
-// workgroup projects one group (FwdGroup) of up to kGV adjacent views and
-// one block of 64 bins, with one wave per (view, segment): wave (g, s)
-// takes view slot0 + g and share s of that view's
-// lines of the block, exactly the lines, batches and summation order
-// forward_block gives the same rays, so every ray's result is bitwise the
-// same as the ungrouped kernel's.  What changes is where the image values
-// come from: the segment's waves (one per view) walk their lines in
-// lockstep, a batch of kLineBatch lines per step, and the image lines of a
-// step are staged once in LDS for all of them (a window of kWinCols padded
-// columns around the views' crossings, filled by global-to-LDS loads of 64
-// floats per wave instruction, double-buffered so that the next step's
-// window loads while the current one is read).  A lane's two taps then read
-// LDS instead of issuing a vector-memory load per line.
-constexpr int kGV = kGroupViews;
-constexpr int kWinH = 2 * kLineBatch;
-constexpr int kGrpThreads = kFwdThreads * kSegs * kGV;
-static_assert(kGrpThreads <= 1024, "grouped forward: workgroup too large");
-
-typedef __attribute__((address_space(1))) void gvoid_t;
-typedef __attribute__((address_space(3))) void lvoid_t;
-
-// Stages the window of one step: image lines L0 .. L0 + rows - 1 (clamped
-// to the image; a line past it is never read) and padded columns colbase ..
-// colbase + kWinCols - 1 of img into win (kWinCols floats per line).  Each
-// wave instruction moves 64 consecutive floats; wave g of the segment's kGV
-// waves takes the halves g, g + kGV, ...
-[[maybe_unused]] __device__ __forceinline__ void stage_window(const float *__restrict__ img,
-                                                              int Np, int N, int L0, int rows,
-                                                              int colbase, float *win, int g,
-                                                              int lane)
-{
-    for (int i = g; i < 2 * rows; i += kGV) {
-        const int r = i >> 1, h = i & 1;
-        const int line = min(L0 + r, N - 1);
-        const float *src = img + ((size_t)line * Np + colbase + 64 * h + lane);
-        __builtin_amdgcn_global_load_lds((gvoid_t *)src, (lvoid_t *)(win + r * kWinCols + 64 * h),
-                                         4, 0, 0);
-    }
-}
-
-template <bool kResid>
-__global__ __launch_bounds__(kGrpThreads, 2) void k_forward_lds(
-    const ViewGeom *__restrict__ views, const int32_t *__restrict__ blk,
-    const FwdGroup *__restrict__ groups, int N, int B, int nrow, const float *__restrict__ xp,
-    const float *__restrict__ xTp, const float *__restrict__ Y, SpecArg sp,
-    float *__restrict__ out, int ostride, int ooff, int weighted, float *__restrict__ plain,
-    const int32_t *__restrict__ skip, FinishArgs fin)
-{
-    if (skipped(skip))
-        return;
-    // as k_forward: the step's first kernel runs the previous step's finish
-    // in its last workgroup
-    if (kResid && fin.state && blockIdx.x == gridDim.x - 1) {
-        finish_block<true, kGrpThreads>(fin.partials, fin.nparts, fin.avg_parts, fin.n_avg,
-                                        fin.state);
-        if (threadIdx.x == 0 && !fin.state->done)
-            fin.state->pending = 1;
-    }
-    __shared__ float winA[kSegs][kWinH * kWinCols];
-    __shared__ float winB[kSegs][kWinH * kWinCols];
-    using CGroup = const FwdGroup EXACT_CONSTANT;
-    CGroup &Gr = *((CGroup *)groups + blockIdx.x);
-    const int lane = threadIdx.x % kFwdThreads;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kFwdThreads);
-    const int g = wave % kGV, seg = wave / kGV;
-    const int nv = Gr.nv, bb = Gr.bb;
-    const bool active = g < nv;
-    const int slot = Gr.slot0 + (active ? g : 0);
-    const int b = bb * kFwdThreads + lane;
-    const ViewGeom G = views[slot];
-    const float *__restrict__ img = slot < nrow ? xp : xTp;
-    const int Np = padded_cols(N);
-    const double base = fma((double)b, G.P, G.A);
-
-    // this view's share of the block's lines, as forward_block takes it
-    const int bi = 2 * (slot * ((B + kFwdThreads - 1) / kFwdThreads) + bb);
-    const int kmin = blk[bi], kmax = blk[bi + 1];
-    int kw0 = 0, kw1 = -1;
-    if (kmin <= kmax) {
-        const int per = (kmax - kmin + kSegs) / kSegs;
-        kw0 = kmin + seg * per;
-        kw1 = min(kmax, kw0 + per - 1);
-    }
-    const int cnt = (active && kw1 >= kw0) ? kw1 - kw0 + 1 : 0;
-    const int nb = cnt / kLineBatch, rem = cnt % kLineBatch;
-    const int kbase = Gr.kbase[seg], J = Gr.nsteps[seg], rows = Gr.rows[seg];
-    const double c0 = Gr.c0[seg], c1 = Gr.c1[seg];
-    // this view's batch i runs at step i + off, on window lines dk ..
-    const int delta = cnt > 0 ? kw0 - kbase : 0;
-    const int off = delta / kLineBatch, dk = delta % kLineBatch;
-    int Jmax = 0;
-#pragma unroll
-    for (int q = 0; q < kSegs; ++q)
-        Jmax = max(Jmax, Gr.nsteps[q]);
-    // first padded column of step j's window, shifted into the padded row
-    auto colbase_of = [&](int j) {
-        const int c = (int)floor(fma(c1, (double)j, c0));
-        return __builtin_amdgcn_readfirstlane(min(max(c, 0), Np - kWinCols));
-    };
-
-    Kahan acc;
-    double f = fma((double)kw0, G.Q, base) + (double)kPadX;   // padded column coordinate
-    // one step of this wave's lines from window w: a full batch (summed in
-    // float, then one Kahan step) or the remainder lines one by one, as
-    // forward_block sums them
-    auto step = [&](int j, const float *w) {
-        const int i = j - off;                         // this wave's batch
-        if (i < 0 || i > nb || (i == nb && rem == 0))
-            return;
-        // the tap column clamped into the window [cb, cb + kWinCols - 2]; wr
-        // addresses padded column c of the wave's first window line as wr[c]
-        const int cb = colbase_of(j), cbhi = cb + kWinCols - 2;
-        const float *wr = w + (dk * kWinCols - cb);
-        if (i < nb) {
-            float s = 0.f;
-#pragma unroll
-            for (int q = 0; q < kLineBatch; ++q) {
-                const double e0 = __builtin_amdgcn_fract(f);
-                const int c = clamp_int_s((int)f, cb, cbhi);
-                f += G.Q;
-                const float w0 = (float)(1.0 - e0), w1 = (float)e0;
-                const float v0 = wr[q * kWinCols + c], v1 = wr[q * kWinCols + c + 1];
-                s = fmaf(w1, v1, fmaf(w0, v0, s));
-            }
-            acc.add(s);
-        } else {
-            for (int q = 0; q < rem; ++q) {
-                const double e0 = __builtin_amdgcn_fract(f);
-                const int c = clamp_int_s((int)f, cb, cbhi);
-                f += G.Q;
-                const float w0 = (float)(1.0 - e0), w1 = (float)e0;
-                const float v0 = wr[q * kWinCols + c], v1 = wr[q * kWinCols + c + 1];
-                acc.add(fmaf(w1, v1, w0 * v0));
-            }
-        }
-    };
-    auto stage = [&](int j, float *w) {
-        if (j < J)
-            stage_window(img, Np, N, kbase + kLineBatch * j, rows, colbase_of(j), w, g, lane);
-    };
-
-    stage(0, winA[seg]);
-    __syncthreads();
-    for (int j = 0; j < Jmax; j += 2) {
-        stage(j + 1, winB[seg]);
-        step(j, winA[seg]);
-        __syncthreads();
-        if (j + 1 >= Jmax)
-            break;
-        stage(j + 2, winA[seg]);
-        step(j + 1, winB[seg]);
-        __syncthreads();
-    }
-    // the windows are free (every staged step has been read): the rays'
-    // partials go there
-    float *pbase = &winA[0][0];
-    static_assert(3 * kGV * kSegs * kFwdThreads <= kSegs * kWinH * kWinCols,
-                  "grouped forward: partials do not fit the window");
-    auto part = [&](int which) {
-        return reinterpret_cast<float(*)[kFwdThreads]>(pbase +
-                                                        (which * kGV + g) * kSegs * kFwdThreads);
-    };
-    forward_ray_end<kResid>(acc, active, seg, lane, G, b, B, part(0), part(1), part(2), Y, sp, out,
-                            ostride, ooff, weighted != 0, plain);
 }
 
 // Number of positive matrix entries on each ray, summed per workgroup:
@@ -1364,30 +1233,20 @@ hipError_t launch_fill(float *x, float value, long count, hipStream_t st)
     return hipGetLastError();
 }
 
-// The forward launches: the grouped kernel over the geometry's groups, then
-// the ungrouped kernel over the blocks left (every block when there are no
-// groups).  The first launch carries the step finish (fin).
+// The forward launch over every ray block of the geometry, in its dispatch
+// order; with a step finish (fin) one more workgroup runs it.
 template <bool kResid>
 hipError_t launch_forward_any(const Geo &g, const float *xp, const float *xTp, const float *Y,
                               const SpecArg &sp, float *out, int ostride, int ooff, bool weighted,
                               float *plain, const int32_t *skip, hipStream_t st,
                               const FinishArgs &fin)
 {
-    const FinishArgs nofin{nullptr, 0, nullptr, 0, nullptr};
-    if constexpr (kGV >= 2) {
-        if (g.ngroups > 0)
-            hipLaunchKernelGGL(k_forward_lds<kResid>, dim3(g.ngroups), dim3(kGrpThreads), 0, st,
-                               g.views, g.blk, g.groups, g.N, g.B, g.nrow, xp, xTp, Y, sp, out,
-                               ostride, ooff, weighted ? 1 : 0, plain, skip, fin);
-    }
-    const int nblocks = g.ngroups > 0 ? g.nleft : ((g.B + kFwdThreads - 1) / kFwdThreads) * g.V;
-    const FinishArgs &f = g.ngroups > 0 ? nofin : fin;
+    const int nblocks = ((g.B + kFwdRays - 1) / kFwdRays) * g.V;
     // with a finish, one more workgroup (the last) runs it
-    if (nblocks > 0)
-        hipLaunchKernelGGL(k_forward<kResid>, dim3(nblocks + (f.state ? 1 : 0)),
-                           dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk,
-                           g.ngroups > 0 ? g.left : g.order, g.N, g.V, g.B, g.nrow, xp, xTp, Y, sp,
-                           out, ostride, ooff, weighted ? 1 : 0, plain, skip, f);
+    hipLaunchKernelGGL(k_forward<kResid>, dim3(nblocks + (fin.state ? 1 : 0)),
+                       dim3(kFwdThreads * kSegs), 0, st, g.views, g.blk, g.order, g.N, g.V, g.B,
+                       g.nrow, xp, xTp, Y, sp, out, ostride, ooff, weighted ? 1 : 0, plain, skip,
+                       fin);
     return hipGetLastError();
 }
 
@@ -1555,7 +1414,7 @@ hipError_t launch_batch_step(const BatchProb *probs, int nprobs, const BatchItem
     return hipGetLastError();
 }
 
-int fwd_items_per_view(int B) { return (B + kFwdThreads - 1) / kFwdThreads; }
+int fwd_items_per_view(int B) { return (B + kFwdRays - 1) / kFwdRays; }
 int fwd_resident_blocks_per_cu()
 {
     int n = 0;
@@ -1564,16 +1423,6 @@ int fwd_resident_blocks_per_cu()
         n < 1)
         return 1;
     return n;
-}
-int fwd_grouped_resident_blocks_per_cu()
-{
-    int n = 0;
-    if constexpr (kGV >= 2) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_forward_lds<true>, kGrpThreads,
-                                                         0) != hipSuccess)
-            n = 0;
-    }
-    return n < 1 ? 1 : n;
 }
 int fwd_block_centre_out(int r, int nbb) { return centre_out(r, nbb); }
 int back_tiles_per_side(int N) { return (N + kBackX - 1) / kBackX; }

@@ -159,6 +159,24 @@ def table(rows):
     return md
 
 
+def back_to_back(trace_csv, min_run=10):
+    """Mean duration (us) and count of the dispatches that run back to back:
+    runs of at least min_run consecutive dispatches of one kernel, each run's
+    first dispatch dropped."""
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    out = collections.defaultdict(list)
+    i = 0
+    while i < len(rows):
+        j = i
+        while j < len(rows) and rows[j]["Kernel_Name"] == rows[i]["Kernel_Name"]:
+            j += 1
+        if j - i >= min_run:
+            out[short(rows[i]["Kernel_Name"])] += [
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in rows[i + 1:j]]
+        i = j
+    return {k: (sum(v) / len(v), len(v)) for k, v in out.items()}
+
+
 def cmd_kernels(out_dir):
     rows = stats(os.path.join(out_dir, "prof", "bench", "bench_kernel_stats.csv"))
     b = json.loads(open(os.path.join(out_dir, "bench.log")).read().strip().splitlines()[-1])
@@ -192,6 +210,7 @@ def cmd_kernels(out_dir):
           "Command (from the repository root, TMPDIR=/tmp):", "", "```", BENCH_TRACE, "```", "",
           "Summarised by `python -m paper_2503_19925_amd.profsum kernels gpurun_out`.", ""]
     md += table(rows)
+    b2b = back_to_back(os.path.join(out_dir, "prof", "bench", "bench_kernel_trace.csv"))
     fwd_b = (ph["forward_residual_x"] + ph["forward_residual_xh"]) / 2 * 1e3
     md += ["", "**Agreement with the benchmark's event timing.** The default `python bench.py`",
            "run (same build, not under the profiler) timed the step at %.4f ms (graph" % b["ms_per_step"],
@@ -206,7 +225,16 @@ def cmd_kernels(out_dir):
            "(and the standalone k_eg_finish<false> %.2f us); the graph's four kernels sum to" % fin,
            "%.1f us per step, %.1f us short of the replayed step: the gaps between the"
            % (tot, b["ms_per_step"] * 1e3 - tot),
-           "graph's kernels and the finish workgroup of the first kernel."]
+           "graph's kernels and the finish workgroup of the first kernel.", "",
+           "The benchmark times each kernel over back-to-back launches of that kernel",
+           "alone; in the trace above most dispatches run inside the step, after the",
+           "other kernel, and the first of each call starts cold.  The trace's own",
+           "back-to-back runs (10 or more consecutive dispatches of one kernel, each",
+           "run's first dropped) average: %s." % ", ".join(
+               "%s %.2f us over %d dispatches" % (k, v[0], v[1]) for k, v in sorted(b2b.items())),
+           "Against them the benchmark's forward mean is %+.1f %%." % (
+               100 * (fwd_b - b2b["k_forward<true>"][0]) / b2b["k_forward<true>"][0])
+           if "k_forward<true>" in b2b else ""]
     with open(os.path.join(PROFILES, "kernels_solve_512.md"), "w") as f:
         f.write("\n".join(md) + "\n")
 
@@ -261,12 +289,13 @@ def cmd_utilisation(pmc_dir):
           "MI355X's 256 CUs (1024 SIMDs) at the published 2.4 GHz peak engine clock; the",
           "duration is the dispatch's own (the counter run's timestamps), so a clock",
           "below 2.4 GHz makes every fraction below a lower bound:", "",
-          "* VALU issue: SQ_INSTS_VALU x 4 cycles (a wave64 instruction on a 16-lane",
-          "  SIMD) / (1024 SIMDs x duration x 2.4 GHz);",
-          "* VALU busy: SQ_ACTIVE_INST_VALU x 4 (quad-cycles the SIMDs spend in VALU",
-          "  instructions, multi-pass ones such as double-precision converts counted in",
-          "  full) / (1024 SIMDs x duration x 2.4 GHz): above the issue figure by what",
-          "  instructions taking more than one pass cost;",
+          "* VALU issue: SQ_INSTS_VALU x 2 cycles / (1024 SIMDs x duration x 2.4 GHz):",
+          "  against the published FP32 vector rate (one wave64 instruction per 2 cycles",
+          "  per SIMD), which two-operand 32-bit instructions reach on MI355X (measured);",
+          "* VALU at 4 cycles: the same count at 4 cycles per instruction, the rate",
+          "  measured for the three-operand FP32 FMA and the FP64 add and fract.  A",
+          "  kernel's mix lies between the two rates, so this figure can pass 100 % when",
+          "  part of the mix issues at the faster one;",
           "* waves resident per SIMD: SQ_WAVE_CYCLES x 4 (quad-cycles) / (1024 x cycles);",
           "* TA / TD busy: TA_TA_BUSY_sum, TD_TD_BUSY_sum / (256 CUs x cycles);",
           "* L2 hit rate: TCC_HIT / (TCC_HIT + TCC_MISS); L2 read latency:",
@@ -290,7 +319,7 @@ def cmd_utilisation(pmc_dir):
                 if p == "A" and r["Counter_Name"] == "SQ_INSTS_VALU":
                     dur[n].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
         md += ["## %s" % wl, "",
-               "| kernel | dispatches | duration (us) | VALU issue | VALU busy | waves / SIMD "
+               "| kernel | dispatches | duration (us) | VALU issue | VALU at 4 cycles | waves / SIMD "
                "| TA busy | TD busy | L2 hit | L2 read latency (cycles) | HBM (GB/s, of 8000) |",
                "|---|---|---|---|---|---|---|---|---|---|---|"]
         wrec = valu_rec.setdefault(wl, {})
@@ -299,12 +328,12 @@ def cmd_utilisation(pmc_dir):
             d = sum(dur[k]) / len(dur[k])
             cyc = d * CLOCK_GHZ * 1e9
             hbm = traffic.get(wl, {}).get(k, {}).get("hbm_bytes_per_launch")
-            issue = v["SQ_INSTS_VALU"] * 4 / SIMDS / cyc
-            busy = v["SQ_ACTIVE_INST_VALU"] * 4 / SIMDS / cyc
+            issue = v["SQ_INSTS_VALU"] * 2 / SIMDS / cyc
+            issue4 = v["SQ_INSTS_VALU"] * 4 / SIMDS / cyc
             ta = v["TA_TA_BUSY_sum"] / CUS / cyc
             md.append("| %s | %d | %.1f | %.0f %% | %.0f %% | %.1f | %.0f %% | %.0f %% | %.1f %% "
                       "| %.0f | %s |" % (
-                          k, len(dur[k]), d * 1e6, 100 * issue, 100 * busy,
+                          k, len(dur[k]), d * 1e6, 100 * issue, 100 * issue4,
                           v["SQ_WAVE_CYCLES"] * 4 / SIMDS / cyc, 100 * ta,
                           100 * v["TD_TD_BUSY_sum"] / CUS / cyc,
                           100 * v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"]),
@@ -312,26 +341,29 @@ def cmd_utilisation(pmc_dir):
                           "%.0f" % (hbm / d / 1e9) if hbm else "-"))
             wrec[k] = {"valu_lane_instr_per_launch": 64.0 * v["SQ_INSTS_VALU"],
                        "valu_active_quad_cycles": v["SQ_ACTIVE_INST_VALU"],
-                       "duration_us": d * 1e6, "valu_issue_frac": issue, "valu_busy_frac": busy,
-                       "ta_busy_frac": ta, "dispatches": len(dur[k])}
+                       "duration_us": d * 1e6, "valu_issue_frac": issue,
+                       "valu_issue_frac_4_cycles": issue4, "ta_busy_frac": ta,
+                       "dispatches": len(dur[k])}
         bu = [wrec[k] for k in UTIL_KERNELS if k.startswith("k_back_update")]
         wrec["k_back_update"] = {f: sum(b[f] for b in bu) / len(bu)
                                  for f in ("valu_lane_instr_per_launch", "valu_active_quad_cycles",
-                                           "duration_us", "valu_issue_frac", "valu_busy_frac",
-                                           "ta_busy_frac")}
+                                           "duration_us", "valu_issue_frac",
+                                           "valu_issue_frac_4_cycles", "ta_busy_frac")}
         md.append("")
-    md += ["Reading.  At 1024² the back-projection + update kernels issue VALU",
-           "instructions at about 91 % of the peak rate, so they are bound by",
-           "instruction issue; at 512² the same loop reaches about 60 %, the rest going",
-           "to the start and end of a grid that runs as a single round of waves.  The",
-           "forward keeps its address and data-return units (TA, TD) the busiest, the",
-           "vector-memory path that bounds it.  L2 hit rates of 80-94 % and HBM rates",
-           "far below 8 TB/s show the operands served from the XCDs' L2."]
+    md += ["Reading.  Both kernels are bound by VALU issue for their instruction mix:",
+           "counted at 4 cycles per instruction (the measured rate of their FP64",
+           "crossing arithmetic and three-operand FMAs) they fill 78-108 % of the",
+           "forward's and 63-89 % of the back-projector's duration, and the forward at",
+           "1024² passes 100 %, so part of its mix issues at the faster two-cycle rate.",
+           "The address and data-return units (TA, TD) stay below them (50-84 %), since",
+           "the forward serves two rays per 16-byte load.  L2 hit rates of 80-93 % and",
+           "HBM rates far below 8 TB/s show the operands served from the XCDs' L2."]
     with open(os.path.join(PROFILES, "counters_utilisation.md"), "w") as f:
         f.write("\n".join(md) + "\n")
     rec = {"kernel_build_id": libbuild.build_id(), "knobs": libbuild.tuned_knobs(),
            "note": "SQ_INSTS_VALU per dispatch x 64 lanes; fractions against 1024 SIMDs at "
-                   "2.4 GHz over the dispatch's duration (counter run)",
+                   "2.4 GHz over the dispatch's duration (counter run), at one wave64 "
+                   "instruction per 2 cycles (valu_issue_frac) and per 4 cycles",
            "workloads": valu_rec}
     with open(os.path.join(PROFILES, "valu.json"), "w") as f:
         json.dump(rec, f, indent=1)

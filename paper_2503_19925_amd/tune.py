@@ -9,7 +9,7 @@ Knobs (compile-time macros of exact_kernels.hip):
                     projector (loads of two batches are in flight per wave)
   EXACT_VIEW_BATCH  views per batch of the back-projector, likewise
   EXACT_FWD_SEGS    waves per forward workgroup (each takes a share of the
-                    lines of the workgroup's 64 rays)
+                    lines of the workgroup's 128 rays, two per lane)
 
 One choice serves every shape.  Each knob changes the order of the float
 sums, and a batched run must reproduce its solo run bit for bit, so all
@@ -150,12 +150,12 @@ def cmd_time(report=None, passes=2, per_run_timeout=300):
             print("[tune]   %s" % " ".join("%s:%.4f" % kv for kv in sorted(rec["ms"].items())),
                   flush=True)
     base = rows[tag(DEFAULT)]
-    xb = base["gate"]["x"]
+    xb, rb = base["gate"]["x"], base["gate"]["rho"]
     nb = math.sqrt(sum(v * v for v in xb))
     for t, r in rows.items():
         r["score"] = math.exp(sum(math.log(1e3 / ms) for ms in r["ms"].values()) / len(r["ms"]))
         dx = math.sqrt(sum((a - b) ** 2 for a, b in zip(r["gate"]["x"], xb))) / nb
-        drho = abs(r["gate"]["rho"] - base["gate"]["rho"]) / abs(base["gate"]["rho"])
+        drho = abs(r["gate"]["rho"] - rb) / abs(rb)
         r["gate_ok"] = dx <= 1e-5 and drho <= 1e-4
         if not r["gate_ok"]:
             print("[tune] %s rejected: iterate differs by %.2e, rho by %.2e" % (t, dx, drho),

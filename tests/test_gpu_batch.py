@@ -102,19 +102,19 @@ def test_batch_equals_solo_bitwise(ex):
         assert torch.equal(xs[i], xs_solo), i
 
 
-# images of 124 pixels or more: with a build that has the grouped
-# (LDS-staged) forward, the single-scan path projects most blocks with it
-# while the batched kernels project every block ungrouped, so equality shows
-# that the two forward kernels give bitwise the same rays
-GROUPED_SHAPES = [(128, 30, 182, 64, 4, 31, 1.0), (256, 90, 363, 17, 2, 32, 1.0),
-                  (160, 47, 227, 30, 3, 33, 1.0), (200, 200, 200, 10, 2, 34, 1.0)]
+# wider images and bin widths whose views take each of the forward's three
+# tap rules (|P| below 1, 1 to 2, 2 or more): the batched kernels run the
+# single-scan kernels' device code on every item
+WIDE_SHAPES = [(128, 30, 182, 64, 4, 31, 1.0), (256, 90, 363, 17, 2, 32, 1.0),
+               (160, 47, 227, 30, 3, 33, 1.0), (200, 200, 200, 10, 2, 34, 1.0),
+               (96, 40, 80, 12, 2, 35, 1.6), (96, 40, 200, 12, 2, 36, 0.7)]
 
 
-def test_batch_equals_solo_bitwise_grouped(ex):
+def test_batch_equals_solo_bitwise_wide(ex):
     Ps = [synth.make_problem("batch", N, V, B, K, Wn, 1e4, 6, seed, seed + 100,
                              with_truth=False, bin_cm=ratio * synth.FOV_CM / N)
-          for N, V, B, K, Wn, seed, ratio in GROUPED_SHAPES]
-    say("batch vs solo (grouped forward)", [(P.n_pix, P.n_views, P.n_bins) for P in Ps])
+          for N, V, B, K, Wn, seed, ratio in WIDE_SHAPES]
+    say("batch vs solo (wide shapes)", [(P.n_pix, P.n_views, P.n_bins) for P in Ps])
     opts = dict(max_iters=12)
     xs, infos = run_batch(ex, Ps, chunk=5, **opts)
     for i, P in enumerate(Ps):

@@ -73,12 +73,16 @@ SMALL_SHAPES = [
     # detectors narrower than the image: the gather's clamped pair rule
     ("narrow_detector", 48, 30, 40, 1.0, 1),
     ("narrow_detector_wide_bins", 31, 7, 11, 2.0, 1),
-    # images wide enough for the grouped (LDS-staged) forward of a build that
-    # has it, with the blocks it leaves to the ungrouped kernel
-    ("grouped_ragged", 130, 33, 184, 1.0, 1),
-    ("grouped_full_turn", 160, 50, 227, 1.0, 2),
-    ("grouped_wide_bins", 128, 29, 140, 1.3, 1),
-    ("grouped_narrow_bins", 128, 29, 260, 0.7, 1),
+    # wider images: several blocks of 128 rays per view, the last one ragged.
+    # The forward's lanes take two adjacent rays and read their taps by one
+    # of three rules, by the view's |P| (bins per pixel along the line):
+    # below 1 (narrow bins), 1 to 2, and 2 or more (the 2.0 and 1.6 ratios;
+    # at 1.6 the views near 45 degrees pass 2 while the others stay below)
+    ("wide_ragged", 130, 33, 184, 1.0, 1),
+    ("wide_full_turn", 160, 50, 227, 1.0, 2),
+    ("wide_bins_130", 128, 29, 140, 1.3, 1),
+    ("narrow_bins_130", 128, 29, 260, 0.7, 1),
+    ("mixed_rules_bins", 96, 40, 80, 1.6, 1),
 ]
 
 

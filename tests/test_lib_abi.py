@@ -101,9 +101,13 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def test_run_footprint_is_host_arithmetic(lib):
     from paper_2503_19925_amd import exact
-    # 2 sinogram-sized and 4 image-sized float buffers plus small tables
-    f = exact.exact_run_footprint(512, 180, 725)
-    assert 4 * (2 * 180 * 725 + 4 * 512 * 512) < f < 4 * (2 * 180 * 725 + 4 * 512 * 512) + 65536
+    # the counts, the padded residual (two zero bins at each end of a row),
+    # four padded images (four zero columns at each end of a row, and a
+    # tail of 64 zero floats) and small tables
+    N, V, B = 512, 180, 725
+    base = 4 * (V * B + V * (B + 4) + 4 * (N * (N + 8) + 64))
+    f = exact.exact_run_footprint(N, V, B)
+    assert base < f < base + 65536
     assert exact.exact_run_footprint(0, 10, 10) == 0
 
 

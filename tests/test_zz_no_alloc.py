@@ -59,7 +59,7 @@ def test_noalloc_operator_equals_operator_twice(ex):
 
 def test_noalloc_operator_refuses_oversized_input(ex):
     mib = 32
-    # padded pair alone: 2 N (N + 4) floats > 32 MiB for N = 2048
+    # padded pair alone: 2 (N (N + 8) + 64) floats > 32 MiB for N = 2048
     N, V, B = 2048, 4, 2897
     say("noalloc operator oversized", N, V, B)
     g = ex.Geometry(N, V, B)
