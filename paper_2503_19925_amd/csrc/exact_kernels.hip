@@ -250,12 +250,18 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 
 // A forward lane takes two adjacent rays of a view.  On every line the ray
 // with the lower crossing (in columns) is at flo and the other at fhi =
-// flo + |P|, both advanced exactly by Q per line.  Each ray's taps are the
-// single-ray rule's: weights (float)(1 - e) and (float)e, e = f - floor(f),
-// of columns floor(f) and floor(f) + 1, the column being the truncated f
-// clamped into the padded row (every crossing with a tap inside the image
-// has f >= 1, where truncation is floor; any other reads padding zeros, as
-// do lines the ray does not reach).
+// flo + |P|, both advanced exactly by Q per line.  The crossings lie on the
+// 2^-32 grid with |f| < 2^20, so the lane holds them as 64-bit integers F =
+// f 2^32: the high word is floor(f) and the low word is 2^32 (f -
+// floor(f)), and F += Q 2^32 is exact.  Each ray's taps are the single-ray
+// rule's: columns floor(f) and floor(f) + 1 with weights (float)(1 - e) and
+// (float)e, e = f - floor(f), the column clamped into the padded row (every
+// crossing with a tap inside the image has f >= 1; any other reads padding
+// zeros, as do lines the ray does not reach).  The lane forms the weights
+// times 2^32, (float)(2^32 - lo) and (float)lo: the exact values rounded
+// once, so each is the unit weight times 2^32 exactly, and the ray's sums
+// carry that factor until forward_pair_end removes it (every step of the
+// sums scales exactly).
 //
 // kMode 0 (|P| < 1) and 1 (1 <= |P| < 2): the four taps lie in the four
 // columns c .. c + 3 from the lower ray's column c, which one 16-byte load
@@ -270,24 +276,34 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 // load per ray (measured on MI355X with the forward's access pattern).
 // kMode 2 (|P| >= 2): one 8-byte load per ray.
 struct PairTaps {
-    float l0, l1, h0, h1;   // weights: lower ray, upper ray
+    float l0, l1, h0, h1;   // weights times 2^32: lower ray, upper ray
     float v0, v1, v2, v3;   // modes 0, 1: columns c .. c + 3; mode 2: lower pair, upper pair
     bool up;                // modes 0, 1: d > kMode
 };
 
-template <int kMode>
-__device__ __forceinline__ void pair_fetch(double &flo, double &fhi, int cmax, double Q,
-                                           const float *__restrict__ img, int rowoff, PairTaps &t)
+// x 2^32 as a 64-bit integer, for x on the 2^-32 grid with |x| < 2^20 (exact).
+__device__ __forceinline__ long long fixed32(double x)
 {
-    const double elo = __builtin_amdgcn_fract(flo);   // exact, in [0, 1)
-    const double ehi = __builtin_amdgcn_fract(fhi);
-    const int clo = clamp_int<0>((int)flo, cmax);
-    const int chi = clamp_int<0>((int)fhi, cmax);
-    flo += Q;                                          // exact
+    return (long long)(x * 4294967296.0);
+}
+
+template <int kMode>
+__device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, int cmax,
+                                           long long Q, const float *__restrict__ img,
+                                           int rowoff, PairTaps &t)
+{
+    const unsigned elo = (unsigned)flo, ehi = (unsigned)fhi;   // 2^32 (f - floor(f))
+    const int clo = clamp_int<0>((int)(flo >> 32), cmax);     // floor(f), clamped
+    const int chi = clamp_int<0>((int)(fhi >> 32), cmax);
+    flo += Q;                                                  // exact
     fhi += Q;
-    t.l0 = (float)(1.0 - elo);
-    t.l1 = (float)elo;
-    t.h0 = (float)(1.0 - ehi);
+    // one running crossing per ray (kept opaque: otherwise the compiler
+    // forms every unrolled line's crossing from the first and keeps them all
+    // live)
+    asm("" : "+v"(flo), "+v"(fhi));
+    t.l0 = (float)(4294967296.0 - (double)elo);                // 2^32 (1 - e), rounded once
+    t.l1 = (float)elo;                                         // 2^32 e, rounded once
+    t.h0 = (float)(4294967296.0 - (double)ehi);
     t.h1 = (float)ehi;
     const unsigned i = (unsigned)(rowoff + clo);
     if (kMode < 2) {
@@ -335,9 +351,9 @@ __device__ __forceinline__ void pair_apply(const PairTaps &t, float &slo, float 
 // between them would make the compiler wait for the loads) and scheduling
 // barriers that keep that order.
 template <int kMode>
-__device__ __forceinline__ void pair_lines(double flo, double fhi, int kw0, int kw1, int cmax,
-                                           double Q, int Np, const float *__restrict__ img,
-                                           Kahan &alo, Kahan &ahi)
+__device__ __forceinline__ void pair_lines(long long flo, long long fhi, int kw0, int kw1,
+                                           int cmax, long long Q, int Np,
+                                           const float *__restrict__ img, Kahan &alo, Kahan &ahi)
 {
     PairTaps ta[kLineBatch], tb[kLineBatch];
     int k = kw0;
@@ -431,7 +447,8 @@ __device__ __forceinline__ void forward_pair_end(const Kahan &ae, const Kahan &a
         tot.add(ps[u][r]);
         tot.add(-pc[u][r]);
     }
-    float val = tot.value() * G.wstep;
+    // the sums carry the weights' factor 2^32 (removed exactly)
+    float val = (tot.value() * 0x1p-32f) * G.wstep;
     if (kResid) {
         const float sp0 = fmaxf(val, 0.f) + ((sp.bg && ray) ? sp.bg[i] : 0.f);
         float m = 0.f;
@@ -497,18 +514,20 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
         kw0 = kmin + seg * per;
         kw1 = min(kmax, kw0 + per - 1);
     }
-    // padded column coordinates of the lane's rays on line kw0
+    // padded column coordinates of the lane's rays on line kw0 (exact), as
+    // 2^-32 fixed point
     const double fe = fma((double)kw0, G.Q, fma((double)(b0 + 2 * lane), G.P, G.A)) + (double)kPadX;
     const double fo = fma((double)kw0, G.Q, fma((double)(b0 + 2 * lane + 1), G.P, G.A)) + (double)kPadX;
+    const long long Fe = fixed32(fe), Fo = fixed32(fo), Qf = fixed32(G.Q);
     const bool rising = G.P >= 0.0;                 // ray 2l + 1 crosses to the right of ray 2l
     const double aP = fabs(G.P);
     Kahan alo, ahi;
     if (aP < 1.0)
-        pair_lines<0>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+        pair_lines<0>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     else if (aP < 2.0)
-        pair_lines<1>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+        pair_lines<1>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     else
-        pair_lines<2>(rising ? fe : fo, rising ? fo : fe, kw0, kw1, cmax, G.Q, Np, img, alo, ahi);
+        pair_lines<2>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     forward_pair_end<kResid>(rising ? alo : ahi, rising ? ahi : alo, seg, lane, G, b0, B, part_s,
                              part_c, part_m, Y, sp, out, ostride, ooff, weighted, plain);
 }
