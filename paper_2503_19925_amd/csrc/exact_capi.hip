@@ -908,16 +908,30 @@ void fill_info(const Problem &p, const SolveState &h, exact_solve_info *info,
     info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Enqueue `n` replays of `exec` on `own`, ordered after and before `user`.
-void replay(hipGraphExec_t exec, int n, hipStream_t own, hipStream_t user)
+// Steps per replay of a multi-step graph (a solver's or a batch's): a graph
+// launch costs the host and the GPU a fixed overhead, which the steps of one
+// graph share.  Steps after a run stops are no-ops on the device either way.
+#ifndef EXACT_GRAPH_STEPS
+#define EXACT_GRAPH_STEPS 8
+#endif
+constexpr int kGraphSteps = EXACT_GRAPH_STEPS;
+static_assert(kGraphSteps >= 1, "steps per graph");
+
+// n steps on stream own, ordered after the work on `user` and before what
+// `user` enqueues next: replays of `multi` (kGraphSteps steps each), then of
+// `one` for the rest.
+void replay_steps(hipGraphExec_t one, hipGraphExec_t multi, int n, hipStream_t own,
+                  hipStream_t user)
 {
     hipEvent_t ev;
     hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
     hipError_t e = hipEventRecord(ev, user);
     if (e == hipSuccess)
         e = hipStreamWaitEvent(own, ev, 0);
-    for (int c = 0; c < n && e == hipSuccess; ++c)
-        e = hipGraphLaunch(exec, own);
+    for (int c = 0; c + kGraphSteps <= n && e == hipSuccess; c += kGraphSteps)
+        e = hipGraphLaunch(multi, own);
+    for (int c = n - n % kGraphSteps; c < n && e == hipSuccess; ++c)
+        e = hipGraphLaunch(one, own);
     if (e == hipSuccess)
         e = hipEventRecord(ev, own);
     if (e == hipSuccess)
@@ -1032,7 +1046,8 @@ struct exact_solver_s {
     std::unique_ptr<DevBuf> state;
     std::unique_ptr<PinnedState> hs;
     Problem prob;
-    Graph step;
+    Graph step;       // one step
+    Graph steps;      // kGraphSteps steps
     std::chrono::steady_clock::time_point t0;
 
     ~exact_solver_s()
@@ -1040,6 +1055,7 @@ struct exact_solver_s {
         if (own && own->st)
             (void)hipStreamSynchronize(own->st);
         step.reset();
+        steps.reset();
     }
 };
 
@@ -1057,8 +1073,16 @@ exact_solver_s *solver_build(exact_geometry_s *g, const exact_spectrum *sp, cons
     problem_init(s->prob, g, sp, y_dev, x_dev, o, s->state->as<SolveState>(), s->own->st);
     const Problem &p = s->prob;
     s->step.capture(s->own->st, [&]() { return enqueue_step(p, s->own->st); });
+    s->steps.capture(s->own->st, [&]() {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+            e = enqueue_step(p, s->own->st);
+        return e;
+    });
     return s.release();
 }
+
+
 
 int solver_poll(exact_solver_s *s, exact_solve_info *info)
 {
@@ -1086,13 +1110,15 @@ struct exact_batch_s {
     bool dirty = true;
     std::unique_ptr<DevBuf> descs, fwd, back;
     int nprob = 0, nfwd = 0, nback = 0;
-    Graph step;
+    Graph step;       // one step of every running scan
+    Graph steps;      // kGraphSteps such steps
 
     ~exact_batch_s()
     {
         if (own && own->st)
             (void)hipStreamSynchronize(own->st);
         step.reset();
+        steps.reset();
         if (hstates)
             (void)hipHostFree(hstates);
     }
@@ -1148,6 +1174,12 @@ void batch_rebuild(exact_batch_s *b)
     const exact::BatchItem *f = b->fwd->as<exact::BatchItem>(), *bk = b->back->as<exact::BatchItem>();
     b->step.capture(st, [&]() {
         return exact::launch_batch_step(dp, b->nprob, f, b->nfwd, bk, b->nback, st);
+    });
+    b->steps.capture(st, [&]() {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+            e = exact::launch_batch_step(dp, b->nprob, f, b->nfwd, bk, b->nback, st);
+        return e;
     });
     b->dirty = false;
 }
@@ -1346,7 +1378,7 @@ int exact_solver_step(exact_solver s, int32_t n_steps, void *stream)
             fail(-EINVAL, "solver is NULL");
         if (n_steps < 0)
             fail(-EINVAL, "n_steps must be >= 0");
-        replay(s->step.exec, n_steps, s->own->st, (hipStream_t)stream);
+        replay_steps(s->step.exec, s->steps.exec, n_steps, s->own->st, (hipStream_t)stream);
         return 0;
     });
 }
@@ -1383,7 +1415,7 @@ int exact_solve(exact_geometry g, const exact_spectrum *sp, const float *y_dev, 
         exact_solve_info local;
         while (launched < o.max_iters) {
             const int chunk = std::min(o.check_every, o.max_iters - launched);
-            replay(s->step.exec, chunk, s->own->st, (hipStream_t)stream);
+            replay_steps(s->step.exec, s->steps.exec, chunk, s->own->st, (hipStream_t)stream);
             launched += chunk;
             if (solver_poll(s.get(), &local))
                 break;
@@ -1492,7 +1524,7 @@ int exact_batch_step(exact_batch bh, int32_t n_steps, void *stream)
             batch_rebuild(b);
         if (b->nprob == 0 || n_steps == 0)
             return 0;
-        replay(b->step.exec, n_steps, b->own->st, (hipStream_t)stream);
+        replay_steps(b->step.exec, b->steps.exec, n_steps, b->own->st, (hipStream_t)stream);
         return 0;
     });
 }

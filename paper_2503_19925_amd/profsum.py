@@ -190,7 +190,8 @@ def cmd_kernels(out_dir):
     tot = 2 * fwd + bh + bf
     md = ["# Kernel times, workload solve_512 (EXACT step)", "",
           "512x512 image, 180 views over 180 deg, 725 bins, K=30 energy bins, 3 windows.",
-          "One EG step is a captured graph of four kernels: k_forward<true> (forward",
+          "One EG step is four kernels (the solver replays captured graphs of eight",
+          "steps): k_forward<true> (forward",
           "projection + spectral residual at x_t, written weighted into the padded",
           "residual; one more workgroup, dispatched last, runs the previous step's finish),",
           "k_back_update<true, true, false> (back-projection + half-step update +",
@@ -223,9 +224,12 @@ def cmd_kernels(out_dir):
                fwd, fwd_b, 100 * (fwd_b - fwd) / fwd),
            "k_back_update<true, true, false> %.2f us, k_back_update<true, false, false> %.2f us" % (bh, bf),
            "(and the standalone k_eg_finish<false> %.2f us); the graph's four kernels sum to" % fin,
-           "%.1f us per step, %.1f us short of the replayed step: the gaps between the"
-           % (tot, b["ms_per_step"] * 1e3 - tot),
-           "graph's kernels and the finish workgroup of the first kernel.", "",
+           ("%.1f us per step, %.1f us short of the replayed step: the gaps between the "
+            "graph's kernels and the finish workgroup of the first kernel."
+            % (tot, b["ms_per_step"] * 1e3 - tot)) if tot <= b["ms_per_step"] * 1e3 else
+           ("%.1f us per step, above the replayed step's %.1f us: the profiler lengthens "
+            "each dispatch, and without it the gaps between the graph's kernels (eight "
+            "steps per graph) take less than that." % (tot, b["ms_per_step"] * 1e3)), "",
            "The benchmark times each kernel over back-to-back launches of that kernel",
            "alone; in the trace above most dispatches run inside the step, after the",
            "other kernel, and the first of each call starts cold.  The trace's own",
