@@ -627,6 +627,47 @@ def test_solver_profile_steps_equal_graph_steps(ex):
     g.close()
 
 
+def test_solver_step_grouping_is_bitwise_neutral(ex):
+    """A solver's steps run as replays of an eight-step graph and then of a
+    one-step graph for the rest: 13 steps in one call, 5 then 8, and 13 one
+    at a time give bitwise the same iterate and state; and a run that stops
+    inside an eight-step replay (max_iters 11) stops at its step with the
+    iterate of an eleven-step run."""
+    P = synth.config_problem("small_64")
+    say("solver step grouping")
+    g = ex.Geometry(P.n_pix, P.n_views, P.n_bins)
+    y = t32(P.y)
+    xs, infos = [], []
+    for calls in ([13], [5, 8], [1] * 13):
+        x = torch.zeros(g.d, device=DEV)
+        sv = ex.Solver(g, P.mu, P.I, y, x, max_iters=100)
+        for n in calls:
+            sv.step(n)
+        _, info = sv.poll()
+        torch.cuda.synchronize()
+        xs.append(x)
+        infos.append(info)
+        sv.close()
+    assert all(i["iters"] == 13 for i in infos), infos
+    assert all(torch.equal(xs[0], x) for x in xs[1:])
+    assert all(i["resid"] == infos[0]["resid"] for i in infos)
+    # stopping inside a replay: later steps of the graph are no-ops
+    xa, xb = torch.zeros(g.d, device=DEV), torch.zeros(g.d, device=DEV)
+    sa = ex.Solver(g, P.mu, P.I, y, xa, max_iters=11)
+    sa.step(16)
+    _, ia = sa.poll()
+    sb = ex.Solver(g, P.mu, P.I, y, xb, max_iters=100)
+    for _ in range(11):
+        sb.step(1)
+    _, ib = sb.poll()
+    torch.cuda.synchronize()
+    assert ia["iters"] == ib["iters"] == 11
+    assert torch.equal(xa, xb)
+    sa.close()
+    sb.close()
+    g.close()
+
+
 def test_scalar_worked_example_on_gpu(ex):
     """The hand-worked one-pixel example (tests/golden/eg_scalar.txt)."""
     say("scalar EG example")
