@@ -65,10 +65,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 64 * 2.4e9 / 2 / 1e12
 # VALU instructions of the inner loops, counted in their gfx950 assembly
 # (Kahan steps included): per pixel and view in the gather (clamp-free
-# form, which the benchmark geometry uses), per ray and line in the forward.
-# Used only when no counter reading of the current build is committed.
+# form, which the benchmark geometry uses), per ray and line in the forward
+# (two rays per lane).  Used only when no counter reading of the current
+# build is committed; the counters also see the forward's lanes on lines
+# their rays miss, its epilogue and loop control (about 17.7 per ray-line).
 VALU_PER_PIXEL_VIEW = 14.0
-VALU_PER_RAY_LINE = 12.5
+VALU_PER_RAY_LINE = 12.0
 KERNEL_FWD = "k_forward<true>"
 KERNEL_BU = "k_back_update"
 
