@@ -27,7 +27,7 @@ __device__ __forceinline__ bool dskip(const int32_t *skip)
 // Rows [blockIdx.x * rpb, min(n, (blockIdx.x + 1) * rpb)) of A (n x d,
 // row-major); thread t owns columns t + 256 c, c < C.  linear: r_i = s_i
 // (the power iteration's A^T A x), else the spectral residual.  Rows go in
-// batches of RB; the next batch's loads are issued before the current
+// batches of RB; later batches' loads are issued before the current
 // batch's block reduction, so they stay in flight across its barrier.
 template <int C, int RB>
 __device__ __forceinline__ void dense_load(const float *__restrict__ A, long row0, long i1, int d,
@@ -67,12 +67,12 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
     }
     const long i0 = (long)blockIdx.x * rpb;
     const long i1 = min(n, i0 + rpb);
-    float a[RB][C];
-    dense_load<C, RB>(A, i0, i1, d, t, a);
     int buf = 0;
-    for (long i = i0; i < i1; i += RB) {
-        float an[RB][C];
-        dense_load<C, RB>(A, i + RB, i1, d, t, an);
+    // rows i .. i + RB - 1 (held in a): inner products with x (a fixed-order
+    // block reduction: the wave's lanes, then the four waves in order), the
+    // residual, and r_i a_i into the partial gradient; one barrier, with the
+    // LDS slots alternating between batches
+    auto sum_batch = [&](const float(&a)[RB][C], long i) {
         float dot[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
@@ -110,13 +110,23 @@ __global__ __launch_bounds__(kDT) void k_dense_F(const float *__restrict__ A, lo
             for (int c = 0; c < C; ++c)
                 g[c] = fmaf(a[q][c], r, g[c]);
         }
-        // the other LDS buffer takes the next batch: no second barrier
         buf ^= 1;
-#pragma unroll
-        for (int q = 0; q < RB; ++q)
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                a[q][c] = an[q][c];
+    };
+    // two register sets used alternately, without copies: one batch's loads
+    // stay in flight while the other is summed (a third set, with two
+    // batches in flight, measured 10 % slower: its registers cost more
+    // occupancy than the deeper prefetch gains)
+    float a0[RB][C], a1[RB][C];
+    dense_load<C, RB>(A, i0, i1, d, t, a0);
+    for (long i = i0; i < i1; i += 2 * RB) {
+        dense_load<C, RB>(A, i + RB, i1, d, t, a1);
+        sum_batch(a0, i);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + RB >= i1)
+            break;
+        dense_load<C, RB>(A, i + 2 * RB, i1, d, t, a0);
+        sum_batch(a1, i + RB);
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
