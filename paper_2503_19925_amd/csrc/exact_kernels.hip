@@ -265,20 +265,30 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 //
 // kMode 0 (|P| < 1) and 1 (1 <= |P| < 2): the four taps lie in the four
 // columns c .. c + 3 from the lower ray's column c, which one 16-byte load
-// (at a 4-byte-aligned address) reads.  The upper ray's first tap is column
-// c + d, d = chi - c; unclamped d is kMode or kMode + 1, so a select
-// between those two offsets places it.  Clamping only lowers d, and then
-// the upper ray's taps and the columns read in their place are all padding
-// (at the row's start kPadX >= 3 zero columns; at its end the last two
-// padded columns and the next row's first, or the buffer's zero tail).
+// (at a 4-byte-aligned address) reads.  The lane keeps only the lower
+// crossing: with |P| 2^32 = kMode 2^32 + p (p < 2^32), the upper ray's low
+// word is lo + p mod 2^32 and its column is c + d, d = kMode + the carry of
+// that add, so the carry selects between the two offsets.  If c is clamped
+// (f < 0 or f > cmax), both rays' taps lie in the padding, and the columns
+// c + d, c + d + 1 read in place of the upper ray's are padding too (at the
+// row's start kPadX >= 3 zero columns; at its end the last two padded
+// columns and the next row's first, or the buffer's zero tail).  An
+// unclamped c whose upper ray passes cmax reads the same padding columns
+// the clamped column would.
 // Lanes read neighbouring columns, and this one load serves two rays: the
 // address unit takes about a third less time per tap than with one 8-byte
 // load per ray (measured on MI355X with the forward's access pattern).
 // kMode 2 (|P| >= 2): one 8-byte load per ray.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));   // 4-byte aligned
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
 struct PairTaps {
     float l0, l1, h0, h1;   // weights times 2^32: lower ray, upper ray
-    float v0, v1, v2, v3;   // modes 0, 1: columns c .. c + 3; mode 2: lower pair, upper pair
-    bool up;                // modes 0, 1: d > kMode
+    // modes 0, 1: columns c .. c + 3; mode 2: lower pair, upper pair (one
+    // vector, so that the loop-carried set stays one register tuple)
+    f4 v;
+    bool up;                // modes 0, 1: d = kMode + 1
 };
 
 // x 2^32 as a 64-bit integer, for x on the 2^-32 grid with |x| < 2^20 (exact).
@@ -288,19 +298,31 @@ __device__ __forceinline__ long long fixed32(double x)
 }
 
 template <int kMode>
-__device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, int cmax,
-                                           long long Q, const float *__restrict__ img,
-                                           int rowoff, PairTaps &t)
+__device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, unsigned pfrac,
+                                           int cmax, long long Q,
+                                           const float *__restrict__ img, int rowoff,
+                                           PairTaps &t)
 {
-    const unsigned elo = (unsigned)flo, ehi = (unsigned)fhi;   // 2^32 (f - floor(f))
+    const unsigned elo = (unsigned)flo;                        // 2^32 (f - floor(f))
     const int clo = clamp_int<0>((int)(flo >> 32), cmax);     // floor(f), clamped
-    const int chi = clamp_int<0>((int)(fhi >> 32), cmax);
+    unsigned ehi;
+    int chi = 0;
+    if (kMode < 2) {
+        t.up = __builtin_uadd_overflow(elo, pfrac, &ehi);     // upper ray: d = kMode + carry
+    } else {
+        ehi = (unsigned)fhi;
+        chi = clamp_int<0>((int)(fhi >> 32), cmax);
+        t.up = false;
+        fhi += Q;
+    }
     flo += Q;                                                  // exact
-    fhi += Q;
     // one running crossing per ray (kept opaque: otherwise the compiler
     // forms every unrolled line's crossing from the first and keeps them all
     // live)
-    asm("" : "+v"(flo), "+v"(fhi));
+    if (kMode < 2)
+        asm("" : "+v"(flo));
+    else
+        asm("" : "+v"(flo), "+v"(fhi));
     t.l0 = (float)(4294967296.0 - (double)elo);                // 2^32 (1 - e), rounded once
     t.l1 = (float)elo;                                         // 2^32 e, rounded once
     t.h0 = (float)(4294967296.0 - (double)ehi);
@@ -308,18 +330,12 @@ __device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, int c
     const unsigned i = (unsigned)(rowoff + clo);
     if (kMode < 2) {
         const float *p = (const float *)((const char *)img + (i << 2));
-        t.v0 = p[0];
-        t.v1 = p[1];
-        t.v2 = p[2];
-        t.v3 = p[3];
-        t.up = chi - clo > kMode;
+        t.v = *(const f4u *)p;
     } else {
         const unsigned j = (unsigned)(rowoff + chi);
-        t.v0 = at(img, i);
-        t.v1 = at(img + 1, i);
-        t.v2 = at(img, j);
-        t.v3 = at(img + 1, j);
-        t.up = false;
+        const f2u a = *(const f2u *)((const char *)img + (i << 2));
+        const f2u b = *(const f2u *)((const char *)img + (j << 2));
+        t.v = f4{a.x, a.y, b.x, b.y};
     }
 }
 
@@ -328,17 +344,17 @@ __device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, int c
 template <int kMode>
 __device__ __forceinline__ void pair_apply(const PairTaps &t, float &slo, float &shi)
 {
-    slo = fmaf(t.l1, t.v1, fmaf(t.l0, t.v0, slo));
+    slo = fmaf(t.l1, t.v.y, fmaf(t.l0, t.v.x, slo));
     float a, b;
     if (kMode == 0) {
-        a = t.up ? t.v1 : t.v0;
-        b = t.up ? t.v2 : t.v1;
+        a = t.up ? t.v.y : t.v.x;
+        b = t.up ? t.v.z : t.v.y;
     } else if (kMode == 1) {
-        a = t.up ? t.v2 : t.v1;
-        b = t.up ? t.v3 : t.v2;
+        a = t.up ? t.v.z : t.v.y;
+        b = t.up ? t.v.w : t.v.z;
     } else {
-        a = t.v2;
-        b = t.v3;
+        a = t.v.z;
+        b = t.v.w;
     }
     shi = fmaf(t.h1, b, fmaf(t.h0, a, shi));
 }
@@ -346,56 +362,46 @@ __device__ __forceinline__ void pair_apply(const PairTaps &t, float &slo, float 
 // The lines kw0 .. kw1 of the padded image img for a lane's two rays,
 // from crossings flo, fhi on line kw0, into Kahan sums (lower ray, upper
 // ray).  Batches of kLineBatch lines are summed in float before one Kahan
-// step.  Software-pipelined: the next batch's loads are issued before the
-// current batch is summed, with two register sets used alternately (a copy
-// between them would make the compiler wait for the loads) and scheduling
-// barriers that keep that order.
+// step.  Software-pipelined with one register set: each line's taps are
+// used and the slot is at once refilled with the next batch's line, so a
+// batch of loads is in flight while the current batch is summed, and no
+// value moves between registers from one batch to the next.
 template <int kMode>
-__device__ __forceinline__ void pair_lines(long long flo, long long fhi, int kw0, int kw1,
-                                           int cmax, long long Q, int Np,
+__device__ __forceinline__ void pair_lines(long long flo, long long fhi, unsigned pfrac, int kw0,
+                                           int kw1, int cmax, long long Q, int Np,
                                            const float *__restrict__ img, Kahan &alo, Kahan &ahi)
 {
-    PairTaps ta[kLineBatch], tb[kLineBatch];
+    PairTaps t[kLineBatch];
     int k = kw0;
-    auto fetch = [&](PairTaps(&t)[kLineBatch]) {
+    const int nb = kw1 >= kw0 ? (kw1 - kw0 + 1) / kLineBatch : 0;
+    if (nb > 0) {
 #pragma unroll
         for (int q = 0; q < kLineBatch; ++q)
-            pair_fetch<kMode>(flo, fhi, cmax, Q, img, (k + q) * Np, t[q]);
+            pair_fetch<kMode>(flo, fhi, pfrac, cmax, Q, img, (k + q) * Np, t[q]);
         k += kLineBatch;
-    };
-    auto apply = [&](const PairTaps(&t)[kLineBatch]) {
+        for (int i = 1; i < nb; ++i) {
+            float slo = 0.f, shi = 0.f;
+#pragma unroll
+            for (int q = 0; q < kLineBatch; ++q) {
+                pair_apply<kMode>(t[q], slo, shi);
+                pair_fetch<kMode>(flo, fhi, pfrac, cmax, Q, img, (k + q) * Np, t[q]);
+            }
+            k += kLineBatch;
+            alo.add(slo);
+            ahi.add(shi);
+        }
         float slo = 0.f, shi = 0.f;
 #pragma unroll
         for (int q = 0; q < kLineBatch; ++q)
             pair_apply<kMode>(t[q], slo, shi);
         alo.add(slo);
         ahi.add(shi);
-    };
-    const int nb = kw1 >= kw0 ? (kw1 - kw0 + 1) / kLineBatch : 0;
-    if (nb > 0) {
-        fetch(ta);
-        int i = 1;
-        for (; i + 1 < nb; i += 2) {
-            fetch(tb);
-            apply(ta);
-            __builtin_amdgcn_sched_barrier(0);
-            fetch(ta);
-            apply(tb);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (i < nb) {
-            fetch(tb);
-            apply(ta);
-            apply(tb);
-        } else {
-            apply(ta);
-        }
     }
     for (; k <= kw1; ++k) {
-        PairTaps t;
-        pair_fetch<kMode>(flo, fhi, cmax, Q, img, k * Np, t);
+        PairTaps u;
+        pair_fetch<kMode>(flo, fhi, pfrac, cmax, Q, img, k * Np, u);
         float slo = 0.f, shi = 0.f;
-        pair_apply<kMode>(t, slo, shi);
+        pair_apply<kMode>(u, slo, shi);
         alo.add(slo);
         ahi.add(shi);
     }
@@ -521,13 +527,15 @@ __device__ __forceinline__ void forward_block(const ViewGeom *__restrict__ views
     const long long Fe = fixed32(fe), Fo = fixed32(fo), Qf = fixed32(G.Q);
     const bool rising = G.P >= 0.0;                 // ray 2l + 1 crosses to the right of ray 2l
     const double aP = fabs(G.P);
+    const unsigned pfrac = (unsigned)fixed32(aP);   // |P| 2^32 mod 2^32
+    const long long Flo = rising ? Fe : Fo, Fhi = rising ? Fo : Fe;
     Kahan alo, ahi;
     if (aP < 1.0)
-        pair_lines<0>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
+        pair_lines<0>(Flo, Fhi, pfrac, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     else if (aP < 2.0)
-        pair_lines<1>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
+        pair_lines<1>(Flo, Fhi, pfrac, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     else
-        pair_lines<2>(rising ? Fe : Fo, rising ? Fo : Fe, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
+        pair_lines<2>(Flo, Fhi, pfrac, kw0, kw1, cmax, Qf, Np, img, alo, ahi);
     forward_pair_end<kResid>(rising ? alo : ahi, rising ? ahi : alo, seg, lane, G, b0, B, part_s,
                              part_c, part_m, Y, sp, out, ostride, ooff, weighted, plain);
 }
