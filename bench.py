@@ -70,7 +70,7 @@ VALU_PEAK_TOPS = 256 * 4 * 64 * 2.4e9 / 2 / 1e12
 # build is committed; the counters also see the forward's lanes on lines
 # their rays miss, its epilogue and loop control (about 17.7 per ray-line).
 VALU_PER_PIXEL_VIEW = 14.0
-VALU_PER_RAY_LINE = 12.0
+VALU_PER_RAY_LINE = 10.25
 KERNEL_FWD = "k_forward<true>"
 KERNEL_BU = "k_back_update"
 

@@ -240,12 +240,13 @@ long block_weight(const std::vector<int32_t> &blk, size_t i)
 // weight w[i] (the lines it walks).  The hardware hands workgroups to the
 // XCDs in turn and fills each CU with `per_cu` of them at once, so
 // workgroups i and i + cus * k share a CU in the first round.  Longest
-// items first; the first cus * per_cu go to the CUs' slots greedily (each
-// to the CU with the fewest lines so far among those with a free slot), so
-// that every CU's first round holds about the same number of lines; the
-// rest follow, longest first, into slots as they free.  Returns the item of
-// each workgroup.  The order changes which workgroup projects which rays,
-// never the arithmetic.
+// items first; the first min(n, cus * per_cu) go to the CUs' slots greedily
+// (each to the CU with the fewest lines so far among those with a free
+// slot: slot k of CU c is workgroup c + cus * k, which must exist), so that
+// every CU's first round holds about the same number of lines; the rest
+// follow, longest first, into slots as they free.  Returns the item of each
+// workgroup.  The order changes which workgroup projects which rays, never
+// the arithmetic.
 std::vector<int32_t> balanced_order(const std::vector<long> &w, int cus, int per_cu)
 {
     const int n = (int)w.size();
@@ -254,15 +255,16 @@ std::vector<int32_t> balanced_order(const std::vector<long> &w, int cus, int per
         idx[(size_t)i] = i;
     std::stable_sort(idx.begin(), idx.end(),
                      [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
-    const long first = (long)cus * per_cu;
-    if (cus < 1 || per_cu < 1 || n < first)
+    if (cus < 1 || per_cu < 1)
         return idx;
+    const long first = std::min((long)cus * per_cu, (long)n);
     std::vector<long> load((size_t)cus, 0);
     std::vector<int> used((size_t)cus, 0);
     for (long r = 0; r < first; ++r) {
         int best = -1;
         for (int c = 0; c < cus; ++c)
-            if (used[(size_t)c] < per_cu && (best < 0 || load[(size_t)c] < load[(size_t)best]))
+            if (c + (long)cus * used[(size_t)c] < first &&
+                (best < 0 || load[(size_t)c] < load[(size_t)best]))
                 best = c;
         order[(size_t)best + (size_t)cus * used[(size_t)best]] = idx[(size_t)r];
         load[(size_t)best] += w[(size_t)idx[(size_t)r]];

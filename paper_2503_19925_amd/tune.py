@@ -6,7 +6,8 @@
 
 Knobs (compile-time macros of exact_kernels.hip):
   EXACT_LINE_BATCH  image lines per software-pipelined batch of the forward
-                    projector (loads of two batches are in flight per wave)
+                    projector (the next batch's loads are in flight while a
+                    batch is summed)
   EXACT_VIEW_BATCH  views per batch of the back-projector, likewise
   EXACT_FWD_SEGS    waves per forward workgroup (each takes a share of the
                     lines of the workgroup's 128 rays, two per lane)
