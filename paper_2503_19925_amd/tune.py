@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 from paper_2503_19925_amd import build as libbuild  # noqa: E402
 
 VARIANT_DIR = os.path.join(HERE, "_tune")
-GRID = {"EXACT_LINE_BATCH": (2, 4, 6), "EXACT_VIEW_BATCH": (2, 4, 6), "EXACT_FWD_SEGS": (2, 4, 8)}
+GRID = {"EXACT_LINE_BATCH": (2, 4, 6, 8), "EXACT_VIEW_BATCH": (2, 4, 6), "EXACT_FWD_SEGS": (2, 4, 8)}
 DEFAULT = dict(libbuild.DEFAULT_KNOBS)
 # (name, N, V, B, K, Wn, I0, timed steps)
 CLASSES = [("256", 256, 180, 363, 30, 3, 1e4, 400), ("512", 512, 180, 725, 30, 3, 1e4, 300),
