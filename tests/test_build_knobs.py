@@ -27,4 +27,4 @@ def test_defines_and_build_id_follow_the_knobs():
 
 def test_tuner_grid_holds_the_defaults():
     assert tune.tag(tune.DEFAULT) in {tune.tag(k) for k in tune.variants()}
-    assert len(list(tune.variants())) == 27
+    assert len(list(tune.variants())) == 36
