@@ -16,6 +16,10 @@
     python -m paper_2503_19925_amd.profsum tests <kernel_stats.csv> <pytest log>
         a kernel trace of the GPU test suite -> profiles/kernels_gpu_tests.md,
         checked against every kernel compiled into libexact.so.
+    python -m paper_2503_19925_amd.profsum batched <kernel_trace.csv> <bench stderr> [out.md]
+        a kernel trace of the benchmark's batched leg (BATCHED_TRACE) -> out.md
+        (default profiles/kernels_batched.md): the batched phase's busy time,
+        its kernels, the per-step split and the serial leg's kernel time.
 
 traffic.json and valu.json carry the build id (kernel source and tile
 knobs) the counters were taken on; bench.py reports their figures only while
@@ -52,6 +56,10 @@ LARGE_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_o
 LARGE_BENCH = ("python3 bench.py --workload large_1024 --steps 20 --warmup 3 --proj-reps 10 "
                "--kernel-reps 10 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
                "--dense-steps 0 --to-tol 1e-4")
+BATCHED_TRACE = ("rocprofv3 --kernel-trace --output-format csv -d <trace dir> -o b -- python3 "
+                 "bench.py --steps 5 --warmup 2 --proj-reps 2 --kernel-reps 2 --cpu-steps 0 "
+                 "--tv-steps -1 --dense-steps 0 --background-steps 0 --served 0 "
+                 "--large-to-tol 0 --batch 64 2> <bench stderr>")
 TESTS_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_tests "
                "-o tests -- python3 -u -m pytest tests -m gpu -x -q --timeout 600 "
                "--timeout-method thread")
@@ -435,6 +443,99 @@ def cmd_tests(stats_csv, log):
     print("wrote kernels_gpu_tests.md; %d compiled, %d not launched" % (len(allk), len(missing)))
 
 
+# ------------------------------------------------------------- batched leg
+
+def step_kind(name):
+    """The step kernel a dispatch belongs to (batched or single-scan), or
+    None."""
+    n = short(name)
+    for k in ("kb_forward", "kb_back_update", "kb_finish", "k_forward", "k_back_update",
+              "k_eg_finish"):
+        if n == k or n.startswith(k + "<"):
+            return k
+    return None
+
+
+def cmd_batched(trace_csv, err_log, out=None):
+    out = out or os.path.join(PROFILES, "kernels_batched.md")
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                  for r in csv.DictReader(open(trace_csv)))
+    err = open(err_log).read()
+    t_ser = float(re.search(r"serial: ([0-9.]+) s", err).group(1))
+    t_bat = float(re.search(r"batched: ([0-9.]+) s", err).group(1))
+    kb = [r for r in rows if (step_kind(r[2]) or "").startswith("kb_")]
+    t0, t1 = kb[0][0], kb[-1][1]
+    phase = [r for r in rows if r[0] >= t0 and r[1] <= t1]
+    busy = sum(b - a for a, b, _ in phase)
+    per = collections.defaultdict(lambda: [0, 0])
+    for a, b, n in phase:
+        per[short(n)][0] += 1
+        per[short(n)][1] += b - a
+    # steps: each batched step ends with its kb_finish
+    steps, cur, start = [], collections.Counter(), None
+    for a, b, n in kb:
+        start = a if start is None else start
+        cur[step_kind(n)] += b - a
+        if step_kind(n) == "kb_finish":
+            steps.append((start, b, cur))
+            cur, start = collections.Counter(), None
+    ser = collections.defaultdict(lambda: [0, 0])
+    for a, b, n in rows:
+        k = step_kind(n)
+        if b < t0 and k in ("k_forward", "k_back_update", "k_eg_finish"):
+            ser[k][0] += 1
+            ser[k][1] += b - a
+    md = ["# Kernel times of the batched leg (64 scans to natural residual 1e-4)", "",
+          "The benchmark's batched leg alone: 64 uneven scans (N in {128..768}, 30-360",
+          "views, 10-64 energy bins, 2-4 windows; seed 401), each solved to rho <= 1e-4",
+          "one at a time (serial) and then all together in one batch.  Command (from",
+          "the repository root, TMPDIR=/tmp; the raw trace stays on the GPU box):", "",
+          "```", BATCHED_TRACE, "```", "",
+          "Summarised by `python -m paper_2503_19925_amd.profsum batched "
+          "<trace dir>/b_kernel_trace.csv <bench stderr> <out.md>`.", "",
+          "Wall time in this (profiled) run: serial %.2f s, batched %.2f s.  The profiler" % (
+              t_ser, t_bat),
+          "adds a cost to every dispatch, and the serial leg makes about 40 times as many",
+          "as the batched one, so these walls are not the benchmark's; the kernel times",
+          "below are the comparison.", "",
+          "**Batched phase** (first to last batched kernel): %.3f s, of which kernels %.3f s "
+          "(%.1f %% busy), %d dispatches, %d steps." % (
+              (t1 - t0) / 1e9, busy / 1e9, 100.0 * busy / (t1 - t0), len(phase), len(steps)), "",
+          "| kernel | calls | avg (us) | total (s) |", "|---|---|---|---|"]
+    for k, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        md.append("| %s | %d | %.2f | %.3f |" % (k, c, t / c / 1e3, t / 1e9))
+    md += ["", "Per batched step, by share of the steps (scans drop out as they converge):",
+           "", "| steps | time (s) | per step (us) | forwards (us) | back + update (us) |",
+           "|---|---|---|---|---|"]
+    n = len(steps)
+    for lo, hi in ((0, 0.5), (0.5, 0.8), (0.8, 0.9), (0.9, 1.0)):
+        seg = steps[int(lo * n):int(hi * n)]
+        if not seg:
+            continue
+        tot = sum(b - a for a, b, _ in seg)
+        fw = sum(c.get("kb_forward", 0) for _, _, c in seg)
+        bu = sum(c.get("kb_back_update", 0) for _, _, c in seg)
+        md.append("| %d-%d | %.3f | %.1f | %.1f | %.1f |" % (
+            int(lo * n), int(hi * n), tot / 1e9, tot / len(seg) / 1e3, fw / len(seg) / 1e3,
+            bu / len(seg) / 1e3))
+    md += ["", "**Serial leg's kernels** (every single-scan step kernel before the batched "
+           "phase; the run's few other solve_512 steps are among them):", "",
+           "| kernel | calls | avg (us) | total (s) |", "|---|---|---|---|"]
+    for k in ("k_forward", "k_back_update", "k_eg_finish"):
+        if k in ser:
+            c, t = ser[k]
+            md.append("| %s | %d | %.2f | %.3f |" % (k, c, t / c / 1e3, t / 1e9))
+    per_kind = collections.Counter()
+    for a, b, nme in phase:
+        per_kind[step_kind(nme)] += b - a
+    md += ["", "Batched against serial kernel time: forwards %.2fx, back-projection + "
+           "update %.2fx." % (ser["k_forward"][1] / max(per_kind["kb_forward"], 1),
+                              ser["k_back_update"][1] / max(per_kind["kb_back_update"], 1))]
+    with open(out, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote", out)
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a[:1] == ["counters"] and len(a) == 3:
@@ -445,5 +546,7 @@ if __name__ == "__main__":
         cmd_utilisation(a[1])
     elif a[:1] == ["tests"] and len(a) == 3:
         cmd_tests(a[1], a[2])
+    elif a[:1] == ["batched"] and len(a) in (3, 4):
+        cmd_batched(a[1], a[2], a[3] if len(a) == 4 else None)
     else:
         raise SystemExit(__doc__)
