@@ -250,9 +250,10 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 
 // A forward lane takes two adjacent rays of a view.  On every line the ray
 // with the lower crossing (in columns) is at flo and the other at fhi =
-// flo + |P|, both advanced exactly by Q per line.  The crossings lie on the
-// 2^-32 grid with |f| < 2^20, so the lane holds them as 64-bit integers F =
-// f 2^32: the high word is floor(f) and the low word is 2^32 (f -
+// flo + |P|, both advanced exactly by Q per line (kMode 2 keeps both; kMode
+// 0 and 1 keep flo only and derive the other, below).  The crossings lie on
+// the 2^-32 grid with |f| < 2^20, so the lane holds them as 64-bit integers
+// F = f 2^32: the high word is floor(f) and the low word is 2^32 (f -
 // floor(f)), and F += Q 2^32 is exact.  Each ray's taps are the single-ray
 // rule's: columns floor(f) and floor(f) + 1 with weights (float)(1 - e) and
 // (float)e, e = f - floor(f), the column clamped into the padded row (every
@@ -269,10 +270,10 @@ __device__ __forceinline__ float at(const float *__restrict__ base, unsigned i)
 // crossing: with |P| 2^32 = kMode 2^32 + p (p < 2^32), the upper ray's low
 // word is lo + p mod 2^32 and its column is c + d, d = kMode + the carry of
 // that add, so the carry selects between the two offsets.  If c is clamped
-// (f < 0 or f > cmax), both rays' taps lie in the padding, and the columns
-// c + d, c + d + 1 read in place of the upper ray's are padding too (at the
-// row's start kPadX >= 3 zero columns; at its end the last two padded
-// columns and the next row's first, or the buffer's zero tail).  An
+// (floor(f) < 0 or floor(f) > cmax), both rays' taps lie in the padding, and
+// the columns c + d, c + d + 1 read in place of the upper ray's are padding
+// too (at the row's start kPadX >= 3 zero columns; at its end the last two
+// padded columns and the next row's first, or the buffer's zero tail).  An
 // unclamped c whose upper ray passes cmax reads the same padding columns
 // the clamped column would.
 // Lanes read neighbouring columns, and this one load serves two rays: the
