@@ -543,8 +543,7 @@ int exact_forward(exact_geometry g, const float *x_dev, float *s_dev, void *stre
         hipStream_t st = (hipStream_t)stream;
         const size_t dp = (size_t)exact::padded_image_floats(g->N);
         AsyncBuf xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st);
-        hip_check(hipMemsetAsync(xp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
-        hip_check(hipMemsetAsync(xTp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        // the pad kernel writes the pair's zero padding too
         hip_check(exact::launch_pad_pair(x_dev, xp.as<float>(), xTp.as<float>(), g->N, st),
                   "pad_pair");
         hip_check(exact::launch_forward(geo_of(g), xp.as<float>(), xTp.as<float>(), s_dev, g->B, 0,
@@ -563,7 +562,7 @@ int exact_backproject(exact_geometry g, const float *r_dev, float *img_dev, void
         hipStream_t st = (hipStream_t)stream;
         const size_t np = (size_t)g->V * exact::padded_bins(g->B);
         AsyncBuf rw(np * sizeof(float), st);
-        hip_check(hipMemsetAsync(rw.p, 0, np * sizeof(float), st), "hipMemsetAsync");
+        // the weighing kernel writes the rows' zero padding too
         hip_check(exact::launch_weigh_rows(geo_of(g), r_dev, rw.as<float>(), st), "weigh_rows");
         hip_check(exact::launch_back(geo_of(g), rw.as<float>(), img_dev, 1.0f, nullptr, st),
                   "back");
@@ -585,8 +584,8 @@ int exact_operator(exact_geometry g, const exact_spectrum *sp, const float *y_de
         const size_t np = (size_t)g->V * exact::padded_bins(g->B);
         AsyncBuf Y(n * sizeof(float), st), xp(dp * sizeof(float), st), xTp(dp * sizeof(float), st),
             rp(np * sizeof(float), st);
-        hip_check(hipMemsetAsync(xp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
-        hip_check(hipMemsetAsync(xTp.p, 0, dp * sizeof(float), st), "hipMemsetAsync");
+        // the pad kernel writes the image pair's zero padding; the forward
+        // writes only the residual's interior bins, so its padding is cleared
         hip_check(hipMemsetAsync(rp.p, 0, np * sizeof(float), st), "hipMemsetAsync");
         hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, Y.as<float>(), nullptr, st),
                   "window_sum");
@@ -667,10 +666,9 @@ int exact_operator_noalloc(exact_geometry g, const exact_spectrum *sp, const flo
         float *rp = reinterpret_cast<float *>(base + orp);
         hipStream_t st = (hipStream_t)stream;
         // the array keeps the previous call's contents: the padding the
-        // projectors read must be zero again (fill kernels, not memsets, so
-        // that the call can be captured into a graph)
-        hip_check(exact::launch_fill(xp, 0.f, (long)dp, st), "fill");
-        hip_check(exact::launch_fill(xTp, 0.f, (long)dp, st), "fill");
+        // projectors read must be zero again.  The pad kernel writes the
+        // image pair's padding; the residual's is cleared by a fill kernel
+        // (not a memset, so that the call can be captured into a graph).
         hip_check(exact::launch_fill(rp, 0.f, (long)np, st), "fill");
         hip_check(exact::launch_window_sum(y_dev, sp->n_windows, n, Y, nullptr, st), "window_sum");
         hip_check(exact::launch_pad_pair(x_dev, xp, xTp, g->N, st), "pad_pair");

@@ -820,15 +820,19 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back(
 }
 
 // rw[vidx][kPadB + b] = wstep * r[vidx][b] for the view in table slot
-// blockIdx.y (the padding of rw is zero already).
+// blockIdx.y, and the row's 2 kPadB padding bins set to zero (by the row's
+// first block), so rw needs no clearing before.
 __global__ __launch_bounds__(256) void k_weigh_rows(const ViewGeom *__restrict__ views, int B,
                                                     const float *__restrict__ r,
                                                     float *__restrict__ rw)
 {
     const ViewGeom G = views[blockIdx.y];
     const int b = blockIdx.x * 256 + threadIdx.x;
+    float *row = rw + (size_t)G.vidx * padded_bins(B);
     if (b < B)
-        rw[(size_t)G.vidx * padded_bins(B) + kPadB + b] = r[(size_t)G.vidx * B + b] * G.wstep;
+        row[kPadB + b] = r[(size_t)G.vidx * B + b] * G.wstep;
+    if (blockIdx.x == 0 && threadIdx.x < 2 * kPadB)
+        row[threadIdx.x < kPadB ? threadIdx.x : B + threadIdx.x] = 0.f;
 }
 
 // The projected update on one 16 x 16 tile once g = scale (A^T r) is known
@@ -905,8 +909,11 @@ __global__ __launch_bounds__(kBackX *kBackY * 2) void k_back_update(
 
 // ------------------------------------------------------ elementwise / tiles
 
-// x into the padded pair: row-major copy xp and transpose xTp (interiors;
-// the padding is zero already), the transpose through an LDS tile.
+// x into the padded pair: row-major copy xp and transpose xTp, the
+// transpose through an LDS tile; the padding (kPadX columns at each end of
+// every row, and the kImgTail floats after the last row) is set to zero
+// too, grid-stride over its N 2 kPadX + kImgTail floats per buffer, so the
+// pair needs no clearing before.
 __global__ __launch_bounds__(kTile * 8) void k_pad_pair(const float *__restrict__ x,
                                                         float *__restrict__ xp,
                                                         float *__restrict__ xTp, int N)
@@ -914,6 +921,24 @@ __global__ __launch_bounds__(kTile * 8) void k_pad_pair(const float *__restrict_
     __shared__ float tile[kTile][kTile + 1];
     const int Np = padded_cols(N);
     const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+    {
+        const long edge = (long)N * 2 * kPadX, pad = edge + kImgTail;
+        const long nthr = (long)gridDim.x * gridDim.y * blockDim.x * blockDim.y;
+        for (long k = ((long)blockIdx.y * gridDim.x + blockIdx.x) * (blockDim.x * blockDim.y) +
+                      threadIdx.y * blockDim.x + threadIdx.x;
+             k < pad; k += nthr) {
+            long a;
+            if (k < edge) {
+                const long row = k / (2 * kPadX);
+                const int c = (int)(k % (2 * kPadX));
+                a = row * Np + (c < kPadX ? c : N + c);   // right padding: kPadX + N + (c - kPadX)
+            } else {
+                a = (long)N * Np + (k - edge);
+            }
+            xp[a] = 0.f;
+            xTp[a] = 0.f;
+        }
+    }
     for (int rr = threadIdx.y; rr < kTile; rr += 8) {
         const int iy = by + rr, ix = bx + threadIdx.x;
         if (iy < N && ix < N) {
