@@ -1614,8 +1614,9 @@ void validate_tv_opts(const exact_tv_opts &o)
 // Device work of the TV projection for one image size: the FGP fields, the
 // TV-ball and Dykstra buffers and the reduction results.  A proximal solve
 // is a short run of kernel launches (the weight a kernel argument) ending in
-// the point's TV, which the last kernel writes to pinned host memory; the
-// host waits for the stream and reads it.  A search keeps its current
+// the point's TV, which the last kernel writes to pinned host memory, and
+// after it a sequence word; the host polls that word (no wake-up latency of
+// a blocking stream wait) and reads the result.  A search keeps its current
 // result in one of two output buffers and solves into the other, so keeping
 // a point moves no data.
 struct TvWork {
@@ -1623,8 +1624,11 @@ struct TvWork {
     long d = 0;
     exact_tv_opts o;
     std::unique_ptr<DevBuf> p, q, r, s, p2, q2, r2, s2, xb[2], w, z, dp, dq, parts;
-    double *h = nullptr;       // pinned, coherent: [1..2] reduction results
+    double *h = nullptr;       // pinned, coherent: [1..2] reduction results, [3] the sequence word
     double *hd = nullptr;      // its device address
+    unsigned *fh = nullptr;    // the sequence word, host address
+    unsigned *fd = nullptr;    // and device address
+    unsigned seq = 0;          // the last sequence number handed out
     int solves = 0;
 
     TvWork(int n, const exact_tv_opts &opts, hipStream_t) : N(n), d((long)n * n), o(opts)
@@ -1636,6 +1640,9 @@ struct TvWork {
         hip_check(hipHostMalloc((void **)&h, 32, hipHostMallocMapped | hipHostMallocCoherent),
                   "hipHostMalloc");
         hip_check(hipHostGetDevicePointer((void **)&hd, h, 0), "hipHostGetDevicePointer");
+        fh = reinterpret_cast<unsigned *>(h + 3);
+        fd = reinterpret_cast<unsigned *>(hd + 3);
+        __atomic_store_n(fh, 0u, __ATOMIC_RELEASE);
     }
     ~TvWork()
     {
@@ -1643,28 +1650,57 @@ struct TvWork {
             (void)hipHostFree(h);
     }
 
-    // The reduction result(s) the stream's last kernels wrote to h[1..2].
-    double sync1(hipStream_t st)
+    // The next sequence number (never 0, the word's initial value).
+    unsigned next()
     {
-        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (++seq == 0)
+            ++seq;
+        return seq;
+    }
+    // Waits until the kernel that writes sequence number `want` has posted
+    // it, by polling the pinned word.  After 2 s without it, a stream
+    // synchronize waits for the stream and reports any error, and the word
+    // must then hold `want`.
+    void wait(unsigned want, hipStream_t st)
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (long spin = 1;; ++spin) {
+            if (__atomic_load_n(fh, __ATOMIC_ACQUIRE) == want)
+                return;
+            if (spin % 4096 == 0 &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                if (__atomic_load_n(fh, __ATOMIC_ACQUIRE) != want)
+                    fail(-EIO, "a TV reduction result was not posted");
+                return;
+            }
+        }
+    }
+    // The reduction result the kernel posting `want` wrote to h[1].
+    double sync1(unsigned want, hipStream_t st)
+    {
+        wait(want, st);
         return h[1];
     }
     double tv_of(const float *img, hipStream_t st)
     {
-        hip_check(exact::launch_tv_norm(img, N, parts->as<double>(), hd + 1, st), "tv_norm");
-        return sync1(st);
+        const unsigned q1 = next();
+        hip_check(exact::launch_tv_norm(img, N, parts->as<double>(), hd + 1, st, fd, q1),
+                  "tv_norm");
+        return sync1(q1, st);
     }
     // xb[k] = TV-regularized point of w for weight l; returns TV(xb[k]).
     double solve(int k, double l, hipStream_t st)
     {
+        const unsigned q1 = next();
         hip_check(exact::launch_prox(w->as<float>(), p->as<float>(), q->as<float>(),
                                      r->as<float>(), s->as<float>(), p2->as<float>(),
                                      q2->as<float>(), r2->as<float>(), s2->as<float>(), l,
                                      o.prox_iters, xb[k]->as<float>(), N, parts->as<double>(),
-                                     hd + 1, st),
+                                     hd + 1, st, fd, q1),
                   "prox");
         ++solves;
-        return sync1(st);
+        return sync1(q1, st);
     }
     void copy(float *dst, const float *src, hipStream_t st)
     {
@@ -1776,15 +1812,17 @@ struct TvWork {
         hip_check(hipMemsetAsync(qp, 0, (size_t)d * 4, st), "hipMemsetAsync");
         int k = 0;
         while (k < o.max_outer) {
+            const unsigned q1 = next();
             hip_check(exact::launch_dyk_pre(zp, pp, w->as<float>(), N, parts->as<double>(),
-                                            hd + 1, st),
+                                            hd + 1, st, fd, q1),
                       "dyk_pre");
-            const float *y = tv_ball(tau, sync1(st), st);
+            const float *y = tv_ball(tau, sync1(q1, st), st);
+            const unsigned q2 = next();
             hip_check(exact::launch_dyk_post(w->as<float>(), y, pp, qp, zp, d,
-                                             parts->as<double>(), hd + 1, st),
+                                             parts->as<double>(), hd + 1, st, fd, q2),
                       "dyk_post");
             ++k;
-            if (std::sqrt(sync1(st)) <= o.dyk_tol)
+            if (std::sqrt(sync1(q2, st)) <= o.dyk_tol)
                 break;
         }
         copy(outp, zp, st);
@@ -1881,6 +1919,7 @@ int exact_project_tv(int32_t n_pix, const float *z_dev, double tau, const exact_
         TvWork W(n_pix, o, own.st);
         const int rounds = W.project(z_dev, out_dev, tau, own.st);
         const double tv = W.tv_of(out_dev, own.st);
+        hip_check(hipStreamSynchronize(own.st), "hipStreamSynchronize");
         if (info) {
             info->rounds = rounds;
             info->solves = W.solves;
@@ -1936,10 +1975,11 @@ int exact_solve_tv(exact_geometry g, const exact_spectrum *sp, const float *y_de
             hip_check(exact::launch_pad_pair(xh.as<float>(), p.xhp->as<float>(), p.xhTp->as<float>(),
                                              g->N, st),
                       "pad_pair");
+            const unsigned q1 = W.next();
             hip_check(exact::launch_diff2(xh.as<float>(), x_dev, d, W.parts->as<double>(),
-                                          W.hd + 1, st),
+                                          W.hd + 1, st, W.fd, q1),
                       "diff2");
-            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            W.wait(q1, st);
             rho = W.h[2] > 0.0 ? std::sqrt(W.h[1] / W.h[2]) : -1.0;
             gradient(p.xhp->as<float>(), p.xhTp->as<float>());
             hip_check(exact::launch_axpy(x_dev, grad.as<float>(), gf, v.as<float>(), d, st), "axpy");

@@ -294,26 +294,33 @@ int num_flat_parts(long d);     // partial sums of the flat reductions
 // (>= 1) FGP steps from zero, and out[0] = TV(x) in double (parts:
 // num_tv_parts(N)).  p, q, r, s and p2, q2, r2, s2 are work fields of N*N
 // floats (the state alternates between the two sets); out may be pinned
-// host memory's device address.  Launch sequence only.
+// host memory's device address.  Launch sequence only.  Here and in the
+// launchers below that write a result to out: with flag not null (pinned
+// host memory's device address), the last kernel then writes seq to *flag,
+// ordered after the result at system scope, for a host that polls.
 hipError_t launch_prox(const float *b, float *p, float *q, float *r, float *s, float *p2,
                        float *q2, float *r2, float *s2, double lam, int iters, float *x, int N,
-                       double *parts, double *out, hipStream_t st);
+                       double *parts, double *out, hipStream_t st, unsigned *flag = nullptr,
+                       unsigned seq = 0);
 // out[0] = TV(x) in double (parts: num_tv_parts(N) doubles; out may be
 // pinned host memory's device address, as for the Dykstra sums below).
-hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st);
+hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st,
+                          unsigned *flag = nullptr, unsigned seq = 0);
 // Dykstra's round around the TV projection: w = z + p and out[0] = TV(w)
 // before it (parts: num_tv_parts(N)); after it p = w - y, z = max(0, y + q),
 // q = y + q - z and out[0] = ||z_new - z_old||^2.
 hipError_t launch_dyk_pre(const float *z, const float *p, float *w, int N, double *parts,
-                          double *out, hipStream_t st);
+                          double *out, hipStream_t st, unsigned *flag = nullptr,
+                          unsigned seq = 0);
 hipError_t launch_dyk_post(const float *w, const float *y, float *p, float *q, float *z, long d,
-                           double *parts, double *out, hipStream_t st);
+                           double *parts, double *out, hipStream_t st, unsigned *flag = nullptr,
+                           unsigned seq = 0);
 // z = x - gamma g.
 hipError_t launch_axpy(const float *x, const float *g, float gamma, float *z, long d,
                        hipStream_t st);
 // out[0] = ||a - b||^2, out[1] = ||b||^2 in double (parts: 2 num_flat_parts(d)).
 hipError_t launch_diff2(const float *a, const float *b, long d, double *parts, double *out,
-                        hipStream_t st);
+                        hipStream_t st, unsigned *flag = nullptr, unsigned seq = 0);
 
 // ---- dense measurement matrix (exact_dense.hip)
 

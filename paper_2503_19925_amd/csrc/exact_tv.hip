@@ -237,17 +237,31 @@ __global__ __launch_bounds__(kTvX *kTvY) void k_tv_parts(const float *__restrict
         parts[blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
-// out[0] = fixed-order sum of parts[0..n).
+// After a finish kernel's results: with flag not null, seq to *flag, ordered
+// after the results at system scope, so that a host polling pinned memory
+// for seq can read the results as soon as it sees it.
+__device__ __forceinline__ void post_seq(unsigned *flag, unsigned seq)
+{
+    if (flag) {
+        __threadfence_system();
+        __hip_atomic_store(flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// out[0] = fixed-order sum of parts[0..n); then post_seq.
 __global__ __launch_bounds__(kTvRed) void k_sum_finish(const double *__restrict__ parts, int n,
-                                                       double *__restrict__ out)
+                                                       double *__restrict__ out, unsigned *flag,
+                                                       unsigned seq)
 {
     __shared__ double red[kTvRed];
     double v = 0.0;
     for (int k = threadIdx.x; k < n; k += kTvRed)
         v += parts[k];
     v = block_sum1(v, red);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         out[0] = v;
+        post_seq(flag, seq);
+    }
 }
 
 // w = z + p, and per-block double sums of |grad w| as k_tv_parts forms
@@ -331,8 +345,10 @@ __global__ __launch_bounds__(kTvRed) void k_diff2(const float *__restrict__ a,
     }
 }
 
+// out[0..1] = fixed-order sums of parts[2k] and parts[2k + 1]; then post_seq.
 __global__ __launch_bounds__(kTvRed) void k_sum2_finish(const double *__restrict__ parts, int n,
-                                                        double *__restrict__ out)
+                                                        double *__restrict__ out, unsigned *flag,
+                                                        unsigned seq)
 {
     __shared__ double red[kTvRed];
     double a = 0.0, b = 0.0;
@@ -346,6 +362,7 @@ __global__ __launch_bounds__(kTvRed) void k_sum2_finish(const double *__restrict
     if (threadIdx.x == 0) {
         out[0] = a;
         out[1] = b;
+        post_seq(flag, seq);
     }
 }
 
@@ -369,7 +386,7 @@ int num_flat_parts(long d) { return flat_blocks(d); }
 
 hipError_t launch_prox(const float *b, float *p, float *q, float *r, float *s, float *p2,
                        float *q2, float *r2, float *s2, double lam, int iters, float *x, int N,
-                       double *parts, double *out, hipStream_t st)
+                       double *parts, double *out, hipStream_t st, unsigned *flag, unsigned seq)
 {
     const dim3 grid((N + kFgpTile - 1) / kFgpTile, (N + kFgpTile - 1) / kFgpTile);
     double t = 1.0;
@@ -394,31 +411,36 @@ hipError_t launch_prox(const float *b, float *p, float *q, float *r, float *s, f
     }
     hipLaunchKernelGGL(k_fgp_final, tv_grid(N), dim3(kTvX, kTvY), 0, st, b, p, q, lam, x, N,
                        parts);
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out);
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out,
+                       flag, seq);
     return hipGetLastError();
 }
 
-hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st)
+hipError_t launch_tv_norm(const float *x, int N, double *parts, double *out, hipStream_t st,
+                          unsigned *flag, unsigned seq)
 {
     hipLaunchKernelGGL(k_tv_parts, tv_grid(N), dim3(kTvX, kTvY), 0, st, x, N, parts);
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out);
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out,
+                       flag, seq);
     return hipGetLastError();
 }
 
 hipError_t launch_dyk_pre(const float *z, const float *p, float *w, int N, double *parts,
-                          double *out, hipStream_t st)
+                          double *out, hipStream_t st, unsigned *flag, unsigned seq)
 {
     hipLaunchKernelGGL(k_dyk_pre, tv_grid(N), dim3(kTvX, kTvY), 0, st, z, p, N, w, parts);
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out);
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, num_tv_parts(N), out,
+                       flag, seq);
     return hipGetLastError();
 }
 
 hipError_t launch_dyk_post(const float *w, const float *y, float *p, float *q, float *z, long d,
-                           double *parts, double *out, hipStream_t st)
+                           double *parts, double *out, hipStream_t st, unsigned *flag,
+                           unsigned seq)
 {
     const int nb = flat_blocks(d);
     hipLaunchKernelGGL(k_dyk_post, dim3(nb), dim3(kTvRed), 0, st, w, y, p, q, z, d, parts);
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, nb, out);
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kTvRed), 0, st, parts, nb, out, flag, seq);
     return hipGetLastError();
 }
 
@@ -430,11 +452,11 @@ hipError_t launch_axpy(const float *x, const float *g, float gamma, float *z, lo
 }
 
 hipError_t launch_diff2(const float *a, const float *b, long d, double *parts, double *out,
-                        hipStream_t st)
+                        hipStream_t st, unsigned *flag, unsigned seq)
 {
     const int nb = flat_blocks(d);
     hipLaunchKernelGGL(k_diff2, dim3(nb), dim3(kTvRed), 0, st, a, b, d, parts);
-    hipLaunchKernelGGL(k_sum2_finish, dim3(1), dim3(kTvRed), 0, st, parts, nb, out);
+    hipLaunchKernelGGL(k_sum2_finish, dim3(1), dim3(kTvRed), 0, st, parts, nb, out, flag, seq);
     return hipGetLastError();
 }
 

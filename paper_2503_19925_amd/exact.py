@@ -94,6 +94,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libexact.so is not built (%s); run "
                           "`python -m paper_2503_19925_amd.build`" % LIB_PATH)
+    # torch first: the library then binds to the HIP runtime torch loaded.
+    # Loaded the other way round, the process holds two HIP runtimes and
+    # torch finds no GPU.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
     sig = {
