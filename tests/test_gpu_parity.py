@@ -83,6 +83,11 @@ SMALL_SHAPES = [
     ("wide_bins_130", 128, 29, 140, 1.3, 1),
     ("narrow_bins_130", 128, 29, 260, 0.7, 1),
     ("mixed_rules_bins", 96, 40, 80, 1.6, 1),
+    # detectors far wider than the image, so that most lanes' crossings are
+    # clamped into the padding on one side or the other, under each rule:
+    # |P| in [1.5, 2.1] (two-tap and separate loads), [0.5, 0.71] (|P| < 1)
+    ("mostly_missed_wide_bins", 24, 9, 180, 1.5, 1),
+    ("mostly_missed_narrow_bins", 20, 7, 300, 0.5, 1),
 ]
 
 
