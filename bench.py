@@ -224,9 +224,11 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q))
 
 
-def batched_leg(count, torch, exact, synth):
+def batched_leg(count, torch, exact, synth, serial=True):
     """Same scans, one at a time and batched; wall time includes each scan's
-    set-up (validation, power iteration) on both sides."""
+    set-up (validation, power iteration) on both sides.  serial = False skips
+    the one-at-a-time pass (for profiling the batched kernels alone); the
+    serial figures and the bitwise comparison are then None."""
     tol, cap = 1e-4, 5000
     Ps = [synth.make_problem("batch%d" % i, with_truth=False, **d)
           for i, d in enumerate(synth.batch_draws(count, 401))]
@@ -236,7 +238,7 @@ def batched_leg(count, torch, exact, synth):
     log("batched leg: %d scans generated" % count)
     xs_serial, iters_serial, done_serial = [], [], []
     t0 = time.perf_counter()
-    for P, g, y in zip(Ps, geos, ys):
+    for P, g, y in (zip(Ps, geos, ys) if serial else ()):
         x = torch.zeros(g.d, device="cuda")
         info = exact.exact_solve(g, P.mu, P.I, y, x, max_iters=cap, tol=tol, check_every=32)
         if len(xs_serial) % 16 == 15:
@@ -244,8 +246,9 @@ def batched_leg(count, torch, exact, synth):
         xs_serial.append(x)
         iters_serial.append(info["iters"])
         done_serial.append(time.perf_counter() - t0)
-    t_serial = time.perf_counter() - t0
-    log("serial: %.2f s" % t_serial)
+    t_serial = time.perf_counter() - t0 if serial else None
+    if serial:
+        log("serial: %.2f s" % t_serial)
     footprint = sum(exact.exact_run_footprint(P.n_pix, P.n_views, P.n_bins) for P in Ps)
     xs = [torch.zeros(g.d, device="cuda") for g in geos]
     torch.cuda.synchronize()
@@ -264,18 +267,21 @@ def batched_leg(count, torch, exact, synth):
     stats = [b.poll(s) for s in slots]
     b.close()
     log("batched: %.2f s" % t_batch)
-    same = all(st[1]["iters"] == it for st, it in zip(stats, iters_serial)) and \
-        all(torch.equal(a, c) for a, c in zip(xs, xs_serial))
+    same = (all(st[1]["iters"] == it for st, it in zip(stats, iters_serial)) and
+            all(torch.equal(a, c) for a, c in zip(xs, xs_serial))) if serial else None
     capped = sum(1 for st in stats if st[0] == exact.CAPPED)
     for g in geos:
         g.close()
     t_done = [done_at[s] for s in slots]
     return {"scans": count, "tol": tol, "max_iters": cap,
-            "serial_recon_per_s": count / t_serial, "batched_recon_per_s": count / t_batch,
-            "speedup": t_serial / t_batch, "bitwise_equal_to_serial": bool(same),
-            "capped": capped, "mean_iters": sum(iters_serial) / count,
+            "serial_recon_per_s": count / t_serial if serial else None,
+            "batched_recon_per_s": count / t_batch,
+            "speedup": t_serial / t_batch if serial else None,
+            "bitwise_equal_to_serial": bool(same) if serial else None,
+            "capped": capped, "mean_iters": sum(st[1]["iters"] for st in stats) / count,
             "batched_p50_s": pct(t_done, 50), "batched_p99_s": pct(t_done, 99),
-            "serial_p50_s": pct(done_serial, 50), "serial_p99_s": pct(done_serial, 99)}
+            "serial_p50_s": pct(done_serial, 50) if serial else None,
+            "serial_p99_s": pct(done_serial, 99) if serial else None}
 
 
 def tv_leg(P, gamma, steps, torch, exact, synth):
@@ -505,6 +511,8 @@ def main():
                     help="timed steps of the workload with known materials (0 to skip)")
     ap.add_argument("--served", type=int, default=300,
                     help="requests in the served leg (0 to skip)")
+    ap.add_argument("--batch-serial", type=int, default=1,
+                    help="0: skip the batched leg's one-at-a-time pass (profiling)")
     ap.add_argument("--served-serial", type=int, default=1,
                     help="also serve the stream one request at a time (0 to skip)")
     ap.add_argument("--served-policy", default="sjf", choices=("sjf", "fcfs"),
@@ -659,7 +667,8 @@ def main():
 
     dense = dense_leg(4096, 20, args.dense_steps, torch, exact) if args.dense_steps > 0 else None
 
-    batched = batched_leg(args.batch, torch, exact, synth) if args.batch > 0 else None
+    batched = (batched_leg(args.batch, torch, exact, synth, serial=args.batch_serial > 0)
+               if args.batch > 0 else None)
     served = (served_leg(args.served, torch, exact, synth, serial=args.served_serial > 0,
                          policy=args.served_policy,
                          work_cap=args.served_cap if args.served_cap > 0 else None,

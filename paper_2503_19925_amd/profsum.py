@@ -16,6 +16,10 @@
     python -m paper_2503_19925_amd.profsum tests <kernel_stats.csv> <pytest log>
         a kernel trace of the GPU test suite -> profiles/kernels_gpu_tests.md,
         checked against every kernel compiled into libexact.so.
+    python -m paper_2503_19925_amd.profsum batched_counters <counter csv> [out.md]
+        one counter pass (BATCHED_PMC) over the batched leg alone ->
+        out.md (default profiles/counters_batched.md): VALU issue and waves
+        resident of the batched kernels.
     python -m paper_2503_19925_amd.profsum batched <kernel_trace.csv> <bench stderr> [out.md]
         a kernel trace of the benchmark's batched leg (BATCHED_TRACE) -> out.md
         (default profiles/kernels_batched.md): the batched phase's busy time,
@@ -60,6 +64,11 @@ BATCHED_TRACE = ("rocprofv3 --kernel-trace --output-format csv -d <trace dir> -o
                  "bench.py --steps 5 --warmup 2 --proj-reps 2 --kernel-reps 2 --cpu-steps 0 "
                  "--tv-steps -1 --dense-steps 0 --background-steps 0 --served 0 "
                  "--large-to-tol 0 --batch 64 2> <bench stderr>")
+BATCHED_PMC_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE"
+BATCHED_PMC = ("timeout -s KILL 300 rocprofv3 --pmc " + BATCHED_PMC_COUNTERS + " --output-format csv "
+               "-d <run dir> -o run -- python3 bench.py --steps 5 --warmup 2 --proj-reps 2 "
+               "--kernel-reps 2 --cpu-steps 0 --tv-steps -1 --dense-steps 0 --background-steps 0 "
+               "--served 0 --large-to-tol 0 --batch 64 --batch-serial 0")
 TESTS_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_tests "
                "-o tests -- python3 -u -m pytest tests -m gpu -x -q --timeout 600 "
                "--timeout-method thread")
@@ -536,6 +545,50 @@ def cmd_batched(trace_csv, err_log, out=None):
     print("wrote", out)
 
 
+def cmd_batched_counters(counter_csv, out=None):
+    out = out or os.path.join(PROFILES, "counters_batched.md")
+    per = collections.defaultdict(dict)        # dispatch -> counter -> value
+    meta = {}
+    for r in csv.DictReader(open(counter_csv)):
+        k = step_kind(r["Kernel_Name"])
+        if k not in ("kb_forward", "kb_back_update"):
+            continue
+        d = r["Dispatch_Id"]
+        per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        meta[d] = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]), k)
+    rows = sorted((meta[d][0], meta[d][1], meta[d][2], per[d]) for d in per)
+    md = ["# VALU issue of the batched kernels (hardware counters)", "",
+          "One rocprofv3 counter pass over the benchmark's batched leg alone (64 uneven",
+          "scans to rho <= 1e-4 in one batch, without the one-at-a-time pass).  Command",
+          "(from the repository root, TMPDIR=/tmp):", "", "```", BATCHED_PMC, "```", "",
+          "Summarised by `python -m paper_2503_19925_amd.profsum batched_counters "
+          "<run dir>/run_counter_collection.csv <out.md>`.", "",
+          "Fractions as in `counters_utilisation.md` (1024 SIMDs at the published 2.4 GHz,",
+          "the dispatch's own duration from the counter run; VALU issue at 2 cycles per",
+          "instruction, and at 4), time-weighted over the dispatches of each kind.  Early",
+          "dispatches hold all 64 scans' work; later ones fewer, as scans converge.", "",
+          "| kernel | dispatches | part of the run (by dispatch order) | mean duration (us) | VALU issue "
+          "| VALU at 4 cycles | waves / SIMD |", "|---|---|---|---|---|---|---|"]
+    for k in ("kb_forward", "kb_back_update"):
+        rs = [r for r in rows if r[2] == k]
+        n = len(rs)
+        for lo, hi in ((0.0, 0.5), (0.5, 0.8), (0.8, 1.0), (0.0, 1.0)):
+            seg = rs[int(lo * n):int(hi * n)]
+            if not seg:
+                continue
+            cyc = sum((b - a) for a, b, _, _ in seg) * 1e-9 * CLOCK_GHZ * 1e9
+            valu = sum(c.get("SQ_INSTS_VALU", 0.0) for _, _, _, c in seg)
+            wc = sum(c.get("SQ_WAVE_CYCLES", 0.0) for _, _, _, c in seg)
+            md.append("| %s | %d | %d-%d %% | %.1f | %.0f %% | %.0f %% | %.1f |" % (
+                k, len(seg), round(100 * lo), round(100 * hi),
+                sum((b - a) for a, b, _, _ in seg) / len(seg) / 1e3,
+                100 * valu * 2 / SIMDS / cyc, 100 * valu * 4 / SIMDS / cyc,
+                wc * 4 / SIMDS / cyc))
+    with open(out, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote", out)
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a[:1] == ["counters"] and len(a) == 3:
@@ -546,6 +599,8 @@ if __name__ == "__main__":
         cmd_utilisation(a[1])
     elif a[:1] == ["tests"] and len(a) == 3:
         cmd_tests(a[1], a[2])
+    elif a[:1] == ["batched_counters"] and len(a) in (2, 3):
+        cmd_batched_counters(a[1], a[2] if len(a) == 3 else None)
     elif a[:1] == ["batched"] and len(a) in (3, 4):
         cmd_batched(a[1], a[2], a[3] if len(a) == 4 else None)
     else:
