@@ -18,7 +18,7 @@ bound by VALU instruction issue (no dense contraction, and on-chip reuse
 serves nearly all operand traffic), so the roofline is taken against the
 VALU issue rate: the kernel's VALU lane-instructions per launch (from the
 hardware counter SQ_INSTS_VALU of the committed profile when it was taken on
-this build, else the instruction count of its inner loop) over its average
+the library as built now, else the instruction count of its inner loop) over its average
 launch duration, measured live with HIP events around back-to-back launches
 on the solver's stream.  Beside it: measured HBM bytes and rate, and the
 algorithmic bytes (4 B per nonzero of A), labelled as not a bound.  The CPU
@@ -534,7 +534,7 @@ def main():
                     help="run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
