@@ -408,7 +408,7 @@ def cmd_utilisation(pmc_dir):
 
 def compiled_kernels():
     """Every kernel in libexact.so's device code, from the device assembly of
-    this build's sources."""
+    the library's current sources."""
     names = []
     with tempfile.TemporaryDirectory() as tmp:
         for src in libbuild.SOURCES:
