@@ -52,7 +52,8 @@ def defines(knobs):
 # sources whose text decides what the step's kernels do (the kernels, the
 # shared declarations, and the host code that builds the kernels' tables and
 # work lists)
-KERNEL_SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_internal.h", "csrc/exact_capi.hip"]
+KERNEL_SOURCES = ["csrc/exact_kernels.hip", "csrc/exact_internal.h", "csrc/exact_capi.hip",
+                  "csrc/exact_tables.h"]
 
 
 def build_id(knobs=None):
