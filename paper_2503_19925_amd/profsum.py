@@ -47,13 +47,13 @@ from paper_2503_19925_amd import build as libbuild  # noqa: E402
 
 COPY_MIB = 256
 PMC_COMMAND = ("timeout -s KILL 150 rocprofv3 --pmc <counter> --output-format csv -d "
-               "gpurun_out/pmc/<counter> -o run -- python3 bench.py --steps 5 --warmup 2 "
+               "<out>/pmc/<counter> -o run -- python3 bench.py --steps 5 --warmup 2 "
                "--proj-reps 5 --kernel-reps 5 --batch 0 --served 0 --cpu-steps 0 "
                "--large-to-tol 0 --calibrate-copy-mb 256")
-BENCH_TRACE = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/bench --output-format csv "
+BENCH_TRACE = ("rocprofv3 --kernel-trace --stats -d <out>/prof/bench --output-format csv "
                "-o bench -- python3 bench.py --steps 50 --warmup 5 --cpu-steps 0 --batch 0 "
                "--served 0 --large-to-tol 0 --kernel-reps 20")
-LARGE_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_large "
+LARGE_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_large "
                "-o large -- python3 bench.py --workload large_1024 --steps 10 --warmup 2 "
                "--proj-reps 5 --kernel-reps 5 --batch 0 --served 0 --cpu-steps 0 --tv-steps -1 "
                "--dense-steps 0")
@@ -69,7 +69,7 @@ BATCHED_PMC = ("timeout -s KILL 300 rocprofv3 --pmc " + BATCHED_PMC_COUNTERS + "
                "-d <run dir> -o run -- python3 bench.py --steps 5 --warmup 2 --proj-reps 2 "
                "--kernel-reps 2 --cpu-steps 0 --tv-steps -1 --dense-steps 0 --background-steps 0 "
                "--served 0 --large-to-tol 0 --batch 64 --batch-serial 0")
-TESTS_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_tests "
+TESTS_TRACE = ("rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_tests "
                "-o tests -- python3 -u -m pytest tests -m gpu -x -q --timeout 600 "
                "--timeout-method thread")
 
@@ -121,8 +121,9 @@ def cmd_counters(pmc_dir, workload):
           "(5 timed EG steps, 5 profiled steps, 5 standalone projector calls each, power",
           "iteration, the known-background, TV-ball and dense legs, plus three 256 MiB",
           "device copies for calibration).  From the repository root, TMPDIR=/tmp,",
+          "`<out>` an output directory,",
           "`<counter>` = `FETCH_SIZE`, then `WRITE_SIZE`:", "", "```", PMC_COMMAND, "```", "",
-          "Summarised by `python -m paper_2503_19925_amd.profsum counters gpurun_out/pmc %s`."
+          "Summarised by `python -m paper_2503_19925_amd.profsum counters <out>/pmc %s`."
           % workload, "",
           "**Calibration.** Each 256 MiB copy (262,144 KiB read and written) reads",
           "FETCH_SIZE = %.1f KiB and WRITE_SIZE = %.1f KiB per dispatch, so reads are"
@@ -225,8 +226,9 @@ def cmd_kernels(out_dir):
           "a scratch image), the known-background leg (the same kernels),"
           "the TV-ball leg (k_fgp_steps, k_fgp_final, k_tv_parts, k_dyk_*, and the EG",
           "kernels of two steps) and the dense leg (k_dense_*).", "",
-          "Command (from the repository root, TMPDIR=/tmp):", "", "```", BENCH_TRACE, "```", "",
-          "Summarised by `python -m paper_2503_19925_amd.profsum kernels gpurun_out`.", ""]
+          "Command (from the repository root, TMPDIR=/tmp, `<out>` an output",
+          "directory):", "", "```", BENCH_TRACE, "```", "",
+          "Summarised by `python -m paper_2503_19925_amd.profsum kernels <out>`.", ""]
     md += table(rows)
     b2b = back_to_back(os.path.join(out_dir, "prof", "bench", "bench_kernel_trace.csv"))
     fwd_b = (ph["forward_residual_x"] + ph["forward_residual_xh"]) / 2 * 1e3
@@ -281,8 +283,9 @@ def cmd_kernels(out_dir):
           "1024x1024 image, 720 views over 180 deg, 1448 bins, K=64 energy bins, 4 windows,",
           "I0=1e3.  nnz(A) = 1,357,334,016 (device count); algorithmic bytes per",
           "back-projection 5.43e9.", "",
-          "Command (from the repository root, TMPDIR=/tmp):", "", "```", LARGE_TRACE, "```", "",
-          "Summarised by `python -m paper_2503_19925_amd.profsum kernels gpurun_out`.", ""]
+          "Command (from the repository root, TMPDIR=/tmp, `<out>` an output",
+          "directory):", "", "```", LARGE_TRACE, "```", "",
+          "Summarised by `python -m paper_2503_19925_amd.profsum kernels <out>`.", ""]
     md += table(rl)
     md += ["", "Benchmark line of the same workload (HIP events, not under the profiler):",
            "`%s`:" % LARGE_BENCH,
@@ -313,12 +316,13 @@ UTIL_KERNELS = ("k_forward<true>", "k_back_update<true, true, false>",
 def cmd_utilisation(pmc_dir):
     md = ["# Unit utilisation of the step's kernels (hardware counters)", "",
           "Two rocprofv3 counter passes per workload on a short benchmark run (from",
-          "the repository root, TMPDIR=/tmp; `<workload>` = `solve_512`, then",
+          "the repository root, TMPDIR=/tmp, `<out>` an output directory;",
+          "`<workload>` = `solve_512`, then",
           "`large_1024`; `<pass>` = A, then B):", "", "```",
           "timeout -s KILL 120 rocprofv3 --pmc <counters of the pass> --output-format csv "
-          "-d gpurun_out/pmc3/<workload>_<pass> -o run -- " + UTIL_BENCH, "```", "",
+          "-d <out>/pmc3/<workload>_<pass> -o run -- " + UTIL_BENCH, "```", "",
           "Pass A: `%s`." % UTIL_PASSES["A"], "", "Pass B: `%s`." % UTIL_PASSES["B"], "",
-          "Summarised by `python -m paper_2503_19925_amd.profsum utilisation gpurun_out/pmc3`.",
+          "Summarised by `python -m paper_2503_19925_amd.profsum utilisation <out>/pmc3`.",
           "", "Figures per dispatch (mean over the run's dispatches of the kernel), against",
           "MI355X's 256 CUs (1024 SIMDs) at the published 2.4 GHz peak engine clock; the",
           "duration is the dispatch's own (the counter run's timestamps), so a clock",
@@ -440,9 +444,10 @@ def cmd_tests(stats_csv, log):
           ("No instantiation is left unlaunched: each runs in at least one GPU test\n"
            "whose results are checked.") if not missing else
           "Not launched: %s." % ", ".join(missing), "",
-          "Command (from the repository root, TMPDIR=/tmp):", "", "```", TESTS_TRACE, "```", "",
+          "Command (from the repository root, TMPDIR=/tmp, `<out>` an output",
+          "directory):", "", "```", TESTS_TRACE, "```", "",
           "Summarised by `python -m paper_2503_19925_amd.profsum tests "
-          "gpurun_out/prof_tests/tests_kernel_stats.csv gpurun_out/tests_traced.log`.", "",
+          "<out>/prof_tests/tests_kernel_stats.csv <out>/tests_traced.log`.", "",
           "Result: %s." % result, "", "| kernel | launches |", "|---|---|"]
     md += ["| %s | %d |" % (k, launched.get(k, 0)) for k in allk]
     other = sorted(set(launched) - set(allk))
@@ -498,7 +503,7 @@ def cmd_batched(trace_csv, err_log, out=None):
           "The benchmark's batched leg alone: 64 uneven scans (N in {128..768}, 30-360",
           "views, 10-64 energy bins, 2-4 windows; seed 401), each solved to rho <= 1e-4",
           "one at a time (serial) and then all together in one batch.  Command (from",
-          "the repository root, TMPDIR=/tmp; the raw trace stays on the GPU box):", "",
+          "the repository root, TMPDIR=/tmp; the raw trace is not kept):", "",
           "```", BATCHED_TRACE, "```", "",
           "Summarised by `python -m paper_2503_19925_amd.profsum batched "
           "<trace dir>/b_kernel_trace.csv <bench stderr> <out.md>`.", "",
