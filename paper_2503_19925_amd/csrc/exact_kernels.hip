@@ -298,6 +298,17 @@ __device__ __forceinline__ long long fixed32(double x)
     return (long long)(x * 4294967296.0);
 }
 
+// (float)(2^32 - w) for a low word w = 2^32 e: the weight 1 - e times 2^32,
+// rounded once.  For w > 0 the exact value is the 32-bit integer -w, whose
+// conversion rounds to nearest even as the float cast of the real does; w =
+// 0 gives 2^32 exactly.
+__device__ __forceinline__ float weight_lo(unsigned w)
+{
+    unsigned n;
+    const bool borrow = __builtin_usub_overflow(0u, w, &n);   // w > 0
+    return borrow ? (float)n : 4294967296.0f;
+}
+
 template <int kMode>
 __device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, unsigned pfrac,
                                            int cmax, long long Q,
@@ -324,9 +335,9 @@ __device__ __forceinline__ void pair_fetch(long long &flo, long long &fhi, unsig
         asm("" : "+v"(flo));
     else
         asm("" : "+v"(flo), "+v"(fhi));
-    t.l0 = (float)(4294967296.0 - (double)elo);                // 2^32 (1 - e), rounded once
+    t.l0 = weight_lo(elo);                                     // 2^32 (1 - e), rounded once
     t.l1 = (float)elo;                                         // 2^32 e, rounded once
-    t.h0 = (float)(4294967296.0 - (double)ehi);
+    t.h0 = weight_lo(ehi);
     t.h1 = (float)ehi;
     const unsigned i = (unsigned)(rowoff + clo);
     if (kMode < 2) {

@@ -266,6 +266,44 @@ def test_adjoint_identity_on_gpu(ex):
     g.close()
 
 
+@pytest.mark.parametrize("case", [
+    ("bins_as_wide_as_pixels", 20, 7, 29, 1.0),     # forward: one 16-byte load per lane
+    ("narrow_bins", 20, 7, 60, 0.45),               # |P| < 1; gather over a reach of bins
+    ("wide_bins", 20, 7, 12, 2.5),                  # |P| >= 2: one 8-byte load per ray
+], ids=lambda c: c[0])
+def test_forward_matrix_equals_gather_matrix(ex, case):
+    """Every entry of A, read column by column from the forward projector
+    (one-hot images) and row by row from the gather back-projector (one-hot
+    sinograms), is the same float: both sides form the tent weight 1 - |f - j|
+    exactly and round it once, then multiply by the same float path length,
+    and a one-hot input leaves one nonzero term in every sum."""
+    name, N, V, B, ratio = case
+    say("matrix", name, N, V, B)
+    g = ex.Geometry(N, V, B, pixel_cm=0.1, bin_cm=0.1 * ratio)
+    Af = np.zeros((g.n, g.d), dtype=np.float32)
+    Ab = np.zeros((g.n, g.d), dtype=np.float32)
+    x = torch.zeros(g.d, device=DEV)
+    s = torch.empty(g.n, device=DEV)
+    for j in range(g.d):
+        x.zero_()
+        x[j] = 1.0
+        ex.exact_forward(g, x, s)
+        Af[:, j] = s.cpu().numpy()
+    r = torch.zeros(g.n, device=DEV)
+    img = torch.empty(g.d, device=DEV)
+    for i in range(g.n):
+        r.zero_()
+        r[i] = 1.0
+        ex.exact_backproject(g, r, img)
+        Ab[i, :] = img.cpu().numpy()
+    torch.cuda.synchronize()
+    g.close()
+    assert np.count_nonzero(Af) > 2 * g.n
+    diff = np.nonzero(Af.view(np.uint32) != Ab.view(np.uint32))
+    assert diff[0].size == 0, "%d entries differ; first (ray, pixel) %s: %r vs %r" % (
+        diff[0].size, (diff[0][0], diff[1][0]), Af[diff][0], Ab[diff][0])
+
+
 def test_determinism(ex):
     N, V, B = 128, 45, 182
     say("determinism", N, V, B)
