@@ -162,3 +162,33 @@ def test_clamp_free_pairs_stay_in_the_row(N, V, B, half_turns, ratio, expect):
         T = ((A - PAD_B * P) - j) + k * Q
         bf = np.trunc(-T * (1.0 / P))
         assert bf.min() >= 0 and bf.max() + 1 <= B + 2 * PAD_B - 1
+
+
+def test_forward_lower_weight_from_the_32_bit_negate():
+    """The forward projector forms the lower tap's weight times 2^32, the
+    float of 2^32 - w for the crossing's low word w, as the 32-bit negate -w
+    converted once (and 2^32 itself for w = 0).  For w > 0 the negate is the
+    exact value, so its correctly rounded conversion is the weight: checked
+    here against the definition (the exact value in double, rounded once) on
+    the ends of the range, on every low word whose value sits at or next to
+    a float rounding tie, and on random words."""
+    rng = np.random.default_rng(5)
+    edge = [0, 1, 2, 3, 2 ** 24 - 1, 2 ** 24, 2 ** 24 + 1, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 1,
+            2 ** 32 - 2, 2 ** 32 - 1]
+    ties = []
+    for e in range(24, 33):                 # 2^32 - w in [2^(e-1), 2^e): ulp 2^(e-24)
+        ulp = 2 ** (e - 24)
+        m = rng.integers(2 ** 23, 2 ** 24, size=2000, dtype=np.int64)
+        for off in (-1, 0, 1):
+            v = m * ulp + ulp // 2 + off    # at and next to a tie
+            v = v[(v >= 1) & (v <= 2 ** 32)]
+            ties.append(2 ** 32 - v)
+    w = np.concatenate([np.array(edge, dtype=np.int64)] + ties +
+                       [rng.integers(0, 2 ** 32, size=1 << 20, dtype=np.int64)]).astype(np.uint32)
+    want = (4294967296.0 - w.astype(np.float64)).astype(np.float32)
+    neg = (np.uint32(0) - w).astype(np.uint32)
+    got = np.where(w > 0, neg.astype(np.float32), np.float32(4294967296.0))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    # a plausible slip, rounding the low word before subtracting, is caught
+    slip = np.float32(4294967296.0) - w.astype(np.float32)
+    assert not np.array_equal(slip.view(np.uint32), want.view(np.uint32))
